@@ -1,0 +1,34 @@
+"""CPU float64 oracle of CLAMP's forward-model agent, prior and consensus step.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import or run anything in this package; the
+GPU library never calls it and shares no code with it.
+
+Each function is a plain, slow transcription of the passage it cites in
+"CLAMP: Majorized Plug-and-Play for Coherent 3D Lidar Imaging" (Allen, Rabb,
+Buzzard, Bouman).  numpy's FFT serves as the DFT primitive; everything else is
+written out in the paper's order and notation.
+
+Pinned against closed forms, brute force and invariants (tests/test_oracle_*):
+operator (brute-force DFT, Parseval, adjoint, projector), gradient (finite
+differences), step size (numerical line search, exact decrement), aperture
+ablation (one-step closed form), r-update (exact-prox cubic, sigma^2 -> inf
+limit, monotone on downward moves), Mann iteration (quadratic-agent consensus
+optimum), Gaussian prior (dense circular convolution).  The full trajectory of
+Algorithm 2 on a synthetic scene has no printed value in the paper: parity
+unpinned beyond those invariants and the vanishing consensus error.
+"""
+
+from .operator import (  # noqa: F401
+    pupil_mask, aperture_fraction, dft2, idft2, apply_A, apply_AH, apply_AHA,
+)
+from .agent import (  # noqa: F401
+    noise_floor_weight, h_objective, neg_grad_h, exact_step, cov_diag,
+    qs_prox, forward_agent, beta_schedule,
+)
+from .prior import gaussian_taps, gaussian_smooth  # noqa: F401
+from .mace import (  # noqa: F401
+    agent_weights, weighted_average, mann_step, convergence_error, mu_residual,
+)
+from .clamp import ClampState, clamp_init, clamp_iteration, clamp_run  # noqa: F401
+from .metrics import scale_fit, nrmse, psnr  # noqa: F401
