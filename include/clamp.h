@@ -1,0 +1,212 @@
+/* clamp.h — C ABI of the MI355X (gfx950) CLAMP forward-model library.
+ *
+ * CLAMP ("CLAMP: Majorized Plug-and-Play for Coherent 3D Lidar Imaging",
+ * Allen, Rabb, Buzzard, Bouman) reconstructs a speckle-free reflectivity r
+ * from L coherent looks y_l = A g_l + eta_l with A = D(a) F (Sec. II-B,
+ * eq. A).  This library runs the data-parallel hot path of its MACE loop
+ * (Alg. 2) on one GPU:
+ *   - the aperture operator A, its adjoint A^H and A^H A (clamp_aperture_op);
+ *   - the initialisation of Alg. 2 (clamp_fwd_init);
+ *   - one application of every forward agent: covariance diagonal, one exact
+ *     steepest-descent step on mu_l, quadratic-surrogate r-update of App. A
+ *     (clamp_fwd_agent);
+ *   - a fixed Gaussian smoothing prior agent (clamp_prior_gauss);
+ *   - the Mann consensus step of Alg. 1 with the convergence error
+ *     (clamp_mace_step).
+ *
+ * Conventions shared by every call
+ *   Grid.   A scene is nz range slices of ny x nx pixels, x fastest:
+ *           element (z, y, x) of an image sits at (z*ny + y)*nx + x, which is
+ *           the lexicographic order of Sec. II-B.  Look l of a stacked array
+ *           starts at l*n with n = nx*ny*nz.
+ *   F.      The orthonormal 2D DFT of each range slice, forward kernel
+ *           exp(-2 pi i (u y/ny + v x/nx)) / sqrt(nx ny).  (With a range
+ *           aperture that passes every range frequency this equals the
+ *           paper's 3D operator up to a unitary change of data coordinates.)
+ *   Pupil.  a[u][v] = 1 where su^2 + sv^2 <= R^2 in signed DFT indices
+ *           (su = u for u < ny/2, else u - ny), or a caller-given binary mask.
+ *   Compact pupil layout.  Pupil-plane vectors that the method only ever
+ *           reads on the pupil are stored as P values per slice (P = ||a||_1
+ *           per slice): the pupil samples column by column (v increasing),
+ *           rows u increasing inside a column.  clamp_plan_pupil_index
+ *           returns the u*nx + v position of each of the P entries.
+ *   Types.  complex64 = interleaved float pairs (re, im).  Every array
+ *           argument is a DEVICE pointer owned by the caller unless stated;
+ *           the library never allocates or frees on the calls that take a
+ *           stream, and it never synchronises the stream.  Work is enqueued
+ *           on `hip_stream` (a hipStream_t; NULL = the default stream).
+ *   Workspace.  `workspace` is caller-owned device memory of at least
+ *           clamp_plan_workspace_size bytes, 256-byte aligned; its contents
+ *           are scratch between calls.  Calls that overlap in time need
+ *           separate workspaces.
+ *   Errors.  Arguments are validated before anything is enqueued; an invalid
+ *           argument returns a negative status and enqueues nothing.  A
+ *           failed launch returns CLAMP_EDEVICE.  clamp_last_error gives a
+ *           message for the calling thread's last non-OK status.
+ *           Numerical trouble (non-finite values, r <= 0, gamma < 0) is not a
+ *           status: kernels OR bits into the caller's device fault word.
+ */
+#ifndef CLAMP_H
+#define CLAMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t clamp_status;
+#define CLAMP_OK 0
+#define CLAMP_EINVAL (-1)       /* null pointer, bad scalar, bad index     */
+#define CLAMP_ESHAPE (-2)       /* sizes inconsistent with the plan        */
+#define CLAMP_EUNSUPPORTED (-3) /* FFT length not in the supported set     */
+#define CLAMP_EDEVICE (-4)      /* HIP error (no device, launch failure)   */
+#define CLAMP_ENOMEM (-5)       /* device allocation failed in plan_create */
+
+/* clamp_aperture_op directions (Sec. II-B, eq. A). */
+#define CLAMP_FWD 0     /* out = A x      = D(a) F x                         */
+#define CLAMP_ADJ 1     /* out = A^H x    = F^H D(a) x                       */
+#define CLAMP_NORMAL 2  /* out = A^H A x  (an orthogonal projector)          */
+
+/* Fault bits written to the device fault word. */
+#define CLAMP_FAULT_NONFINITE 1u  /* a non-finite mu, r or gamma            */
+#define CLAMP_FAULT_RNONPOS 2u    /* an r-update returned r <= 0            */
+#define CLAMP_FAULT_GAMMA 4u      /* a negative or non-finite step size     */
+
+/* Supported FFT lengths for nx and ny: 32, 64, 128, 192, 256, 384, 512. */
+
+typedef struct clamp_plan clamp_plan;
+
+/* One scene.  pupil_mask, when not NULL, is a HOST array [ny][nx] (nonzero =
+ * the aperture passes that DFT sample) and overrides pupil_radius; it is
+ * copied by clamp_plan_create. */
+typedef struct {
+    int32_t nx, ny, nz;   /* pixels per row, rows per slice, range slices   */
+    int32_t looks;        /* L, number of looks (>= 1)                      */
+    float pupil_radius;   /* R of the circular pupil, in DFT samples (> 0)  */
+    const uint8_t* pupil_mask;
+} clamp_scene;
+
+/* Scalars of Alg. 2 and App. A (host memory). */
+typedef struct {
+    float sigma_w2;       /* data-noise variance sigma_w^2 (> 0)             */
+    float sigma2;         /* proximal parameter sigma^2 of eq. prox (> 0)    */
+    float rho;            /* Mann relaxation, in (0, 1)                      */
+    float beta;           /* surrogate interval factor of App. A (> 1)       */
+    float mu_init_scale;  /* s_mu: mu_l starts at s_mu A^H y_l (> 0)         */
+    const float* upsilon; /* HOST [n_agents] agent weights, summing to 1     */
+    int32_t n_agents;     /* L (forward agents only) or L + 1 (with prior)   */
+} clamp_params;
+
+/* Per-look state of the forward agents (device memory, caller-owned).
+ *   mu    complex64 [L][n]   posterior means mu_l (eq. mu2).
+ *   resid complex64 [L][nz][P] D(a)(y_l - A mu_l) in the compact layout.
+ *   r     float32 [n_agents][n]  agent outputs; r[l] (l < L) is also look l's
+ *         surrogate anchor r'_l, and slice L (when present) is the prior's. */
+typedef struct {
+    void* mu;
+    void* resid;
+    float* r;
+} clamp_fwd_state;
+
+/* Builds device tables for `nscenes` scenes: FFT twiddles (computed in
+ * float64, rounded to float32), pupil tables and tile counts.  Allocates
+ * device memory on the current device (CLAMP_ENOMEM on failure,
+ * CLAMP_EDEVICE without a usable device).  *out is owned by the caller and
+ * released with clamp_plan_destroy.  CLAMP_EUNSUPPORTED for an nx or ny
+ * outside the supported set; CLAMP_EINVAL for an empty pupil. */
+clamp_status clamp_plan_create(const clamp_scene* scenes, int32_t nscenes,
+                               clamp_plan** out);
+
+/* Releases the plan's device tables.  NULL is accepted. */
+clamp_status clamp_plan_destroy(clamp_plan* plan);
+
+/* Bytes of workspace the calls below need for any scene of the plan. */
+clamp_status clamp_plan_workspace_size(const clamp_plan* plan, size_t* bytes);
+
+/* Host query: pupil samples per slice P, band columns B (columns with at
+ * least one pupil sample) and alpha = P / (nx ny) (Sec. III-B). */
+clamp_status clamp_plan_pupil_info(const clamp_plan* plan, int32_t scene,
+                                   int32_t* P, int32_t* B, double* alpha);
+
+/* Host query: writes the P positions u*nx + v of the compact layout into the
+ * HOST array idx[P]. */
+clamp_status clamp_plan_pupil_index(const clamp_plan* plan, int32_t scene,
+                                    int32_t* idx);
+
+/* Aperture operator of eq. A on nbatch stacked volumes:
+ * in, out complex64 [nbatch][nz][ny][nx] (full grids; CLAMP_FWD writes zeros
+ * outside the pupil, CLAMP_ADJ reads only pupil samples).  in and out must
+ * not overlap.  nbatch >= 0 (0 enqueues nothing). */
+clamp_status clamp_aperture_op(const clamp_plan* plan, int32_t scene, int32_t dir,
+                               const void* in, void* out, int32_t nbatch,
+                               void* workspace, void* hip_stream);
+
+/* Initialisation of Alg. 2 from the looks y_full complex64 [L][nz][ny][nx]
+ * (only pupil samples are read):
+ *   b_l = A^H y_l;  r0 = (1/L) sum_l |b_l|^2, floored at 1e-12 mean(r0);
+ *   mu_l = s_mu b_l;  resid_l = (1 - s_mu) D(a) y_l  (exact, as A A^H = D(a));
+ *   state->r[j] = r0 and w[j] = r0 for every agent j < n_agents;
+ *   ahy2[l] = ||A^H y_l||^2 (device double [L]) for the mu-residual. */
+clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene,
+                            const clamp_params* params, const void* y_full,
+                            clamp_fwd_state* state, float* w, double* ahy2,
+                            void* workspace, void* hip_stream);
+
+/* One application of every forward agent (Alg. 2, the per-look loop body;
+ * Sec. III-B; App. A), all looks in parallel:
+ *   c = sigma_w^2 r' / (alpha r' + sigma_w^2) with r' = r[l];
+ *   d = A^H resid / sigma_w^2 - omega mu, omega = 1/(r' + sigma_w^2/alpha);
+ *   gamma = ||d||^2 / (||A d||^2 / sigma_w^2 + sum omega |d|^2) (0 if d = 0);
+ *   mu += gamma d;  resid -= gamma D(a) F d;
+ *   r[l] = quadratic-surrogate prox at v = w[l] with s = c + |mu|^2, beta.
+ * w: float32 [L][n] (the forward agents' slices of the Mann state).
+ * diag: device double [L][8] = {gamma, ||d||^2, ||A d||^2, sum omega|d|^2,
+ *   ||resid||^2 before, sum omega|mu|^2 before, ||resid||^2 after,
+ *   sum omega|mu|^2 after}; h = ||resid||^2/(2 sigma_w^2) + sum omega|mu|^2/2
+ *   up to a constant, so h before - h after = gamma ||d||^2 / 2.
+ * fault: device uint32, OR-ed with CLAMP_FAULT_* bits (never cleared). */
+clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene,
+                             const clamp_params* params, clamp_fwd_state* state,
+                             const float* w, double* diag, uint32_t* fault,
+                             void* workspace, void* hip_stream);
+
+/* Fixed prior agent: out = periodic separable 3D Gaussian smoothing of in
+ * (float32 [n] each; standard deviation sigma_vox voxels, 7 taps per axis,
+ * taps normalised to sum 1).  in and out must not overlap. */
+clamp_status clamp_prior_gauss(const clamp_plan* plan, int32_t scene, float sigma_vox,
+                               const float* in, float* out,
+                               void* workspace, void* hip_stream);
+
+/* Mann step of Alg. 1 over n_agents stacked images (float32 [n_agents][n]):
+ *   x = 2 r - w;  w <- w + 2 rho (sum_j upsilon_j x_j - r);
+ *   wbar (float32 [n]) = sum_j upsilon_j w_j of the updated w;
+ *   conv_err (device double [1]) = ||r - G(w)|| / ||G(w)|| with G built from
+ *   the w passed in (eq. mace-convergence-error). */
+clamp_status clamp_mace_step(const clamp_plan* plan, int32_t scene,
+                             const clamp_params* params, float* w, const float* r,
+                             float* wbar, double* conv_err,
+                             void* workspace, void* hip_stream);
+
+/* Optional per-stage timing (for benchmarks).  While enabled, every call
+ * that takes a stream records a pair of HIP events on that stream around
+ * each of its stages; clamp_plan_get_timing waits for the recorded events,
+ * writes the summed milliseconds and launch counts of each stage
+ * (HOST arrays of CLAMP_STAGES entries, see clamp_stage_name) and forgets
+ * the records.  Enabling timing makes the plan unsafe to share between
+ * threads.  Creating events can fail with CLAMP_EDEVICE. */
+#define CLAMP_STAGES 12
+clamp_status clamp_plan_set_timing(clamp_plan* plan, int32_t enable);
+clamp_status clamp_plan_get_timing(clamp_plan* plan, double* total_ms, int32_t* launches);
+/* Name of a timing stage ("" outside [0, CLAMP_STAGES)). */
+const char* clamp_stage_name(int32_t stage);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char* clamp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLAMP_H */

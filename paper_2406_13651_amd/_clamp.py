@@ -1,0 +1,276 @@
+"""ctypes binding of libclamp.so (include/clamp.h), argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Arrays are
+torch tensors on a HIP device; the binding checks their device, dtype,
+contiguity and size against the plan (the C ABI only sees pointers), passes
+`data_ptr()` and the current stream, and turns a non-OK status into
+ClampError.  There is no fallback: without the compiled library, importing
+this module raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclamp.so")
+
+CLAMP_OK = 0
+CLAMP_EINVAL = -1
+CLAMP_ESHAPE = -2
+CLAMP_EUNSUPPORTED = -3
+CLAMP_EDEVICE = -4
+CLAMP_ENOMEM = -5
+
+CLAMP_FWD = 0
+CLAMP_ADJ = 1
+CLAMP_NORMAL = 2
+
+FAULT_NONFINITE = 1
+FAULT_RNONPOS = 2
+FAULT_GAMMA = 4
+
+DIAG = 8  # doubles of diagnostics per look
+STAGES = 12  # timing stages
+
+
+class ClampError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("clamp status %d: %s" % (status, msg))
+        self.status = status
+
+
+class clamp_scene(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("looks", ctypes.c_int32), ("pupil_radius", ctypes.c_float),
+                ("pupil_mask", ctypes.c_void_p)]
+
+
+class clamp_params(ctypes.Structure):
+    _fields_ = [("sigma_w2", ctypes.c_float), ("sigma2", ctypes.c_float), ("rho", ctypes.c_float),
+                ("beta", ctypes.c_float), ("mu_init_scale", ctypes.c_float),
+                ("upsilon", ctypes.POINTER(ctypes.c_float)), ("n_agents", ctypes.c_int32)]
+
+
+class clamp_fwd_state(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_void_p), ("resid", ctypes.c_void_p), ("r", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libclamp.so is not built (run paper_2406_13651_amd/build.py or "
+                          "__graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    sig = {
+        "clamp_plan_create": [ctypes.POINTER(clamp_scene), i32, ctypes.POINTER(P)],
+        "clamp_plan_destroy": [P],
+        "clamp_plan_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
+        "clamp_plan_pupil_info": [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(ctypes.c_double)],
+        "clamp_plan_pupil_index": [P, i32, ctypes.POINTER(i32)],
+        "clamp_aperture_op": [P, i32, i32, P, P, i32, P, P],
+        "clamp_fwd_init": [P, i32, ctypes.POINTER(clamp_params), P, ctypes.POINTER(clamp_fwd_state),
+                           P, P, P, P],
+        "clamp_fwd_agent": [P, i32, ctypes.POINTER(clamp_params), ctypes.POINTER(clamp_fwd_state),
+                            P, P, P, P, P],
+        "clamp_prior_gauss": [P, i32, ctypes.c_float, P, P, P, P],
+        "clamp_mace_step": [P, i32, ctypes.POINTER(clamp_params), P, P, P, P, P, P],
+        "clamp_plan_set_timing": [P, i32],
+        "clamp_plan_get_timing": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    lib.clamp_last_error.argtypes = []
+    lib.clamp_last_error.restype = ctypes.c_char_p
+    lib.clamp_stage_name.argtypes = [i32]
+    lib.clamp_stage_name.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def _check(status):
+    if status != CLAMP_OK:
+        raise ClampError(status, lib.clamp_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype, numel, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must live on the GPU" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Scene:
+    """Host description of one scene (mirrors clamp_scene)."""
+
+    def __init__(self, nx, ny, nz, looks, radius=0.0, mask=None):
+        self.nx, self.ny, self.nz, self.looks = int(nx), int(ny), int(nz), int(looks)
+        self.radius = float(radius)
+        self.mask = None
+        if mask is not None:
+            import numpy as np
+            m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+            if m.shape != (self.ny, self.nx):
+                raise ValueError("mask must be [ny, nx]")
+            self.mask = m
+
+    @property
+    def n(self):
+        return self.nx * self.ny * self.nz
+
+
+class Plan:
+    """Owns a clamp_plan*; released with clamp_plan_destroy."""
+
+    def __init__(self, handle, scenes):
+        self.handle = handle
+        self.scenes = scenes
+        self.info = [clamp_plan_pupil_info(self, i) for i in range(len(scenes))]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.clamp_plan_destroy(h)
+            self.handle = None
+
+    def workspace(self, device=None):
+        nbytes = clamp_plan_workspace_size(self)
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def clamp_plan_create(scenes):
+    scenes = list(scenes)
+    arr = (clamp_scene * len(scenes))()
+    for i, s in enumerate(scenes):
+        arr[i].nx, arr[i].ny, arr[i].nz, arr[i].looks = s.nx, s.ny, s.nz, s.looks
+        arr[i].pupil_radius = s.radius
+        arr[i].pupil_mask = s.mask.ctypes.data if s.mask is not None else None
+    h = ctypes.c_void_p()
+    _check(lib.clamp_plan_create(arr, len(scenes), ctypes.byref(h)))
+    return Plan(h, scenes)
+
+
+def clamp_plan_workspace_size(plan):
+    b = ctypes.c_size_t()
+    _check(lib.clamp_plan_workspace_size(plan.handle, ctypes.byref(b)))
+    return b.value
+
+
+def clamp_plan_pupil_info(plan, scene):
+    P = ctypes.c_int32()
+    B = ctypes.c_int32()
+    a = ctypes.c_double()
+    _check(lib.clamp_plan_pupil_info(plan.handle, scene, ctypes.byref(P), ctypes.byref(B), ctypes.byref(a)))
+    return {"P": P.value, "B": B.value, "alpha": a.value}
+
+
+def clamp_plan_pupil_index(plan, scene):
+    import numpy as np
+    P = plan.info[scene]["P"]
+    out = np.empty(P, dtype=np.int32)
+    _check(lib.clamp_plan_pupil_index(plan.handle, scene, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return out
+
+
+def clamp_aperture_op(plan, scene, direction, x, out, nbatch, workspace, stream=None):
+    s = plan.scenes[scene]
+    n = s.n * int(nbatch)
+    _check(lib.clamp_aperture_op(plan.handle, scene, int(direction),
+                                 _ptr(x, torch.complex64, n, "in"), _ptr(out, torch.complex64, n, "out"),
+                                 int(nbatch), _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan),
+                                                   "workspace"), _stream(stream)))
+
+
+def make_params(sigma_w2, sigma2, rho, beta, mu_init_scale, upsilon):
+    ups = (ctypes.c_float * len(upsilon))(*[float(u) for u in upsilon])
+    p = clamp_params(float(sigma_w2), float(sigma2), float(rho), float(beta), float(mu_init_scale),
+                     ctypes.cast(ups, ctypes.POINTER(ctypes.c_float)), len(upsilon))
+    p._keep = ups
+    return p
+
+
+def _state(plan, scene, mu, resid, r, n_agents):
+    s = plan.scenes[scene]
+    P = plan.info[scene]["P"]
+    st = clamp_fwd_state(_ptr(mu, torch.complex64, s.looks * s.n, "mu").value,
+                         _ptr(resid, torch.complex64, s.looks * s.nz * P, "resid").value,
+                         _ptr(r, torch.float32, n_agents * s.n, "r").value)
+    return st
+
+
+def clamp_fwd_init(plan, scene, params, y_full, mu, resid, r, w, ahy2, workspace, stream=None):
+    s = plan.scenes[scene]
+    st = _state(plan, scene, mu, resid, r, params.n_agents)
+    _check(lib.clamp_fwd_init(plan.handle, scene, ctypes.byref(params),
+                              _ptr(y_full, torch.complex64, s.looks * s.n, "y_full"), ctypes.byref(st),
+                              _ptr(w, torch.float32, params.n_agents * s.n, "w"),
+                              _ptr(ahy2, torch.float64, s.looks, "ahy2"),
+                              _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
+                              _stream(stream)))
+
+
+def clamp_fwd_agent(plan, scene, params, mu, resid, r, w, diag, fault, workspace, stream=None):
+    s = plan.scenes[scene]
+    st = _state(plan, scene, mu, resid, r, s.looks)
+    _check(lib.clamp_fwd_agent(plan.handle, scene, ctypes.byref(params), ctypes.byref(st),
+                               _ptr(w, torch.float32, s.looks * s.n, "w"),
+                               _ptr(diag, torch.float64, s.looks * DIAG, "diag"),
+                               _ptr(fault, torch.int32, 1, "fault"),
+                               _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
+                               _stream(stream)))
+
+
+def clamp_prior_gauss(plan, scene, sigma_vox, x, out, workspace, stream=None):
+    s = plan.scenes[scene]
+    _check(lib.clamp_prior_gauss(plan.handle, scene, float(sigma_vox), _ptr(x, torch.float32, s.n, "in"),
+                                 _ptr(out, torch.float32, s.n, "out"),
+                                 _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
+                                 _stream(stream)))
+
+
+def clamp_mace_step(plan, scene, params, w, r, wbar, conv_err, workspace, stream=None):
+    s = plan.scenes[scene]
+    na = params.n_agents
+    _check(lib.clamp_mace_step(plan.handle, scene, ctypes.byref(params), _ptr(w, torch.float32, na * s.n, "w"),
+                               _ptr(r, torch.float32, na * s.n, "r"), _ptr(wbar, torch.float32, s.n, "wbar"),
+                               _ptr(conv_err, torch.float64, 1, "conv_err"),
+                               _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
+                               _stream(stream)))
+
+
+def clamp_plan_set_timing(plan, enable):
+    _check(lib.clamp_plan_set_timing(plan.handle, 1 if enable else 0))
+
+
+def clamp_plan_get_timing(plan):
+    """{stage name: (total ms, launches)} of the records since the last call."""
+    ms = (ctypes.c_double * STAGES)()
+    cnt = (ctypes.c_int32 * STAGES)()
+    _check(lib.clamp_plan_get_timing(plan.handle, ms, cnt))
+    return {clamp_stage_name(i): (ms[i], cnt[i]) for i in range(STAGES) if cnt[i] > 0}
+
+
+def clamp_stage_name(stage):
+    return lib.clamp_stage_name(int(stage)).decode()

@@ -1,0 +1,112 @@
+"""CLAMP (Alg. 2) driven through the C ABI: initialisation, then per iteration
+every forward agent, the prior agent and the Mann consensus step, all on one
+HIP stream with no host synchronisation inside an iteration.
+
+Readings shared with the library (each also stated in include/clamp.h):
+beta_k = 1 + 2 / ln(k + 1) for the 1-based iteration k (App. A); agent
+weights 1/(2L) per look and 1/2 for the prior, or 1/L per look without a
+prior (Sec. III-A); rho = 0.5 (Sec. V-A).
+"""
+
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import _clamp as C
+
+
+def beta_schedule(k: int) -> float:
+    """Interval factor of the quadratic surrogate, App. A, at iteration k >= 1."""
+    return 1.0 + 2.0 / math.log(k + 1.0)
+
+
+def agent_weights(looks: int, with_prior: bool):
+    if with_prior:
+        return [0.5 / looks] * looks + [0.5]
+    return [1.0 / looks] * looks
+
+
+class ClampGPU:
+    """State and loop of one CLAMP reconstruction on the current GPU."""
+
+    def __init__(self, nx, ny, nz, looks, radius, sigma_w2, sigma2, with_prior=True, rho=0.5,
+                 mu_scale=1.0, prior_sigma=1.0, mask=None, device="cuda"):
+        self.scene = C.Scene(nx, ny, nz, looks, radius, mask)
+        self.plan = C.clamp_plan_create([self.scene])
+        self.info = self.plan.info[0]
+        self.dev = torch.device(device)
+        self.ws = self.plan.workspace(self.dev)
+        self.with_prior = with_prior
+        self.L = looks
+        self.N = looks + 1 if with_prior else looks
+        self.n = self.scene.n
+        self.sigma_w2 = float(sigma_w2)
+        self.sigma2 = float(sigma2)
+        self.rho = float(rho)
+        self.mu_scale = float(mu_scale)
+        self.prior_sigma = float(prior_sigma)
+        self.upsilon = agent_weights(looks, with_prior)
+        f = dict(device=self.dev)
+        self.mu = torch.zeros(looks, nz, ny, nx, dtype=torch.complex64, **f)
+        self.resid = torch.zeros(looks, nz, self.info["P"], dtype=torch.complex64, **f)
+        self.r = torch.zeros(self.N, nz, ny, nx, dtype=torch.float32, **f)
+        self.w = torch.zeros(self.N, nz, ny, nx, dtype=torch.float32, **f)
+        self.wbar = torch.zeros(nz, ny, nx, dtype=torch.float32, **f)
+        self.diag = torch.zeros(looks, C.DIAG, dtype=torch.float64, **f)
+        self.fault = torch.zeros(1, dtype=torch.int32, **f)
+        self.conv = torch.zeros(1, dtype=torch.float64, **f)
+        self.ahy2 = torch.zeros(looks, dtype=torch.float64, **f)
+        self.k = 0
+
+    def params(self, beta=2.0):
+        return C.make_params(self.sigma_w2, self.sigma2, self.rho, beta, self.mu_scale, self.upsilon)
+
+    def init(self, y):
+        """Alg. 2 initialisation from looks y (complex64 [L, nz, ny, nx], on the GPU)."""
+        C.clamp_fwd_init(self.plan, 0, self.params(), y, self.mu, self.resid, self.r, self.w, self.ahy2, self.ws)
+        self.fault.zero_()
+        self.k = 0
+
+    def fwd_agents(self, beta):
+        C.clamp_fwd_agent(self.plan, 0, self.params(beta), self.mu, self.resid, self.r, self.w,
+                          self.diag, self.fault, self.ws)
+
+    def prior(self):
+        C.clamp_prior_gauss(self.plan, 0, self.prior_sigma, self.w[self.L], self.r[self.L], self.ws)
+
+    def mace(self):
+        C.clamp_mace_step(self.plan, 0, self.params(), self.w, self.r, self.wbar, self.conv, self.ws)
+
+    def iterate(self):
+        """One pass of the Alg. 2 loop body; returns nothing (no host sync)."""
+        self.k += 1
+        self.fwd_agents(beta_schedule(self.k))
+        if self.with_prior:
+            self.prior()
+        self.mace()
+
+    def run(self, iters, on_iter=None):
+        for _ in range(iters):
+            self.iterate()
+            if on_iter is not None:
+                on_iter(self)
+        return self.wbar
+
+    # -- diagnostics (these synchronise) ---------------------------------
+    def h_values(self):
+        """(h before, h after) of each look's mu-step, up to a constant."""
+        d = self.diag.double().cpu()
+        h0 = d[:, 4] / (2 * self.sigma_w2) + d[:, 5] / 2
+        h1 = d[:, 6] / (2 * self.sigma_w2) + d[:, 7] / 2
+        return h0, h1
+
+    def mu_residual(self):
+        """Noise-floored mu-residual of eq. residual: mean_l ||d_l|| / ||A^H y_l / sigma_w^2||."""
+        d = self.diag.double().cpu()
+        a = self.ahy2.double().cpu()
+        return float(torch.mean(torch.sqrt(d[:, 1]) * self.sigma_w2 / torch.sqrt(a)))
+
+    def conv_err(self):
+        return float(self.conv.item())

@@ -1,0 +1,653 @@
+// C ABI of the CLAMP forward-model library: argument validation, plan
+// tables, workspace layout and the launch sequences of each call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/clamp.h"
+#include "internal.h"
+
+using clampk::ColArgs;
+using clampk::RowArgs;
+using clampk::SceneTables;
+
+namespace {
+
+thread_local std::string g_err;
+
+clamp_status fail(clamp_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+clamp_status ok() {
+    return CLAMP_OK;
+}
+
+clamp_status hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return CLAMP_OK;
+    return fail(CLAMP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool size_supported(int n) {
+    switch (n) {
+        case 32: case 64: case 128: case 192: case 256: case 384: case 512: return true;
+        default: return false;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t T, T2, dfd, prow, pcf, pci, pupd, pres, pmace, scal, g0, g1, total;
+};
+
+struct Scene {
+    clamp_scene sc{};
+    int P = 0, B = 0, Bs = 0, tiles = 0;
+    double alpha = 0.0;
+    std::vector<int> band_cols, band_pos, col_off, row_idx, pidx;
+    std::vector<void*> dev;  // device allocations owned by this scene
+    SceneTables tab{};
+    Layout ws{};
+    size_t n() const { return (size_t)sc.nx * sc.ny * sc.nz; }
+};
+
+}  // namespace
+
+// Timing stages; the names are returned by clamp_stage_name.
+enum Stage {
+    ST_COL_INV = 0, ST_ROW_GRAD, ST_COL_FWD, ST_GAMMA, ST_ROW_UPDATE, ST_RESID, ST_DIAG,
+    ST_PRIOR, ST_MACE, ST_INIT, ST_OPERATOR, ST_OTHER
+};
+const char* const kStageNames[CLAMP_STAGES] = {
+    "col_inv", "row_grad", "col_fwd", "gamma", "row_update", "resid_update", "diag_after",
+    "prior_gauss", "mace_step", "init", "aperture_op", "other"};
+
+struct TimingRecord {
+    int stage;
+    hipEvent_t start, stop;
+};
+
+struct clamp_plan {
+    int device = 0;
+    std::vector<Scene> scenes;
+    size_t ws_bytes = 0;
+    bool timing = false;
+    std::vector<TimingRecord> records;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+void free_scene(Scene& s) {
+    for (void* p : s.dev) (void)hipFree(p);
+    s.dev.clear();
+}
+
+template <typename T>
+clamp_status upload(Scene& s, const std::vector<T>& h, const T** out) {
+    void* p = nullptr;
+    const size_t bytes = h.size() * sizeof(T) > 0 ? h.size() * sizeof(T) : sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) return fail(CLAMP_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+        return fail(CLAMP_EDEVICE, "hipMalloc: %s", hipGetErrorString(e));
+    }
+    s.dev.push_back(p);
+    if (!h.empty()) {
+        e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(CLAMP_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    }
+    *out = static_cast<const T*>(p);
+    return CLAMP_OK;
+}
+
+std::vector<float2> twiddles(int n) {
+    std::vector<float2> t(n);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int m = 0; m < n; ++m) {
+        const double ang = -two_pi * (double)m / (double)n;
+        t[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    return t;
+}
+
+clamp_status build_scene(const clamp_scene& in, Scene& s) {
+    s.sc = in;
+    s.sc.pupil_mask = nullptr;
+    const int nx = in.nx, ny = in.ny;
+    std::vector<uint8_t> mask((size_t)nx * ny, 0);
+    if (in.pupil_mask != nullptr) {
+        for (size_t i = 0; i < mask.size(); ++i) mask[i] = in.pupil_mask[i] ? 1 : 0;
+    } else {
+        const double r2 = (double)in.pupil_radius * (double)in.pupil_radius;
+        for (int u = 0; u < ny; ++u) {
+            const long su = (2 * u >= ny) ? u - ny : u;
+            for (int v = 0; v < nx; ++v) {
+                const long sv = (2 * v >= nx) ? v - nx : v;
+                mask[(size_t)u * nx + v] = (double)(su * su + sv * sv) <= r2 ? 1 : 0;
+            }
+        }
+    }
+    s.band_pos.assign(nx, -1);
+    s.pidx.assign((size_t)nx * ny, -1);
+    s.col_off.clear();
+    s.row_idx.clear();
+    s.band_cols.clear();
+    for (int v = 0; v < nx; ++v) {
+        bool any = false;
+        for (int u = 0; u < ny; ++u) any = any || mask[(size_t)u * nx + v];
+        if (!any) continue;
+        s.band_pos[v] = (int)s.band_cols.size();
+        s.band_cols.push_back(v);
+        s.col_off.push_back((int)s.row_idx.size());
+        for (int u = 0; u < ny; ++u)
+            if (mask[(size_t)u * nx + v]) {
+                s.pidx[(size_t)u * nx + v] = (int)s.row_idx.size();
+                s.row_idx.push_back(u);
+            }
+    }
+    s.col_off.push_back((int)s.row_idx.size());
+    s.P = (int)s.row_idx.size();
+    s.B = (int)s.band_cols.size();
+    if (s.P == 0) return fail(CLAMP_EINVAL, "pupil passes no DFT sample");
+    s.Bs = (s.B + 15) / 16 * 16;
+    s.tiles = (s.B + clampk::kTileCols - 1) / clampk::kTileCols;
+    s.alpha = (double)s.P / ((double)nx * ny);
+    return CLAMP_OK;
+}
+
+clamp_status upload_scene(Scene& s) {
+    SceneTables& t = s.tab;
+    t.nx = s.sc.nx;
+    t.ny = s.sc.ny;
+    t.nz = s.sc.nz;
+    t.P = s.P;
+    t.B = s.B;
+    t.Bs = s.Bs;
+    t.tiles = s.tiles;
+    clamp_status st;
+    if ((st = upload(s, twiddles(s.sc.nx), &t.tw_x)) != CLAMP_OK) return st;
+    if ((st = upload(s, twiddles(s.sc.ny), &t.tw_y)) != CLAMP_OK) return st;
+    if ((st = upload(s, s.band_cols, &t.band_cols)) != CLAMP_OK) return st;
+    if ((st = upload(s, s.band_pos, &t.band_pos)) != CLAMP_OK) return st;
+    if ((st = upload(s, s.col_off, &t.col_off)) != CLAMP_OK) return st;
+    if ((st = upload(s, s.row_idx, &t.row_idx)) != CLAMP_OK) return st;
+    if ((st = upload(s, s.pidx, &t.pidx)) != CLAMP_OK) return st;
+    return CLAMP_OK;
+}
+
+void layout_scene(Scene& s) {
+    const size_t L = (size_t)s.sc.looks;
+    const size_t band = L * s.sc.nz * s.sc.ny * (size_t)s.Bs * sizeof(float2);
+    Layout& w = s.ws;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    w.T = take(band);
+    w.T2 = take(band);
+    w.dfd = take(L * s.sc.nz * (size_t)s.P * sizeof(float2));
+    w.prow = take(L * clampk::row_blocks(s.tab) * 3 * sizeof(double));
+    w.pcf = take(L * clampk::col_blocks(s.tab) * sizeof(double));
+    w.pci = take(L * clampk::col_blocks(s.tab) * sizeof(double));
+    w.pupd = take(L * clampk::row_blocks(s.tab) * sizeof(double));
+    w.pres = take(L * clampk::resid_blocks(s.tab) * sizeof(double));
+    w.pmace = take((size_t)clampk::mace_blocks(s.n()) * 2 * sizeof(double));
+    w.scal = take(64 * sizeof(double));
+    w.g0 = take(s.n() * sizeof(float));
+    w.g1 = take(s.n() * sizeof(float));
+    w.total = o;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+clamp_status check_plan_scene(const clamp_plan* plan, int32_t scene) {
+    if (plan == nullptr) return fail(CLAMP_EINVAL, "plan is NULL");
+    if (scene < 0 || scene >= (int32_t)plan->scenes.size())
+        return fail(CLAMP_EINVAL, "scene index %d out of range [0, %zu)", scene, plan->scenes.size());
+    return CLAMP_OK;
+}
+
+clamp_status check_ws(const void* ws) {
+    if (ws == nullptr) return fail(CLAMP_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(CLAMP_EINVAL, "workspace is not 256-byte aligned");
+    return CLAMP_OK;
+}
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.f; }
+
+clamp_status check_params(const Scene& s, const clamp_params* p, bool need_prox) {
+    if (p == nullptr) return fail(CLAMP_EINVAL, "params is NULL");
+    if (!finite_pos(p->sigma_w2)) return fail(CLAMP_EINVAL, "sigma_w2 must be finite and > 0");
+    if (need_prox) {
+        if (!finite_pos(p->sigma2)) return fail(CLAMP_EINVAL, "sigma2 must be finite and > 0");
+        if (!(std::isfinite(p->beta) && p->beta > 1.f)) return fail(CLAMP_EINVAL, "beta must be finite and > 1");
+    }
+    if (!(p->rho > 0.f && p->rho < 1.f)) return fail(CLAMP_EINVAL, "rho must lie in (0, 1)");
+    if (!finite_pos(p->mu_init_scale)) return fail(CLAMP_EINVAL, "mu_init_scale must be finite and > 0");
+    const int L = s.sc.looks;
+    if (p->n_agents != L && p->n_agents != L + 1)
+        return fail(CLAMP_EINVAL, "n_agents must be looks (%d) or looks + 1", L);
+    if (p->n_agents > 64) return fail(CLAMP_EINVAL, "at most 64 agents");
+    if (s.n() >= ((size_t)1 << 31)) return fail(CLAMP_ESHAPE, "a look must hold fewer than 2^31 voxels");
+    if (p->upsilon == nullptr) return fail(CLAMP_EINVAL, "upsilon is NULL");
+    double sum = 0.0;
+    for (int j = 0; j < p->n_agents; ++j) {
+        if (!(std::isfinite(p->upsilon[j]) && p->upsilon[j] >= 0.f))
+            return fail(CLAMP_EINVAL, "upsilon[%d] must be finite and >= 0", j);
+        sum += p->upsilon[j];
+    }
+    if (std::fabs(sum - 1.0) > 1e-6) return fail(CLAMP_EINVAL, "upsilon sums to %.9g, not 1", sum);
+    return CLAMP_OK;
+}
+
+hipEvent_t take_event(clamp_plan* p) {
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs `launch` (returning hipError_t) with timing events around it when the
+// plan's timing is on.
+template <typename F>
+hipError_t timed(const clamp_plan* cplan, int stage, hipStream_t st, F&& launch) {
+    clamp_plan* p = const_cast<clamp_plan*>(cplan);
+    if (!p->timing) return launch();
+    TimingRecord rec{stage, take_event(p), take_event(p)};
+    if (rec.start == nullptr || rec.stop == nullptr) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(rec.start, st);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(rec.stop, st);
+    p->records.push_back(rec);
+    return e;
+}
+
+ColArgs col_args(const Scene& s, int looks) {
+    ColArgs a{};
+    a.s = s.tab;
+    a.looks = looks;
+    a.scale = (float)(1.0 / std::sqrt((double)s.sc.ny));
+    return a;
+}
+
+RowArgs row_args(const Scene& s, int looks) {
+    RowArgs a{};
+    a.s = s.tab;
+    a.looks = looks;
+    a.scale = (float)(1.0 / std::sqrt((double)s.sc.nx));
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* clamp_last_error(void) { return g_err.c_str(); }
+
+clamp_status clamp_plan_create(const clamp_scene* scenes, int32_t nscenes, clamp_plan** out) {
+    if (out == nullptr) return fail(CLAMP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (scenes == nullptr || nscenes <= 0) return fail(CLAMP_EINVAL, "need at least one scene");
+    for (int i = 0; i < nscenes; ++i) {
+        const clamp_scene& c = scenes[i];
+        if (c.nx <= 0 || c.ny <= 0 || c.nz <= 0 || c.looks <= 0)
+            return fail(CLAMP_EINVAL, "scene %d: sizes and looks must be positive", i);
+        if (!size_supported(c.nx) || !size_supported(c.ny))
+            return fail(CLAMP_EUNSUPPORTED, "scene %d: nx=%d ny=%d; supported: 32 64 128 192 256 384 512", i,
+                        c.nx, c.ny);
+        if (c.pupil_mask == nullptr && !(std::isfinite(c.pupil_radius) && c.pupil_radius > 0.f))
+            return fail(CLAMP_EINVAL, "scene %d: pupil_radius must be > 0 without a mask", i);
+        if ((size_t)c.nx * c.ny * c.nz * (size_t)c.looks > ((size_t)1 << 40))
+            return fail(CLAMP_ESHAPE, "scene %d too large", i);
+    }
+    int dev = 0;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(CLAMP_EDEVICE, "no HIP device available");
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CLAMP_EDEVICE, "hipGetDevice failed");
+    clamp_plan* plan = new (std::nothrow) clamp_plan();
+    if (plan == nullptr) return fail(CLAMP_ENOMEM, "host allocation failed");
+    plan->device = dev;
+    plan->scenes.resize(nscenes);
+    for (int i = 0; i < nscenes; ++i) {
+        clamp_status st = build_scene(scenes[i], plan->scenes[i]);
+        if (st == CLAMP_OK) st = upload_scene(plan->scenes[i]);
+        if (st != CLAMP_OK) {
+            clamp_plan_destroy(plan);
+            return st;
+        }
+        layout_scene(plan->scenes[i]);
+        if (plan->scenes[i].ws.total > plan->ws_bytes) plan->ws_bytes = plan->scenes[i].ws.total;
+    }
+    *out = plan;
+    return ok();
+}
+
+clamp_status clamp_plan_destroy(clamp_plan* plan) {
+    if (plan == nullptr) return CLAMP_OK;
+    for (TimingRecord& r : plan->records) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
+    for (Scene& s : plan->scenes) free_scene(s);
+    delete plan;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_plan_workspace_size(const clamp_plan* plan, size_t* bytes) {
+    if (plan == nullptr || bytes == nullptr) return fail(CLAMP_EINVAL, "NULL argument");
+    *bytes = plan->ws_bytes;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_plan_pupil_info(const clamp_plan* plan, int32_t scene, int32_t* P, int32_t* B,
+                                   double* alpha) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    if (P) *P = s.P;
+    if (B) *B = s.B;
+    if (alpha) *alpha = s.alpha;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_plan_pupil_index(const clamp_plan* plan, int32_t scene, int32_t* idx) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    if (idx == nullptr) return fail(CLAMP_EINVAL, "idx is NULL");
+    const Scene& s = plan->scenes[scene];
+    for (int c = 0; c < s.B; ++c)
+        for (int p = s.col_off[c]; p < s.col_off[c + 1]; ++p) idx[p] = s.row_idx[p] * s.sc.nx + s.band_cols[c];
+    return CLAMP_OK;
+}
+
+clamp_status clamp_aperture_op(const clamp_plan* plan, int32_t scene, int32_t dir, const void* in, void* out,
+                               int32_t nbatch, void* workspace, void* hip_stream) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    if (dir != CLAMP_FWD && dir != CLAMP_ADJ && dir != CLAMP_NORMAL) return fail(CLAMP_EINVAL, "bad direction %d", dir);
+    if (nbatch < 0) return fail(CLAMP_EINVAL, "nbatch must be >= 0");
+    if (nbatch == 0) return CLAMP_OK;
+    if (in == nullptr || out == nullptr) return fail(CLAMP_EINVAL, "in/out is NULL");
+    if ((st = check_ws(workspace)) != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    const size_t n = s.n();
+    if ((const char*)in < (const char*)out + n * nbatch * sizeof(float2) &&
+        (const char*)out < (const char*)in + n * nbatch * sizeof(float2))
+        return fail(CLAMP_EINVAL, "in and out overlap");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    float2* T = at<float2>(workspace, s.ws.T);
+    float2* T2 = at<float2>(workspace, s.ws.T2);
+    float2* dfd = at<float2>(workspace, s.ws.dfd);
+    const float2* src = static_cast<const float2*>(in);
+    float2* dst = static_cast<float2*>(out);
+    for (int b0 = 0; b0 < nbatch; b0 += s.sc.looks) {
+        const int nb = (nbatch - b0 < s.sc.looks) ? nbatch - b0 : s.sc.looks;
+        const float2* x = src + (size_t)b0 * n;
+        float2* y = dst + (size_t)b0 * n;
+        hipError_t e = hipSuccess;
+        if (dir == CLAMP_FWD || dir == CLAMP_NORMAL) {
+            RowArgs ra = row_args(s, nb);
+            ra.img_in = x;
+            ra.band_out = T2;
+            e = clampk::launch_row(clampk::ROW_FWD, ra, stream);
+            if (e == hipSuccess) {
+                ColArgs ca = col_args(s, nb);
+                ca.band_in = T2;
+                ca.cmp_out = dfd;
+                e = clampk::launch_col(clampk::COL_FWD_COMPACT, ca, stream);
+            }
+            if (e == hipSuccess && dir == CLAMP_FWD) e = clampk::launch_scatter_full(s.tab, nb, dfd, y, stream);
+        }
+        if (e == hipSuccess && (dir == CLAMP_ADJ || dir == CLAMP_NORMAL)) {
+            ColArgs ca = col_args(s, nb);
+            if (dir == CLAMP_ADJ) {
+                ca.full_in = x;
+                ca.band_out = T;
+                e = clampk::launch_col(clampk::COL_INV_FULL, ca, stream);
+            } else {
+                ca.cmp_in = dfd;
+                ca.band_out = T;
+                e = clampk::launch_col(clampk::COL_INV_COMPACT, ca, stream);
+            }
+            if (e == hipSuccess) {
+                RowArgs ra = row_args(s, nb);
+                ra.band_in = T;
+                ra.img_out = y;
+                e = clampk::launch_row(clampk::ROW_INV, ra, stream);
+            }
+        }
+        if ((st = hip_check(e, "clamp_aperture_op launch")) != CLAMP_OK) return st;
+    }
+    return CLAMP_OK;
+}
+
+clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene, const clamp_params* params, const void* y_full,
+                            clamp_fwd_state* state, float* w, double* ahy2, void* workspace, void* hip_stream) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    if ((st = check_params(s, params, false)) != CLAMP_OK) return st;
+    if (y_full == nullptr || state == nullptr || w == nullptr || ahy2 == nullptr)
+        return fail(CLAMP_EINVAL, "NULL argument");
+    if (state->mu == nullptr || state->resid == nullptr || state->r == nullptr)
+        return fail(CLAMP_EINVAL, "state has a NULL array");
+    if ((st = check_ws(workspace)) != CLAMP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int L = s.sc.looks;
+    const size_t n = s.n();
+    float2* T = at<float2>(workspace, s.ws.T);
+    double* pci = at<double>(workspace, s.ws.pci);
+    double* pm = at<double>(workspace, s.ws.pmace);
+    double* scal = at<double>(workspace, s.ws.scal);
+    float2* mu = static_cast<float2*>(state->mu);
+
+    ColArgs ca = col_args(s, L);
+    ca.full_in = static_cast<const float2*>(y_full);
+    ca.band_out = T;
+    ca.cmp_out = static_cast<float2*>(state->resid);
+    ca.part = pci;
+    ca.init_keep = 1.f - params->mu_init_scale;
+    hipError_t e = clampk::launch_col(clampk::COL_INV_INIT, ca, stream);
+    if (e == hipSuccess) {
+        RowArgs ra = row_args(s, L);
+        ra.band_in = T;
+        ra.img_out = mu;
+        e = clampk::launch_row(clampk::ROW_INV, ra, stream);
+    }
+    if (e == hipSuccess) e = clampk::launch_sum(pci, clampk::col_blocks(s.tab), L, 1.0, ahy2, stream);
+    if (e == hipSuccess) e = clampk::launch_init_r0(n, L, mu, params->mu_init_scale, state->r, pm, stream);
+    if (e == hipSuccess) e = clampk::launch_sum(pm, clampk::mace_blocks(n), 1, 1.0 / (double)n, scal, stream);
+    if (e == hipSuccess) e = clampk::launch_init_floor(n, params->n_agents, scal, state->r, w, stream);
+    return hip_check(e, "clamp_fwd_init launch");
+}
+
+clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_params* params,
+                             clamp_fwd_state* state, const float* w, double* diag, uint32_t* fault,
+                             void* workspace, void* hip_stream) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    if ((st = check_params(s, params, true)) != CLAMP_OK) return st;
+    if (state == nullptr || w == nullptr || diag == nullptr || fault == nullptr)
+        return fail(CLAMP_EINVAL, "NULL argument");
+    if (state->mu == nullptr || state->resid == nullptr || state->r == nullptr)
+        return fail(CLAMP_EINVAL, "state has a NULL array");
+    if ((st = check_ws(workspace)) != CLAMP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int L = s.sc.looks;
+    float2* T = at<float2>(workspace, s.ws.T);
+    float2* T2 = at<float2>(workspace, s.ws.T2);
+    float2* dfd = at<float2>(workspace, s.ws.dfd);
+    double* prow = at<double>(workspace, s.ws.prow);
+    double* pcf = at<double>(workspace, s.ws.pcf);
+    double* pci = at<double>(workspace, s.ws.pci);
+    double* pupd = at<double>(workspace, s.ws.pupd);
+    double* pres = at<double>(workspace, s.ws.pres);
+    float2* mu = static_cast<float2*>(state->mu);
+    float2* resid = static_cast<float2*>(state->resid);
+
+    const double s2w = params->sigma_w2;
+    const double beta = params->beta;
+    RowArgs ra = row_args(s, L);
+    ra.mu = mu;
+    ra.r = state->r;
+    ra.w = w;
+    ra.diag = diag;
+    ra.fault = fault;
+    ra.inv_s2w = (float)(1.0 / s2w);
+    ra.s2w = (float)s2w;
+    ra.floor_w = (float)(s2w / s.alpha);
+    ra.alpha = (float)s.alpha;
+    ra.sigma2 = params->sigma2;
+    ra.inv_sigma2 = (float)(1.0 / (double)params->sigma2);
+    ra.beta = (float)beta;
+    ra.inv_beta = (float)(1.0 / beta);
+    ra.k_up = (float)((1.0 + beta) / (beta * beta));
+    ra.k_dn = (float)(beta * (1.0 + beta));
+
+    ColArgs ci = col_args(s, L);
+    ci.cmp_in = resid;
+    ci.band_out = T;
+    ci.part = pci;
+    hipError_t e = timed(plan, ST_COL_INV, stream, [&] { return clampk::launch_col(clampk::COL_INV_COMPACT, ci, stream); });
+    if (e == hipSuccess) {
+        RowArgs g = ra;
+        g.band_in = T;
+        g.band_out = T2;
+        g.part = prow;
+        e = timed(plan, ST_ROW_GRAD, stream, [&] { return clampk::launch_row(clampk::ROW_GRAD, g, stream); });
+    }
+    if (e == hipSuccess) {
+        ColArgs cf = col_args(s, L);
+        cf.band_in = T2;
+        cf.cmp_out = dfd;
+        cf.part = pcf;
+        e = timed(plan, ST_COL_FWD, stream, [&] { return clampk::launch_col(clampk::COL_FWD_COMPACT, cf, stream); });
+    }
+    if (e == hipSuccess)
+        e = timed(plan, ST_GAMMA, stream,
+                  [&] { return clampk::launch_gamma(s.tab, L, prow, pcf, pci, 1.0 / s2w, diag, fault, stream); });
+    if (e == hipSuccess) {
+        RowArgs u = ra;
+        u.band_in = T;
+        u.part = pupd;
+        e = timed(plan, ST_ROW_UPDATE, stream, [&] { return clampk::launch_row(clampk::ROW_UPDATE, u, stream); });
+    }
+    if (e == hipSuccess)
+        e = timed(plan, ST_RESID, stream,
+                  [&] { return clampk::launch_resid_update(s.tab, L, resid, dfd, diag, pres, stream); });
+    if (e == hipSuccess)
+        e = timed(plan, ST_DIAG, stream, [&] { return clampk::launch_diag_after(s.tab, L, pupd, pres, diag, stream); });
+    return hip_check(e, "clamp_fwd_agent launch");
+}
+
+clamp_status clamp_prior_gauss(const clamp_plan* plan, int32_t scene, float sigma_vox, const float* in, float* out,
+                               void* workspace, void* hip_stream) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    if (!finite_pos(sigma_vox)) return fail(CLAMP_EINVAL, "sigma_vox must be finite and > 0");
+    if (in == nullptr || out == nullptr) return fail(CLAMP_EINVAL, "in/out is NULL");
+    if (in == out) return fail(CLAMP_EINVAL, "in and out must not overlap");
+    if ((st = check_ws(workspace)) != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    double g[7], sum = 0.0;
+    for (int k = 0; k < 7; ++k) {
+        const double x = (k - 3) / (double)sigma_vox;
+        g[k] = std::exp(-0.5 * x * x);
+        sum += g[k];
+    }
+    float taps[7];
+    for (int k = 0; k < 7; ++k) taps[k] = (float)(g[k] / sum);
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = timed(plan, ST_PRIOR, stream, [&] {
+        return clampk::launch_gauss(s.sc.nx, s.sc.ny, s.sc.nz, taps, in, at<float>(workspace, s.ws.g0),
+                                    at<float>(workspace, s.ws.g1), out, stream);
+    });
+    return hip_check(e, "clamp_prior_gauss launch");
+}
+
+clamp_status clamp_mace_step(const clamp_plan* plan, int32_t scene, const clamp_params* params, float* w,
+                             const float* r, float* wbar, double* conv_err, void* workspace, void* hip_stream) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    if ((st = check_params(s, params, false)) != CLAMP_OK) return st;
+    if (w == nullptr || r == nullptr || wbar == nullptr || conv_err == nullptr)
+        return fail(CLAMP_EINVAL, "NULL argument");
+    if ((st = check_ws(workspace)) != CLAMP_OK) return st;
+    clampk::MaceArgs a{};
+    a.n = s.n();
+    a.n_agents = params->n_agents;
+    for (int j = 0; j < params->n_agents; ++j) a.ups[j] = params->upsilon[j];
+    a.two_rho = 2.f * params->rho;
+    a.w = w;
+    a.r = r;
+    a.wbar = wbar;
+    a.part = at<double>(workspace, s.ws.pmace);
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = timed(plan, ST_MACE, stream, [&] {
+        hipError_t x = clampk::launch_mace(a, stream);
+        if (x == hipSuccess) x = clampk::launch_mace_final(a.part, clampk::mace_blocks(a.n), conv_err, stream);
+        return x;
+    });
+    return hip_check(e, "clamp_mace_step launch");
+}
+
+clamp_status clamp_plan_set_timing(clamp_plan* plan, int32_t enable) {
+    if (plan == nullptr) return fail(CLAMP_EINVAL, "plan is NULL");
+    plan->timing = enable != 0;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_plan_get_timing(clamp_plan* plan, double* total_ms, int32_t* launches) {
+    if (plan == nullptr || total_ms == nullptr || launches == nullptr) return fail(CLAMP_EINVAL, "NULL argument");
+    for (int i = 0; i < CLAMP_STAGES; ++i) {
+        total_ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    clamp_status st = CLAMP_OK;
+    for (TimingRecord& r : plan->records) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (e != hipSuccess && st == CLAMP_OK) st = hip_check(e, "clamp_plan_get_timing");
+        total_ms[r.stage] += ms;
+        launches[r.stage] += 1;
+        plan->pool.push_back(r.start);
+        plan->pool.push_back(r.stop);
+    }
+    plan->records.clear();
+    return st;
+}
+
+const char* clamp_stage_name(int32_t stage) {
+    if (stage < 0 || stage >= CLAMP_STAGES) return "";
+    return kStageNames[stage];
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal interface between the C ABI layer (api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace clampk {
+
+constexpr int kBlock = 256;      // threads per block for every kernel
+constexpr int kTileCols = 16;    // band columns per column-pass block
+constexpr int kDiag = 8;         // doubles of diagnostics per look
+
+// Device tables of one scene (owned by the plan).
+struct SceneTables {
+    int nx, ny, nz;
+    int P;       // pupil samples per slice
+    int B;       // band columns (columns holding pupil samples)
+    int Bs;      // row stride of band-row buffers (B rounded up to 16)
+    int tiles;   // ceil(B / kTileCols)
+    const float2* tw_x;     // [nx] exp(-2 pi i m / nx)
+    const float2* tw_y;     // [ny]
+    const int* band_cols;   // [B] natural column index of each band column
+    const int* band_pos;    // [nx] band index of a column, -1 outside the band
+    const int* col_off;     // [B + 1] compact offsets of each band column
+    const int* row_idx;     // [P] row of each compact entry
+    const int* pidx;        // [ny * nx] compact index of a sample, -1 off-pupil
+};
+
+// Rows per row-pass block for a row length (threads per row = pow2 >= n/8).
+int row_threads(int n);
+int rows_per_block(int n);
+
+// Number of partial-sum blocks per look of each pass.
+inline int row_blocks(const SceneTables& s) {
+    const int rpb = rows_per_block(s.nx);
+    return (s.nz * s.ny + rpb - 1) / rpb;
+}
+inline int col_blocks(const SceneTables& s) { return s.nz * s.tiles; }
+int resid_blocks(const SceneTables& s);
+int mace_blocks(size_t n);
+
+enum ColMode { COL_INV_COMPACT = 0, COL_INV_FULL = 1, COL_INV_INIT = 2, COL_FWD_COMPACT = 3 };
+enum RowMode { ROW_INV = 0, ROW_FWD = 1, ROW_GRAD = 2, ROW_UPDATE = 3 };
+
+struct ColArgs {
+    SceneTables s;
+    int looks;                 // looks in this launch
+    const float2* cmp_in;      // compact [looks][nz][P]      (COL_INV_COMPACT)
+    const float2* full_in;     // full grids [looks][nz][ny][nx] (COL_INV_FULL/INIT)
+    const float2* band_in;     // band rows [looks][nz][ny][Bs]  (COL_FWD_COMPACT)
+    float2* band_out;          // band rows                      (COL_INV_*)
+    float2* cmp_out;           // compact out: D(a)F x (FWD), (1 - s) D(a) y (INIT)
+    double* part;              // [looks][col_blocks] sum of |input or output|^2
+    float scale;               // 1/sqrt(ny)
+    float init_keep;           // 1 - s_mu (COL_INV_INIT)
+};
+
+struct RowArgs {
+    SceneTables s;
+    int looks;
+    const float2* band_in;     // band rows in (INV, GRAD, UPDATE)
+    float2* band_out;          // band rows out (FWD, GRAD)
+    const float2* img_in;      // images in (FWD)
+    float2* img_out;           // images out (INV)
+    float2* mu;                // [looks][n]
+    float* r;                  // [looks][n] anchors in, outputs out (UPDATE)
+    const float* w;            // [looks][n] (UPDATE)
+    const double* diag;        // [looks][8], gamma in slot 0 (UPDATE)
+    double* part;              // GRAD: 3 per block, UPDATE: 1 per block
+    uint32_t* fault;
+    float scale;               // 1/sqrt(nx)
+    float inv_s2w;             // 1/sigma_w^2
+    float s2w;                 // sigma_w^2
+    float floor_w;             // sigma_w^2/alpha
+    float alpha;
+    float sigma2;
+    float inv_sigma2;
+    float beta, inv_beta;
+    float k_up;                // (1 + beta)/beta^2      (xi = beta r')
+    float k_dn;                // beta (1 + beta)        (xi = r'/beta)
+};
+
+hipError_t launch_col(int mode, const ColArgs& a, hipStream_t st);
+hipError_t launch_row(int mode, const RowArgs& a, hipStream_t st);
+hipError_t launch_scatter_full(const SceneTables& s, int looks, const float2* cmp,
+                               float2* full, hipStream_t st);
+hipError_t launch_gamma(const SceneTables& s, int looks, const double* part_row,
+                        const double* part_colfwd, const double* part_colinv,
+                        double inv_s2w, double* diag, uint32_t* fault, hipStream_t st);
+hipError_t launch_resid_update(const SceneTables& s, int looks, float2* resid,
+                               const float2* dfd, const double* diag, double* part,
+                               hipStream_t st);
+hipError_t launch_diag_after(const SceneTables& s, int looks, const double* part_upd,
+                             const double* part_resid, double* diag, hipStream_t st);
+hipError_t launch_init_r0(size_t n, int looks, float2* mu, float s_mu, float* r0,
+                          double* part, hipStream_t st);
+// out[l] = scale * sum_i part[l * count + i] for l < looks
+hipError_t launch_sum(const double* part, int count, int looks, double scale, double* out,
+                      hipStream_t st);
+hipError_t launch_init_floor(size_t n, int n_agents, const double* mean_r0, float* r,
+                             float* w, hipStream_t st);
+
+struct MaceArgs {
+    size_t n;
+    int n_agents;
+    float ups[64];
+    float two_rho;
+    float* w;
+    const float* r;
+    float* wbar;
+    double* part;   // [mace_blocks][2]
+};
+hipError_t launch_mace(const MaceArgs& a, hipStream_t st);
+hipError_t launch_mace_final(const double* part, int blocks, double* conv_err, hipStream_t st);
+
+hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float* in,
+                        float* tmp0, float* tmp1, float* out, hipStream_t st);
+
+}  // namespace clampk

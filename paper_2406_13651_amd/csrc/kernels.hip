@@ -1,0 +1,606 @@
+// Kernels of the CLAMP forward-model agent, prior and consensus step.
+//
+// Data flow of one forward-agent application (all looks in every launch):
+//   1. column pass, inverse:  resid (compact pupil) -> band rows T
+//      (inverse DFT of each band column; only band columns are non-zero)
+//   2. row pass "grad":       T -> A^H resid (inverse row DFT), then
+//      d = A^H resid / sigma_w^2 - omega mu, then the forward row DFT of d,
+//      keeping band columns -> T2; partial sums of ||d||^2, sum omega|d|^2,
+//      sum omega|mu|^2
+//   3. column pass, forward:  T2 -> D(a) F d (compact); partial ||A d||^2
+//   4. gamma:                 exact step size per look, kept on the device
+//   5. row pass "update":     recompute d from T, mu += gamma d, and the
+//      quadratic-surrogate r-update per voxel
+//   6. resid -= gamma D(a) F d on the pupil samples
+// Recomputing d in step 5 costs two row FFTs but saves writing and reading
+// d (16 bytes per voxel-look); T is only half a slice wide at R = N/4.
+#include <math.h>
+
+#include "fft.hpp"
+#include "internal.h"
+
+namespace clampk {
+
+__host__ __device__ constexpr int row_threads_c(int n) {
+    int t = 4;
+    while (t * 8 < n) t *= 2;
+    return t;
+}
+int row_threads(int n) { return row_threads_c(n); }
+int rows_per_block(int n) { return kBlock / row_threads_c(n); }
+
+static int grid_cap(size_t work, int cap) {
+    size_t b = (work + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return (int)(b < (size_t)cap ? b : (size_t)cap);
+}
+int resid_blocks(const SceneTables& s) { return grid_cap((size_t)s.nz * s.P, 512); }
+int mace_blocks(size_t n) { return grid_cap(n, 2048); }
+
+// Sum of K doubles over the block, written by thread 0 to out[0..K).
+template <int K>
+__device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
+    __shared__ double red[K][kBlock / 64];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        v[k] = x;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k][wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
+            out[k] = s;
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_or_fault(uint32_t bits, uint32_t* fault) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
+    if ((threadIdx.x & 63) == 0 && bits != 0u && fault != nullptr) atomicOr(fault, bits);
+}
+
+// ---------------------------------------------------------------------------
+// Column pass over a tile of kTileCols band columns of one slice of one look.
+template <int NY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
+    constexpr int TC = kTileCols;
+    constexpr int TPC = kBlock / TC;
+    __shared__ float2 tw[NY];
+    __shared__ float2 tile[NY * TC];
+    const SceneTables& s = a.s;
+    const int tid = threadIdx.x;
+    const int tile_i = blockIdx.x % s.tiles;
+    const int zl = blockIdx.x / s.tiles;  // look * nz + z
+    const int c0 = tile_i * TC;
+    for (int i = tid; i < NY; i += kBlock) tw[i] = s.tw_y[i];
+    double acc[1] = {0.0};
+
+    if constexpr (MODE == COL_INV_COMPACT) {
+        for (int i = tid; i < NY * TC; i += kBlock) tile[i] = make_float2(0.f, 0.f);
+        __syncthreads();
+        const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
+        if (bc < s.B) {
+            const float2* src = a.cmp_in + (size_t)zl * s.P;
+            const int p1 = s.col_off[bc + 1];
+            float f = 0.f;
+            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
+                const float2 val = src[p];
+                tile[s.row_idx[p] * TC + c] = val;
+                f += cabs2(val);
+            }
+            acc[0] = f;
+        }
+    } else if constexpr (MODE == COL_INV_FULL || MODE == COL_INV_INIT) {
+        const int c = tid % TC, bc = c0 + c;
+        const int v = bc < s.B ? s.band_cols[bc] : 0;
+        const float2* src = a.full_in + (size_t)zl * s.ny * s.nx;
+        float f = 0.f;
+        for (int y = tid / TC; y < NY; y += TPC) {
+            float2 val = make_float2(0.f, 0.f);
+            if (bc < s.B) {
+                const int pi = s.pidx[y * s.nx + v];
+                if (pi >= 0) {
+                    val = src[(size_t)y * s.nx + v];
+                    if constexpr (MODE == COL_INV_INIT) {
+                        a.cmp_out[(size_t)zl * s.P + pi] = cscale(val, a.init_keep);
+                        f += cabs2(val);
+                    }
+                }
+            }
+            tile[y * TC + c] = val;
+        }
+        acc[0] = f;
+    } else {  // COL_FWD_COMPACT
+        const int c = tid % TC, bc = c0 + c;
+        const float2* src = a.band_in + (size_t)zl * s.ny * s.Bs;
+        for (int y = tid / TC; y < NY; y += TPC)
+            tile[y * TC + c] = bc < s.B ? src[(size_t)y * s.Bs + bc] : make_float2(0.f, 0.f);
+    }
+
+    if constexpr (MODE == COL_FWD_COMPACT)
+        fft_lds<NY, TPC, -1>(tile + tid % TC, TC, tid / TC, tw);
+    else
+        fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
+
+    if constexpr (MODE == COL_FWD_COMPACT) {
+        const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
+        if (bc < s.B) {
+            float2* dst = a.cmp_out + (size_t)zl * s.P;
+            const int p1 = s.col_off[bc + 1];
+            float f = 0.f;
+            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
+                const float2 val = cscale(tile[s.row_idx[p] * TC + c], a.scale);
+                dst[p] = val;
+                f += cabs2(val);
+            }
+            acc[0] = f;
+        }
+    } else {
+        const int c = tid % TC, bc = c0 + c;
+        if (bc < s.B) {
+            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs;
+            for (int y = tid / TC; y < NY; y += TPC)
+                dst[(size_t)y * s.Bs + bc] = cscale(tile[y * TC + c], a.scale);
+        }
+    }
+    if (a.part != nullptr) {
+        // block index = (look * nz + z) * tiles + tile = look * col_blocks + z * tiles + tile
+        block_sum_store<1>(acc, a.part + blockIdx.x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass: RPB rows of length NX per block, TR threads per row.
+template <int NX, int MODE>
+__global__ __launch_bounds__(kBlock) void k_row(RowArgs a) {
+    constexpr int TR = row_threads_c(NX);
+    constexpr int RPB = kBlock / TR;
+    constexpr int S1 = (MODE == ROW_FWD) ? -1 : +1;
+    __shared__ float2 tw[NX];
+    __shared__ int bpos[NX];
+    __shared__ int bcol[NX];
+    __shared__ float2 buf[RPB * NX];
+    const SceneTables& s = a.s;
+    const int tid = threadIdx.x;
+    const int ri = tid / TR, t = tid % TR;
+    const int look = blockIdx.y;
+    const int rows = s.nz * s.ny;
+    const int row = blockIdx.x * RPB + ri;
+    const bool active = row < rows;
+    for (int i = tid; i < NX; i += kBlock) {
+        tw[i] = s.tw_x[i];
+        bpos[i] = s.band_pos[i];
+        bcol[i] = i < s.B ? s.band_cols[i] : 0;
+    }
+    __syncthreads();
+    float2* rb = buf + ri * NX;
+    const size_t img = ((size_t)look * rows + (active ? row : 0)) * NX;
+    const size_t band = ((size_t)look * rows + (active ? row : 0)) * s.Bs;
+
+    if constexpr (MODE == ROW_FWD) {
+        if (active)
+            for (int x = t; x < NX; x += TR) rb[x] = a.img_in[img + x];
+    } else {
+        if (active)
+            for (int x = t; x < NX; x += TR) {
+                const int bp = bpos[x];
+                rb[x] = bp >= 0 ? a.band_in[band + bp] : make_float2(0.f, 0.f);
+            }
+    }
+    fft_lds<NX, TR, S1>(rb, 1, t, tw);
+
+    if constexpr (MODE == ROW_INV) {
+        if (active)
+            for (int x = t; x < NX; x += TR) a.img_out[img + x] = cscale(rb[x], a.scale);
+    } else if constexpr (MODE == ROW_FWD) {
+        if (active)
+            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[bcol[b]], a.scale);
+    } else if constexpr (MODE == ROW_GRAD) {
+        float dd = 0.f, wd = 0.f, wm = 0.f;
+        if (active)
+            for (int x = t; x < NX; x += TR) {
+                const float2 ahr = cscale(rb[x], a.scale);
+                const float2 m = a.mu[img + x];
+                const float rp = a.r[img + x];
+                const float om = 1.f / (rp + a.floor_w);
+                const float2 d = make_float2(ahr.x * a.inv_s2w - om * m.x, ahr.y * a.inv_s2w - om * m.y);
+                rb[x] = d;
+                const float d2 = cabs2(d);
+                dd += d2;
+                wd += om * d2;
+                wm += om * cabs2(m);
+            }
+        fft_lds<NX, TR, -1>(rb, 1, t, tw);
+        if (active)
+            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[bcol[b]], a.scale);
+        double acc[3] = {dd, wd, wm};
+        block_sum_store<3>(acc, a.part + ((size_t)look * gridDim.x + blockIdx.x) * 3);
+    } else {  // ROW_UPDATE
+        const float gamma = (float)a.diag[(size_t)look * kDiag];
+        float wm1 = 0.f;
+        uint32_t fb = 0u;
+        if (active)
+            for (int x = t; x < NX; x += TR) {
+                const float2 ahr = cscale(rb[x], a.scale);
+                const float2 m = a.mu[img + x];
+                const float rp = a.r[img + x];
+                const float v = a.w[img + x];
+                const float om = 1.f / (rp + a.floor_w);
+                const float2 d = make_float2(ahr.x * a.inv_s2w - om * m.x, ahr.y * a.inv_s2w - om * m.y);
+                const float2 m1 = make_float2(m.x + gamma * d.x, m.y + gamma * d.y);
+                a.mu[img + x] = m1;
+                // covariance diagonal with A^H A ~ alpha I, and s = c + |mu|^2
+                const float c = a.s2w * rp / (a.alpha * rp + a.s2w);
+                const float sv = c + cabs2(m1);
+                // quadratic surrogate of r/r' + s/r, interpolating its
+                // derivative at r' and xi; written with s/r' first so that
+                // small anchors stay in float32 range
+                const float inv = 1.f / rp;
+                const float sr = sv * inv;
+                const float dq = inv * (1.f - sr);                  // q'(r')
+                const float D = dq + (rp - v) * a.inv_sigma2;       // rho'(r')
+                const bool down = D > 0.f;
+                const float xi = down ? rp * a.inv_beta : rp * a.beta;
+                const float qa = sr * inv * inv * (down ? a.k_dn : a.k_up);
+                const float qb = dq - qa * rp;
+                float rn = (v - a.sigma2 * qb) / (1.f + a.sigma2 * qa);
+                if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
+                rn = fminf(fmaxf(rn, fminf(rp, xi)), fmaxf(rp, xi));
+                if (!(rn > 0.f)) fb |= 2u;
+                a.r[img + x] = rn;
+                wm1 += om * cabs2(m1);
+            }
+        wave_or_fault(fb, a.fault);
+        double acc[1] = {wm1};
+        block_sum_store<1>(acc, a.part + (size_t)look * gridDim.x + blockIdx.x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_scatter_full(SceneTables s, size_t total,
+                                                         const float2* cmp, float2* full) {
+    const size_t per = (size_t)s.ny * s.nx;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
+        const size_t zl = i / per, pos = i - zl * per;
+        const int p = s.pidx[pos];
+        full[i] = p >= 0 ? cmp[zl * s.P + p] : make_float2(0.f, 0.f);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gamma(int nrow, int ncol, const double* prow,
+                                                  const double* pcf, const double* pci,
+                                                  double inv_s2w, double* diag, uint32_t* fault) {
+    const int look = blockIdx.x;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nrow; i += kBlock) {
+        const double* p = prow + ((size_t)look * nrow + i) * 3;
+        v[0] += p[0];
+        v[1] += p[1];
+        v[2] += p[2];
+    }
+    for (int i = threadIdx.x; i < ncol; i += kBlock) {
+        v[3] += pcf[(size_t)look * ncol + i];
+        v[4] += pci[(size_t)look * ncol + i];
+    }
+    __shared__ double tot[5];
+    block_sum_store<5>(v, tot);
+    if (threadIdx.x == 0) {
+        const double dd = tot[0], wd = tot[1], wm = tot[2], ad = tot[3], r2 = tot[4];
+        const double den = ad * inv_s2w + wd;
+        const double g = dd > 0.0 ? dd / den : 0.0;
+        double* o = diag + (size_t)look * kDiag;
+        o[0] = g;
+        o[1] = dd;
+        o[2] = ad;
+        o[3] = wd;
+        o[4] = r2;
+        o[5] = wm;
+        if (!(g >= 0.0) || !isfinite(g)) atomicOr(fault, 4u | 1u);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_resid(size_t per_look, float2* resid, const float2* dfd,
+                                                  const double* diag, double* part) {
+    const int look = blockIdx.y;
+    const float g = (float)diag[(size_t)look * kDiag];
+    float2* R = resid + per_look * look;
+    const float2* D = dfd + per_look * look;
+    float f = 0.f;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < per_look; i += (size_t)gridDim.x * kBlock) {
+        float2 x = R[i];
+        const float2 d = D[i];
+        x.x -= g * d.x;
+        x.y -= g * d.y;
+        R[i] = x;
+        f += cabs2(x);
+    }
+    double acc[1] = {f};
+    block_sum_store<1>(acc, part + (size_t)look * gridDim.x + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_diag_after(int nrow, int nres, const double* pupd,
+                                                       const double* pres, double* diag) {
+    const int look = blockIdx.x;
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < nrow; i += kBlock) v[0] += pupd[(size_t)look * nrow + i];
+    for (int i = threadIdx.x; i < nres; i += kBlock) v[1] += pres[(size_t)look * nres + i];
+    __shared__ double tot[2];
+    block_sum_store<2>(v, tot);
+    if (threadIdx.x == 0) {
+        diag[(size_t)look * kDiag + 6] = tot[1];
+        diag[(size_t)look * kDiag + 7] = tot[0];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_r0(size_t n, int looks, float2* mu, float s_mu,
+                                                    float* r0, double* part) {
+    const float inv_l = 1.f / (float)looks;
+    double f = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        float acc = 0.f;
+        for (int l = 0; l < looks; ++l) {
+            const float2 b = mu[(size_t)l * n + i];
+            acc += cabs2(b);
+            mu[(size_t)l * n + i] = cscale(b, s_mu);
+        }
+        const float r = acc * inv_l;
+        r0[i] = r;
+        f += r;
+    }
+    double v[1] = {f};
+    block_sum_store<1>(v, part + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum(const double* part, int count, double scale, double* out) {
+    const int look = blockIdx.x;
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < count; i += kBlock) v[0] += part[(size_t)look * count + i];
+    __shared__ double tot[1];
+    block_sum_store<1>(v, tot);
+    if (threadIdx.x == 0) out[look] = tot[0] * scale;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_floor(size_t n, int n_agents, const double* mean_r0,
+                                                       float* r, float* w) {
+    const float fl = (float)(1e-12 * mean_r0[0]);
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        const float v = fmaxf(r[i], fl);
+        for (int j = 0; j < n_agents; ++j) {
+            r[(size_t)j * n + i] = v;
+            w[(size_t)j * n + i] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Mann step: one voxel per thread, every agent's w and r held in registers.
+// Each agent's slice is addressed from a wave-uniform base pointer plus the
+// 32-bit voxel offset, so the per-agent loads need no per-lane 64-bit address.
+template <int NA>
+__global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
+    const unsigned n = (unsigned)a.n;
+    double num = 0.0, den = 0.0;
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        float wv[NA], rv[NA];
+        float wb = 0.f, rb = 0.f;
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            if (j < a.n_agents) {
+                wv[j] = (a.w + (size_t)j * n)[i];
+                rv[j] = (a.r + (size_t)j * n)[i];
+                wb += a.ups[j] * wv[j];
+                rb += a.ups[j] * rv[j];
+            }
+        }
+        const float xb = 2.f * rb - wb;
+        float wbn = 0.f, nm = 0.f;
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            if (j < a.n_agents) {
+                const float dr = rv[j] - wb;
+                nm += dr * dr;
+                const float wn = wv[j] + a.two_rho * (xb - rv[j]);
+                (a.w + (size_t)j * n)[i] = wn;
+                wbn += a.ups[j] * wn;
+            }
+        }
+        a.wbar[i] = wbn;
+        num += nm;
+        den += (double)a.n_agents * wb * wb;
+    }
+    double v[2] = {num, den};
+    block_sum_store<2>(v, a.part + (size_t)blockIdx.x * 2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mace_final(const double* part, int blocks, double* conv) {
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < blocks; i += kBlock) {
+        v[0] += part[(size_t)i * 2];
+        v[1] += part[(size_t)i * 2 + 1];
+    }
+    __shared__ double tot[2];
+    block_sum_store<2>(v, tot);
+    if (threadIdx.x == 0) conv[0] = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+struct Taps7 {
+    float g[7];
+};
+
+template <int AXIS>
+__global__ __launch_bounds__(kBlock) void k_gauss(int nx, int ny, int nz, Taps7 t, const float* in, float* out) {
+    const size_t n = (size_t)nx * ny * nz;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        const int x = (int)(i % nx);
+        const int y = (int)((i / nx) % ny);
+        const size_t z = i / ((size_t)nx * ny);
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const int off = k - 3;
+            size_t j;
+            if constexpr (AXIS == 0) {
+                j = i - x + (size_t)((x + off + nx) % nx);
+            } else if constexpr (AXIS == 1) {
+                j = i + (size_t)(((y + off + ny) % ny) - y) * nx;
+            } else {
+                const size_t zz = (size_t)(((int)z + off + nz) % nz);
+                j = i + (zz - z) * (size_t)nx * ny;
+            }
+            acc += t.g[k] * in[j];
+        }
+        out[i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+#define CLAMP_SIZES(X) X(32) X(64) X(128) X(192) X(256) X(384) X(512)
+
+template <int MODE>
+static hipError_t col_dispatch(const ColArgs& a, hipStream_t st) {
+    const dim3 grid((unsigned)((size_t)a.looks * a.s.nz * a.s.tiles));
+    switch (a.s.ny) {
+#define CASE(N)                                                                  \
+    case N:                                                                      \
+        hipLaunchKernelGGL((k_col<N, MODE>), grid, dim3(kBlock), 0, st, a);      \
+        break;
+        CLAMP_SIZES(CASE)
+#undef CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_col(int mode, const ColArgs& a, hipStream_t st) {
+    if (a.looks <= 0) return hipSuccess;
+    switch (mode) {
+        case COL_INV_COMPACT: return col_dispatch<COL_INV_COMPACT>(a, st);
+        case COL_INV_FULL: return col_dispatch<COL_INV_FULL>(a, st);
+        case COL_INV_INIT: return col_dispatch<COL_INV_INIT>(a, st);
+        case COL_FWD_COMPACT: return col_dispatch<COL_FWD_COMPACT>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int MODE>
+static hipError_t row_dispatch(const RowArgs& a, hipStream_t st) {
+    const dim3 grid((unsigned)row_blocks(a.s), (unsigned)a.looks);
+    switch (a.s.nx) {
+#define CASE(N)                                                                  \
+    case N:                                                                      \
+        hipLaunchKernelGGL((k_row<N, MODE>), grid, dim3(kBlock), 0, st, a);      \
+        break;
+        CLAMP_SIZES(CASE)
+#undef CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_row(int mode, const RowArgs& a, hipStream_t st) {
+    if (a.looks <= 0) return hipSuccess;
+    switch (mode) {
+        case ROW_INV: return row_dispatch<ROW_INV>(a, st);
+        case ROW_FWD: return row_dispatch<ROW_FWD>(a, st);
+        case ROW_GRAD: return row_dispatch<ROW_GRAD>(a, st);
+        case ROW_UPDATE: return row_dispatch<ROW_UPDATE>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_scatter_full(const SceneTables& s, int looks, const float2* cmp, float2* full,
+                               hipStream_t st) {
+    const size_t total = (size_t)looks * s.nz * s.ny * s.nx;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_full, dim3(grid_cap(total, 8192)), dim3(kBlock), 0, st, s, total, cmp, full);
+    return hipGetLastError();
+}
+
+hipError_t launch_gamma(const SceneTables& s, int looks, const double* part_row, const double* part_colfwd,
+                          const double* part_colinv, double inv_s2w, double* diag, uint32_t* fault,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_gamma, dim3(looks), dim3(kBlock), 0, st, row_blocks(s), col_blocks(s), part_row,
+                       part_colfwd, part_colinv, inv_s2w, diag, fault);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_update(const SceneTables& s, int looks, float2* resid, const float2* dfd,
+                               const double* diag, double* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_resid, dim3(resid_blocks(s), looks), dim3(kBlock), 0, st, (size_t)s.nz * s.P, resid,
+                       dfd, diag, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_after(const SceneTables& s, int looks, const double* pupd, const double* pres,
+                             double* diag, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_after, dim3(looks), dim3(kBlock), 0, st, row_blocks(s), resid_blocks(s), pupd,
+                       pres, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_r0(size_t n, int looks, float2* mu, float s_mu, float* r0, double* part,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_init_r0, dim3(mace_blocks(n)), dim3(kBlock), 0, st, n, looks, mu, s_mu, r0, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* part, int count, int looks, double scale, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum, dim3(looks), dim3(kBlock), 0, st, part, count, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_floor(size_t n, int n_agents, const double* mean_r0, float* r, float* w,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_init_floor, dim3(mace_blocks(n)), dim3(kBlock), 0, st, n, n_agents, mean_r0, r, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_mace(const MaceArgs& a, hipStream_t st) {
+    const dim3 grid(mace_blocks(a.n));
+    if (a.n_agents <= 8)
+        hipLaunchKernelGGL(k_mace<8>, grid, dim3(kBlock), 0, st, a);
+    else if (a.n_agents <= 16)
+        hipLaunchKernelGGL(k_mace<16>, grid, dim3(kBlock), 0, st, a);
+    else if (a.n_agents <= 32)
+        hipLaunchKernelGGL(k_mace<32>, grid, dim3(kBlock), 0, st, a);
+    else if (a.n_agents <= 64)
+        hipLaunchKernelGGL(k_mace<64>, grid, dim3(kBlock), 0, st, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_mace_final(const double* part, int blocks, double* conv_err, hipStream_t st) {
+    hipLaunchKernelGGL(k_mace_final, dim3(1), dim3(kBlock), 0, st, part, blocks, conv_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float* in, float* tmp0,
+                        float* tmp1, float* out, hipStream_t st) {
+    Taps7 t;
+    for (int k = 0; k < 7; ++k) t.g[k] = taps7[k];
+    const size_t n = (size_t)nx * ny * nz;
+    const dim3 grid(grid_cap(n, 8192));
+    hipLaunchKernelGGL(k_gauss<0>, grid, dim3(kBlock), 0, st, nx, ny, nz, t, in, tmp0);
+    hipLaunchKernelGGL(k_gauss<1>, grid, dim3(kBlock), 0, st, nx, ny, nz, t, tmp0, tmp1);
+    hipLaunchKernelGGL(k_gauss<2>, grid, dim3(kBlock), 0, st, nx, ny, nz, t, tmp1, out);
+    return hipGetLastError();
+}
+
+}  // namespace clampk
