@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--workload", default="full")
     ap.add_argument("--sigma2", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="before the timed region, copy MIB mebibytes once with a plain device copy, as a "
+                         "known-size reference for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -97,6 +100,14 @@ def main():
                    device=dev)
     yt = torch.from_numpy(y).to(dev)
     g.init(yt)
+    if args.copy_probe > 0:
+        nfl = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(nfl, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (nfl * 4, nfl * 4))
+        del src, dst
     log("warmup %d iterations" % args.warmup)
     for _ in range(args.warmup):
         g.iterate()
