@@ -146,6 +146,8 @@ clamp_status build_scene(const clamp_scene& in, Scene& s) {
     s.col_off.clear();
     s.row_idx.clear();
     s.band_cols.clear();
+    // compact layout: pupil samples band column by band column (v
+    // increasing), rows u increasing inside a column
     for (int v = 0; v < nx; ++v) {
         bool any = false;
         for (int u = 0; u < ny; ++u) any = any || mask[(size_t)u * nx + v];
@@ -164,7 +166,7 @@ clamp_status build_scene(const clamp_scene& in, Scene& s) {
     s.B = (int)s.band_cols.size();
     if (s.P == 0) return fail(CLAMP_EINVAL, "pupil passes no DFT sample");
     s.Bs = (s.B + 15) / 16 * 16;
-    s.tiles = (s.B + clampk::kTileCols - 1) / clampk::kTileCols;
+    s.tiles = (s.B + clampk::col_tile_cols(ny) - 1) / clampk::col_tile_cols(ny);
     s.alpha = (double)s.P / ((double)nx * ny);
     return CLAMP_OK;
 }

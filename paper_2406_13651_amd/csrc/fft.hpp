@@ -108,10 +108,24 @@ __host__ __device__ constexpr bool fft_len_ok(int n) {
     return n == 1;
 }
 
-// One Stockham stage and the ones after it.  buf[i * stride] is element i of
-// this group's vector; t in [0, T) is the thread's rank in the group.  Every
-// thread of the block must call this (it contains block barriers).
-template <int N, int T, int S, int STAGE, int NS>
+// Position of element i of a padded LDS vector: one float2 of padding after
+// every 16 elements (PADSH = 4) spreads the radix-R autosort stores over the
+// LDS banks; PADSH = 0 means no padding.
+template <int PADSH>
+__host__ __device__ constexpr int lds_pos(int i) {
+    if constexpr (PADSH > 0) return i + (i >> PADSH);
+    else return i;
+}
+template <int N, int PADSH>
+__host__ __device__ constexpr int lds_len() {
+    return lds_pos<PADSH>(N - 1) + 1;
+}
+
+// One Stockham stage and the ones after it.  buf[lds_pos(i) * stride] is
+// element i of this group's vector; t in [0, T) is the thread's rank in the
+// group.  Every thread of the block must call this (it contains block
+// barriers).
+template <int N, int T, int S, int PADSH, int STAGE, int NS>
 __device__ __forceinline__ void fft_stages(float2* buf, int stride, int t, const float2* tw) {
     if constexpr (STAGE < num_stages(N)) {
         constexpr int R = radix_at(N, STAGE);
@@ -124,7 +138,7 @@ __device__ __forceinline__ void fft_stages(float2* buf, int stride, int t, const
             const int j = t + p * T;
             if ((NB % T == 0) || j < NB) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[p][r] = buf[(j + r * NB) * stride];
+                for (int r = 0; r < R; ++r) v[p][r] = buf[lds_pos<PADSH>(j + r * NB) * stride];
             }
         }
         __syncthreads();
@@ -144,22 +158,22 @@ __device__ __forceinline__ void fft_stages(float2* buf, int stride, int t, const
                 Bfly<R, S>::run(v[p]);
                 const int base = (j / NS) * NS * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) buf[(base + r * NS) * stride] = v[p][r];
+                for (int r = 0; r < R; ++r) buf[lds_pos<PADSH>(base + r * NS) * stride] = v[p][r];
             }
         }
         __syncthreads();
-        fft_stages<N, T, S, STAGE + 1, NS * R>(buf, stride, t, tw);
+        fft_stages<N, T, S, PADSH, STAGE + 1, NS * R>(buf, stride, t, tw);
     }
 }
 
 // Unnormalised length-N DFT of buf (S = -1 forward, +1 inverse), in place.
 // Starts with a block barrier, so writes made to buf before the call are
 // visible, and ends with one, so the result is visible to the whole block.
-template <int N, int T, int S>
+template <int N, int T, int S, int PADSH = 0>
 __device__ __forceinline__ void fft_lds(float2* buf, int stride, int t, const float2* tw) {
     static_assert(fft_len_ok(N), "FFT length must be 2^a 3^b");
     __syncthreads();
-    fft_stages<N, T, S, 0, 1>(buf, stride, t, tw);
+    fft_stages<N, T, S, PADSH, 0, 1>(buf, stride, t, tw);
 }
 
 }  // namespace clampk

@@ -8,7 +8,11 @@
 namespace clampk {
 
 constexpr int kBlock = 256;      // threads per block for every kernel
-constexpr int kTileCols = 16;    // band columns per column-pass block
+
+// Band columns per column-pass work item: 16 (128-byte row segments) up to
+// length 256; 8 for longer columns, which keeps each thread's share of an
+// item at 16 values.
+__host__ __device__ constexpr int col_tile_cols(int ny) { return ny >= 384 ? 8 : 16; }
 constexpr int kDiag = 8;         // doubles of diagnostics per look
 
 // Device tables of one scene (owned by the plan).
@@ -17,12 +21,12 @@ struct SceneTables {
     int P;       // pupil samples per slice
     int B;       // band columns (columns holding pupil samples)
     int Bs;      // row stride of band-row buffers (B rounded up to 16)
-    int tiles;   // ceil(B / kTileCols)
+    int tiles;   // ceil(B / col_tile_cols(ny))
     const float2* tw_x;     // [nx] exp(-2 pi i m / nx)
     const float2* tw_y;     // [ny]
     const int* band_cols;   // [B] natural column index of each band column
     const int* band_pos;    // [nx] band index of a column, -1 outside the band
-    const int* col_off;     // [B + 1] compact offsets of each band column
+    const int* col_off;     // [B + 1] compact offset of each band column
     const int* row_idx;     // [P] row of each compact entry
     const int* pidx;        // [ny * nx] compact index of a sample, -1 off-pupil
 };

@@ -35,7 +35,7 @@ static int grid_cap(size_t work, int cap) {
     return (int)(b < (size_t)cap ? b : (size_t)cap);
 }
 int resid_blocks(const SceneTables& s) { return grid_cap((size_t)s.nz * s.P, 512); }
-int mace_blocks(size_t n) { return grid_cap(n, 2048); }
+int mace_blocks(size_t n) { return grid_cap(n / 2, 2048); }
 
 // Sum of K doubles over the block, written by thread 0 to out[0..K).
 template <int K>
@@ -72,10 +72,15 @@ __device__ __forceinline__ void wave_or_fault(uint32_t bits, uint32_t* fault) {
 }
 
 // ---------------------------------------------------------------------------
-// Column pass over a tile of kTileCols band columns of one slice of one look.
-template <int NY, int MODE>
-__global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
-    constexpr int TC = kTileCols;
+// Column passes.  A work item is a tile of TC band columns of one slice of one
+// look.  The compact pupil layout is column-major (band column by band
+// column, rows increasing), so a tile's pupil samples are TC contiguous runs.
+//
+// Inverse pass from the compact layout: one item per block; the tile is
+// zeroed, the runs are scattered into it, and the columns are transformed.
+template <int NY>
+__global__ __launch_bounds__(kBlock) void k_col_inv_compact(ColArgs a) {
+    constexpr int TC = col_tile_cols(NY);
     constexpr int TPC = kBlock / TC;
     __shared__ float2 tw[NY];
     __shared__ float2 tile[NY * TC];
@@ -85,11 +90,10 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
     const int zl = blockIdx.x / s.tiles;  // look * nz + z
     const int c0 = tile_i * TC;
     for (int i = tid; i < NY; i += kBlock) tw[i] = s.tw_y[i];
+    for (int i = tid; i < NY * TC; i += kBlock) tile[i] = make_float2(0.f, 0.f);
+    __syncthreads();
     double acc[1] = {0.0};
-
-    if constexpr (MODE == COL_INV_COMPACT) {
-        for (int i = tid; i < NY * TC; i += kBlock) tile[i] = make_float2(0.f, 0.f);
-        __syncthreads();
+    {
         const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
         if (bc < s.B) {
             const float2* src = a.cmp_in + (size_t)zl * s.P;
@@ -102,76 +106,139 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
             }
             acc[0] = f;
         }
-    } else if constexpr (MODE == COL_INV_FULL || MODE == COL_INV_INIT) {
+    }
+    fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
+    {
         const int c = tid % TC, bc = c0 + c;
-        const int v = bc < s.B ? s.band_cols[bc] : 0;
-        const float2* src = a.full_in + (size_t)zl * s.ny * s.nx;
+        if (bc < s.B) {
+            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bc;
+            for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + c], a.scale);
+        }
+    }
+    // block index = (look * nz + z) * tiles + tile = look * col_blocks + z * tiles + tile
+    if (a.part != nullptr) block_sum_store<1>(acc, a.part + blockIdx.x);
+}
+
+// Dense-input column passes (forward from band rows; inverse from full
+// grids).  Blocks are persistent and walk the items with a stride of the
+// grid size; each thread keeps the next item's inputs in registers, loaded
+// while the current item's column FFTs run, so the HBM latency of one item
+// hides behind the LDS work of the previous one.  Thread (tid / TC, tid % TC)
+// loads rows y = tid / TC + k * TPC of column tid % TC.
+template <int NY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
+    constexpr int TC = col_tile_cols(NY);
+    constexpr int TPC = kBlock / TC;       // threads per column
+    constexpr int PT = NY / TPC;           // values per thread per item
+    static_assert(NY % TPC == 0, "column length must be a multiple of the threads per column");
+    constexpr bool FWD = (MODE == COL_FWD_COMPACT);
+    __shared__ float2 tw[NY];
+    __shared__ float2 tile[NY * TC];
+    const SceneTables& s = a.s;
+    const int tid = threadIdx.x;
+    const int items = a.looks * s.nz * s.tiles;
+    for (int i = tid; i < NY; i += kBlock) tw[i] = s.tw_y[i];
+
+    float2 pre[PT];
+    double acc_in = 0.0;  // sum |input|^2 of the prefetched item (init loads)
+
+    auto load_item = [&](int item) {
+        const int tile_i = item % s.tiles;
+        const int zl = item / s.tiles;
+        const int c = tid % TC, bc = tile_i * TC + c;
         float f = 0.f;
-        for (int y = tid / TC; y < NY; y += TPC) {
-            float2 val = make_float2(0.f, 0.f);
-            if (bc < s.B) {
-                const int pi = s.pidx[y * s.nx + v];
-                if (pi >= 0) {
-                    val = src[(size_t)y * s.nx + v];
-                    if constexpr (MODE == COL_INV_INIT) {
-                        a.cmp_out[(size_t)zl * s.P + pi] = cscale(val, a.init_keep);
-                        f += cabs2(val);
+        if constexpr (FWD) {
+            const float2* src = a.band_in + (size_t)zl * s.ny * s.Bs + bc;
+#pragma unroll
+            for (int k = 0; k < PT; ++k)
+                pre[k] = bc < s.B ? src[(size_t)(tid / TC + k * TPC) * s.Bs] : make_float2(0.f, 0.f);
+        } else {  // COL_INV_FULL, COL_INV_INIT
+            const int v = bc < s.B ? s.band_cols[bc] : 0;
+            const float2* src = a.full_in + (size_t)zl * s.ny * s.nx;
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int y = tid / TC + k * TPC;
+                float2 val = make_float2(0.f, 0.f);
+                if (bc < s.B) {
+                    const int pi = s.pidx[y * s.nx + v];
+                    if (pi >= 0) {
+                        val = src[(size_t)y * s.nx + v];
+                        if constexpr (MODE == COL_INV_INIT) {
+                            a.cmp_out[(size_t)zl * s.P + pi] = cscale(val, a.init_keep);
+                            f += cabs2(val);
+                        }
                     }
                 }
+                pre[k] = val;
             }
-            tile[y * TC + c] = val;
         }
-        acc[0] = f;
-    } else {  // COL_FWD_COMPACT
-        const int c = tid % TC, bc = c0 + c;
-        const float2* src = a.band_in + (size_t)zl * s.ny * s.Bs;
-        for (int y = tid / TC; y < NY; y += TPC)
-            tile[y * TC + c] = bc < s.B ? src[(size_t)y * s.Bs + bc] : make_float2(0.f, 0.f);
-    }
+        acc_in = f;
+    };
 
-    if constexpr (MODE == COL_FWD_COMPACT)
-        fft_lds<NY, TPC, -1>(tile + tid % TC, TC, tid / TC, tw);
-    else
-        fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
+    int item = blockIdx.x;
+    if (item < items) load_item(item);
+    for (; item < items; item += gridDim.x) {
+        const int tile_i = item % s.tiles;
+        const int zl = item / s.tiles;
+        const int c0 = tile_i * TC;
+        double acc[1] = {acc_in};
+        __syncthreads();  // the previous item's readers of `tile` are done
+#pragma unroll
+        for (int k = 0; k < PT; ++k) tile[(tid / TC + k * TPC) * TC + tid % TC] = pre[k];
+        const int next = item + gridDim.x;
+        if (next < items) load_item(next);
 
-    if constexpr (MODE == COL_FWD_COMPACT) {
-        const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
-        if (bc < s.B) {
-            float2* dst = a.cmp_out + (size_t)zl * s.P;
-            const int p1 = s.col_off[bc + 1];
+        if constexpr (FWD)
+            fft_lds<NY, TPC, -1>(tile + tid % TC, TC, tid / TC, tw);
+        else
+            fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
+
+        if constexpr (FWD) {
+            const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
             float f = 0.f;
-            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
-                const float2 val = cscale(tile[s.row_idx[p] * TC + c], a.scale);
-                dst[p] = val;
-                f += cabs2(val);
+            if (bc < s.B) {
+                float2* dst = a.cmp_out + (size_t)zl * s.P;
+                const int p1 = s.col_off[bc + 1];
+                for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
+                    const float2 val = cscale(tile[s.row_idx[p] * TC + c], a.scale);
+                    dst[p] = val;
+                    f += cabs2(val);
+                }
             }
             acc[0] = f;
+        } else {
+            const int c = tid % TC, bc = c0 + c;
+            if (bc < s.B) {
+                float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bc;
+                for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + c], a.scale);
+            }
         }
-    } else {
-        const int c = tid % TC, bc = c0 + c;
-        if (bc < s.B) {
-            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs;
-            for (int y = tid / TC; y < NY; y += TPC)
-                dst[(size_t)y * s.Bs + bc] = cscale(tile[y * TC + c], a.scale);
-        }
-    }
-    if (a.part != nullptr) {
-        // block index = (look * nz + z) * tiles + tile = look * col_blocks + z * tiles + tile
-        block_sum_store<1>(acc, a.part + blockIdx.x);
+        // item index = (look * nz + z) * tiles + tile = look * col_blocks + z * tiles + tile
+        if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Row pass: RPB rows of length NX per block, TR threads per row.
+// Row pass: RPB rows of length NX per block, TR threads per row.  The
+// per-voxel streams of the fused modes (mu, the anchor r', w) are loaded into
+// registers at the start, so their latency overlaps the band-row load and
+// the first FFT.
 template <int NX, int MODE>
 __global__ __launch_bounds__(kBlock) void k_row(RowArgs a) {
     constexpr int TR = row_threads_c(NX);
     constexpr int RPB = kBlock / TR;
+    constexpr int PX = (NX + TR - 1) / TR;          // row samples per thread
     constexpr int S1 = (MODE == ROW_FWD) ? -1 : +1;
+    constexpr int PAD = 4;                          // one float2 of padding per 16
+    constexpr int RS = lds_len<NX, PAD>();          // padded row length in LDS
+    constexpr bool FUSED = (MODE == ROW_GRAD || MODE == ROW_UPDATE);
+    // Stream prefetch pays off for the gradient pass; the update pass already
+    // runs near the read/write bandwidth ceiling and loads its streams late.
+    constexpr bool PREFETCH = (MODE == ROW_GRAD);
     __shared__ float2 tw[NX];
     __shared__ int bpos[NX];
     __shared__ int bcol[NX];
-    __shared__ float2 buf[RPB * NX];
+    __shared__ float2 buf[RPB * RS];
     const SceneTables& s = a.s;
     const int tid = threadIdx.x;
     const int ri = tid / TR, t = tid % TR;
@@ -179,89 +246,115 @@ __global__ __launch_bounds__(kBlock) void k_row(RowArgs a) {
     const int rows = s.nz * s.ny;
     const int row = blockIdx.x * RPB + ri;
     const bool active = row < rows;
+    const size_t img = ((size_t)look * rows + (active ? row : 0)) * NX;
+    const size_t band = ((size_t)look * rows + (active ? row : 0)) * s.Bs;
+
+    float2 m[FUSED ? PX : 1];
+    float rp[FUSED ? PX : 1];
+    float wv[MODE == ROW_UPDATE ? PX : 1];
+    auto load_streams = [&]() {
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) {
+                    m[k] = a.mu[img + x];
+                    rp[k] = a.r[img + x];
+                    if constexpr (MODE == ROW_UPDATE) wv[k] = a.w[img + x];
+                }
+            }
+        }
+    };
+    if constexpr (PREFETCH) load_streams();
     for (int i = tid; i < NX; i += kBlock) {
         tw[i] = s.tw_x[i];
         bpos[i] = s.band_pos[i];
         bcol[i] = i < s.B ? s.band_cols[i] : 0;
     }
     __syncthreads();
-    float2* rb = buf + ri * NX;
-    const size_t img = ((size_t)look * rows + (active ? row : 0)) * NX;
-    const size_t band = ((size_t)look * rows + (active ? row : 0)) * s.Bs;
+    float2* rb = buf + ri * RS;
 
     if constexpr (MODE == ROW_FWD) {
         if (active)
-            for (int x = t; x < NX; x += TR) rb[x] = a.img_in[img + x];
+            for (int x = t; x < NX; x += TR) rb[lds_pos<PAD>(x)] = a.img_in[img + x];
     } else {
         if (active)
             for (int x = t; x < NX; x += TR) {
                 const int bp = bpos[x];
-                rb[x] = bp >= 0 ? a.band_in[band + bp] : make_float2(0.f, 0.f);
+                rb[lds_pos<PAD>(x)] = bp >= 0 ? a.band_in[band + bp] : make_float2(0.f, 0.f);
             }
     }
-    fft_lds<NX, TR, S1>(rb, 1, t, tw);
+    fft_lds<NX, TR, S1, PAD>(rb, 1, t, tw);
 
     if constexpr (MODE == ROW_INV) {
         if (active)
-            for (int x = t; x < NX; x += TR) a.img_out[img + x] = cscale(rb[x], a.scale);
+            for (int x = t; x < NX; x += TR) a.img_out[img + x] = cscale(rb[lds_pos<PAD>(x)], a.scale);
     } else if constexpr (MODE == ROW_FWD) {
         if (active)
-            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[bcol[b]], a.scale);
+            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(bcol[b])], a.scale);
     } else if constexpr (MODE == ROW_GRAD) {
         float dd = 0.f, wd = 0.f, wm = 0.f;
-        if (active)
-            for (int x = t; x < NX; x += TR) {
-                const float2 ahr = cscale(rb[x], a.scale);
-                const float2 m = a.mu[img + x];
-                const float rp = a.r[img + x];
-                const float om = 1.f / (rp + a.floor_w);
-                const float2 d = make_float2(ahr.x * a.inv_s2w - om * m.x, ahr.y * a.inv_s2w - om * m.y);
-                rb[x] = d;
-                const float d2 = cabs2(d);
-                dd += d2;
-                wd += om * d2;
-                wm += om * cabs2(m);
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) {
+                    const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
+                    const float om = 1.f / (rp[k] + a.floor_w);
+                    const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
+                    rb[lds_pos<PAD>(x)] = d;
+                    const float d2 = cabs2(d);
+                    dd += d2;
+                    wd += om * d2;
+                    wm += om * cabs2(m[k]);
+                }
             }
-        fft_lds<NX, TR, -1>(rb, 1, t, tw);
+        }
+        fft_lds<NX, TR, -1, PAD>(rb, 1, t, tw);
         if (active)
-            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[bcol[b]], a.scale);
+            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(bcol[b])], a.scale);
         double acc[3] = {dd, wd, wm};
         block_sum_store<3>(acc, a.part + ((size_t)look * gridDim.x + blockIdx.x) * 3);
     } else {  // ROW_UPDATE
+        if constexpr (!PREFETCH) load_streams();
         const float gamma = (float)a.diag[(size_t)look * kDiag];
         float wm1 = 0.f;
         uint32_t fb = 0u;
-        if (active)
-            for (int x = t; x < NX; x += TR) {
-                const float2 ahr = cscale(rb[x], a.scale);
-                const float2 m = a.mu[img + x];
-                const float rp = a.r[img + x];
-                const float v = a.w[img + x];
-                const float om = 1.f / (rp + a.floor_w);
-                const float2 d = make_float2(ahr.x * a.inv_s2w - om * m.x, ahr.y * a.inv_s2w - om * m.y);
-                const float2 m1 = make_float2(m.x + gamma * d.x, m.y + gamma * d.y);
-                a.mu[img + x] = m1;
-                // covariance diagonal with A^H A ~ alpha I, and s = c + |mu|^2
-                const float c = a.s2w * rp / (a.alpha * rp + a.s2w);
-                const float sv = c + cabs2(m1);
-                // quadratic surrogate of r/r' + s/r, interpolating its
-                // derivative at r' and xi; written with s/r' first so that
-                // small anchors stay in float32 range
-                const float inv = 1.f / rp;
-                const float sr = sv * inv;
-                const float dq = inv * (1.f - sr);                  // q'(r')
-                const float D = dq + (rp - v) * a.inv_sigma2;       // rho'(r')
-                const bool down = D > 0.f;
-                const float xi = down ? rp * a.inv_beta : rp * a.beta;
-                const float qa = sr * inv * inv * (down ? a.k_dn : a.k_up);
-                const float qb = dq - qa * rp;
-                float rn = (v - a.sigma2 * qb) / (1.f + a.sigma2 * qa);
-                if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
-                rn = fminf(fmaxf(rn, fminf(rp, xi)), fmaxf(rp, xi));
-                if (!(rn > 0.f)) fb |= 2u;
-                a.r[img + x] = rn;
-                wm1 += om * cabs2(m1);
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) {
+                    const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
+                    const float r0 = rp[k];
+                    const float v = wv[k];
+                    const float om = 1.f / (r0 + a.floor_w);
+                    const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
+                    const float2 m1 = make_float2(m[k].x + gamma * d.x, m[k].y + gamma * d.y);
+                    a.mu[img + x] = m1;
+                    // covariance diagonal with A^H A ~ alpha I, and s = c + |mu|^2
+                    const float c = a.s2w * r0 / (a.alpha * r0 + a.s2w);
+                    const float sv = c + cabs2(m1);
+                    // quadratic surrogate of r/r' + s/r, interpolating its
+                    // derivative at r' and xi; written with s/r' first so that
+                    // small anchors stay in float32 range
+                    const float inv = 1.f / r0;
+                    const float sr = sv * inv;
+                    const float dq = inv * (1.f - sr);                  // q'(r')
+                    const float D = dq + (r0 - v) * a.inv_sigma2;       // rho'(r')
+                    const bool down = D > 0.f;
+                    const float xi = down ? r0 * a.inv_beta : r0 * a.beta;
+                    const float qa = sr * inv * inv * (down ? a.k_dn : a.k_up);
+                    const float qb = dq - qa * r0;
+                    float rn = (v - a.sigma2 * qb) / (1.f + a.sigma2 * qa);
+                    if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
+                    rn = fminf(fmaxf(rn, fminf(r0, xi)), fmaxf(r0, xi));
+                    if (!(rn > 0.f)) fb |= 2u;
+                    a.r[img + x] = rn;
+                    wm1 += om * cabs2(m1);
+                }
             }
+        }
         wave_or_fault(fb, a.fault);
         double acc[1] = {wm1};
         block_sum_store<1>(acc, a.part + (size_t)look * gridDim.x + blockIdx.x);
@@ -385,40 +478,48 @@ __global__ __launch_bounds__(kBlock) void k_init_floor(size_t n, int n_agents, c
 }
 
 // ---------------------------------------------------------------------------
-// Mann step: one voxel per thread, every agent's w and r held in registers.
-// Each agent's slice is addressed from a wave-uniform base pointer plus the
-// 32-bit voxel offset, so the per-agent loads need no per-lane 64-bit address.
+// Mann step: two adjacent voxels per thread, every agent's w and r held in
+// registers (NA >= n_agents, a multiple of 8).  Each agent's slice is
+// addressed from a wave-uniform base pointer plus a 32-bit voxel offset.
 template <int NA>
 __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
     const unsigned n = (unsigned)a.n;
+    const unsigned n2 = n / 2;
     double num = 0.0, den = 0.0;
-    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        float wv[NA], rv[NA];
-        float wb = 0.f, rb = 0.f;
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n2; i += gridDim.x * kBlock) {
+        float2 wv[NA], rv[NA];
+        float2 wb = make_float2(0.f, 0.f), rb = make_float2(0.f, 0.f);
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
             if (j < a.n_agents) {
-                wv[j] = (a.w + (size_t)j * n)[i];
-                rv[j] = (a.r + (size_t)j * n)[i];
-                wb += a.ups[j] * wv[j];
-                rb += a.ups[j] * rv[j];
+                wv[j] = reinterpret_cast<const float2*>(a.w + (size_t)j * n)[i];
+                rv[j] = reinterpret_cast<const float2*>(a.r + (size_t)j * n)[i];
+                const float u = a.ups[j];
+                wb.x += u * wv[j].x;
+                wb.y += u * wv[j].y;
+                rb.x += u * rv[j].x;
+                rb.y += u * rv[j].y;
             }
         }
-        const float xb = 2.f * rb - wb;
-        float wbn = 0.f, nm = 0.f;
+        const float2 xb = make_float2(2.f * rb.x - wb.x, 2.f * rb.y - wb.y);
+        float2 wbn = make_float2(0.f, 0.f);
+        float nm = 0.f;
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
             if (j < a.n_agents) {
-                const float dr = rv[j] - wb;
-                nm += dr * dr;
-                const float wn = wv[j] + a.two_rho * (xb - rv[j]);
-                (a.w + (size_t)j * n)[i] = wn;
-                wbn += a.ups[j] * wn;
+                const float dx = rv[j].x - wb.x, dy = rv[j].y - wb.y;
+                nm += dx * dx + dy * dy;
+                const float2 wn = make_float2(wv[j].x + a.two_rho * (xb.x - rv[j].x),
+                                              wv[j].y + a.two_rho * (xb.y - rv[j].y));
+                reinterpret_cast<float2*>(a.w + (size_t)j * n)[i] = wn;
+                const float u = a.ups[j];
+                wbn.x += u * wn.x;
+                wbn.y += u * wn.y;
             }
         }
-        a.wbar[i] = wbn;
+        reinterpret_cast<float2*>(a.wbar)[i] = wbn;
         num += nm;
-        den += (double)a.n_agents * wb * wb;
+        den += (double)a.n_agents * ((double)wb.x * wb.x + (double)wb.y * wb.y);
     }
     double v[2] = {num, den};
     block_sum_store<2>(v, a.part + (size_t)blockIdx.x * 2);
@@ -440,29 +541,60 @@ struct Taps7 {
     float g[7];
 };
 
-template <int AXIS>
-__global__ __launch_bounds__(kBlock) void k_gauss(int nx, int ny, int nz, Taps7 t, const float* in, float* out) {
-    const size_t n = (size_t)nx * ny * nz;
+// Periodic 7-tap filter along x (contiguous).
+__global__ __launch_bounds__(kBlock) void k_gauss_x(int nx, size_t n, Taps7 t, const float* in, float* out) {
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
         const int x = (int)(i % nx);
-        const int y = (int)((i / nx) % ny);
-        const size_t z = i / ((size_t)nx * ny);
+        const size_t row = i - x;
         float acc = 0.f;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            const int off = k - 3;
-            size_t j;
-            if constexpr (AXIS == 0) {
-                j = i - x + (size_t)((x + off + nx) % nx);
-            } else if constexpr (AXIS == 1) {
-                j = i + (size_t)(((y + off + ny) % ny) - y) * nx;
-            } else {
-                const size_t zz = (size_t)(((int)z + off + nz) % nz);
-                j = i + (zz - z) * (size_t)nx * ny;
-            }
-            acc += t.g[k] * in[j];
-        }
+        for (int k = 0; k < 7; ++k) acc += t.g[k] * in[row + (size_t)((x + k - 3 + nx) % nx)];
         out[i] = acc;
+    }
+}
+
+// Periodic 7-tap filter along a strided axis of length len (stride `inner`
+// elements): each thread slides a register window down a chunk of CH
+// samples, so every input is read once per chunk plus a 6-sample halo.
+template <int CH>
+__global__ __launch_bounds__(kBlock) void k_gauss_strided(int len, size_t inner, size_t outer, Taps7 t,
+                                                          const float* in, float* out) {
+    const int chunks = (len + CH - 1) / CH;
+    const size_t work = outer * (size_t)chunks;
+    for (size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x; idx < work; idx += (size_t)gridDim.x * kBlock) {
+        const size_t o = idx % outer;
+        const int c = (int)(idx / outer);
+        const size_t base = (o / inner) * inner * (size_t)len + (o % inner);
+        const int y0 = c * CH;
+        float win[CH + 6];
+#pragma unroll
+        for (int k = 0; k < CH + 6; ++k) {
+            int yy = (y0 + k - 3) % len;
+            if (yy < 0) yy += len;
+            win[k] = in[base + (size_t)yy * inner];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (y0 + k < len) {
+                float acc = 0.f;
+#pragma unroll
+                for (int q = 0; q < 7; ++q) acc += t.g[q] * win[k + q];
+                out[base + (size_t)(y0 + k) * inner] = acc;
+            }
+        }
+    }
+}
+
+static void gauss_axis(int len, size_t inner, size_t outer, const Taps7& t, const float* in, float* out,
+                       hipStream_t st) {
+    if (len >= 32) {
+        const size_t work = outer * ((len + 31) / 32);
+        hipLaunchKernelGGL(k_gauss_strided<32>, dim3(grid_cap(work, 8192)), dim3(kBlock), 0, st, len, inner, outer,
+                           t, in, out);
+    } else {
+        const size_t work = outer * ((len + 7) / 8);
+        hipLaunchKernelGGL(k_gauss_strided<8>, dim3(grid_cap(work, 8192)), dim3(kBlock), 0, st, len, inner, outer, t,
+                           in, out);
     }
 }
 
@@ -470,13 +602,32 @@ __global__ __launch_bounds__(kBlock) void k_gauss(int nx, int ny, int nz, Taps7 
 // Launchers
 #define CLAMP_SIZES(X) X(32) X(64) X(128) X(192) X(256) X(384) X(512)
 
+static int g_col_grid_cap = 0;
+
+// Persistent grid of the column pass: enough blocks for every CU to hold as
+// many items as its LDS allows, never more blocks than items.
+static int col_grid(size_t items) {
+    if (g_col_grid_cap == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        g_col_grid_cap = cus * 8;
+    }
+    return (int)(items < (size_t)g_col_grid_cap ? items : (size_t)g_col_grid_cap);
+}
+
 template <int MODE>
 static hipError_t col_dispatch(const ColArgs& a, hipStream_t st) {
-    const dim3 grid((unsigned)((size_t)a.looks * a.s.nz * a.s.tiles));
+    const size_t items = (size_t)a.looks * a.s.nz * a.s.tiles;
+    const dim3 grid((unsigned)(MODE == COL_INV_COMPACT ? items : col_grid(items)));
     switch (a.s.ny) {
-#define CASE(N)                                                                  \
-    case N:                                                                      \
-        hipLaunchKernelGGL((k_col<N, MODE>), grid, dim3(kBlock), 0, st, a);      \
+#define CASE(N)                                                                          \
+    case N:                                                                              \
+        if constexpr (MODE == COL_INV_COMPACT)                                           \
+            hipLaunchKernelGGL((k_col_inv_compact<N>), grid, dim3(kBlock), 0, st, a);    \
+        else                                                                             \
+            hipLaunchKernelGGL((k_col<N, MODE>), grid, dim3(kBlock), 0, st, a);          \
         break;
         CLAMP_SIZES(CASE)
 #undef CASE
@@ -572,17 +723,18 @@ hipError_t launch_init_floor(size_t n, int n_agents, const double* mean_r0, floa
 }
 
 hipError_t launch_mace(const MaceArgs& a, hipStream_t st) {
+    if (a.n % 2 != 0) return hipErrorInvalidValue;
     const dim3 grid(mace_blocks(a.n));
-    if (a.n_agents <= 8)
-        hipLaunchKernelGGL(k_mace<8>, grid, dim3(kBlock), 0, st, a);
-    else if (a.n_agents <= 16)
-        hipLaunchKernelGGL(k_mace<16>, grid, dim3(kBlock), 0, st, a);
-    else if (a.n_agents <= 32)
-        hipLaunchKernelGGL(k_mace<32>, grid, dim3(kBlock), 0, st, a);
-    else if (a.n_agents <= 64)
-        hipLaunchKernelGGL(k_mace<64>, grid, dim3(kBlock), 0, st, a);
-    else
-        return hipErrorInvalidValue;
+    switch ((a.n_agents + 7) / 8) {
+#define CASE(K)                                                              \
+    case K:                                                                  \
+        hipLaunchKernelGGL(k_mace<8 * K>, grid, dim3(kBlock), 0, st, a);     \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -596,10 +748,10 @@ hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float*
     Taps7 t;
     for (int k = 0; k < 7; ++k) t.g[k] = taps7[k];
     const size_t n = (size_t)nx * ny * nz;
-    const dim3 grid(grid_cap(n, 8192));
-    hipLaunchKernelGGL(k_gauss<0>, grid, dim3(kBlock), 0, st, nx, ny, nz, t, in, tmp0);
-    hipLaunchKernelGGL(k_gauss<1>, grid, dim3(kBlock), 0, st, nx, ny, nz, t, tmp0, tmp1);
-    hipLaunchKernelGGL(k_gauss<2>, grid, dim3(kBlock), 0, st, nx, ny, nz, t, tmp1, out);
+    hipLaunchKernelGGL(k_gauss_x, dim3(grid_cap(n, 8192)), dim3(kBlock), 0, st, nx, n, t, in, tmp0);
+    // y: stride nx, outer index runs over (z, x); z: stride nx*ny, outer over (y, x)
+    gauss_axis(ny, (size_t)nx, (size_t)nz * nx, t, tmp0, tmp1, st);
+    gauss_axis(nz, (size_t)nx * ny, (size_t)nx * ny, t, tmp1, out, st);
     return hipGetLastError();
 }
 

@@ -105,7 +105,7 @@ def test_pupil_index_is_column_major_disk(C):
     u, v = idx // 256, idx % 256
     assert np.all(mask[u, v])
     key = v.astype(np.int64) * 256 + u
-    assert np.all(np.diff(key) > 0)
+    assert np.all(np.diff(key) > 0)  # column by column, rows increasing
 
 
 def test_zero_batch_and_errors(C):
