@@ -189,6 +189,66 @@ clamp_status clamp_mace_step(const clamp_plan* plan, int32_t scene,
                              float* wbar, double* conv_err,
                              void* workspace, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: every scene of a plan advanced together, one CLAMP iteration per
+ * clamp_batch_step.  Each stage runs as persistent launches over device work
+ * queues of (scene, look, row group or column tile) items; the FFT passes
+ * launch once per FFT length present, the other stages once for all scenes.
+ * The interval factor of App. A is beta_k = 1 + 2 / ln(k + 1) for iteration k
+ * = (device iteration counter) + 1, read on the device, so a step has no
+ * changing host arguments: clamp_batch_capture records one step in a HIP
+ * graph and clamp_batch_replay launches it repeatedly.
+ * ------------------------------------------------------------------------ */
+typedef struct clamp_batch clamp_batch;
+
+/* One scene of a batch (device pointers, caller-owned; the same arrays the
+ * single-scene calls take).  params.beta is ignored (see above). */
+typedef struct {
+    clamp_params params;    /* n_agents = L or L + 1, at most 40 in a batch   */
+    clamp_fwd_state state;  /* mu, resid, r (r: float32 [n_agents][n])        */
+    float* w;               /* float32 [n_agents][n]                          */
+    float* wbar;            /* float32 [n]                                    */
+    double* diag;           /* double [L][8], as clamp_fwd_agent              */
+    float prior_sigma;      /* Gaussian prior width when n_agents = L + 1     */
+} clamp_batch_scene;
+
+/* Workspace bytes of a batch over every scene of the plan (the scenes'
+ * single-call workspaces laid end to end). */
+clamp_status clamp_batch_workspace_size(const clamp_plan* plan, size_t* bytes);
+
+/* Creates a batch over all nscenes scenes of the plan.  scenes: HOST array
+ * [nscenes].  fault: device uint32; conv_err: device double [nscenes] (the
+ * convergence error of each scene's last step).  Allocates device queues and
+ * tables; the iteration counter starts at 0.  *out is released with
+ * clamp_batch_destroy. */
+clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene* scenes, uint32_t* fault,
+                                double* conv_err, void* workspace, clamp_batch** out);
+clamp_status clamp_batch_destroy(clamp_batch* batch);
+
+/* Sets the device iteration counter (iterations already done) on the stream. */
+clamp_status clamp_batch_set_iteration(clamp_batch* batch, int32_t done, void* hip_stream);
+
+/* One CLAMP iteration of every scene: forward agents, prior agents of the
+ * scenes that have one, Mann step, then the counter advances. */
+clamp_status clamp_batch_step(clamp_batch* batch, void* hip_stream);
+
+/* Persistent grid sizes in blocks per compute unit of the row and column
+ * passes (both > 0). */
+clamp_status clamp_batch_set_tiles(clamp_batch* batch, int32_t row_blocks_per_cu, int32_t col_blocks_per_cu);
+
+/* Times the passes that only write the workspace (inverse and forward column
+ * passes, gradient row pass) for a set of grid sizes on the current state,
+ * keeps the fastest, and reports them (HOST int32 [2], may be NULL).
+ * Synchronises the stream. */
+clamp_status clamp_batch_autotune(clamp_batch* batch, void* hip_stream, int32_t* chosen);
+
+/* Records one clamp_batch_step into a HIP graph (the stream must not be the
+ * NULL stream), replacing any earlier recording. */
+clamp_status clamp_batch_capture(clamp_batch* batch, void* hip_stream);
+
+/* Launches the recorded graph `iters` times on the stream. */
+clamp_status clamp_batch_replay(clamp_batch* batch, int32_t iters, void* hip_stream);
+
 /* Optional per-stage timing (for benchmarks).  While enabled, every call
  * that takes a stream records a pair of HIP events on that stream around
  * each of its stages; clamp_plan_get_timing waits for the recorded events,

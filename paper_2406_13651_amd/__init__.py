@@ -9,4 +9,4 @@ from ._clamp import (  # noqa: F401
     clamp_plan_create, clamp_plan_pupil_index, clamp_plan_pupil_info, clamp_plan_workspace_size,
     clamp_prior_gauss, make_params, CLAMP_FWD, CLAMP_ADJ, CLAMP_NORMAL,
 )
-from .clamp import ClampGPU, agent_weights, beta_schedule  # noqa: F401
+from .clamp import ClampBatchGPU, ClampGPU, agent_weights, beta_schedule  # noqa: F401

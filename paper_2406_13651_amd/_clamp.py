@@ -59,6 +59,11 @@ class clamp_fwd_state(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_void_p), ("resid", ctypes.c_void_p), ("r", ctypes.c_void_p)]
 
 
+class clamp_batch_scene(ctypes.Structure):
+    _fields_ = [("params", clamp_params), ("state", clamp_fwd_state), ("w", ctypes.c_void_p),
+                ("wbar", ctypes.c_void_p), ("diag", ctypes.c_void_p), ("prior_sigma", ctypes.c_float)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libclamp.so is not built (run paper_2406_13651_amd/build.py or "
@@ -81,6 +86,15 @@ def _load():
         "clamp_prior_gauss": [P, i32, ctypes.c_float, P, P, P, P],
         "clamp_mace_step": [P, i32, ctypes.POINTER(clamp_params), P, P, P, P, P, P],
         "clamp_plan_set_timing": [P, i32],
+        "clamp_batch_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
+        "clamp_batch_create": [P, ctypes.POINTER(clamp_batch_scene), P, P, P, ctypes.POINTER(P)],
+        "clamp_batch_destroy": [P],
+        "clamp_batch_set_iteration": [P, i32, P],
+        "clamp_batch_step": [P, P],
+        "clamp_batch_set_tiles": [P, i32, i32],
+        "clamp_batch_autotune": [P, P, ctypes.POINTER(i32)],
+        "clamp_batch_capture": [P, P],
+        "clamp_batch_replay": [P, i32, P],
         "clamp_plan_get_timing": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
@@ -274,3 +288,73 @@ def clamp_plan_get_timing(plan):
 
 def clamp_stage_name(stage):
     return lib.clamp_stage_name(int(stage)).decode()
+
+
+# -- batches ---------------------------------------------------------------
+
+def clamp_batch_workspace_size(plan):
+    b = ctypes.c_size_t()
+    _check(lib.clamp_batch_workspace_size(plan.handle, ctypes.byref(b)))
+    return b.value
+
+
+class Batch:
+    """Owns a clamp_batch*; released with clamp_batch_destroy."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.clamp_batch_destroy(h)
+            self.handle = None
+
+
+def clamp_batch_create(plan, scenes, fault, conv_err, workspace):
+    """scenes: list of dicts with params (clamp_params), mu, resid, r, w, wbar,
+    diag (tensors) and prior_sigma."""
+    arr = (clamp_batch_scene * len(scenes))()
+    for i, sc in enumerate(scenes):
+        s = plan.scenes[i]
+        na = sc["params"].n_agents
+        st = _state(plan, i, sc["mu"], sc["resid"], sc["r"], na)
+        arr[i].params = sc["params"]
+        arr[i].state = st
+        arr[i].w = _ptr(sc["w"], torch.float32, na * s.n, "w").value
+        arr[i].wbar = _ptr(sc["wbar"], torch.float32, s.n, "wbar").value
+        arr[i].diag = _ptr(sc["diag"], torch.float64, s.looks * DIAG, "diag").value
+        arr[i].prior_sigma = float(sc.get("prior_sigma", 1.0))
+    h = ctypes.c_void_p()
+    _check(lib.clamp_batch_create(plan.handle, arr, _ptr(fault, torch.int32, 1, "fault"),
+                                  _ptr(conv_err, torch.float64, len(scenes), "conv_err"),
+                                  _ptr(workspace, torch.uint8, clamp_batch_workspace_size(plan), "workspace"),
+                                  ctypes.byref(h)))
+    return Batch(h, [sc["params"] for sc in scenes])
+
+
+def clamp_batch_set_iteration(batch, done, stream=None):
+    _check(lib.clamp_batch_set_iteration(batch.handle, int(done), _stream(stream)))
+
+
+def clamp_batch_step(batch, stream=None):
+    _check(lib.clamp_batch_step(batch.handle, _stream(stream)))
+
+
+def clamp_batch_set_tiles(batch, row_blocks_per_cu, col_blocks_per_cu):
+    _check(lib.clamp_batch_set_tiles(batch.handle, int(row_blocks_per_cu), int(col_blocks_per_cu)))
+
+
+def clamp_batch_autotune(batch, stream=None):
+    out = (ctypes.c_int32 * 2)()
+    _check(lib.clamp_batch_autotune(batch.handle, _stream(stream), out))
+    return {"row_blocks_per_cu": out[0], "col_blocks_per_cu": out[1]}
+
+
+def clamp_batch_capture(batch, stream):
+    _check(lib.clamp_batch_capture(batch.handle, _stream(stream)))
+
+
+def clamp_batch_replay(batch, iters, stream):
+    _check(lib.clamp_batch_replay(batch.handle, int(iters), _stream(stream)))

@@ -110,3 +110,73 @@ class ClampGPU:
 
     def conv_err(self):
         return float(self.conv.item())
+
+
+class ClampBatchGPU:
+    """Many CLAMP reconstructions of uneven size advanced together: each
+    iteration is one batched step (persistent launches over work queues of
+    every scene), optionally replayed from a captured HIP graph."""
+
+    def __init__(self, scenes, device="cuda"):
+        """scenes: list of dicts with nx, ny, nz, looks, radius, sigma_w2,
+        sigma2 and optional with_prior (default True), rho, mu_scale,
+        prior_sigma."""
+        self.dev = torch.device(device)
+        self.specs = [dict(sc) for sc in scenes]
+        self.plan = C.clamp_plan_create([C.Scene(sc["nx"], sc["ny"], sc["nz"], sc["looks"], sc["radius"])
+                                         for sc in scenes])
+        self.ws = torch.empty(max(C.clamp_batch_workspace_size(self.plan), 256), dtype=torch.uint8,
+                              device=self.dev)
+        self.fault = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.conv = torch.zeros(len(scenes), dtype=torch.float64, device=self.dev)
+        self.states = []
+        f = dict(device=self.dev)
+        for i, sc in enumerate(self.specs):
+            L = sc["looks"]
+            wp = sc.get("with_prior", True)
+            N = L + 1 if wp else L
+            shape = (sc["nz"], sc["ny"], sc["nx"])
+            P = self.plan.info[i]["P"]
+            st = {
+                "with_prior": wp,
+                "ups": agent_weights(L, wp),
+                "mu": torch.zeros((L,) + shape, dtype=torch.complex64, **f),
+                "resid": torch.zeros(L, sc["nz"], P, dtype=torch.complex64, **f),
+                "r": torch.zeros((N,) + shape, dtype=torch.float32, **f),
+                "w": torch.zeros((N,) + shape, dtype=torch.float32, **f),
+                "wbar": torch.zeros(shape, dtype=torch.float32, **f),
+                "diag": torch.zeros(L, C.DIAG, dtype=torch.float64, **f),
+                "ahy2": torch.zeros(L, dtype=torch.float64, **f),
+                "prior_sigma": float(sc.get("prior_sigma", 1.0)),
+            }
+            st["params"] = C.make_params(sc["sigma_w2"], sc["sigma2"], sc.get("rho", 0.5), 2.0,
+                                         sc.get("mu_scale", 1.0), st["ups"])
+            self.states.append(st)
+        self.batch = C.clamp_batch_create(self.plan, self.states, self.fault, self.conv, self.ws)
+        self.k = 0
+
+    def init(self, ys):
+        """Alg. 2 initialisation of every scene from its looks (complex64 GPU tensors)."""
+        for i, (st, y) in enumerate(zip(self.states, ys)):
+            C.clamp_fwd_init(self.plan, i, st["params"], y, st["mu"], st["resid"], st["r"], st["w"], st["ahy2"],
+                             self.ws)
+        C.clamp_batch_set_iteration(self.batch, 0)
+        self.fault.zero_()
+        self.k = 0
+
+    def step(self, stream=None):
+        C.clamp_batch_step(self.batch, stream)
+        self.k += 1
+
+    def capture(self, stream):
+        C.clamp_batch_capture(self.batch, stream)
+
+    def replay(self, iters, stream):
+        C.clamp_batch_replay(self.batch, iters, stream)
+        self.k += iters
+
+    def autotune(self, stream=None):
+        return C.clamp_batch_autotune(self.batch, stream)
+
+    def voxel_looks(self):
+        return sum(sc["looks"] * sc["nx"] * sc["ny"] * sc["nz"] for sc in self.specs)

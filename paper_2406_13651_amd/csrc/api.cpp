@@ -653,3 +653,396 @@ const char* clamp_stage_name(int32_t stage) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches
+namespace {
+
+constexpr int kBetaLen = 1 << 16;
+const int kLengths[clampk::kSizeClasses] = {512, 384, 256, 192, 128, 64, 32};
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+}  // namespace
+
+struct clamp_batch {
+    const clamp_plan* plan = nullptr;
+    clampk::BatchLaunch launch{};
+    std::vector<void*> dev;
+    int cus = 256;
+    int row_per_cu = 8, col_per_cu = 4;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void batch_free(clamp_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void* p : b->dev) (void)hipFree(p);
+    b->dev.clear();
+}
+
+template <typename T>
+clamp_status batch_upload(clamp_batch* b, const std::vector<T>& h, T** out) {
+    void* p = nullptr;
+    const size_t bytes = (h.empty() ? 1 : h.size()) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? CLAMP_ENOMEM : CLAMP_EDEVICE, "hipMalloc: %s",
+                                     hipGetErrorString(e));
+    b->dev.push_back(p);
+    if (!h.empty() && (e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(CLAMP_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    *out = static_cast<T*>(p);
+    return CLAMP_OK;
+}
+
+void batch_grids(clamp_batch* b) {
+    clampk::BatchLaunch& L = b->launch;
+    auto cap = [&](int count, int per_cu) { return count < b->cus * per_cu ? count : b->cus * per_cu; };
+    for (int g = 0; g < L.nseg[0]; ++g) L.seg_grid[0][g] = cap(L.seg_count[0][g], b->row_per_cu);
+    for (int g = 0; g < L.nseg[1]; ++g) L.seg_grid[1][g] = cap(L.seg_count[1][g], b->col_per_cu);
+    L.grid[clampk::Q_LOOK] = L.count[clampk::Q_LOOK];
+    L.grid[clampk::Q_SCENE] = L.count[clampk::Q_SCENE];
+    for (int q : {clampk::Q_RESID, clampk::Q_VOX, clampk::Q_PRIOR_X, clampk::Q_PRIOR_Y, clampk::Q_PRIOR_Z})
+        L.grid[q] = cap(L.count[q], 8);
+}
+
+hipError_t batch_run(clamp_batch* b, hipStream_t st) {
+    using namespace clampk;
+    const clamp_plan* p = b->plan;
+    const int stages[] = {BS_COL_INV, BS_ROW_GRAD, BS_COL_FWD, BS_GAMMA, BS_ROW_UPDATE, BS_RESID, BS_DIAG,
+                          BS_PRIOR};
+    const int timing_stage[] = {ST_COL_INV, ST_ROW_GRAD, ST_COL_FWD, ST_GAMMA, ST_ROW_UPDATE, ST_RESID, ST_DIAG,
+                                ST_PRIOR};
+    for (int i = 0; i < (int)(sizeof stages / sizeof stages[0]); ++i) {
+        const hipError_t e = timed(p, timing_stage[i], st, [&] { return batch_stage(stages[i], b->launch, st); });
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = timed(p, ST_MACE, st, [&] {
+        hipError_t x = batch_stage(BS_MACE, b->launch, st);
+        if (x == hipSuccess) x = batch_stage(BS_MACE_FINAL, b->launch, st);
+        return x;
+    });
+    if (e == hipSuccess) e = batch_stage(BS_NEXT_ITER, b->launch, st);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+clamp_status clamp_batch_workspace_size(const clamp_plan* plan, size_t* bytes) {
+    if (plan == nullptr || bytes == nullptr) return fail(CLAMP_EINVAL, "NULL argument");
+    size_t total = 0;
+    for (const Scene& s : plan->scenes) total += align256(s.ws.total);
+    *bytes = total;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene* scenes, uint32_t* fault,
+                                double* conv_err, void* workspace, clamp_batch** out) {
+    using namespace clampk;
+    if (out == nullptr) return fail(CLAMP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (plan == nullptr || scenes == nullptr || fault == nullptr || conv_err == nullptr)
+        return fail(CLAMP_EINVAL, "NULL argument");
+    clamp_status st = check_ws(workspace);
+    if (st != CLAMP_OK) return st;
+    const int ns = (int)plan->scenes.size();
+    std::vector<SceneBatch> hb(ns);
+    std::vector<BatchItem> q[Q_COUNT];
+    // row and column items grouped by FFT length, longest first
+    std::vector<BatchItem> rows_by_len[kSizeClasses], cols_by_len[kSizeClasses];
+    size_t ws_off = 0;
+    for (int i = 0; i < ns; ++i) {
+        const Scene& s = plan->scenes[i];
+        const clamp_batch_scene& bs = scenes[i];
+        if ((st = check_params(s, &bs.params, true)) != CLAMP_OK) return fail(st, "scene %d: %s", i, g_err.c_str());
+        if (bs.params.n_agents > 40) return fail(CLAMP_EUNSUPPORTED, "scene %d: a batch holds at most 40 agents", i);
+        if (bs.state.mu == nullptr || bs.state.resid == nullptr || bs.state.r == nullptr || bs.w == nullptr ||
+            bs.wbar == nullptr || bs.diag == nullptr)
+            return fail(CLAMP_EINVAL, "scene %d: NULL array", i);
+        const bool with_prior = bs.params.n_agents == s.sc.looks + 1;
+        if (with_prior && !finite_pos(bs.prior_sigma))
+            return fail(CLAMP_EINVAL, "scene %d: prior_sigma must be > 0", i);
+        void* w0 = static_cast<char*>(workspace) + ws_off;
+        ws_off += align256(s.ws.total);
+        const int L = s.sc.looks;
+        const size_t n = s.n();
+        SceneBatch& sb = hb[i];
+        const double s2w = bs.params.sigma_w2;
+        RowArgs ra = row_args(s, L);
+        ra.mu = static_cast<float2*>(bs.state.mu);
+        ra.r = bs.state.r;
+        ra.w = bs.w;
+        ra.diag = bs.diag;
+        ra.fault = fault;
+        ra.inv_s2w = (float)(1.0 / s2w);
+        ra.s2w = (float)s2w;
+        ra.floor_w = (float)(s2w / s.alpha);
+        ra.alpha = (float)s.alpha;
+        ra.sigma2 = bs.params.sigma2;
+        ra.inv_sigma2 = (float)(1.0 / (double)bs.params.sigma2);
+        sb.grad = ra;
+        sb.grad.band_in = at<float2>(w0, s.ws.T);
+        sb.grad.band_out = at<float2>(w0, s.ws.T2);
+        sb.grad.part = at<double>(w0, s.ws.prow);
+        sb.update = ra;
+        sb.update.band_in = at<float2>(w0, s.ws.T);
+        sb.update.part = at<double>(w0, s.ws.pupd);
+        sb.cinv = col_args(s, L);
+        sb.cinv.cmp_in = static_cast<const float2*>(bs.state.resid);
+        sb.cinv.band_out = at<float2>(w0, s.ws.T);
+        sb.cinv.part = at<double>(w0, s.ws.pci);
+        sb.cfwd = col_args(s, L);
+        sb.cfwd.band_in = at<float2>(w0, s.ws.T2);
+        sb.cfwd.cmp_out = at<float2>(w0, s.ws.dfd);
+        sb.cfwd.part = at<double>(w0, s.ws.pcf);
+        sb.gam = GammaArgs{row_blocks(s.tab), col_blocks(s.tab), at<double>(w0, s.ws.prow), at<double>(w0, s.ws.pcf),
+                           at<double>(w0, s.ws.pci), 1.0 / s2w, bs.diag, fault};
+        sb.res = ResidArgs{(size_t)s.sc.nz * s.P, resid_blocks(s.tab), static_cast<float2*>(bs.state.resid),
+                           at<float2>(w0, s.ws.dfd), bs.diag, at<double>(w0, s.ws.pres)};
+        sb.dia = DiagArgs{row_blocks(s.tab), resid_blocks(s.tab), at<double>(w0, s.ws.pupd), at<double>(w0, s.ws.pres),
+                          bs.diag};
+        MaceArgs m{};
+        m.n = n;
+        m.n_agents = bs.params.n_agents;
+        for (int j = 0; j < m.n_agents; ++j) m.ups[j] = bs.params.upsilon[j];
+        m.two_rho = 2.f * bs.params.rho;
+        m.w = bs.w;
+        m.r = bs.state.r;
+        m.wbar = bs.wbar;
+        m.part = at<double>(w0, s.ws.pmace);
+        sb.mace = m;
+        sb.mace_chunks = mace_blocks(n);
+        sb.with_prior = with_prior ? 1 : 0;
+        sb.conv = conv_err + i;
+        PriorArgs pr{};
+        pr.nx = s.sc.nx;
+        pr.ny = s.sc.ny;
+        pr.nz = s.sc.nz;
+        if (with_prior) {
+            double g[7], sum = 0.0;
+            for (int k = 0; k < 7; ++k) {
+                const double x = (k - 3) / (double)bs.prior_sigma;
+                g[k] = std::exp(-0.5 * x * x);
+                sum += g[k];
+            }
+            for (int k = 0; k < 7; ++k) pr.g[k] = (float)(g[k] / sum);
+            pr.in = bs.w + (size_t)L * n;
+            pr.out = bs.state.r + (size_t)L * n;
+            pr.tmp0 = at<float>(w0, s.ws.g0);
+            pr.tmp1 = at<float>(w0, s.ws.g1);
+        }
+        sb.prior = pr;
+        // work items
+        int li = 0, ci = 0;
+        for (int k = 0; k < kSizeClasses; ++k) {
+            if (kLengths[k] == s.sc.nx) li = k;
+            if (kLengths[k] == s.sc.ny) ci = k;
+        }
+        for (int l = 0; l < L; ++l)
+            for (int g = 0; g < row_blocks(s.tab); ++g) rows_by_len[li].push_back(BatchItem{i, l, g, 0});
+        for (int it = 0; it < L * s.sc.nz * s.tiles; ++it) cols_by_len[ci].push_back(BatchItem{i, it, 0, 0});
+        for (int l = 0; l < L; ++l) {
+            q[Q_LOOK].push_back(BatchItem{i, l, 0, 0});
+            for (int c = 0; c < resid_blocks(s.tab); ++c) q[Q_RESID].push_back(BatchItem{i, l, c, 0});
+        }
+        for (int c = 0; c < sb.mace_chunks; ++c) q[Q_VOX].push_back(BatchItem{i, 0, c, 0});
+        q[Q_SCENE].push_back(BatchItem{i, 0, 0, 0});
+        if (with_prior) {
+            const size_t ux = (n + kPriorChunk - 1) / kPriorChunk;
+            const size_t uy = ((size_t)prior_strided_units(s.sc.ny, (size_t)s.sc.nz * s.sc.nx) + kPriorChunk - 1) / kPriorChunk;
+            const size_t uz = ((size_t)prior_strided_units(s.sc.nz, (size_t)s.sc.nx * s.sc.ny) + kPriorChunk - 1) / kPriorChunk;
+            for (size_t c = 0; c < ux; ++c) q[Q_PRIOR_X].push_back(BatchItem{i, 0, (int)c, 0});
+            for (size_t c = 0; c < uy; ++c) q[Q_PRIOR_Y].push_back(BatchItem{i, 0, (int)c, 0});
+            for (size_t c = 0; c < uz; ++c) q[Q_PRIOR_Z].push_back(BatchItem{i, 0, (int)c, 0});
+        }
+    }
+    clamp_batch* b = new (std::nothrow) clamp_batch();
+    if (b == nullptr) return fail(CLAMP_ENOMEM, "host allocation failed");
+    b->plan = plan;
+    b->cus = device_cus();
+    BatchLaunch& L = b->launch;
+    for (int side = 0; side < 2; ++side) {
+        std::vector<BatchItem>* by = side == 0 ? rows_by_len : cols_by_len;
+        std::vector<BatchItem>& dst = q[side == 0 ? Q_ROW : Q_COL];
+        L.nseg[side] = 0;
+        for (int k = 0; k < kSizeClasses; ++k) {
+            if (by[k].empty()) continue;
+            const int g = L.nseg[side]++;
+            L.seg_len[side][g] = kLengths[k];
+            L.seg_off[side][g] = (int)dst.size();
+            L.seg_count[side][g] = (int)by[k].size();
+            dst.insert(dst.end(), by[k].begin(), by[k].end());
+        }
+    }
+    SceneBatch* d_scenes = nullptr;
+    if ((st = batch_upload(b, hb, &d_scenes)) != CLAMP_OK) {
+        batch_free(b);
+        delete b;
+        return st;
+    }
+    L.scenes = d_scenes;
+    for (int k = 0; k < Q_COUNT; ++k) {
+        BatchItem* d = nullptr;
+        if ((st = batch_upload(b, q[k], &d)) != CLAMP_OK) {
+            batch_free(b);
+            delete b;
+            return st;
+        }
+        L.queue[k] = d;
+        L.count[k] = (int)q[k].size();
+    }
+    std::vector<float> beta(kBetaLen);
+    for (int k = 0; k < kBetaLen; ++k) beta[k] = (float)(1.0 + 2.0 / std::log((double)k + 2.0));
+    float* d_beta = nullptr;
+    std::vector<int> zero(1, 0);
+    int* d_iter = nullptr;
+    if ((st = batch_upload(b, beta, &d_beta)) != CLAMP_OK || (st = batch_upload(b, zero, &d_iter)) != CLAMP_OK) {
+        batch_free(b);
+        delete b;
+        return st;
+    }
+    L.beta_table = d_beta;
+    L.beta_len = kBetaLen;
+    L.iter = d_iter;
+    L.fault = fault;
+    batch_grids(b);
+    *out = b;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_batch_destroy(clamp_batch* batch) {
+    if (batch == nullptr) return CLAMP_OK;
+    batch_free(batch);
+    delete batch;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_batch_set_iteration(clamp_batch* batch, int32_t done, void* hip_stream) {
+    if (batch == nullptr || done < 0) return fail(CLAMP_EINVAL, "bad argument");
+    return hip_check(clampk::batch_set_iter(batch->launch.iter, done, static_cast<hipStream_t>(hip_stream)),
+                     "clamp_batch_set_iteration");
+}
+
+clamp_status clamp_batch_step(clamp_batch* batch, void* hip_stream) {
+    if (batch == nullptr) return fail(CLAMP_EINVAL, "batch is NULL");
+    return hip_check(batch_run(batch, static_cast<hipStream_t>(hip_stream)), "clamp_batch_step launch");
+}
+
+clamp_status clamp_batch_set_tiles(clamp_batch* batch, int32_t row_blocks_per_cu, int32_t col_blocks_per_cu) {
+    if (batch == nullptr || row_blocks_per_cu <= 0 || col_blocks_per_cu <= 0) return fail(CLAMP_EINVAL, "bad argument");
+    batch->row_per_cu = row_blocks_per_cu;
+    batch->col_per_cu = col_blocks_per_cu;
+    batch_grids(batch);
+    return CLAMP_OK;
+}
+
+clamp_status clamp_batch_autotune(clamp_batch* batch, void* hip_stream, int32_t* chosen) {
+    using namespace clampk;
+    if (batch == nullptr) return fail(CLAMP_EINVAL, "batch is NULL");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(CLAMP_EDEVICE, "hipEventCreate failed");
+    }
+    hipError_t err = hipSuccess;
+    auto keep = [&](hipError_t x) {
+        if (err == hipSuccess) err = x;
+    };
+    auto time_stages = [&](std::initializer_list<int> stages) -> float {
+        float best = 1e30f;
+        for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+            keep(hipEventRecord(e0, st));
+            for (int sg : stages) keep(batch_stage(sg, batch->launch, st));
+            keep(hipEventRecord(e1, st));
+            keep(hipEventSynchronize(e1));
+            float ms = 0.f;
+            keep(hipEventElapsedTime(&ms, e0, e1));
+            if (err == hipSuccess && ms < best) best = ms;
+        }
+        return best;
+    };
+    const int cands[] = {1, 2, 4, 8, 16};
+    int best_col = batch->col_per_cu, best_row = batch->row_per_cu;
+    float tbest = 1e30f;
+    for (int c : cands) {
+        batch->col_per_cu = c;
+        batch_grids(batch);
+        const float t = time_stages({BS_COL_INV, BS_COL_FWD});
+        if (t < tbest) { tbest = t; best_col = c; }
+    }
+    batch->col_per_cu = best_col;
+    tbest = 1e30f;
+    for (int c : cands) {
+        batch->row_per_cu = c;
+        batch_grids(batch);
+        const float t = time_stages({BS_ROW_GRAD});
+        if (t < tbest) { tbest = t; best_row = c; }
+    }
+    batch->row_per_cu = best_row;
+    batch_grids(batch);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_check(err, "clamp_batch_autotune");
+    if (chosen) {
+        chosen[0] = best_row;
+        chosen[1] = best_col;
+    }
+    return CLAMP_OK;
+}
+
+clamp_status clamp_batch_capture(clamp_batch* batch, void* hip_stream) {
+    if (batch == nullptr) return fail(CLAMP_EINVAL, "batch is NULL");
+    if (hip_stream == nullptr) return fail(CLAMP_EINVAL, "capture needs a non-NULL stream");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    clamp_plan* p = const_cast<clamp_plan*>(batch->plan);
+    const bool timing = p->timing;
+    p->timing = false;  // no event records inside the graph
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    hipGraph_t g = nullptr;
+    if (e == hipSuccess) {
+        const hipError_t run = batch_run(batch, st);
+        e = hipStreamEndCapture(st, &g);
+        if (e == hipSuccess) e = run;
+    }
+    p->timing = timing;
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_check(e, "clamp_batch_capture");
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_check(e, "hipGraphInstantiate");
+    }
+    if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+    if (batch->graph) (void)hipGraphDestroy(batch->graph);
+    batch->graph = g;
+    batch->exec = x;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_batch_replay(clamp_batch* batch, int32_t iters, void* hip_stream) {
+    if (batch == nullptr || iters < 0) return fail(CLAMP_EINVAL, "bad argument");
+    if (batch->exec == nullptr) return fail(CLAMP_EINVAL, "nothing captured");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    for (int i = 0; i < iters; ++i) {
+        const hipError_t e = hipGraphLaunch(batch->exec, st);
+        if (e != hipSuccess) return hip_check(e, "hipGraphLaunch");
+    }
+    return CLAMP_OK;
+}
+
+}  // extern "C"

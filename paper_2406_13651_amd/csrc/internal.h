@@ -31,16 +31,21 @@ struct SceneTables {
     const int* pidx;        // [ny * nx] compact index of a sample, -1 off-pupil
 };
 
-// Rows per row-pass block for a row length (threads per row = pow2 >= n/8).
-int row_threads(int n);
-int rows_per_block(int n);
+// Threads per row of a row-pass block (the power of two >= n/8) and rows per
+// block.
+__host__ __device__ constexpr int row_threads(int n) {
+    int t = 4;
+    while (t * 8 < n) t *= 2;
+    return t;
+}
+__host__ __device__ constexpr int rows_per_block(int n) { return kBlock / row_threads(n); }
 
 // Number of partial-sum blocks per look of each pass.
-inline int row_blocks(const SceneTables& s) {
+__host__ __device__ inline int row_blocks(const SceneTables& s) {
     const int rpb = rows_per_block(s.nx);
     return (s.nz * s.ny + rpb - 1) / rpb;
 }
-inline int col_blocks(const SceneTables& s) { return s.nz * s.tiles; }
+__host__ __device__ inline int col_blocks(const SceneTables& s) { return s.nz * s.tiles; }
 int resid_blocks(const SceneTables& s);
 int mace_blocks(size_t n);
 
@@ -120,5 +125,98 @@ hipError_t launch_mace_final(const double* part, int blocks, double* conv_err, h
 
 hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float* in,
                         float* tmp0, float* tmp1, float* out, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Batched passes over many scenes.  Each stage is one persistent launch that
+// walks a device queue of work items of every scene.
+
+struct BatchItem {
+    int scene;
+    int a;  // look, or column-pass item (look * nz + z) * tiles + tile
+    int b;  // row group, or chunk
+    int pad;
+};
+
+struct GammaArgs {
+    int nrow, ncol;
+    const double* prow;
+    const double* pcf;
+    const double* pci;
+    double inv_s2w;
+    double* diag;
+    uint32_t* fault;
+};
+
+struct ResidArgs {
+    size_t per_look;
+    int chunks;
+    float2* resid;
+    const float2* dfd;
+    const double* diag;
+    double* part;
+};
+
+struct DiagArgs {
+    int nrow, nres;
+    const double* pupd;
+    const double* pres;
+    double* diag;
+};
+
+struct PriorArgs {
+    int nx, ny, nz;
+    float g[7];
+    const float* in;
+    float* tmp0;
+    float* tmp1;
+    float* out;
+};
+
+// Everything the batched stages need to know about one scene.
+struct SceneBatch {
+    RowArgs grad, update;
+    ColArgs cinv, cfwd;
+    GammaArgs gam;
+    ResidArgs res;
+    DiagArgs dia;
+    MaceArgs mace;
+    PriorArgs prior;
+    int mace_chunks;
+    int with_prior;
+    double* conv;
+};
+
+enum BatchQueue { Q_COL = 0, Q_ROW, Q_LOOK, Q_RESID, Q_VOX, Q_PRIOR_X, Q_PRIOR_Y, Q_PRIOR_Z, Q_SCENE, Q_COUNT };
+
+constexpr int kSizeClasses = 7;  // supported FFT lengths
+
+struct BatchLaunch {
+    const SceneBatch* scenes;   // device [nscenes]
+    const BatchItem* queue[Q_COUNT];
+    int count[Q_COUNT];
+    int grid[Q_COUNT];          // persistent grid size of each stage
+    // The row and column queues are ordered by FFT length (nx for rows, ny
+    // for columns); each length class is a segment with its own launch.
+    int seg_len[2][kSizeClasses];
+    int seg_off[2][kSizeClasses];
+    int seg_count[2][kSizeClasses];
+    int seg_grid[2][kSizeClasses];
+    int nseg[2];
+    const float* beta_table;    // device [beta_len]
+    int beta_len;
+    int* iter;                  // device iteration counter (iterations done)
+    uint32_t* fault;
+};
+
+// Items of the batched prior passes: chunk sizes in work units.
+constexpr int kPriorChunk = 4 * kBlock;
+int prior_strided_units(int len, size_t outer);
+
+hipError_t batch_stage(int stage, const BatchLaunch& b, hipStream_t st);
+hipError_t batch_set_iter(int* iter, int value, hipStream_t st);
+enum BatchStage {
+    BS_COL_INV = 0, BS_ROW_GRAD, BS_COL_FWD, BS_GAMMA, BS_ROW_UPDATE, BS_RESID, BS_DIAG,
+    BS_PRIOR, BS_MACE, BS_MACE_FINAL, BS_NEXT_ITER
+};
 
 }  // namespace clampk

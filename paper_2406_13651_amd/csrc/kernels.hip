@@ -16,18 +16,9 @@
 // d (16 bytes per voxel-look); T is only half a slice wide at R = N/4.
 #include <math.h>
 
-#include "fft.hpp"
-#include "internal.h"
+#include "passes.hpp"
 
 namespace clampk {
-
-__host__ __device__ constexpr int row_threads_c(int n) {
-    int t = 4;
-    while (t * 8 < n) t *= 2;
-    return t;
-}
-int row_threads(int n) { return row_threads_c(n); }
-int rows_per_block(int n) { return kBlock / row_threads_c(n); }
 
 static int grid_cap(size_t work, int cap) {
     size_t b = (work + kBlock - 1) / kBlock;
@@ -37,86 +28,17 @@ static int grid_cap(size_t work, int cap) {
 int resid_blocks(const SceneTables& s) { return grid_cap((size_t)s.nz * s.P, 512); }
 int mace_blocks(size_t n) { return grid_cap(n / 2, 2048); }
 
-// Sum of K doubles over the block, written by thread 0 to out[0..K).
-template <int K>
-__device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
-    __shared__ double red[K][kBlock / 64];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double x = v[k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-        v[k] = x;
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) red[k][wid] = v[k];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-#pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
-            out[k] = s;
-        }
-    }
-}
-
-__device__ __forceinline__ void wave_or_fault(uint32_t bits, uint32_t* fault) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
-    if ((threadIdx.x & 63) == 0 && bits != 0u && fault != nullptr) atomicOr(fault, bits);
-}
-
 // ---------------------------------------------------------------------------
 // Column passes.  A work item is a tile of TC band columns of one slice of one
 // look.  The compact pupil layout is column-major (band column by band
 // column, rows increasing), so a tile's pupil samples are TC contiguous runs.
 //
-// Inverse pass from the compact layout: one item per block; the tile is
-// zeroed, the runs are scattered into it, and the columns are transformed.
+// Inverse pass from the compact layout: one item per block.
 template <int NY>
 __global__ __launch_bounds__(kBlock) void k_col_inv_compact(ColArgs a) {
-    constexpr int TC = col_tile_cols(NY);
-    constexpr int TPC = kBlock / TC;
     __shared__ float2 tw[NY];
-    __shared__ float2 tile[NY * TC];
-    const SceneTables& s = a.s;
-    const int tid = threadIdx.x;
-    const int tile_i = blockIdx.x % s.tiles;
-    const int zl = blockIdx.x / s.tiles;  // look * nz + z
-    const int c0 = tile_i * TC;
-    for (int i = tid; i < NY; i += kBlock) tw[i] = s.tw_y[i];
-    for (int i = tid; i < NY * TC; i += kBlock) tile[i] = make_float2(0.f, 0.f);
-    __syncthreads();
-    double acc[1] = {0.0};
-    {
-        const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
-        if (bc < s.B) {
-            const float2* src = a.cmp_in + (size_t)zl * s.P;
-            const int p1 = s.col_off[bc + 1];
-            float f = 0.f;
-            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
-                const float2 val = src[p];
-                tile[s.row_idx[p] * TC + c] = val;
-                f += cabs2(val);
-            }
-            acc[0] = f;
-        }
-    }
-    fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
-    {
-        const int c = tid % TC, bc = c0 + c;
-        if (bc < s.B) {
-            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bc;
-            for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + c], a.scale);
-        }
-    }
-    // block index = (look * nz + z) * tiles + tile = look * col_blocks + z * tiles + tile
-    if (a.part != nullptr) block_sum_store<1>(acc, a.part + blockIdx.x);
+    __shared__ float2 tile[NY * col_tile_cols(NY)];
+    col_inv_item<NY>(a, blockIdx.x, tw, tile, true);
 }
 
 // Dense-input column passes (forward from band rows; inverse from full
@@ -219,146 +141,17 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Row pass: RPB rows of length NX per block, TR threads per row.  The
-// per-voxel streams of the fused modes (mu, the anchor r', w) are loaded into
-// registers at the start, so their latency overlaps the band-row load and
-// the first FFT.
+// Row pass: RPB rows of length NX per block, TR threads per row; block
+// (x, y) = (row group, look).
 template <int NX, int MODE>
 __global__ __launch_bounds__(kBlock) void k_row(RowArgs a) {
-    constexpr int TR = row_threads_c(NX);
-    constexpr int RPB = kBlock / TR;
-    constexpr int PX = (NX + TR - 1) / TR;          // row samples per thread
-    constexpr int S1 = (MODE == ROW_FWD) ? -1 : +1;
-    constexpr int PAD = 4;                          // one float2 of padding per 16
-    constexpr int RS = lds_len<NX, PAD>();          // padded row length in LDS
-    constexpr bool FUSED = (MODE == ROW_GRAD || MODE == ROW_UPDATE);
-    // Stream prefetch pays off for the gradient pass; the update pass already
-    // runs near the read/write bandwidth ceiling and loads its streams late.
-    constexpr bool PREFETCH = (MODE == ROW_GRAD);
     __shared__ float2 tw[NX];
     __shared__ int bpos[NX];
     __shared__ int bcol[NX];
-    __shared__ float2 buf[RPB * RS];
-    const SceneTables& s = a.s;
-    const int tid = threadIdx.x;
-    const int ri = tid / TR, t = tid % TR;
-    const int look = blockIdx.y;
-    const int rows = s.nz * s.ny;
-    const int row = blockIdx.x * RPB + ri;
-    const bool active = row < rows;
-    const size_t img = ((size_t)look * rows + (active ? row : 0)) * NX;
-    const size_t band = ((size_t)look * rows + (active ? row : 0)) * s.Bs;
-
-    float2 m[FUSED ? PX : 1];
-    float rp[FUSED ? PX : 1];
-    float wv[MODE == ROW_UPDATE ? PX : 1];
-    auto load_streams = [&]() {
-        if (active) {
-#pragma unroll
-            for (int k = 0; k < PX; ++k) {
-                const int x = t + k * TR;
-                if (NX % TR == 0 || x < NX) {
-                    m[k] = a.mu[img + x];
-                    rp[k] = a.r[img + x];
-                    if constexpr (MODE == ROW_UPDATE) wv[k] = a.w[img + x];
-                }
-            }
-        }
-    };
-    if constexpr (PREFETCH) load_streams();
-    for (int i = tid; i < NX; i += kBlock) {
-        tw[i] = s.tw_x[i];
-        bpos[i] = s.band_pos[i];
-        bcol[i] = i < s.B ? s.band_cols[i] : 0;
-    }
-    __syncthreads();
-    float2* rb = buf + ri * RS;
-
-    if constexpr (MODE == ROW_FWD) {
-        if (active)
-            for (int x = t; x < NX; x += TR) rb[lds_pos<PAD>(x)] = a.img_in[img + x];
-    } else {
-        if (active)
-            for (int x = t; x < NX; x += TR) {
-                const int bp = bpos[x];
-                rb[lds_pos<PAD>(x)] = bp >= 0 ? a.band_in[band + bp] : make_float2(0.f, 0.f);
-            }
-    }
-    fft_lds<NX, TR, S1, PAD>(rb, 1, t, tw);
-
-    if constexpr (MODE == ROW_INV) {
-        if (active)
-            for (int x = t; x < NX; x += TR) a.img_out[img + x] = cscale(rb[lds_pos<PAD>(x)], a.scale);
-    } else if constexpr (MODE == ROW_FWD) {
-        if (active)
-            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(bcol[b])], a.scale);
-    } else if constexpr (MODE == ROW_GRAD) {
-        float dd = 0.f, wd = 0.f, wm = 0.f;
-        if (active) {
-#pragma unroll
-            for (int k = 0; k < PX; ++k) {
-                const int x = t + k * TR;
-                if (NX % TR == 0 || x < NX) {
-                    const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
-                    const float om = 1.f / (rp[k] + a.floor_w);
-                    const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
-                    rb[lds_pos<PAD>(x)] = d;
-                    const float d2 = cabs2(d);
-                    dd += d2;
-                    wd += om * d2;
-                    wm += om * cabs2(m[k]);
-                }
-            }
-        }
-        fft_lds<NX, TR, -1, PAD>(rb, 1, t, tw);
-        if (active)
-            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(bcol[b])], a.scale);
-        double acc[3] = {dd, wd, wm};
-        block_sum_store<3>(acc, a.part + ((size_t)look * gridDim.x + blockIdx.x) * 3);
-    } else {  // ROW_UPDATE
-        if constexpr (!PREFETCH) load_streams();
-        const float gamma = (float)a.diag[(size_t)look * kDiag];
-        float wm1 = 0.f;
-        uint32_t fb = 0u;
-        if (active) {
-#pragma unroll
-            for (int k = 0; k < PX; ++k) {
-                const int x = t + k * TR;
-                if (NX % TR == 0 || x < NX) {
-                    const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
-                    const float r0 = rp[k];
-                    const float v = wv[k];
-                    const float om = 1.f / (r0 + a.floor_w);
-                    const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
-                    const float2 m1 = make_float2(m[k].x + gamma * d.x, m[k].y + gamma * d.y);
-                    a.mu[img + x] = m1;
-                    // covariance diagonal with A^H A ~ alpha I, and s = c + |mu|^2
-                    const float c = a.s2w * r0 / (a.alpha * r0 + a.s2w);
-                    const float sv = c + cabs2(m1);
-                    // quadratic surrogate of r/r' + s/r, interpolating its
-                    // derivative at r' and xi; written with s/r' first so that
-                    // small anchors stay in float32 range
-                    const float inv = 1.f / r0;
-                    const float sr = sv * inv;
-                    const float dq = inv * (1.f - sr);                  // q'(r')
-                    const float D = dq + (r0 - v) * a.inv_sigma2;       // rho'(r')
-                    const bool down = D > 0.f;
-                    const float xi = down ? r0 * a.inv_beta : r0 * a.beta;
-                    const float qa = sr * inv * inv * (down ? a.k_dn : a.k_up);
-                    const float qb = dq - qa * r0;
-                    float rn = (v - a.sigma2 * qb) / (1.f + a.sigma2 * qa);
-                    if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
-                    rn = fminf(fmaxf(rn, fminf(r0, xi)), fmaxf(r0, xi));
-                    if (!(rn > 0.f)) fb |= 2u;
-                    a.r[img + x] = rn;
-                    wm1 += om * cabs2(m1);
-                }
-            }
-        }
-        wave_or_fault(fb, a.fault);
-        double acc[1] = {wm1};
-        block_sum_store<1>(acc, a.part + (size_t)look * gridDim.x + blockIdx.x);
-    }
+    __shared__ float2 buf[row_lds_floats2<NX>()];
+    const RowLds L{tw, bpos, bcol, buf};
+    const BetaVals bv{a.beta, a.inv_beta, a.k_up, a.k_dn};
+    row_item<NX, MODE>(a, blockIdx.y, blockIdx.x, (size_t)blockIdx.y * gridDim.x + blockIdx.x, L, true, bv);
 }
 
 // ---------------------------------------------------------------------------
@@ -375,66 +168,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter_full(SceneTables s, size_t t
 __global__ __launch_bounds__(kBlock) void k_gamma(int nrow, int ncol, const double* prow,
                                                   const double* pcf, const double* pci,
                                                   double inv_s2w, double* diag, uint32_t* fault) {
-    const int look = blockIdx.x;
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < nrow; i += kBlock) {
-        const double* p = prow + ((size_t)look * nrow + i) * 3;
-        v[0] += p[0];
-        v[1] += p[1];
-        v[2] += p[2];
-    }
-    for (int i = threadIdx.x; i < ncol; i += kBlock) {
-        v[3] += pcf[(size_t)look * ncol + i];
-        v[4] += pci[(size_t)look * ncol + i];
-    }
-    __shared__ double tot[5];
-    block_sum_store<5>(v, tot);
-    if (threadIdx.x == 0) {
-        const double dd = tot[0], wd = tot[1], wm = tot[2], ad = tot[3], r2 = tot[4];
-        const double den = ad * inv_s2w + wd;
-        const double g = dd > 0.0 ? dd / den : 0.0;
-        double* o = diag + (size_t)look * kDiag;
-        o[0] = g;
-        o[1] = dd;
-        o[2] = ad;
-        o[3] = wd;
-        o[4] = r2;
-        o[5] = wm;
-        if (!(g >= 0.0) || !isfinite(g)) atomicOr(fault, 4u | 1u);
-    }
+    gamma_item(blockIdx.x, nrow, ncol, prow, pcf, pci, inv_s2w, diag, fault);
 }
 
 __global__ __launch_bounds__(kBlock) void k_resid(size_t per_look, float2* resid, const float2* dfd,
                                                   const double* diag, double* part) {
     const int look = blockIdx.y;
     const float g = (float)diag[(size_t)look * kDiag];
-    float2* R = resid + per_look * look;
-    const float2* D = dfd + per_look * look;
-    float f = 0.f;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < per_look; i += (size_t)gridDim.x * kBlock) {
-        float2 x = R[i];
-        const float2 d = D[i];
-        x.x -= g * d.x;
-        x.y -= g * d.y;
-        R[i] = x;
-        f += cabs2(x);
-    }
+    const float f = resid_range(resid + per_look * look, dfd + per_look * look, g, (size_t)blockIdx.x * kBlock,
+                                per_look, (size_t)gridDim.x * kBlock);
     double acc[1] = {f};
     block_sum_store<1>(acc, part + (size_t)look * gridDim.x + blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_diag_after(int nrow, int nres, const double* pupd,
                                                        const double* pres, double* diag) {
-    const int look = blockIdx.x;
-    double v[2] = {0.0, 0.0};
-    for (int i = threadIdx.x; i < nrow; i += kBlock) v[0] += pupd[(size_t)look * nrow + i];
-    for (int i = threadIdx.x; i < nres; i += kBlock) v[1] += pres[(size_t)look * nres + i];
-    __shared__ double tot[2];
-    block_sum_store<2>(v, tot);
-    if (threadIdx.x == 0) {
-        diag[(size_t)look * kDiag + 6] = tot[1];
-        diag[(size_t)look * kDiag + 7] = tot[0];
-    }
+    diag_after_item(blockIdx.x, nrow, nres, pupd, pres, diag);
 }
 
 __global__ __launch_bounds__(kBlock) void k_init_r0(size_t n, int looks, float2* mu, float s_mu,
@@ -537,52 +286,19 @@ __global__ __launch_bounds__(kBlock) void k_mace_final(const double* part, int b
 }
 
 // ---------------------------------------------------------------------------
-struct Taps7 {
-    float g[7];
-};
-
 // Periodic 7-tap filter along x (contiguous).
 __global__ __launch_bounds__(kBlock) void k_gauss_x(int nx, size_t n, Taps7 t, const float* in, float* out) {
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-        const int x = (int)(i % nx);
-        const size_t row = i - x;
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) acc += t.g[k] * in[row + (size_t)((x + k - 3 + nx) % nx)];
-        out[i] = acc;
-    }
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        out[i] = gauss_x_voxel(nx, t.g, in, i);
 }
 
-// Periodic 7-tap filter along a strided axis of length len (stride `inner`
-// elements): each thread slides a register window down a chunk of CH
-// samples, so every input is read once per chunk plus a 6-sample halo.
+// Periodic 7-tap filter along a strided axis, CH samples per work unit.
 template <int CH>
 __global__ __launch_bounds__(kBlock) void k_gauss_strided(int len, size_t inner, size_t outer, Taps7 t,
                                                           const float* in, float* out) {
-    const int chunks = (len + CH - 1) / CH;
-    const size_t work = outer * (size_t)chunks;
-    for (size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x; idx < work; idx += (size_t)gridDim.x * kBlock) {
-        const size_t o = idx % outer;
-        const int c = (int)(idx / outer);
-        const size_t base = (o / inner) * inner * (size_t)len + (o % inner);
-        const int y0 = c * CH;
-        float win[CH + 6];
-#pragma unroll
-        for (int k = 0; k < CH + 6; ++k) {
-            int yy = (y0 + k - 3) % len;
-            if (yy < 0) yy += len;
-            win[k] = in[base + (size_t)yy * inner];
-        }
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            if (y0 + k < len) {
-                float acc = 0.f;
-#pragma unroll
-                for (int q = 0; q < 7; ++q) acc += t.g[q] * win[k + q];
-                out[base + (size_t)(y0 + k) * inner] = acc;
-            }
-        }
-    }
+    const size_t work = outer * (size_t)((len + CH - 1) / CH);
+    for (size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x; idx < work; idx += (size_t)gridDim.x * kBlock)
+        gauss_strided_unit<CH>(len, inner, outer, t.g, in, out, idx);
 }
 
 static void gauss_axis(int len, size_t inner, size_t outer, const Taps7& t, const float* in, float* out,

@@ -1,0 +1,467 @@
+// Work items of the forward-agent passes as device functions.  A work item
+// is one unit that a block processes: a group of rows of one slice of one
+// look (row passes), a tile of band columns of one slice of one look (column
+// passes), or one look (step size and diagnostics).  The single-scene
+// kernels map one block to one item; the batched kernels walk a queue of
+// items of many scenes, choosing the FFT length of each item at run time.
+// LDS buffers are passed in, so a batched kernel can share one allocation
+// between items of different lengths.
+#pragma once
+
+#include <math.h>
+
+#include "fft.hpp"
+#include "internal.h"
+
+namespace clampk {
+
+constexpr int kRowPad = 4;  // one float2 of LDS padding per 16 row samples
+
+template <int N>
+__host__ __device__ constexpr int row_lds_floats2() {
+    return rows_per_block(N) * lds_len<N, kRowPad>();
+}
+
+// Largest row-pass and column-pass LDS buffers over the supported lengths.
+__host__ __device__ constexpr int max_row_lds() {
+    int m = 0;
+    m = m > row_lds_floats2<32>() ? m : row_lds_floats2<32>();
+    m = m > row_lds_floats2<64>() ? m : row_lds_floats2<64>();
+    m = m > row_lds_floats2<128>() ? m : row_lds_floats2<128>();
+    m = m > row_lds_floats2<192>() ? m : row_lds_floats2<192>();
+    m = m > row_lds_floats2<256>() ? m : row_lds_floats2<256>();
+    m = m > row_lds_floats2<384>() ? m : row_lds_floats2<384>();
+    m = m > row_lds_floats2<512>() ? m : row_lds_floats2<512>();
+    return m;
+}
+__host__ __device__ constexpr int max_col_lds() {
+    int m = 0;
+    const int ns[7] = {32, 64, 128, 192, 256, 384, 512};
+    for (int i = 0; i < 7; ++i) {
+        const int v = ns[i] * col_tile_cols(ns[i]);
+        m = m > v ? m : v;
+    }
+    return m;
+}
+
+// Sum of K doubles over the block, written by thread 0 to out[0..K).
+template <int K>
+__device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
+    __shared__ double red[K][kBlock / 64];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        v[k] = x;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k][wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
+            out[k] = s;
+        }
+    }
+    __syncthreads();  // red may be reused by the next item
+}
+
+__device__ __forceinline__ void wave_or_fault(uint32_t bits, uint32_t* fault) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
+    if ((threadIdx.x & 63) == 0 && bits != 0u && fault != nullptr) atomicOr(fault, bits);
+}
+
+// Interval factor and the derived constants of the surrogate r-update.
+struct BetaVals {
+    float beta, inv_beta, k_up, k_dn;
+};
+__host__ __device__ inline BetaVals beta_vals(double beta) {
+    BetaVals b;
+    b.beta = (float)beta;
+    b.inv_beta = (float)(1.0 / beta);
+    b.k_up = (float)((1.0 + beta) / (beta * beta));  // xi = beta r'
+    b.k_dn = (float)(beta * (1.0 + beta));           // xi = r' / beta
+    return b;
+}
+
+// LDS buffers of a row item: twiddles, band position and band column tables
+// (length NX each) and the padded row buffers.
+struct RowLds {
+    float2* tw;
+    int* bpos;
+    int* bcol;
+    float2* buf;
+};
+
+// ---------------------------------------------------------------------------
+// Row pass over rows [rgroup * RPB, rgroup * RPB + RPB) of look `look`;
+// `slot` indexes the look's partial-sum slots.  `load_tables` reloads the
+// row tables (the caller skips it when the previous item had the same scene).
+template <int NX, int MODE>
+__device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup, size_t slot, const RowLds& L,
+                                         bool load_tables, BetaVals bv) {
+    constexpr int TR = row_threads(NX);
+    constexpr int RPB = rows_per_block(NX);
+    constexpr int PX = (NX + TR - 1) / TR;          // row samples per thread
+    constexpr int S1 = (MODE == ROW_FWD) ? -1 : +1;
+    constexpr int PAD = kRowPad;
+    constexpr int RS = lds_len<NX, PAD>();          // padded row length in LDS
+    constexpr bool FUSED = (MODE == ROW_GRAD || MODE == ROW_UPDATE);
+    // Stream prefetch pays off for the gradient pass; the update pass already
+    // runs near the read/write bandwidth ceiling and loads its streams late.
+    constexpr bool PREFETCH = (MODE == ROW_GRAD);
+    const SceneTables& s = a.s;
+    const int tid = threadIdx.x;
+    const int ri = tid / TR, t = tid % TR;
+    const int rows = s.nz * s.ny;
+    const int row = rgroup * RPB + ri;
+    const bool active = row < rows;
+    const size_t img = ((size_t)look * rows + (active ? row : 0)) * NX;
+    const size_t band = ((size_t)look * rows + (active ? row : 0)) * s.Bs;
+
+    float2 m[FUSED ? PX : 1];
+    float rp[FUSED ? PX : 1];
+    float wv[MODE == ROW_UPDATE ? PX : 1];
+    auto load_streams = [&]() {
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) {
+                    m[k] = a.mu[img + x];
+                    rp[k] = a.r[img + x];
+                    if constexpr (MODE == ROW_UPDATE) wv[k] = a.w[img + x];
+                }
+            }
+        }
+    };
+    if constexpr (PREFETCH) load_streams();
+    __syncthreads();  // the previous item's readers of the LDS buffers are done
+    if (load_tables) {
+        for (int i = tid; i < NX; i += kBlock) {
+            L.tw[i] = s.tw_x[i];
+            L.bpos[i] = s.band_pos[i];
+            L.bcol[i] = i < s.B ? s.band_cols[i] : 0;
+        }
+        __syncthreads();
+    }
+    float2* rb = L.buf + ri * RS;
+
+    if constexpr (MODE == ROW_FWD) {
+        if (active)
+            for (int x = t; x < NX; x += TR) rb[lds_pos<PAD>(x)] = a.img_in[img + x];
+    } else {
+        if (active)
+            for (int x = t; x < NX; x += TR) {
+                const int bp = L.bpos[x];
+                rb[lds_pos<PAD>(x)] = bp >= 0 ? a.band_in[band + bp] : make_float2(0.f, 0.f);
+            }
+    }
+    fft_lds<NX, TR, S1, PAD>(rb, 1, t, L.tw);
+
+    if constexpr (MODE == ROW_INV) {
+        if (active)
+            for (int x = t; x < NX; x += TR) a.img_out[img + x] = cscale(rb[lds_pos<PAD>(x)], a.scale);
+    } else if constexpr (MODE == ROW_FWD) {
+        if (active)
+            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale);
+    } else if constexpr (MODE == ROW_GRAD) {
+        float dd = 0.f, wd = 0.f, wm = 0.f;
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) {
+                    const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
+                    const float om = 1.f / (rp[k] + a.floor_w);
+                    const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
+                    rb[lds_pos<PAD>(x)] = d;
+                    const float d2 = cabs2(d);
+                    dd += d2;
+                    wd += om * d2;
+                    wm += om * cabs2(m[k]);
+                }
+            }
+        }
+        fft_lds<NX, TR, -1, PAD>(rb, 1, t, L.tw);
+        if (active)
+            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale);
+        double acc[3] = {dd, wd, wm};
+        block_sum_store<3>(acc, a.part + slot * 3);
+    } else {  // ROW_UPDATE
+        if constexpr (!PREFETCH) load_streams();
+        const float gamma = (float)a.diag[(size_t)look * kDiag];
+        float wm1 = 0.f;
+        uint32_t fb = 0u;
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) {
+                    const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
+                    const float r0 = rp[k];
+                    const float v = wv[k];
+                    const float om = 1.f / (r0 + a.floor_w);
+                    const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
+                    const float2 m1 = make_float2(m[k].x + gamma * d.x, m[k].y + gamma * d.y);
+                    a.mu[img + x] = m1;
+                    // covariance diagonal with A^H A ~ alpha I, and s = c + |mu|^2
+                    const float c = a.s2w * r0 / (a.alpha * r0 + a.s2w);
+                    const float sv = c + cabs2(m1);
+                    // quadratic surrogate of r/r' + s/r, interpolating its
+                    // derivative at r' and xi; written with s/r' first so that
+                    // small anchors stay in float32 range
+                    const float inv = 1.f / r0;
+                    const float sr = sv * inv;
+                    const float dq = inv * (1.f - sr);                  // q'(r')
+                    const float D = dq + (r0 - v) * a.inv_sigma2;       // rho'(r')
+                    const bool down = D > 0.f;
+                    const float xi = down ? r0 * bv.inv_beta : r0 * bv.beta;
+                    const float qa = sr * inv * inv * (down ? bv.k_dn : bv.k_up);
+                    const float qb = dq - qa * r0;
+                    float rn = (v - a.sigma2 * qb) / (1.f + a.sigma2 * qa);
+                    if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
+                    rn = fminf(fmaxf(rn, fminf(r0, xi)), fmaxf(r0, xi));
+                    if (!(rn > 0.f)) fb |= 2u;
+                    a.r[img + x] = rn;
+                    wm1 += om * cabs2(m1);
+                }
+            }
+        }
+        wave_or_fault(fb, a.fault);
+        double acc[1] = {wm1};
+        block_sum_store<1>(acc, a.part + slot);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse column pass of one tile from the column-major compact layout: the
+// tile is zeroed, the TC contiguous runs are scattered into it, and the
+// columns are transformed and written as band rows.  `item` = zl * tiles +
+// tile, which is also the partial-sum slot of the scene.
+template <int NY>
+__device__ __forceinline__ void col_inv_item(const ColArgs& a, int item, float2* tw, float2* tile,
+                                             bool load_tables) {
+    constexpr int TC = col_tile_cols(NY);
+    constexpr int TPC = kBlock / TC;
+    const SceneTables& s = a.s;
+    const int tid = threadIdx.x;
+    const int tile_i = item % s.tiles;
+    const int zl = item / s.tiles;  // look * nz + z
+    const int c0 = tile_i * TC;
+    __syncthreads();  // the previous item's readers of the LDS buffers are done
+    if (load_tables)
+        for (int i = tid; i < NY; i += kBlock) tw[i] = s.tw_y[i];
+    for (int i = tid; i < NY * TC; i += kBlock) tile[i] = make_float2(0.f, 0.f);
+    __syncthreads();
+    double acc[1] = {0.0};
+    {
+        const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
+        if (bc < s.B) {
+            const float2* src = a.cmp_in + (size_t)zl * s.P;
+            const int p1 = s.col_off[bc + 1];
+            float f = 0.f;
+            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
+                const float2 val = src[p];
+                tile[s.row_idx[p] * TC + c] = val;
+                f += cabs2(val);
+            }
+            acc[0] = f;
+        }
+    }
+    fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
+    {
+        const int c = tid % TC, bc = c0 + c;
+        if (bc < s.B) {
+            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bc;
+            for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + c], a.scale);
+        }
+    }
+    if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
+}
+
+// Forward column pass of one tile from band rows to the compact layout (the
+// batched form; the single-scene kernel pipelines loads across items).
+template <int NY>
+__device__ __forceinline__ void col_fwd_item(const ColArgs& a, int item, float2* tw, float2* tile,
+                                             bool load_tables) {
+    constexpr int TC = col_tile_cols(NY);
+    constexpr int TPC = kBlock / TC;
+    const SceneTables& s = a.s;
+    const int tid = threadIdx.x;
+    const int tile_i = item % s.tiles;
+    const int zl = item / s.tiles;
+    const int c0 = tile_i * TC;
+    __syncthreads();
+    if (load_tables)
+        for (int i = tid; i < NY; i += kBlock) tw[i] = s.tw_y[i];
+    {
+        const int c = tid % TC, bc = c0 + c;
+        const float2* src = a.band_in + (size_t)zl * s.ny * s.Bs + bc;
+        for (int y = tid / TC; y < NY; y += TPC)
+            tile[y * TC + c] = bc < s.B ? src[(size_t)y * s.Bs] : make_float2(0.f, 0.f);
+    }
+    fft_lds<NY, TPC, -1>(tile + tid % TC, TC, tid / TC, tw);
+    double acc[1] = {0.0};
+    {
+        const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
+        if (bc < s.B) {
+            float2* dst = a.cmp_out + (size_t)zl * s.P;
+            const int p1 = s.col_off[bc + 1];
+            float f = 0.f;
+            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
+                const float2 val = cscale(tile[s.row_idx[p] * TC + c], a.scale);
+                dst[p] = val;
+                f += cabs2(val);
+            }
+            acc[0] = f;
+        }
+    }
+    if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
+}
+
+// ---------------------------------------------------------------------------
+// Exact step size of one look from the partial sums of the three passes.
+__device__ __forceinline__ void gamma_item(int look, int nrow, int ncol, const double* prow, const double* pcf,
+                                           const double* pci, double inv_s2w, double* diag, uint32_t* fault) {
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nrow; i += kBlock) {
+        const double* p = prow + ((size_t)look * nrow + i) * 3;
+        v[0] += p[0];
+        v[1] += p[1];
+        v[2] += p[2];
+    }
+    for (int i = threadIdx.x; i < ncol; i += kBlock) {
+        v[3] += pcf[(size_t)look * ncol + i];
+        v[4] += pci[(size_t)look * ncol + i];
+    }
+    __shared__ double tot[5];
+    block_sum_store<5>(v, tot);
+    if (threadIdx.x == 0) {
+        const double dd = tot[0], wd = tot[1], wm = tot[2], ad = tot[3], r2 = tot[4];
+        const double den = ad * inv_s2w + wd;
+        const double g = dd > 0.0 ? dd / den : 0.0;
+        double* o = diag + (size_t)look * kDiag;
+        o[0] = g;
+        o[1] = dd;
+        o[2] = ad;
+        o[3] = wd;
+        o[4] = r2;
+        o[5] = wm;
+        if (!(g >= 0.0) || !isfinite(g)) atomicOr(fault, 4u | 1u);
+    }
+}
+
+// resid -= gamma D(a) F d over entries [begin, end) of one look; returns the
+// thread's share of ||resid||^2.
+__device__ __forceinline__ float resid_range(float2* R, const float2* D, float g, size_t begin, size_t end,
+                                             size_t stride) {
+    float f = 0.f;
+    for (size_t i = begin + threadIdx.x; i < end; i += stride) {
+        float2 x = R[i];
+        const float2 d = D[i];
+        x.x -= g * d.x;
+        x.y -= g * d.y;
+        R[i] = x;
+        f += cabs2(x);
+    }
+    return f;
+}
+
+__device__ __forceinline__ void diag_after_item(int look, int nrow, int nres, const double* pupd,
+                                                const double* pres, double* diag) {
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < nrow; i += kBlock) v[0] += pupd[(size_t)look * nrow + i];
+    for (int i = threadIdx.x; i < nres; i += kBlock) v[1] += pres[(size_t)look * nres + i];
+    __shared__ double tot[2];
+    block_sum_store<2>(v, tot);
+    if (threadIdx.x == 0) {
+        diag[(size_t)look * kDiag + 6] = tot[1];
+        diag[(size_t)look * kDiag + 7] = tot[0];
+    }
+}
+
+// Mann step of voxel i with every agent's w and r in registers (NA >=
+// n_agents); returns (sum_j (r_j - w_bar)^2, n_agents w_bar^2).
+template <int NA>
+__device__ __forceinline__ void mace_voxel(const MaceArgs& a, unsigned n, unsigned i, double& num, double& den) {
+    float wv[NA], rv[NA];
+    float wb = 0.f, rb = 0.f;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        if (j < a.n_agents) {
+            wv[j] = (a.w + (size_t)j * n)[i];
+            rv[j] = (a.r + (size_t)j * n)[i];
+            wb += a.ups[j] * wv[j];
+            rb += a.ups[j] * rv[j];
+        }
+    }
+    const float xb = 2.f * rb - wb;
+    float wbn = 0.f, nm = 0.f;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        if (j < a.n_agents) {
+            const float dr = rv[j] - wb;
+            nm += dr * dr;
+            const float wn = wv[j] + a.two_rho * (xb - rv[j]);
+            (a.w + (size_t)j * n)[i] = wn;
+            wbn += a.ups[j] * wn;
+        }
+    }
+    a.wbar[i] = wbn;
+    num += nm;
+    den += (double)a.n_agents * wb * wb;
+}
+
+struct Taps7 {
+    float g[7];
+};
+
+// Periodic 7-tap filter along x of voxel i.
+__device__ __forceinline__ float gauss_x_voxel(int nx, const float* g, const float* in, size_t i) {
+    const int x = (int)(i % nx);
+    const size_t row = i - x;
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) acc += g[k] * in[row + (size_t)((x + k - 3 + nx) % nx)];
+    return acc;
+}
+
+// Periodic 7-tap filter along a strided axis of length len (stride `inner`
+// elements) for work unit idx = chunk * outer + o: the thread slides a
+// register window down CH samples, reading each input once plus a 6-sample
+// halo.
+template <int CH>
+__device__ __forceinline__ void gauss_strided_unit(int len, size_t inner, size_t outer, const float* g,
+                                                   const float* in, float* out, size_t idx) {
+    const size_t o = idx % outer;
+    const int c = (int)(idx / outer);
+    const size_t base = (o / inner) * inner * (size_t)len + (o % inner);
+    const int y0 = c * CH;
+    float win[CH + 6];
+#pragma unroll
+    for (int k = 0; k < CH + 6; ++k) {
+        int yy = (y0 + k - 3) % len;
+        if (yy < 0) yy += len;
+        win[k] = in[base + (size_t)yy * inner];
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        if (y0 + k < len) {
+            float acc = 0.f;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) acc += g[q] * win[k + q];
+            out[base + (size_t)(y0 + k) * inner] = acc;
+        }
+    }
+}
+
+}  // namespace clampk

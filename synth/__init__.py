@@ -10,6 +10,7 @@ update, no consensus step).
 
 from .scenes import (  # noqa: F401
     CONFIGS,
+    batch_specs,
     SceneSpec,
     facet_scene,
     measure_looks,

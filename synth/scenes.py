@@ -133,25 +133,37 @@ def noise_variance(r: np.ndarray, snr_db: float) -> float:
 
 
 def measure_looks(r: np.ndarray, looks: int, radius: float, sigma_eta2: float,
-                  rngs, out: np.ndarray | None = None) -> np.ndarray:
-    """y[l] = D(a) F (sqrt(r) z_l) + eta_l as complex64 [looks, nz, ny, nx]."""
+                  rngs, out: np.ndarray | None = None, workers: int = 1) -> np.ndarray:
+    """y[l] = D(a) F (sqrt(r) z_l) + eta_l as complex64 [looks, nz, ny, nx].
+
+    Each look draws from its own stream, so `workers` threads give the same
+    looks as one."""
     nz, ny, nx = r.shape
     pupil = synth_pupil(ny, nx, radius)
     if out is None:
         out = np.empty((looks, nz, ny, nx), dtype=np.complex64)
     amp = np.sqrt(r)
     s_noise = math.sqrt(sigma_eta2 / 2.0)
-    for ell in range(looks):
+
+    def one(ell):
         rng = rngs[ell]
         z = (rng.standard_normal(r.shape) + 1j * rng.standard_normal(r.shape)) / math.sqrt(2.0)
         field = np.fft.fft2(amp * z, axes=(-2, -1), norm="ortho")
         field *= pupil
         field += s_noise * (rng.standard_normal(r.shape) + 1j * rng.standard_normal(r.shape))
         out[ell] = field.astype(np.complex64)
+
+    if workers > 1 and looks > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(workers, looks)) as ex:
+            list(ex.map(one, range(looks)))
+    else:
+        for ell in range(looks):
+            one(ell)
     return out
 
 
-def make_problem(spec: SceneSpec, scene_id: int = 0):
+def make_problem(spec: SceneSpec, scene_id: int = 0, workers: int = 1):
     """Scene, looks and noise variance for one seeded workload.
 
     Returns (r_true float64 [nz,ny,nx], y complex64 [L,nz,ny,nx], sigma_eta2).
@@ -161,5 +173,26 @@ def make_problem(spec: SceneSpec, scene_id: int = 0):
     r = facet_scene(spec, np.random.Generator(np.random.PCG64(children[0])))
     s2 = noise_variance(r, spec.snr_db)
     rngs = [np.random.Generator(np.random.PCG64(c)) for c in children[1:]]
-    y = measure_looks(r, spec.looks, spec.radius, s2, rngs)
+    y = measure_looks(r, spec.looks, spec.radius, s2, rngs, workers=workers)
     return r, y, s2
+
+
+def batch_specs(n_scenes=32, seed=0, cap_voxel_looks=2.5e9, sizes=(128, 192, 256, 384, 512),
+                depths=(32, 64, 128), looks=(4, 32), snr_db=10.0):
+    """Uneven scenes for batched runs: N ~ U(sizes), nz ~ U(depths),
+    L ~ U{looks[0] .. looks[1]}, pupil radius N/4, 24 facets, background
+    0.05.  Draws whose total exceeds `cap_voxel_looks` are redrawn (the
+    uncapped recipe averages about 4.5e9 voxel-looks for 32 scenes)."""
+    rng = np.random.Generator(np.random.PCG64(seed_sequence(2, 10_000 + seed)))
+    for _attempt in range(100_000):
+        specs = []
+        total = 0
+        for i in range(n_scenes):
+            n = int(rng.choice(sizes))
+            nz = int(rng.choice(depths))
+            L = int(rng.integers(looks[0], looks[1] + 1))
+            specs.append(SceneSpec("batch%d" % i, n, n, nz, L, n / 4.0, snr_db, 24, 0.05, 1, 2))
+            total += n * n * nz * L
+        if total <= cap_voxel_looks:
+            return specs
+    raise RuntimeError("no draw under the cap")

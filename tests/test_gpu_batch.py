@@ -1,0 +1,124 @@
+"""Batched steps over uneven scenes (persistent launches over work queues,
+graph replay, autotuned grids) against per-scene single-scene steps, which
+the other GPU tests tie to the float64 oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import rel_l2, report
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [
+    # nx, ny, nz, looks, radius, with_prior
+    (64, 64, 8, 3, 16.0, True),
+    (192, 192, 4, 2, 48.0, False),
+    (128, 128, 6, 5, 32.0, True),
+    (32, 32, 16, 4, 8.0, True),
+    (256, 256, 2, 2, 64.0, True),
+]
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch  # noqa: F401
+    import paper_2406_13651_amd as G
+    return G
+
+
+def _problems():
+    out = []
+    for i, (nx, ny, nz, L, R, wp) in enumerate(SPECS):
+        spec = synth.SceneSpec("b%d" % i, nx, ny, nz, L, R, 10.0, 6, 0.05, 1, 7)
+        r, y, s2 = synth.make_problem(spec, i)
+        out.append((spec, y, s2, wp))
+    return out
+
+
+def _scene_dicts(probs, sigma2=1e-3):
+    return [dict(nx=sp.nx, ny=sp.ny, nz=sp.nz, looks=sp.looks, radius=sp.radius, sigma_w2=s2, sigma2=sigma2,
+                 with_prior=wp) for sp, y, s2, wp in probs]
+
+
+def _batch(G, probs):
+    import torch
+    b = G.ClampBatchGPU(_scene_dicts(probs))
+    b.init([torch.from_numpy(y).cuda() for sp, y, s2, wp in probs])
+    return b
+
+
+def test_batch_steps_match_single_scene_runs(G):
+    import torch
+    probs = _problems()
+    b = _batch(G, probs)
+    iters = 6
+    for _ in range(iters):
+        b.step()
+    torch.cuda.synchronize()
+    assert int(b.fault.item()) == 0
+    for i, (sp, y, s2, wp) in enumerate(probs):
+        g = G.ClampGPU(sp.nx, sp.ny, sp.nz, sp.looks, sp.radius, s2, 1e-3, with_prior=wp)
+        g.init(torch.from_numpy(y).cuda())
+        g.run(iters)
+        torch.cuda.synchronize()
+        st = b.states[i]
+        tag = "batch scene %d %dx%dx%d L=%d" % (i, sp.nx, sp.ny, sp.nz, sp.looks)
+        assert report(tag + " w", rel_l2(st["w"].cpu().numpy(), g.w.cpu().numpy()), 1e-6) <= 1e-6
+        assert report(tag + " mu", rel_l2(st["mu"].cpu().numpy(), g.mu.cpu().numpy()), 1e-6) <= 1e-6
+        assert report(tag + " r", rel_l2(st["r"].cpu().numpy(), g.r.cpu().numpy()), 1e-6) <= 1e-6
+        assert abs(b.conv[i].item() - g.conv_err()) <= 1e-9 * max(1.0, g.conv_err())
+
+
+def test_batch_first_scene_matches_oracle(G):
+    import torch
+    probs = _problems()[:1]
+    b = _batch(G, probs)
+    for _ in range(5):
+        b.step()
+    torch.cuda.synchronize()
+    sp, y, s2, wp = probs[0]
+    st, hist = oracle.clamp_run(y, sp.radius, float(np.float32(s2)), float(np.float32(1e-3)), 5, with_prior=wp)
+    err = rel_l2(b.states[0]["wbar"].cpu().numpy(), hist[-1]["wbar"])
+    assert report("batch scene 0 vs oracle, 5 it", err, 1e-4) <= 1e-4
+
+
+def test_graph_replays_match_eager_steps(G):
+    import torch
+    probs = _problems()
+    eager = _batch(G, probs)
+    snaps = []
+    for _ in range(4):
+        eager.step()
+        torch.cuda.synchronize()
+        snaps.append([st["wbar"].cpu().numpy().copy() for st in eager.states])
+    graph = _batch(G, probs)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph.capture(stream)
+    filler = torch.randn(1 << 20, device="cuda")
+    for k in range(4):
+        graph.replay(1, stream)
+        stream.synchronize()
+        filler = filler * 1.0001 + 1.0  # eager work between replays
+        torch.cuda.synchronize()
+        for i, st in enumerate(graph.states):
+            assert np.array_equal(st["wbar"].cpu().numpy(), snaps[k][i]), (k, i)
+    assert int(graph.fault.item()) == 0
+
+
+def test_autotuned_grids_give_identical_results(G):
+    import torch
+    probs = _problems()
+    a = _batch(G, probs)
+    b = _batch(G, probs)
+    chosen = b.autotune()
+    assert chosen["row_blocks_per_cu"] >= 1 and chosen["col_blocks_per_cu"] >= 1
+    for _ in range(3):
+        a.step()
+        b.step()
+    torch.cuda.synchronize()
+    for sa, sb in zip(a.states, b.states):
+        assert np.array_equal(sa["w"].cpu().numpy(), sb["w"].cpu().numpy())
+        assert np.array_equal(sa["mu"].cpu().numpy(), sb["mu"].cpu().numpy())
