@@ -232,13 +232,15 @@ clamp_status clamp_batch_set_iteration(clamp_batch* batch, int32_t done, void* h
  * scenes that have one, Mann step, then the counter advances. */
 clamp_status clamp_batch_step(clamp_batch* batch, void* hip_stream);
 
-/* Persistent grid sizes in blocks per compute unit of the row and column
- * passes (both > 0). */
+/* Grid sizes of the row and column passes in blocks per compute unit, each
+ * block walking the queue with a grid-size stride; 0 = one block per work
+ * item (the default for rows; columns default to 4 per CU). */
 clamp_status clamp_batch_set_tiles(clamp_batch* batch, int32_t row_blocks_per_cu, int32_t col_blocks_per_cu);
 
 /* Times the passes that only write the workspace (inverse and forward column
- * passes, gradient row pass) for a set of grid sizes on the current state,
- * keeps the fastest, and reports them (HOST int32 [2], may be NULL).
+ * passes, gradient row pass) for grid sizes {one block per item, 2, 4, 8, 16
+ * per CU} on the current state, keeps the fastest, and reports them
+ * (HOST int32 [2]: rows, columns; may be NULL).
  * Synchronises the stream. */
 clamp_status clamp_batch_autotune(clamp_batch* batch, void* hip_stream, int32_t* chosen);
 

@@ -157,12 +157,37 @@ class ClampBatchGPU:
 
     def init(self, ys):
         """Alg. 2 initialisation of every scene from its looks (complex64 GPU tensors)."""
-        for i, (st, y) in enumerate(zip(self.states, ys)):
-            C.clamp_fwd_init(self.plan, i, st["params"], y, st["mu"], st["resid"], st["r"], st["w"], st["ahy2"],
-                             self.ws)
+        for i, y in enumerate(ys):
+            self.init_scene(i, y)
+        self.restart()
+
+    def init_scene(self, i, y):
+        """Alg. 2 initialisation of scene i from its looks (complex64 GPU tensor)."""
+        st = self.states[i]
+        C.clamp_fwd_init(self.plan, i, st["params"], y, st["mu"], st["resid"], st["r"], st["w"], st["ahy2"],
+                         self.ws)
+
+    def restart(self):
+        """Iteration counter and fault word back to zero (after init_scene calls)."""
         C.clamp_batch_set_iteration(self.batch, 0)
         self.fault.zero_()
         self.k = 0
+
+    def step_per_scene(self):
+        """The same iteration through the single-scene calls, scene by scene
+        (for comparison with the batched launches)."""
+        self.k += 1
+        beta = beta_schedule(self.k)
+        for i, st in enumerate(self.states):
+            p = C.make_params(self.specs[i]["sigma_w2"], self.specs[i]["sigma2"], self.specs[i].get("rho", 0.5),
+                              beta, self.specs[i].get("mu_scale", 1.0), st["ups"])
+            C.clamp_fwd_agent(self.plan, i, p, st["mu"], st["resid"], st["r"], st["w"], st["diag"], self.fault,
+                              self.ws)
+            L = self.specs[i]["looks"]
+            if st["with_prior"]:
+                C.clamp_prior_gauss(self.plan, i, st["prior_sigma"], st["w"][L], st["r"][L], self.ws)
+            C.clamp_mace_step(self.plan, i, p, st["w"], st["r"], st["wbar"], self.conv[i:i + 1], self.ws)
+        C.clamp_batch_set_iteration(self.batch, self.k)
 
     def step(self, stream=None):
         C.clamp_batch_step(self.batch, stream)

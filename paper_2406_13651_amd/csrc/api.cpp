@@ -676,7 +676,8 @@ struct clamp_batch {
     clampk::BatchLaunch launch{};
     std::vector<void*> dev;
     int cus = 256;
-    int row_per_cu = 8, col_per_cu = 4;
+    // persistent grid sizes in blocks per CU; 0 = one block per work item
+    int row_per_cu = 0, col_per_cu = 4;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -706,13 +707,15 @@ clamp_status batch_upload(clamp_batch* b, const std::vector<T>& h, T** out) {
 
 void batch_grids(clamp_batch* b) {
     clampk::BatchLaunch& L = b->launch;
-    auto cap = [&](int count, int per_cu) { return count < b->cus * per_cu ? count : b->cus * per_cu; };
+    auto cap = [&](int count, int per_cu) {
+        return (per_cu <= 0 || count < b->cus * per_cu) ? count : b->cus * per_cu;
+    };
     for (int g = 0; g < L.nseg[0]; ++g) L.seg_grid[0][g] = cap(L.seg_count[0][g], b->row_per_cu);
     for (int g = 0; g < L.nseg[1]; ++g) L.seg_grid[1][g] = cap(L.seg_count[1][g], b->col_per_cu);
     L.grid[clampk::Q_LOOK] = L.count[clampk::Q_LOOK];
     L.grid[clampk::Q_SCENE] = L.count[clampk::Q_SCENE];
     for (int q : {clampk::Q_RESID, clampk::Q_VOX, clampk::Q_PRIOR_X, clampk::Q_PRIOR_Y, clampk::Q_PRIOR_Z})
-        L.grid[q] = cap(L.count[q], 8);
+        L.grid[q] = L.count[q];
 }
 
 hipError_t batch_run(clamp_batch* b, hipStream_t st) {
@@ -940,7 +943,7 @@ clamp_status clamp_batch_step(clamp_batch* batch, void* hip_stream) {
 }
 
 clamp_status clamp_batch_set_tiles(clamp_batch* batch, int32_t row_blocks_per_cu, int32_t col_blocks_per_cu) {
-    if (batch == nullptr || row_blocks_per_cu <= 0 || col_blocks_per_cu <= 0) return fail(CLAMP_EINVAL, "bad argument");
+    if (batch == nullptr || row_blocks_per_cu < 0 || col_blocks_per_cu < 0) return fail(CLAMP_EINVAL, "bad argument");
     batch->row_per_cu = row_blocks_per_cu;
     batch->col_per_cu = col_blocks_per_cu;
     batch_grids(batch);
@@ -973,7 +976,7 @@ clamp_status clamp_batch_autotune(clamp_batch* batch, void* hip_stream, int32_t*
         }
         return best;
     };
-    const int cands[] = {1, 2, 4, 8, 16};
+    const int cands[] = {0, 2, 4, 8, 16};  // 0: one block per item
     int best_col = batch->col_per_cu, best_row = batch->row_per_cu;
     float tbest = 1e30f;
     for (int c : cands) {

@@ -37,8 +37,8 @@ __global__ __launch_bounds__(kBlock) void kb_row(BatchLaunch b, int off, int cou
     int prev = -1;
     for (int it = blockIdx.x; it < count; it += gridDim.x) {
         const BatchItem w = q[it];
-        const SceneBatch& sb = b.scenes[w.scene];
-        const RowArgs& a = (MODE == ROW_GRAD) ? sb.grad : sb.update;
+        // a private copy: the item's stores cannot alias its arguments
+        const RowArgs a = load_uniform((MODE == ROW_GRAD) ? &b.scenes[w.scene].grad : &b.scenes[w.scene].update);
         const bool load = w.scene != prev;
         prev = w.scene;
         row_item<NX, MODE>(a, w.a, w.b, (size_t)w.a * row_blocks(a.s) + w.b, L, load, bv);
@@ -52,16 +52,25 @@ __global__ __launch_bounds__(kBlock) void kb_col(BatchLaunch b, int off, int cou
     __shared__ float2 tw[NY];
     __shared__ float2 tile[NY * col_tile_cols(NY)];
     const BatchItem* q = b.queue[Q_COL] + off;
-    int prev = -1;
-    for (int it = blockIdx.x; it < count; it += gridDim.x) {
-        const BatchItem w = q[it];
-        const SceneBatch& sb = b.scenes[w.scene];
-        const bool load = w.scene != prev;
-        prev = w.scene;
-        if constexpr (FWD)
-            col_fwd_item<NY>(sb.cfwd, w.a, tw, tile, load);
-        else
-            col_inv_item<NY>(sb.cinv, w.a, tw, tile, load);
+    if constexpr (FWD) {
+        // every item of the segment has column length NY: one twiddle table,
+        // and the next item's band rows load during the current FFTs
+        for (int i = threadIdx.x; i < NY; i += kBlock) tw[i] = b.scenes[q[0].scene].cfwd.s.tw_y[i];
+        __syncthreads();
+        const SceneBatch* scenes = b.scenes;
+        col_fwd_stream<NY>(blockIdx.x, count, gridDim.x, [scenes, q](int pos) {
+            const BatchItem w = q[pos];
+            return ColItemVal{load_uniform(&scenes[w.scene].cfwd), w.a};
+        }, tw, tile);
+    } else {
+        int prev = -1;
+        for (int it = blockIdx.x; it < count; it += gridDim.x) {
+            const BatchItem w = q[it];
+            const bool load = w.scene != prev;
+            prev = w.scene;
+            const ColArgs a = load_uniform(&b.scenes[w.scene].cinv);
+            col_inv_item<NY>(a, w.a, tw, tile, load);
+        }
     }
 }
 
@@ -69,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void kb_gamma(BatchLaunch b) {
     const BatchItem* q = b.queue[Q_LOOK];
     for (int it = blockIdx.x; it < b.count[Q_LOOK]; it += gridDim.x) {
         const BatchItem w = q[it];
-        const GammaArgs& g = b.scenes[w.scene].gam;
+        const GammaArgs g = load_uniform(&b.scenes[w.scene].gam);
         gamma_item(w.a, g.nrow, g.ncol, g.prow, g.pcf, g.pci, g.inv_s2w, g.diag, g.fault);
     }
 }
@@ -78,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void kb_resid(BatchLaunch b) {
     const BatchItem* q = b.queue[Q_RESID];
     for (int it = blockIdx.x; it < b.count[Q_RESID]; it += gridDim.x) {
         const BatchItem w = q[it];
-        const ResidArgs& r = b.scenes[w.scene].res;
+        const ResidArgs r = load_uniform(&b.scenes[w.scene].res);
         const float g = (float)r.diag[(size_t)w.a * kDiag];
         const float f = resid_range(r.resid + r.per_look * w.a, r.dfd + r.per_look * w.a, g, (size_t)w.b * kBlock,
                                     r.per_look, (size_t)r.chunks * kBlock);
@@ -91,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void kb_diag(BatchLaunch b) {
     const BatchItem* q = b.queue[Q_LOOK];
     for (int it = blockIdx.x; it < b.count[Q_LOOK]; it += gridDim.x) {
         const BatchItem w = q[it];
-        const DiagArgs& d = b.scenes[w.scene].dia;
+        const DiagArgs d = load_uniform(&b.scenes[w.scene].dia);
         diag_after_item(w.a, d.nrow, d.nres, d.pupd, d.pres, d.diag);
     }
 }
@@ -101,16 +110,26 @@ __global__ __launch_bounds__(kBlock) void kb_mace(BatchLaunch b) {
     const BatchItem* q = b.queue[Q_VOX];
     for (int it = blockIdx.x; it < b.count[Q_VOX]; it += gridDim.x) {
         const BatchItem w = q[it];
-        const SceneBatch& sb = b.scenes[w.scene];
-        const MaceArgs& m = sb.mace;
+        const MaceArgs& mg = b.scenes[w.scene].mace;
+        MaceArgs m;  // everything but the weights, in scalar registers
+        m.n = __builtin_amdgcn_readfirstlane((int)mg.n);
+        m.n_agents = __builtin_amdgcn_readfirstlane(mg.n_agents);
+        m.two_rho = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(mg.two_rho)));
+        m.w = load_uniform(&mg.w);
+        m.r = load_uniform(&mg.r);
+        m.wbar = load_uniform(&mg.wbar);
+        m.part = load_uniform(&mg.part);
+        float ups[40];
+#pragma unroll
+        for (int j = 0; j < 40; ++j) ups[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(mg.ups[j])));
         const unsigned n = (unsigned)m.n;
-        const unsigned stride = (unsigned)sb.mace_chunks * kBlock;
+        const unsigned stride = (unsigned)__builtin_amdgcn_readfirstlane(b.scenes[w.scene].mace_chunks) * kBlock;
         double num = 0.0, den = 0.0;
         switch ((m.n_agents + 7) / 8) {
 #define CASE(K)                                                                      \
     case K:                                                                          \
         for (unsigned i = (unsigned)w.b * kBlock + threadIdx.x; i < n; i += stride)  \
-            mace_voxel<8 * K>(m, n, i, num, den);                                    \
+            mace_voxel<8 * K>(m, ups, n, i, num, den);                               \
         break;
             CASE(1) CASE(2) CASE(3) CASE(4) CASE(5)
 #undef CASE
@@ -147,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void kb_prior(BatchLaunch b) {
     const BatchItem* q = b.queue[Q];
     for (int it = blockIdx.x; it < b.count[Q]; it += gridDim.x) {
         const BatchItem w = q[it];
-        const PriorArgs& p = b.scenes[w.scene].prior;
+        const PriorArgs p = load_uniform(&b.scenes[w.scene].prior);
         const size_t n = (size_t)p.nx * p.ny * p.nz;
         const size_t begin = (size_t)w.b * kPriorChunk;
         if constexpr (AXIS == 0) {

@@ -41,21 +41,18 @@ __global__ __launch_bounds__(kBlock) void k_col_inv_compact(ColArgs a) {
     col_inv_item<NY>(a, blockIdx.x, tw, tile, true);
 }
 
-// Dense-input column passes (forward from band rows; inverse from full
-// grids).  Blocks are persistent and walk the items with a stride of the
+// Inverse column passes from full grids (initialisation and the operator's
+// adjoint).  Blocks are persistent and walk the items with a stride of the
 // grid size; each thread keeps the next item's inputs in registers, loaded
-// while the current item's column FFTs run, so the HBM latency of one item
-// hides behind the LDS work of the previous one.  Thread (tid / TC, tid % TC)
-// loads rows y = tid / TC + k * TPC of column tid % TC.
+// while the current item's column FFTs run.  Thread (tid / TC, tid % TC)
+// loads rows y = tid / TC + k * TPC of column tid % TC; only pupil samples
+// are read.
 template <int NY, int MODE>
-__global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
+__device__ __forceinline__ void col_dense_inv(const ColArgs& a, float2* tw, float2* tile) {
     constexpr int TC = col_tile_cols(NY);
     constexpr int TPC = kBlock / TC;       // threads per column
     constexpr int PT = NY / TPC;           // values per thread per item
     static_assert(NY % TPC == 0, "column length must be a multiple of the threads per column");
-    constexpr bool FWD = (MODE == COL_FWD_COMPACT);
-    __shared__ float2 tw[NY];
-    __shared__ float2 tile[NY * TC];
     const SceneTables& s = a.s;
     const int tid = threadIdx.x;
     const int items = a.looks * s.nz * s.tiles;
@@ -69,30 +66,23 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
         const int zl = item / s.tiles;
         const int c = tid % TC, bc = tile_i * TC + c;
         float f = 0.f;
-        if constexpr (FWD) {
-            const float2* src = a.band_in + (size_t)zl * s.ny * s.Bs + bc;
+        const int v = bc < s.B ? s.band_cols[bc] : 0;
+        const float2* src = a.full_in + (size_t)zl * s.ny * s.nx;
 #pragma unroll
-            for (int k = 0; k < PT; ++k)
-                pre[k] = bc < s.B ? src[(size_t)(tid / TC + k * TPC) * s.Bs] : make_float2(0.f, 0.f);
-        } else {  // COL_INV_FULL, COL_INV_INIT
-            const int v = bc < s.B ? s.band_cols[bc] : 0;
-            const float2* src = a.full_in + (size_t)zl * s.ny * s.nx;
-#pragma unroll
-            for (int k = 0; k < PT; ++k) {
-                const int y = tid / TC + k * TPC;
-                float2 val = make_float2(0.f, 0.f);
-                if (bc < s.B) {
-                    const int pi = s.pidx[y * s.nx + v];
-                    if (pi >= 0) {
-                        val = src[(size_t)y * s.nx + v];
-                        if constexpr (MODE == COL_INV_INIT) {
-                            a.cmp_out[(size_t)zl * s.P + pi] = cscale(val, a.init_keep);
-                            f += cabs2(val);
-                        }
+        for (int k = 0; k < PT; ++k) {
+            const int y = tid / TC + k * TPC;
+            float2 val = make_float2(0.f, 0.f);
+            if (bc < s.B) {
+                const int pi = s.pidx[y * s.nx + v];
+                if (pi >= 0) {
+                    val = src[(size_t)y * s.nx + v];
+                    if constexpr (MODE == COL_INV_INIT) {
+                        a.cmp_out[(size_t)zl * s.P + pi] = cscale(val, a.init_keep);
+                        f += cabs2(val);
                     }
                 }
-                pre[k] = val;
             }
+            pre[k] = val;
         }
         acc_in = f;
     };
@@ -109,34 +99,31 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
         for (int k = 0; k < PT; ++k) tile[(tid / TC + k * TPC) * TC + tid % TC] = pre[k];
         const int next = item + gridDim.x;
         if (next < items) load_item(next);
-
-        if constexpr (FWD)
-            fft_lds<NY, TPC, -1>(tile + tid % TC, TC, tid / TC, tw);
-        else
-            fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
-
-        if constexpr (FWD) {
-            const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
-            float f = 0.f;
-            if (bc < s.B) {
-                float2* dst = a.cmp_out + (size_t)zl * s.P;
-                const int p1 = s.col_off[bc + 1];
-                for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
-                    const float2 val = cscale(tile[s.row_idx[p] * TC + c], a.scale);
-                    dst[p] = val;
-                    f += cabs2(val);
-                }
-            }
-            acc[0] = f;
-        } else {
-            const int c = tid % TC, bc = c0 + c;
-            if (bc < s.B) {
-                float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bc;
-                for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + c], a.scale);
-            }
+        fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
+        const int c = tid % TC, bc = c0 + c;
+        if (bc < s.B) {
+            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bc;
+            for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + c], a.scale);
         }
         // item index = (look * nz + z) * tiles + tile = look * col_blocks + z * tiles + tile
         if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
+    }
+}
+
+// Persistent dense column passes: the forward pass from band rows (items
+// pipelined by col_fwd_stream) and the inverse passes from full grids.
+template <int NY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
+    __shared__ float2 tw[NY];
+    __shared__ float2 tile[NY * col_tile_cols(NY)];
+    if constexpr (MODE == COL_FWD_COMPACT) {
+        for (int i = threadIdx.x; i < NY; i += kBlock) tw[i] = a.s.tw_y[i];
+        __syncthreads();
+        const ColArgs* ap = &a;
+        col_fwd_stream<NY>(blockIdx.x, a.looks * a.s.nz * a.s.tiles, gridDim.x,
+                           [ap](int pos) { return ColItemRef{ap, pos}; }, tw, tile);
+    } else {
+        col_dense_inv<NY, MODE>(a, tw, tile);
     }
 }
 

@@ -79,6 +79,20 @@ __device__ __forceinline__ void wave_or_fault(uint32_t bits, uint32_t* fault) {
     if ((threadIdx.x & 63) == 0 && bits != 0u && fault != nullptr) atomicOr(fault, bits);
 }
 
+// Copy of a wave-uniform argument block from device memory into scalar
+// registers: the private copy cannot alias the item's stores, and
+// readfirstlane keeps it out of the vector register file.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "argument blocks are whole dwords");
+    T out;
+    const int* src = reinterpret_cast<const int*>(p);
+    int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return out;
+}
+
 // Interval factor and the derived constants of the surrogate r-update.
 struct BetaVals {
     float beta, inv_beta, k_up, k_dn;
@@ -288,8 +302,76 @@ __device__ __forceinline__ void col_inv_item(const ColArgs& a, int item, float2*
     if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
 }
 
-// Forward column pass of one tile from band rows to the compact layout (the
-// batched form; the single-scene kernel pipelines loads across items).
+// Forward column pass over a stream of items (all of column length NY): the
+// block walks items first, first + stride, ..., keeping the next item's band
+// rows in registers, loaded while the current item's column FFTs run.
+// `item_of(i)` returns the (ColArgs, scene item index) of stream position i.
+// The twiddle table must already be in `tw` (it depends on NY only).
+template <int NY, class ItemOf>
+__device__ __forceinline__ void col_fwd_stream(int first, int count, int stride, ItemOf item_of, const float2* tw,
+                                               float2* tile) {
+    constexpr int TC = col_tile_cols(NY);
+    constexpr int TPC = kBlock / TC;
+    constexpr int PT = NY / TPC;
+    static_assert(NY % TPC == 0, "column length must be a multiple of the threads per column");
+    const int tid = threadIdx.x;
+    const int c_ld = tid % TC, y_ld = tid / TC;
+    float2 pre[PT];
+    auto load = [&](int pos) {
+        const auto ai = item_of(pos);
+        const ColArgs& a = ai.get();
+        const SceneTables& s = a.s;
+        const int bc = (ai.item % s.tiles) * TC + c_ld;
+        const float2* src = a.band_in + (size_t)(ai.item / s.tiles) * s.ny * s.Bs + bc;
+#pragma unroll
+        for (int k = 0; k < PT; ++k)
+            pre[k] = bc < s.B ? src[(size_t)(y_ld + k * TPC) * s.Bs] : make_float2(0.f, 0.f);
+    };
+    int pos = first;
+    if (pos < count) load(pos);
+    for (; pos < count; pos += stride) {
+        const auto ai = item_of(pos);
+        const ColArgs& a = ai.get();
+        const SceneTables& s = a.s;
+        const int tile_i = ai.item % s.tiles;
+        const int zl = ai.item / s.tiles;
+        __syncthreads();  // the previous item's readers of `tile` are done
+#pragma unroll
+        for (int k = 0; k < PT; ++k) tile[(y_ld + k * TPC) * TC + c_ld] = pre[k];
+        if (pos + stride < count) load(pos + stride);
+        fft_lds<NY, TPC, -1>(tile + c_ld, TC, y_ld, tw);
+        double acc[1] = {0.0};
+        const int c = tid / TPC, lane = tid % TPC, bc = tile_i * TC + c;
+        if (bc < s.B) {
+            float2* dst = a.cmp_out + (size_t)zl * s.P;
+            const int p1 = s.col_off[bc + 1];
+            float f = 0.f;
+            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
+                const float2 val = cscale(tile[s.row_idx[p] * TC + c], a.scale);
+                dst[p] = val;
+                f += cabs2(val);
+            }
+            acc[0] = f;
+        }
+        if (a.part != nullptr) block_sum_store<1>(acc, a.part + ai.item);
+    }
+}
+
+// Column-pass item handles for col_fwd_stream: by pointer (kernel
+// arguments) or by private copy (arguments read from device memory).
+struct ColItemRef {
+    const ColArgs* args;
+    int item;
+    __device__ const ColArgs& get() const { return *args; }
+};
+struct ColItemVal {
+    ColArgs args;
+    int item;
+    __device__ const ColArgs& get() const { return args; }
+};
+
+// Forward column pass of one tile from band rows to the compact layout,
+// without pipelining.
 template <int NY>
 __device__ __forceinline__ void col_fwd_item(const ColArgs& a, int item, float2* tw, float2* tile,
                                              bool load_tables) {
@@ -392,7 +474,8 @@ __device__ __forceinline__ void diag_after_item(int look, int nrow, int nres, co
 // Mann step of voxel i with every agent's w and r in registers (NA >=
 // n_agents); returns (sum_j (r_j - w_bar)^2, n_agents w_bar^2).
 template <int NA>
-__device__ __forceinline__ void mace_voxel(const MaceArgs& a, unsigned n, unsigned i, double& num, double& den) {
+__device__ __forceinline__ void mace_voxel(const MaceArgs& a, const float* ups, unsigned n, unsigned i, double& num,
+                                           double& den) {
     float wv[NA], rv[NA];
     float wb = 0.f, rb = 0.f;
 #pragma unroll
@@ -400,8 +483,8 @@ __device__ __forceinline__ void mace_voxel(const MaceArgs& a, unsigned n, unsign
         if (j < a.n_agents) {
             wv[j] = (a.w + (size_t)j * n)[i];
             rv[j] = (a.r + (size_t)j * n)[i];
-            wb += a.ups[j] * wv[j];
-            rb += a.ups[j] * rv[j];
+            wb += ups[j] * wv[j];
+            rb += ups[j] * rv[j];
         }
     }
     const float xb = 2.f * rb - wb;
@@ -413,7 +496,7 @@ __device__ __forceinline__ void mace_voxel(const MaceArgs& a, unsigned n, unsign
             nm += dr * dr;
             const float wn = wv[j] + a.two_rho * (xb - rv[j]);
             (a.w + (size_t)j * n)[i] = wn;
-            wbn += a.ups[j] * wn;
+            wbn += ups[j] * wn;
         }
     }
     a.wbar[i] = wbn;
