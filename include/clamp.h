@@ -251,6 +251,47 @@ clamp_status clamp_batch_capture(clamp_batch* batch, void* hip_stream);
 /* Launches the recorded graph `iters` times on the stream. */
 clamp_status clamp_batch_replay(clamp_batch* batch, int32_t iters, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Learned prior agent: a residual 3D CNN denoiser (the learned stand-in for
+ * the paper's deep prior agent, Sec. III-C).  8 convolutions of 3x3x3 taps
+ * with biases and zero padding, channels 1 -> 32 (x6) -> 32 -> 1, ReLU after
+ * the first seven, output H(x) = x + N(x); BF16 weights and activations with
+ * FP32 accumulation on the matrix cores, trained with Adam on the mean
+ * squared error.
+ *
+ * Parameters (float32, CLAMP_CNN_PARAMS values): for each layer l = 0..7,
+ * W_l[27][Cin_l][Cout_l] then b_l[Cout_l], with tap t = 9 (dz+1) + 3 (dy+1) +
+ * (dx+1) for offsets in {-1, 0, 1}; the layer computes
+ *   y[v][co] = b[co] + sum_t sum_ci x[v + off(t)][ci] W[t][ci][co].
+ * Volumes are float32 [nvol][nz][ny][nx] with nx a multiple of 32.
+ * ------------------------------------------------------------------------ */
+#define CLAMP_CNN_PARAMS 167841
+typedef struct clamp_cnn clamp_cnn;
+
+/* Allocates device parameters (zero), Adam moments and BF16 copies. */
+clamp_status clamp_cnn_create(clamp_cnn** out);
+clamp_status clamp_cnn_destroy(clamp_cnn* cnn);
+/* Copies HOST parameters in (and resets the Adam state) or out.  Synchronous. */
+clamp_status clamp_cnn_set_params(clamp_cnn* cnn, const float* params);
+clamp_status clamp_cnn_get_params(const clamp_cnn* cnn, float* params);
+/* Workspace bytes for apply (train = 0) or gradient (train = 1) calls on
+ * nvol volumes of nz x ny x nx. */
+clamp_status clamp_cnn_workspace_size(int32_t nvol, int32_t nz, int32_t ny, int32_t nx, int32_t train,
+                                      size_t* bytes);
+/* out = H(x) per volume (device float32 arrays).  normalize != 0 applies the
+ * scale-free form out = x + m N(x / m) with m the mean of all nvol volumes. */
+clamp_status clamp_cnn_apply(clamp_cnn* cnn, const float* x, float* out, int32_t nvol, int32_t nz, int32_t ny,
+                             int32_t nx, int32_t normalize, void* workspace, void* hip_stream);
+/* Mean squared error of H(x) against target over the batch into *loss
+ * (device double) and its gradient with respect to every parameter into
+ * grad (device float32 [CLAMP_CNN_PARAMS]; NULL keeps it inside the object
+ * for clamp_cnn_adam_step). */
+clamp_status clamp_cnn_grad(clamp_cnn* cnn, const float* x, const float* target, int32_t nvol, int32_t nz,
+                            int32_t ny, int32_t nx, double* loss, float* grad, void* workspace, void* hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * gradient of the last clamp_cnn_grad call that kept it inside the object. */
+clamp_status clamp_cnn_adam_step(clamp_cnn* cnn, float lr, void* hip_stream);
+
 /* Optional per-stage timing (for benchmarks).  While enabled, every call
  * that takes a stream records a pair of HIP events on that stream around
  * each of its stages; clamp_plan_get_timing waits for the recorded events,

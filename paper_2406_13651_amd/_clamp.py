@@ -95,6 +95,14 @@ def _load():
         "clamp_batch_autotune": [P, P, ctypes.POINTER(i32)],
         "clamp_batch_capture": [P, P],
         "clamp_batch_replay": [P, i32, P],
+        "clamp_cnn_create": [ctypes.POINTER(P)],
+        "clamp_cnn_destroy": [P],
+        "clamp_cnn_set_params": [P, ctypes.POINTER(ctypes.c_float)],
+        "clamp_cnn_get_params": [P, ctypes.POINTER(ctypes.c_float)],
+        "clamp_cnn_workspace_size": [i32, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "clamp_cnn_apply": [P, P, P, i32, i32, i32, i32, i32, P, P],
+        "clamp_cnn_grad": [P, P, P, i32, i32, i32, i32, P, P, P, P],
+        "clamp_cnn_adam_step": [P, ctypes.c_float, P],
         "clamp_plan_get_timing": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
@@ -358,3 +366,73 @@ def clamp_batch_capture(batch, stream):
 
 def clamp_batch_replay(batch, iters, stream):
     _check(lib.clamp_batch_replay(batch.handle, int(iters), _stream(stream)))
+
+
+# -- learned prior (CNN) ------------------------------------------------------
+
+CNN_PARAMS = 167841
+
+
+class Cnn:
+    """Owns a clamp_cnn*; released with clamp_cnn_destroy."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib.clamp_cnn_create(ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.clamp_cnn_destroy(h)
+            self.handle = None
+
+
+def clamp_cnn_create():
+    return Cnn()
+
+
+def clamp_cnn_set_params(cnn, params):
+    import numpy as np
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    if p.size != CNN_PARAMS:
+        raise ValueError("expected %d parameters" % CNN_PARAMS)
+    _check(lib.clamp_cnn_set_params(cnn.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+
+def clamp_cnn_get_params(cnn):
+    import numpy as np
+    p = np.empty(CNN_PARAMS, dtype=np.float32)
+    _check(lib.clamp_cnn_get_params(cnn.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return p
+
+
+def clamp_cnn_workspace_size(nvol, nz, ny, nx, train):
+    b = ctypes.c_size_t()
+    _check(lib.clamp_cnn_workspace_size(int(nvol), int(nz), int(ny), int(nx), 1 if train else 0, ctypes.byref(b)))
+    return b.value
+
+
+def clamp_cnn_apply(cnn, x, out, normalize, workspace, stream=None):
+    """x, out: float32 [nvol, nz, ny, nx] (or [nz, ny, nx]) on the GPU."""
+    shape = tuple(x.shape) if x.dim() == 4 else (1,) + tuple(x.shape)
+    nvol, nz, ny, nx = shape
+    n = nvol * nz * ny * nx
+    _check(lib.clamp_cnn_apply(cnn.handle, _ptr(x, torch.float32, n, "x"), _ptr(out, torch.float32, n, "out"),
+                               nvol, nz, ny, nx, 1 if normalize else 0,
+                               _ptr(workspace, torch.uint8, clamp_cnn_workspace_size(nvol, nz, ny, nx, False),
+                                    "workspace"), _stream(stream)))
+
+
+def clamp_cnn_grad(cnn, x, target, loss, workspace, grad=None, stream=None):
+    nvol, nz, ny, nx = x.shape
+    n = nvol * nz * ny * nx
+    g = _ptr(grad, torch.float32, CNN_PARAMS, "grad") if grad is not None else None
+    _check(lib.clamp_cnn_grad(cnn.handle, _ptr(x, torch.float32, n, "x"), _ptr(target, torch.float32, n, "target"),
+                              nvol, nz, ny, nx, _ptr(loss, torch.float64, 1, "loss"), g,
+                              _ptr(workspace, torch.uint8, clamp_cnn_workspace_size(nvol, nz, ny, nx, True),
+                                   "workspace"), _stream(stream)))
+
+
+def clamp_cnn_adam_step(cnn, lr, stream=None):
+    _check(lib.clamp_cnn_adam_step(cnn.handle, float(lr), _stream(stream)))

@@ -35,6 +35,17 @@ clamp_status ok() {
     return CLAMP_OK;
 }
 
+}  // namespace
+
+namespace clampk {
+clamp_status set_error(clamp_status st, const char* msg) {
+    g_err = msg;
+    return st;
+}
+}  // namespace clampk
+
+namespace {
+
 clamp_status hip_check(hipError_t e, const char* what) {
     if (e == hipSuccess) return CLAMP_OK;
     return fail(CLAMP_EDEVICE, "%s: %s", what, hipGetErrorString(e));

@@ -1,0 +1,47 @@
+// Internal interface of the CNN prior kernels (cnn.hip) for the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace clampk {
+
+enum ConvEpi { EPI_RELU = 0, EPI_FINAL = 1, EPI_DGRAD = 2 };
+
+struct ConvArgs {
+    int nvol, nz, ny, nx;          // nx a multiple of 32
+    const uint16_t* in;            // bf16 [voxel][CIN]
+    const uint16_t* w;             // bf16 [27][32][CIN]
+    const float* bias;             // fp32 [32] (EPI_RELU, EPI_FINAL)
+    uint16_t* out;                 // bf16 [voxel][32] (EPI_RELU, EPI_DGRAD)
+    float* out_f32;                // fp32 [voxel] (EPI_FINAL)
+    const float* xin;              // fp32 [voxel] residual input (EPI_FINAL)
+    const float* scale;            // device scalar m of the output (EPI_FINAL), NULL = 1
+    const uint16_t* relu_src;      // bf16 [voxel][32]: ReLU mask source (EPI_DGRAD)
+};
+
+struct WgradArgs {
+    long nvox;                     // multiple of 8
+    int nz, ny, nx;
+    long chunk_steps;              // K-steps of 8 voxels per chunk
+    const uint16_t* act;           // bf16 [voxel][CA]
+    const uint16_t* g;             // bf16 [voxel][CG]
+    float* part;                   // fp32 [chunks][27][32][32]
+};
+
+hipError_t cnn_conv(int cin, int epi, const ConvArgs& a, hipStream_t st);
+hipError_t cnn_pack(const float* x, const float* scale, long nvox, uint16_t* x8, hipStream_t st);
+int cnn_reduce_blocks(long nvox);
+hipError_t cnn_mean(const float* x, long nvox, double* part, float* mean, hipStream_t st);
+hipError_t cnn_loss(const float* out, const float* target, long nvox, uint16_t* g8, double* part, double* loss,
+                    hipStream_t st);
+int cnn_wgrad_chunks(long nvox, long chunk_steps);
+int cnn_bias_blocks(long nvox);
+hipError_t cnn_wgrad(int ca, int cg, const WgradArgs& a, int cin, int cout, float* gw, float* gb, float* bias_part,
+                     hipStream_t st);
+hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float lr, int step, hipStream_t st);
+hipError_t cnn_prep(const float* W, const float* b, int cin, int cout, int cinp, int coutp, uint16_t* wf,
+                    uint16_t* wd, float* bias32, hipStream_t st);
+
+}  // namespace clampk

@@ -1,0 +1,128 @@
+"""GPU parity of the learned prior's BF16 MFMA kernels (forward, weight and
+input gradients) against the float64 oracle run with the same bfloat16
+weights and the same bfloat16 rounding of stored activations and gradients."""
+
+import numpy as np
+import pytest
+
+from oracle import cnn as ocnn
+from helpers import rel_l2, report
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def C():
+    import torch  # noqa: F401
+    import paper_2406_13651_amd._clamp as C
+    return C
+
+
+def flat(params):
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+
+
+def bf16_params(params):
+    """Weights rounded to bfloat16 as the GPU stores them; biases stay float32."""
+    return [(ocnn.bf16_round(w), np.asarray(b, np.float32).astype(np.float64)) for w, b in params]
+
+
+def _setup(C, seed=0, last_scale=0.5, shape=(2, 6, 8, 32)):
+    import torch
+    rng = np.random.default_rng(seed)
+    params = ocnn.init_params(rng, last_scale=last_scale)
+    for i, (w, b) in enumerate(params):
+        if i < len(params) - 1 or last_scale != 0.0:
+            b += 0.05 * rng.standard_normal(b.shape)
+    params = [(w.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)) for w, b in params]
+    net = C.clamp_cnn_create()
+    C.clamp_cnn_set_params(net, flat(params))
+    x = rng.uniform(0.05, 1.0, shape).astype(np.float32)
+    t = rng.uniform(0.05, 1.0, shape).astype(np.float32)
+    return net, params, x, t, torch
+
+
+def test_param_count_and_round_trip(C):
+    net, params, x, t, torch = _setup(C)
+    assert flat(params).size == C.CNN_PARAMS
+    np.testing.assert_array_equal(C.clamp_cnn_get_params(net), flat(params))
+
+
+def test_forward_matches_oracle(C):
+    net, params, x, t, torch = _setup(C)
+    xt = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xt)
+    ws = torch.empty(C.clamp_cnn_workspace_size(*x.shape, False), dtype=torch.uint8, device="cuda")
+    C.clamp_cnn_apply(net, xt, out, False, ws)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    p16 = bf16_params(params)
+    for i in range(x.shape[0]):
+        ref, _ = ocnn.forward(x[i].astype(np.float64), p16, act_round=True)
+        # compare the learned part N(x) = H(x) - x
+        err = rel_l2(got[i] - x[i], ref - x[i])
+        assert report("cnn forward N(x) volume %d" % i, err, 5e-3) <= 5e-3
+
+
+def test_normalized_apply_matches_oracle_and_scales(C):
+    net, params, x, t, torch = _setup(C, seed=1)
+    xv = 0.03 * x[:1]
+    xt = torch.from_numpy(xv).cuda()
+    out = torch.empty_like(xt)
+    ws = torch.empty(C.clamp_cnn_workspace_size(*xv.shape, False), dtype=torch.uint8, device="cuda")
+    C.clamp_cnn_apply(net, xt, out, True, ws)
+    torch.cuda.synchronize()
+    ref = ocnn.denoise(xv[0].astype(np.float64), bf16_params(params), act_round=True)
+    err = rel_l2(out.cpu().numpy()[0] - xv[0], ref - xv[0])
+    assert report("cnn normalized apply", err, 5e-3) <= 5e-3
+
+
+def test_zero_output_layer_is_identity(C):
+    net, params, x, t, torch = _setup(C, last_scale=0.0)
+    xt = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xt)
+    ws = torch.empty(C.clamp_cnn_workspace_size(*x.shape, False), dtype=torch.uint8, device="cuda")
+    C.clamp_cnn_apply(net, xt, out, True, ws)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), x)
+
+
+def test_gradients_match_oracle(C):
+    net, params, x, t, torch = _setup(C, seed=2, shape=(2, 4, 8, 32))
+    xt, tt = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(C.CNN_PARAMS, dtype=torch.float32, device="cuda")
+    ws = torch.empty(C.clamp_cnn_workspace_size(*x.shape, True), dtype=torch.uint8, device="cuda")
+    C.clamp_cnn_grad(net, xt, tt, loss, ws, grad=grad)
+    torch.cuda.synchronize()
+    ref_loss, ref_grads = ocnn.loss_and_grads(x.astype(np.float64), t.astype(np.float64), bf16_params(params),
+                                              act_round=True)
+    assert abs(loss.item() - ref_loss) <= 1e-3 * ref_loss
+    g = grad.cpu().numpy().astype(np.float64)
+    off = 0
+    for l, (w, b) in enumerate(params):
+        gw = g[off:off + w.size].reshape(w.shape)
+        off += w.size
+        gb = g[off:off + b.size]
+        off += b.size
+        ew = rel_l2(gw, ref_grads[l][0])
+        eb = rel_l2(gb, ref_grads[l][1])
+        report("cnn dW layer %d" % l, ew, 2e-2)
+        report("cnn db layer %d" % l, eb, 2e-2)
+        assert ew <= 2e-2 and eb <= 2e-2
+
+
+def test_adam_steps_reduce_loss(C):
+    net, params, x, t, torch = _setup(C, seed=3, last_scale=0.1, shape=(4, 4, 8, 32))
+    # a target the output bias alone can reach: H(x) = x + 0.1
+    t = x + 0.1
+    xt, tt = torch.from_numpy(x).cuda(), torch.from_numpy(t.astype(np.float32)).cuda()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(C.clamp_cnn_workspace_size(*x.shape, True), dtype=torch.uint8, device="cuda")
+    losses = []
+    for _ in range(30):
+        C.clamp_cnn_grad(net, xt, tt, loss, ws)
+        C.clamp_cnn_adam_step(net, 1e-2)
+        torch.cuda.synchronize()
+        losses.append(loss.item())
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 * losses[0]
