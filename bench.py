@@ -172,6 +172,134 @@ def run_batch(args):
     print(json.dumps(result), flush=True)
 
 
+CNN_FWD_FLOP = 335_232      # per voxel: 2 * 27 * (1*32 + 6*32*32 + 32*1)
+CNN_TRAIN_FLOP = 1_003_968  # forward + input gradients of layers 2-8 + weight gradients of all 8
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_learned(args):
+    """Learned form: train the CNN prior agent on seeded denoising pairs, then
+    reconstruct the evaluation scene with the CNN prior, the Gaussian prior
+    (the plain form) and the forward agents alone, and report iterations and
+    wall time of each form to reach the plain form's NRMSE at iteration 50."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2406_13651_amd as G
+    from paper_2406_13651_amd import learned as Lm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("training pairs: %d volumes of 64x64x32 (%s inputs)" % (args.train_pairs, args.train_mode))
+    t0 = time.perf_counter()
+    X, T = Lm.make_pairs(args.train_pairs, seed=0, mode=args.train_mode)
+    t_pairs = time.perf_counter() - t0
+    prior = Lm.CnnPrior(Lm.init_params(0), device=dev)
+    log("training %d epochs, lr %g" % (args.train_epochs, args.lr))
+    hist = Lm.train(prior, X, T, epochs=args.train_epochs, lr=args.lr,
+                    log=lambda m: log("  " + m))
+    del X, T
+    train_tflops = hist["voxels"] * CNN_TRAIN_FLOP / hist["seconds"] / 1e12
+
+    spec = synth.CONFIGS["learned"]
+    log("evaluation scene %dx%dx%d, %d looks" % (spec.nx, spec.ny, spec.nz, spec.looks))
+    r_true, y, s2w = synth.make_problem(spec, 0, workers=16)
+    yt = torch.from_numpy(y).to(dev)
+    rt = torch.from_numpy(r_true.astype(np.float32)).to(dev)
+    del y
+    geo = (spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, args.sigma2)
+    forms = {
+        "plain": lambda: G.ClampGPU(*geo, with_prior=True, device=dev),
+        "learned": lambda: Lm.LearnedClamp(*geo, prior=prior, device=dev),
+        "forward_only": lambda: G.ClampGPU(*geo, with_prior=False, device=dev),
+    }
+    iters = args.eval_iters
+    out = {}
+    for name, make in forms.items():
+        g = make()
+        g.init(yt)
+        trace = [Lm.nrmse(torch.tensordot(torch.tensor(g.upsilon, device=dev, dtype=torch.float32), g.w, 1), rt)]
+        for _ in range(iters):
+            g.iterate()
+            trace.append(Lm.nrmse(g.wbar, rt))
+        conv = g.conv_err()
+        fault = int(g.fault.item())
+        # wall time per iteration, timed without the NRMSE checks
+        g.init(yt)
+        for _ in range(args.warmup):
+            g.iterate()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.iterate()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        out[name] = {"nrmse": [round(v, 5) for v in trace], "ms_per_iter": ms, "conv_err": conv, "fault": fault}
+        log("%-12s nrmse it0 %.4f it%d %.4f min %.4f, %.3f ms/iter, conv %.2e" %
+            (name, trace[0], iters, trace[-1], min(trace), ms, conv))
+        del g
+        torch.cuda.empty_cache()
+
+    # the learned prior alone, timed with events on the stream it runs on
+    w = torch.rand(spec.nz, spec.ny, spec.nx, device=dev) + 0.05
+    o = torch.empty_like(w)
+    for _ in range(3):
+        prior.apply(w, o)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    ev0.record()
+    for _ in range(reps):
+        prior.apply(w, o)
+    ev1.record()
+    torch.cuda.synchronize()
+    cnn_ms = ev0.elapsed_time(ev1) / reps
+    cnn_tflops = spec.n * CNN_FWD_FLOP / (cnn_ms * 1e-3) / 1e12
+
+    target = out["plain"]["nrmse"][min(50, iters)]
+    equal = {"target_nrmse": target, "target": "NRMSE of the plain form (Gaussian prior) at iteration %d"
+             % min(50, iters)}
+    for name, o_ in out.items():
+        hit = next((k for k, v in enumerate(o_["nrmse"]) if k >= 1 and v <= target), None)
+        equal[name] = {"iterations": hit,
+                       "ms": None if hit is None else round(hit * o_["ms_per_iter"], 3),
+                       "iters_per_s": round(1e3 / o_["ms_per_iter"], 2),
+                       "nrmse_final": o_["nrmse"][-1], "nrmse_best": min(o_["nrmse"][1:])}
+    lt = out["learned"]
+    units = spec.looks * spec.n
+    result = {
+        "metric": "fwd-agent voxel-looks/s + HBM GB/s vs peak; CLAMP iters/s at fixed NRMSE",
+        "value": units / (lt["ms_per_iter"] * 1e-3),
+        "unit": "voxel-looks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": lt["ms_per_iter"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (forward agents), bf16 with f32 accumulation (CNN)",
+        "data": "synthetic",
+        "config": {"workload": "learned form: CLAMP iteration with the CNN prior agent, %dx%dx%d, %d looks, "
+                               "pupil radius %g, SNR %g dB; CNN trained on %d seeded 64x64x32 denoising pairs"
+                               % (spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, spec.snr_db,
+                                  args.train_pairs),
+                   "sigma2": args.sigma2, "train_epochs": args.train_epochs, "lr": args.lr,
+                   "train_mode": args.train_mode},
+        "roofline": {"bound": "mfma", "kernel": "cnn_apply (8 convolutions)", "achieved": round(cnn_tflops, 2),
+                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(cnn_tflops / BF16_PEAK_TFLOPS, 4),
+                     "traffic": None},
+        "cnn_apply_ms": round(cnn_ms, 3),
+        "training": {"pairs": args.train_pairs, "pair_synthesis_s": round(t_pairs, 2), "steps": hist["steps"],
+                     "seconds": round(hist["seconds"], 2), "voxels_per_s": hist["voxels"] / hist["seconds"],
+                     "tflops": round(train_tflops, 2), "frac_bf16_peak": round(train_tflops / BF16_PEAK_TFLOPS, 4),
+                     "val_loss": [round(v, 6) for v in hist["val"]], "best_val": hist["best_val"]},
+        "equal_nrmse": equal,
+        "forms": out,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +310,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-cap", type=float, default=2.5e9,
                     help="largest total voxel-looks of the uneven batch draw (--workload batch)")
+    ap.add_argument("--train-pairs", type=int, default=2000, help="training volumes (--workload learned)")
+    ap.add_argument("--train-epochs", type=int, default=10)
+    ap.add_argument("--train-mode", default="awgn", choices=("awgn", "speckle"))
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-iters", type=int, default=50)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy MIB mebibytes once with a plain device copy, as a "
                          "known-size reference for hardware byte counters")
@@ -193,6 +326,9 @@ def main():
 
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "learned":
+        run_learned(args)
         return
 
     import numpy as np

@@ -11,6 +11,7 @@ this module raises.
 from __future__ import annotations
 
 import ctypes
+import sys
 import os
 
 import torch
@@ -171,10 +172,10 @@ class Plan:
         self.scenes = scenes
         self.info = [clamp_plan_pupil_info(self, i) for i in range(len(scenes))]
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing, _destroy=lib.clamp_plan_destroy):
         h = getattr(self, "handle", None)
-        if h:
-            lib.clamp_plan_destroy(h)
+        if h and not _finalizing():  # at interpreter exit the process releases everything
+            _destroy(h)
             self.handle = None
 
     def workspace(self, device=None):
@@ -313,10 +314,10 @@ class Batch:
         self.handle = handle
         self._keep = keep
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing, _destroy=lib.clamp_batch_destroy):
         h = getattr(self, "handle", None)
-        if h:
-            lib.clamp_batch_destroy(h)
+        if h and not _finalizing():  # at interpreter exit the process releases everything
+            _destroy(h)
             self.handle = None
 
 
@@ -381,10 +382,10 @@ class Cnn:
         _check(lib.clamp_cnn_create(ctypes.byref(h)))
         self.handle = h
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing, _destroy=lib.clamp_cnn_destroy):
         h = getattr(self, "handle", None)
-        if h:
-            lib.clamp_cnn_destroy(h)
+        if h and not _finalizing():  # at interpreter exit the process releases everything
+            _destroy(h)
             self.handle = None
 
 
