@@ -311,9 +311,9 @@ def main():
     ap.add_argument("--batch-cap", type=float, default=2.5e9,
                     help="largest total voxel-looks of the uneven batch draw (--workload batch)")
     ap.add_argument("--train-pairs", type=int, default=2000, help="training volumes (--workload learned)")
-    ap.add_argument("--train-epochs", type=int, default=10)
+    ap.add_argument("--train-epochs", type=int, default=12)
     ap.add_argument("--train-mode", default="awgn", choices=("awgn", "speckle"))
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--eval-iters", type=int, default=50)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy MIB mebibytes once with a plain device copy, as a "

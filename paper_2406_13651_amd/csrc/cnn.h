@@ -11,8 +11,10 @@ enum ConvEpi { EPI_RELU = 0, EPI_FINAL = 1, EPI_DGRAD = 2 };
 
 struct ConvArgs {
     int nvol, nz, ny, nx;          // nx a multiple of 32
+    int tiles_x, tiles_y;          // output tiles of 32 x-voxels and 16 rows (set by cnn_conv)
+    int zc, zchunks;               // range slices per block and chunks per volume (set by cnn_conv)
     const uint16_t* in;            // bf16 [voxel][CIN]
-    const uint16_t* w;             // bf16 [27][32][CIN]
+    const uint16_t* wq;            // bf16 weight fragments [9][kQ][32][16] (cnn_prep_q)
     const float* bias;             // fp32 [32] (EPI_RELU, EPI_FINAL)
     uint16_t* out;                 // bf16 [voxel][32] (EPI_RELU, EPI_DGRAD)
     float* out_f32;                // fp32 [voxel] (EPI_FINAL)
@@ -30,7 +32,9 @@ struct WgradArgs {
     float* part;                   // fp32 [chunks][27][32][32]
 };
 
-hipError_t cnn_conv(int cin, int epi, const ConvArgs& a, hipStream_t st);
+hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st);
+size_t cnn_wq_elems(int cinp);
+hipError_t cnn_prep_q(const float* W, int cin, int cout, int flip, int cinp, uint16_t* wq, hipStream_t st);
 hipError_t cnn_pack(const float* x, const float* scale, long nvox, uint16_t* x8, hipStream_t st);
 int cnn_reduce_blocks(long nvox);
 hipError_t cnn_mean(const float* x, long nvox, double* part, float* mean, hipStream_t st);
@@ -41,7 +45,10 @@ int cnn_bias_blocks(long nvox);
 hipError_t cnn_wgrad(int ca, int cg, const WgradArgs& a, int cin, int cout, float* gw, float* gb, float* bias_part,
                      hipStream_t st);
 hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float lr, int step, hipStream_t st);
-hipError_t cnn_prep(const float* W, const float* b, int cin, int cout, int cinp, int coutp, uint16_t* wf,
-                    uint16_t* wd, float* bias32, hipStream_t st);
+// Weight fragments of a layer for the forward (wq, cinp input channels) and
+// backward-data (wqd, coutp input channels; NULL to skip) convolutions and the
+// padded bias.
+hipError_t cnn_prep(const float* W, const float* b, int cin, int cout, int cinp, int coutp, uint16_t* wq,
+                    uint16_t* wqd, float* bias32, hipStream_t st);
 
 }  // namespace clampk

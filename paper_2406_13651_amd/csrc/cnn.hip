@@ -29,6 +29,7 @@ namespace clampk {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kCnnBlock = 256;
 
@@ -51,56 +52,166 @@ __device__ __forceinline__ void tap_offset(int t, int& dz, int& dy, int& dx) {
 __device__ __forceinline__ int d_row(int l, int i) { return (l / 32) * 4 + (i / 4) * 8 + (i % 4); }
 
 // ---------------------------------------------------------------------------
-// Convolution (forward or backward-data) on 32-voxel x runs.
-template <int CIN, int EPI>
-__global__ __launch_bounds__(kCnnBlock) void k_conv(ConvArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * (kCnnBlock / 64) + (threadIdx.x >> 6);
-    const int tiles_x = a.nx / 32;
-    const long tiles = (long)a.nvol * a.nz * a.ny * tiles_x;
-    if (tile >= tiles) return;  // no barriers in this kernel
-    const int xt = tile % tiles_x;
-    long r = tile / tiles_x;
-    const int y = (int)(r % a.ny);
-    r /= a.ny;
-    const int z = (int)(r % a.nz);
-    const int n = (int)(r / a.nz);
-    const int m = lane & 31;
-    const int kh = (lane >> 5) * 4;
-    const int x = xt * 32 + m;
-    v16f acc = {};
-    for (int t = 0; t < 27; ++t) {
-        int dz, dy, dx;
-        tap_offset(t, dz, dy, dx);
-        const int zz = z + dz, yy = y + dy, xx = x + dx;
-        const bool ok = zz >= 0 && zz < a.nz && yy >= 0 && yy < a.ny && xx >= 0 && xx < a.nx;
-        const uint16_t* src = a.in + ((((long)n * a.nz + (ok ? zz : 0)) * a.ny + (ok ? yy : 0)) * a.nx + (ok ? xx : 0)) * CIN;
-        const uint16_t* wt = a.w + ((long)t * 32 + m) * CIN;
+// Convolution (forward or backward-data), tiled implicit GEMM on the
+// 32x32x16 bf16 MFMA.
+//
+// A block of 4 waves owns an output tile of 16 rows x 32 x-voxels and walks a
+// chunk of range slices.  The input slices z-1, z, z+1 (tile plus a one-voxel
+// halo: 18 rows x 34 voxels, zero outside the volume) sit in a ring of three
+// LDS slots; while slice z is computed, slice z+2 is fetched into registers
+// and stored into the slot of z-1 afterwards.  Wave w computes rows 4w..4w+3;
+// for each (dz, dy) tap pair and K fragment q it reads the six input rows the
+// four output rows need once and applies each to up to three output rows
+// (the dy taps).  K fragments: for 32 input channels q = (dx, channel half),
+// 6 per (dz, dy); for 8 input channels q pairs two dx taps (q = 0: dx = -1
+// in k 0..7 and dx = 0 in k 8..15; q = 1: dx = +1 and zeros).  The weights
+// are pre-arranged per fragment (wq[dz][dy][q][cout][16], see k_prep_q).
+//
+// LDS slot layout: 16-byte chunks; for 32 channels the chunk j of voxel
+// (row ys, column xs) sits at (ys * 34 + xs) * 4 + (j ^ ((xs >> 1) & 3)), so
+// that the 8 lanes of one LDS access phase hit 8 distinct 16-byte bank groups.
+constexpr int kTileRows = 16;
+constexpr int kTileCols = 32;
+constexpr int kRingRows = kTileRows + 2;
+constexpr int kRingCols = kTileCols + 2;
+
+template <int CIN>
+struct TileGeo {
+    static constexpr int kChunks = CIN / 8;                              // 16-byte chunks per voxel
+    static constexpr int kSlice = kRingRows * kRingCols * kChunks;      // chunks per ring slot
+    static constexpr int kQ = CIN == 32 ? 6 : 2;                         // K fragments per (dz, dy)
+    static constexpr int kFill = (kSlice + kCnnBlock - 1) / kCnnBlock;  // chunks per thread per slice
+};
+
+template <int CIN>
+__device__ __forceinline__ int ring_pos(int ys, int xs, int j) {
+    if constexpr (CIN == 32) return (ys * kRingCols + xs) * 4 + (j ^ ((xs >> 1) & 3));
+    else return ys * kRingCols + xs;
+}
+
+template <int CIN>
+__device__ __forceinline__ void tile_fetch(const ConvArgs& a, const uint16_t* in, int zin, int y0, int x0,
+                                           uint4 (&pre)[TileGeo<CIN>::kFill]) {
+    using G = TileGeo<CIN>;
 #pragma unroll
-        for (int cb = 0; cb < CIN / 8; ++cb) {
-            v4s av = {0, 0, 0, 0};
-            if (ok) av = *reinterpret_cast<const v4s*>(src + cb * 8 + kh);
-            const v4s bv = *reinterpret_cast<const v4s*>(wt + cb * 8 + kh);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+    for (int i = 0; i < G::kFill; ++i) {
+        const int e = threadIdx.x + i * kCnnBlock;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (e < G::kSlice) {
+            const int j = e % G::kChunks, vox = e / G::kChunks;
+            const int xs = vox % kRingCols, ys = vox / kRingCols;
+            const int y = y0 - 1 + ys, x = x0 - 1 + xs;
+            if (zin >= 0 && zin < a.nz && y >= 0 && y < a.ny && x >= 0 && x < a.nx)
+                v = *reinterpret_cast<const uint4*>(in + (((long)zin * a.ny + y) * a.nx + x) * CIN + j * 8);
+        }
+        pre[i] = v;
+    }
+}
+
+template <int CIN>
+__device__ __forceinline__ void tile_store(uint4* slot, const uint4 (&pre)[TileGeo<CIN>::kFill]) {
+    using G = TileGeo<CIN>;
+#pragma unroll
+    for (int i = 0; i < G::kFill; ++i) {
+        const int e = threadIdx.x + i * kCnnBlock;
+        if (e < G::kSlice) {
+            const int j = e % G::kChunks, vox = e / G::kChunks;
+            slot[ring_pos<CIN>(vox / kRingCols, vox % kRingCols, j)] = pre[i];
         }
     }
-    const long row0 = (((long)n * a.nz + z) * a.ny + y) * a.nx + xt * 32;
-    const int ch = lane & 31;
-    float scale = 1.f;
+}
+
+template <int CIN, int EPI>
+__global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
+    using G = TileGeo<CIN>;
+    __shared__ uint4 ring[3][G::kSlice];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, h = lane >> 5;
+    int b = blockIdx.x;
+    const int xt = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int yt = b % a.tiles_y;
+    b /= a.tiles_y;
+    const int zc = b % a.zchunks;
+    const int vol = b / a.zchunks;
+    const int x0 = xt * kTileCols, y0 = yt * kTileRows;
+    const int z0 = zc * a.zc;
+    const int z1 = z0 + a.zc < a.nz ? z0 + a.zc : a.nz;
+    const long vol_off = (long)vol * a.nz * a.ny * a.nx;
+    const uint16_t* in = a.in + vol_off * CIN;
+
+    uint4 pre[G::kFill];
+    for (int zin = z0 - 1; zin <= z0 + 1; ++zin) {
+        tile_fetch<CIN>(a, in, zin, y0, x0, pre);
+        tile_store<CIN>(ring[(zin + 3) % 3], pre);
+    }
+    __syncthreads();
+
+    float bias_n = 0.f, scale = 1.f;
+    if constexpr (EPI == EPI_RELU) bias_n = a.bias[m];
     if constexpr (EPI == EPI_FINAL) {
+        bias_n = a.bias[0];
         if (a.scale != nullptr) scale = *a.scale;
     }
+    // weight fragment of lane (n = m, k half h): wq[(g * kQ + q) * 32 + m][8h .. 8h + 7]
+    const uint4* wq = reinterpret_cast<const uint4*>(a.wq) + m * 2 + h;
+
+    for (int z = z0; z < z1; ++z) {
+        const bool next = z + 1 < z1;
+        if (next) tile_fetch<CIN>(a, in, z + 2, y0, x0, pre);
+        v16f acc[4];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const long v = row0 + d_row(lane, i);
-        const float val = acc[i];
-        if constexpr (EPI == EPI_RELU) {
-            a.out[v * 32 + ch] = f2bf(fmaxf(val + a.bias[ch], 0.f));
-        } else if constexpr (EPI == EPI_FINAL) {
-            if (ch == 0) a.out_f32[v] = a.xin[v] + scale * (val + a.bias[0]);
-        } else {  // EPI_DGRAD: multiply by the ReLU mask of the layer input
-            const float keep = bf2f(a.relu_src[v * 32 + ch]) > 0.f ? 1.f : 0.f;
-            a.out[v * 32 + ch] = f2bf(val * keep);
+        for (int r = 0; r < 4; ++r) acc[r] = v16f{};
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz) {
+            const uint4* slot = ring[(z + dz + 2) % 3];
+#pragma unroll
+            for (int q = 0; q < G::kQ; ++q) {
+                int xs, j;
+                if constexpr (CIN == 32) {
+                    xs = m + (q >> 1);
+                    j = 2 * (q & 1) + h;
+                } else {
+                    xs = m + (q == 0 ? h : 2);
+                    j = 0;
+                }
+                v8bf A[6];
+#pragma unroll
+                for (int rr = 0; rr < 6; ++rr)
+                    A[rr] = __builtin_bit_cast(v8bf, slot[ring_pos<CIN>(4 * wave + rr, xs, j)]);
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const v8bf B = __builtin_bit_cast(v8bf, wq[((dz * 3 + dy) * G::kQ + q) * 64]);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[r + dy], B, acc[r], 0, 0, 0);
+                }
+            }
+        }
+        // epilogue: lane holds output channel m for 16 voxels of each of its 4 rows
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int y = y0 + 4 * wave + r;
+            if (y >= a.ny) break;
+            const long row0 = vol_off + ((long)z * a.ny + y) * a.nx + x0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const long v = row0 + d_row(lane, i);
+                const float val = acc[r][i];
+                if constexpr (EPI == EPI_RELU) {
+                    a.out[v * 32 + m] = f2bf(fmaxf(val + bias_n, 0.f));
+                } else if constexpr (EPI == EPI_FINAL) {
+                    if (m == 0) a.out_f32[v] = a.xin[v] + scale * (val + bias_n);
+                } else {  // EPI_DGRAD: multiply by the ReLU mask of the layer input
+                    const float keep = bf2f(a.relu_src[v * 32 + m]) > 0.f ? 1.f : 0.f;
+                    a.out[v * 32 + m] = f2bf(val * keep);
+                }
+            }
+        }
+        if (next) {
+            __syncthreads();  // every wave is done with the slot of z - 1
+            tile_store<CIN>(ring[(z + 2) % 3], pre);
+            __syncthreads();
         }
     }
 }
@@ -269,22 +380,42 @@ __global__ __launch_bounds__(kCnnBlock) void k_adam(float* p, float* m, float* v
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// BF16 weight copies of one layer from the fp32 parameters W[t][cin][cout]:
-// forward wf[t][32][CINP] (output channel major) and backward-data
-// wd[t][32][COUTP] = W[26 - t] with the channel roles swapped; padded
-// entries are zero.  Also the zero-padded bias copy.
-__global__ __launch_bounds__(kCnnBlock) void k_prep(const float* W, const float* b, int cin, int cout, int cinp,
-                                                    int coutp, uint16_t* wf, uint16_t* wd, float* bias32) {
-    const int e = blockIdx.x * kCnnBlock + threadIdx.x;
-    if (e < 27 * 32 * cinp) {  // wf[t][n][k]
-        const int k = e % cinp, nn = (e / cinp) % 32, t = e / (cinp * 32);
-        wf[e] = (k < cin && nn < cout) ? f2bf(W[(t * cin + k) * cout + nn]) : (uint16_t)0;
-    }
-    if (wd != nullptr && e < 27 * 32 * coutp) {  // wd[t][n = ci][k = co]
-        const int k = e % coutp, nn = (e / coutp) % 32, t = e / (coutp * 32);
-        wd[e] = (k < cout && nn < cin) ? f2bf(W[((26 - t) * cin + nn) * cout + k]) : (uint16_t)0;
-    }
+// Zero-padded fp32 copy of a layer's bias.
+__global__ void k_prep_bias(const float* b, int cout, float* bias32) {
+    const int e = threadIdx.x;
     if (e < 32) bias32[e] = e < cout ? b[e] : 0.f;
+}
+
+// Weight fragments of the tiled convolution: wq[g = 3 dz + dy][q][n][kk]
+// (bf16) for K fragment q of the input-channel count CINP (8 or 32), from the
+// fp32 W[t][cin][cout].  Forward: the effective weight is W[t][ci][co];
+// backward data (flip): W[26 - t][co][ci] with the channel roles swapped.
+// Entries beyond the real channel counts and the zero half of the last
+// 8-channel fragment are zero.
+__global__ __launch_bounds__(kCnnBlock) void k_prep_q(const float* W, int cin, int cout, int flip, int cinp,
+                                                     uint16_t* wq) {
+    const int nq = cinp == 32 ? 6 : 2;
+    const int e = blockIdx.x * kCnnBlock + threadIdx.x;
+    if (e >= 9 * nq * 32 * 16) return;
+    const int kk = e % 16, n = (e / 16) % 32, q = (e / 512) % nq, g = e / (512 * nq);
+    const int dz = g / 3, dy = g % 3;
+    int dxi, ci;
+    bool zero = false;
+    if (cinp == 32) {
+        dxi = q >> 1;
+        ci = 16 * (q & 1) + kk;
+    } else {
+        const int hh = kk >> 3;
+        ci = kk & 7;
+        dxi = q == 0 ? hh : 2;
+        zero = q == 1 && hh == 1;
+    }
+    const int t = 9 * dz + 3 * dy + dxi;
+    const int ein = flip ? cout : cin, eout = flip ? cin : cout;
+    float w = 0.f;
+    if (!zero && ci < ein && n < eout)
+        w = flip ? W[((26 - t) * cin + n) * cout + ci] : W[(t * cin + ci) * cout + n];
+    wq[e] = f2bf(w);
 }
 
 // ---------------------------------------------------------------------------
@@ -295,9 +426,15 @@ static int grid_for(long work, int per_block, int cap) {
     return (int)(g < cap ? g : cap);
 }
 
-hipError_t cnn_conv(int cin, int epi, const ConvArgs& a, hipStream_t st) {
-    const long tiles = (long)a.nvol * a.nz * a.ny * (a.nx / 32);
-    const dim3 grid((unsigned)((tiles + 3) / 4));
+hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st) {
+    a.tiles_x = a.nx / kTileCols;
+    a.tiles_y = (a.ny + kTileRows - 1) / kTileRows;
+    // range slices per block: fewer when the volume gives too few tiles to fill the chip
+    const long tiles = (long)a.nvol * a.tiles_x * a.tiles_y;
+    a.zc = 8;
+    while (a.zc > 2 && tiles * ((a.nz + a.zc - 1) / a.zc) < 1024) a.zc /= 2;
+    a.zchunks = (a.nz + a.zc - 1) / a.zc;
+    const dim3 grid((unsigned)(tiles * a.zchunks));
 #define LAUNCH(CI, EP) hipLaunchKernelGGL((k_conv<CI, EP>), grid, dim3(kCnnBlock), 0, st, a)
     if (cin == 8 && epi == EPI_RELU) LAUNCH(8, EPI_RELU);
     else if (cin == 32 && epi == EPI_RELU) LAUNCH(32, EPI_RELU);
@@ -306,6 +443,15 @@ hipError_t cnn_conv(int cin, int epi, const ConvArgs& a, hipStream_t st) {
     else if (cin == 32 && epi == EPI_DGRAD) LAUNCH(32, EPI_DGRAD);
     else return hipErrorInvalidValue;
 #undef LAUNCH
+    return hipGetLastError();
+}
+
+size_t cnn_wq_elems(int cinp) { return (size_t)9 * (cinp == 32 ? 6 : 2) * 32 * 16; }
+
+hipError_t cnn_prep_q(const float* W, int cin, int cout, int flip, int cinp, uint16_t* wq, hipStream_t st) {
+    const int n = (int)cnn_wq_elems(cinp);
+    hipLaunchKernelGGL(k_prep_q, dim3((n + kCnnBlock - 1) / kCnnBlock), dim3(kCnnBlock), 0, st, W, cin, cout, flip,
+                       cinp, wq);
     return hipGetLastError();
 }
 
@@ -364,11 +510,12 @@ hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float l
     return hipGetLastError();
 }
 
-hipError_t cnn_prep(const float* W, const float* b, int cin, int cout, int cinp, int coutp, uint16_t* wf,
-                    uint16_t* wd, float* bias32, hipStream_t st) {
-    const int n = 27 * 32 * (cinp > coutp ? cinp : coutp);
-    hipLaunchKernelGGL(k_prep, dim3((n + kCnnBlock - 1) / kCnnBlock), dim3(kCnnBlock), 0, st, W, b, cin, cout, cinp,
-                       coutp, wf, wd, bias32);
+hipError_t cnn_prep(const float* W, const float* b, int cin, int cout, int cinp, int coutp, uint16_t* wq,
+                    uint16_t* wqd, float* bias32, hipStream_t st) {
+    hipError_t e = cnn_prep_q(W, cin, cout, 0, cinp, wq, st);
+    if (e == hipSuccess && wqd != nullptr) e = cnn_prep_q(W, cin, cout, 1, coutp, wqd, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prep_bias, dim3(1), dim3(32), 0, st, b, cout, bias32);
     return hipGetLastError();
 }
 

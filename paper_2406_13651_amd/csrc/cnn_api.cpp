@@ -104,8 +104,8 @@ struct clamp_cnn {
     float* m = nullptr;
     float* v = nullptr;
     float* grad = nullptr;
-    uint16_t* wf[kLayers] = {};
-    uint16_t* wd[kLayers] = {};
+    uint16_t* wq[kLayers] = {};   // forward weight fragments
+    uint16_t* wqd[kLayers] = {};  // backward-data weight fragments
     float* bias32[kLayers] = {};
     int step = 0;
     std::vector<void*> dev;
@@ -127,7 +127,7 @@ clamp_status alloc(clamp_cnn* c, size_t count, T** out) {
 hipError_t prep_all(clamp_cnn* c, hipStream_t st) {
     for (int l = 0; l < kLayers; ++l) {
         const hipError_t e = clampk::cnn_prep(c->params + w_offset(l), c->params + b_offset(l), cin_of(l), cout_of(l),
-                                              cinp_of(l), coutp_of(l), c->wf[l], l > 0 ? c->wd[l] : nullptr,
+                                              cinp_of(l), coutp_of(l), c->wq[l], l > 0 ? c->wqd[l] : nullptr,
                                               c->bias32[l], st);
         if (e != hipSuccess) return e;
     }
@@ -154,7 +154,7 @@ hipError_t forward(clamp_cnn* c, const float* x, float* out, const float* scale,
     for (int l = 0; l < kLayers && e == hipSuccess; ++l) {
         ConvArgs a = conv_args(nvol, nz, ny, nx);
         a.in = in;
-        a.w = c->wf[l];
+        a.wq = c->wq[l];
         a.bias = c->bias32[l];
         if (l < kLayers - 1) {
             uint16_t* dst = acts ? acts[l + 1] : ((l % 2 == 0) ? ping : pong);
@@ -187,8 +187,8 @@ clamp_status clamp_cnn_create(clamp_cnn** out) {
     if (st == CLAMP_OK) st = alloc(c, CLAMP_CNN_PARAMS, &c->v);
     if (st == CLAMP_OK) st = alloc(c, CLAMP_CNN_PARAMS, &c->grad);
     for (int l = 0; l < kLayers && st == CLAMP_OK; ++l) {
-        st = alloc(c, (size_t)27 * 32 * cinp_of(l), &c->wf[l]);
-        if (st == CLAMP_OK) st = alloc(c, (size_t)27 * 32 * coutp_of(l), &c->wd[l]);
+        st = alloc(c, clampk::cnn_wq_elems(cinp_of(l)), &c->wq[l]);
+        if (st == CLAMP_OK) st = alloc(c, clampk::cnn_wq_elems(coutp_of(l)), &c->wqd[l]);
         if (st == CLAMP_OK) st = alloc(c, 32, &c->bias32[l]);
     }
     if (st == CLAMP_OK) {
@@ -298,7 +298,7 @@ clamp_status clamp_cnn_grad(clamp_cnn* cnn, const float* x, const float* target,
         if (e == hipSuccess && l > 0) {
             ConvArgs a = conv_args(nvol, nz, ny, nx);
             a.in = gl;
-            a.w = cnn->wd[l];
+            a.wq = cnn->wqd[l];
             a.relu_src = acts[l];
             a.out = gbuf[l % 2];
             e = clampk::cnn_conv(coutp_of(l), clampk::EPI_DGRAD, a, s);

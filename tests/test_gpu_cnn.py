@@ -48,8 +48,14 @@ def test_param_count_and_round_trip(C):
     np.testing.assert_array_equal(C.clamp_cnn_get_params(net), flat(params))
 
 
-def test_forward_matches_oracle(C):
-    net, params, x, t, torch = _setup(C)
+# shapes: one ragged row tile; several row and x tiles with ragged rows and
+# a ragged last range chunk; a taller volume with full 8-slice range chunks
+SHAPES = [(2, 6, 8, 32), (1, 11, 37, 64), (1, 20, 16, 32)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_matches_oracle(C, shape):
+    net, params, x, t, torch = _setup(C, shape=shape)
     xt = torch.from_numpy(x).cuda()
     out = torch.empty_like(xt)
     ws = torch.empty(C.clamp_cnn_workspace_size(*x.shape, False), dtype=torch.uint8, device="cuda")
@@ -61,7 +67,7 @@ def test_forward_matches_oracle(C):
         ref, _ = ocnn.forward(x[i].astype(np.float64), p16, act_round=True)
         # compare the learned part N(x) = H(x) - x
         err = rel_l2(got[i] - x[i], ref - x[i])
-        assert report("cnn forward N(x) volume %d" % i, err, 5e-3) <= 5e-3
+        assert report("cnn forward N(x) %s volume %d" % (shape, i), err, 5e-3) <= 5e-3
 
 
 def test_normalized_apply_matches_oracle_and_scales(C):
@@ -87,8 +93,9 @@ def test_zero_output_layer_is_identity(C):
     np.testing.assert_array_equal(out.cpu().numpy(), x)
 
 
-def test_gradients_match_oracle(C):
-    net, params, x, t, torch = _setup(C, seed=2, shape=(2, 4, 8, 32))
+@pytest.mark.parametrize("shape", [(2, 4, 8, 32), (1, 9, 21, 64)])
+def test_gradients_match_oracle(C, shape):
+    net, params, x, t, torch = _setup(C, seed=2, shape=shape)
     xt, tt = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     grad = torch.zeros(C.CNN_PARAMS, dtype=torch.float32, device="cuda")
@@ -107,8 +114,8 @@ def test_gradients_match_oracle(C):
         off += b.size
         ew = rel_l2(gw, ref_grads[l][0])
         eb = rel_l2(gb, ref_grads[l][1])
-        report("cnn dW layer %d" % l, ew, 2e-2)
-        report("cnn db layer %d" % l, eb, 2e-2)
+        report("cnn dW layer %d %s" % (l, shape), ew, 2e-2)
+        report("cnn db layer %d %s" % (l, shape), eb, 2e-2)
         assert ew <= 2e-2 and eb <= 2e-2
 
 
@@ -126,3 +133,39 @@ def test_adam_steps_reduce_loss(C):
         torch.cuda.synchronize()
         losses.append(loss.item())
     assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 * losses[0]
+
+
+def test_forward_full_size_sampled(C):
+    """At the full evaluation size (64 x 256 x 256, the launch configuration of
+    the learned-form benchmark) sampled outputs match the oracle run on the
+    receptive field around each sample (8 layers: +-8 voxels, clipped at the
+    volume boundary, where both sides pad with zeros)."""
+    import torch
+    shape = (1, 64, 256, 256)
+    rng = np.random.default_rng(7)
+    params = ocnn.init_params(rng, last_scale=0.5)
+    for w, b in params:
+        b += 0.05 * rng.standard_normal(b.shape)
+    params = [(w.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)) for w, b in params]
+    net = C.clamp_cnn_create()
+    C.clamp_cnn_set_params(net, flat(params))
+    x = rng.uniform(0.05, 1.0, shape).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xt)
+    ws = torch.empty(C.clamp_cnn_workspace_size(*shape, False), dtype=torch.uint8, device="cuda")
+    C.clamp_cnn_apply(net, xt, out, False, ws)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[0].astype(np.float64)
+    p16 = bf16_params(params)
+    samples = [(31, 100, 77), (0, 0, 0), (63, 255, 255), (7, 16, 32), (40, 15, 31), (8, 200, 128)]
+    errs = []
+    for c in samples:
+        lo = [max(0, c[d] - 8) for d in range(3)]
+        hi = [min(shape[1 + d], c[d] + 9) for d in range(3)]
+        crop = x[0, lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]].astype(np.float64)
+        ref, _ = ocnn.forward(crop, p16, act_round=True)
+        r = ref[c[0] - lo[0], c[1] - lo[1], c[2] - lo[2]] - x[0][c]
+        g = got[c] - x[0][c]
+        errs.append(abs(g - r) / max(abs(r), 1e-3))
+    err = max(errs)
+    assert report("cnn forward 64x256x256 sampled voxels", err, 2e-2) <= 2e-2
