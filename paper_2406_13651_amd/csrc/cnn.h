@@ -14,7 +14,7 @@ struct ConvArgs {
     int tiles_x, tiles_y;          // output tiles of 32 x-voxels and 16 rows (set by cnn_conv)
     int zc, zchunks;               // range slices per block and chunks per volume (set by cnn_conv)
     const uint16_t* in;            // bf16 [voxel][CIN]
-    const uint16_t* wq;            // bf16 weight fragments [9][kQ][32][16] (cnn_prep_q)
+    const uint16_t* wq;            // bf16 weight fragments [9][kQ][2][32][8] (cnn_prep_q)
     const float* bias;             // fp32 [32] (EPI_RELU, EPI_FINAL)
     uint16_t* out;                 // bf16 [voxel][32] (EPI_RELU, EPI_DGRAD)
     float* out_f32;                // fp32 [voxel] (EPI_FINAL)

@@ -42,6 +42,22 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Two floats as packed bf16 (lo in bits 0..15), round to nearest even: one
+// hardware conversion instruction on gfx950.
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    const v2bf v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// Mask of a dword of two bf16 ReLU outputs: each half is all ones when that
+// value is > 0 (sign clear, not zero), else zero.
+__device__ __forceinline__ uint32_t relu_keep2(uint32_t k) {
+    const uint32_t lo = ((k & 0x8000u) == 0u && (k & 0x7fffu) != 0u) ? 0x0000ffffu : 0u;
+    const uint32_t hi = ((k & 0x80000000u) == 0u && (k & 0x7fff0000u) != 0u) ? 0xffff0000u : 0u;
+    return lo | hi;
+}
+
 __device__ __forceinline__ void tap_offset(int t, int& dz, int& dy, int& dx) {
     dz = t / 9 - 1;
     dy = (t / 3) % 3 - 1;
@@ -56,20 +72,30 @@ __device__ __forceinline__ int d_row(int l, int i) { return (l / 32) * 4 + (i / 
 // 32x32x16 bf16 MFMA.
 //
 // A block of 4 waves owns an output tile of 16 rows x 32 x-voxels and walks a
-// chunk of range slices.  The input slices z-1, z, z+1 (tile plus a one-voxel
-// halo: 18 rows x 34 voxels, zero outside the volume) sit in a ring of three
-// LDS slots; while slice z is computed, slice z+2 is fetched into registers
-// and stored into the slot of z-1 afterwards.  Wave w computes rows 4w..4w+3;
-// for each (dz, dy) tap pair and K fragment q it reads the six input rows the
-// four output rows need once and applies each to up to three output rows
-// (the dy taps).  K fragments: for 32 input channels q = (dx, channel half),
-// 6 per (dz, dy); for 8 input channels q pairs two dx taps (q = 0: dx = -1
-// in k 0..7 and dx = 0 in k 8..15; q = 1: dx = +1 and zeros).  The weights
-// are pre-arranged per fragment (wq[dz][dy][q][cout][16], see k_prep_q).
+// chunk of range slices.  Input slices (tile plus a one-voxel halo: 18 rows x
+// 34 voxels, zero outside the volume) live in two LDS slots: output slice z
+// takes its dz = -1 and dz = 0 taps from the slots holding input z - 1 and z,
+// then input z + 1 (fetched into registers during the previous step) replaces
+// input z - 1 and the dz = +1 taps follow, while input z + 2 is fetched.
+// Every weight fragment of the layer stays in LDS for the whole block, so the
+// MFMA loop reads only LDS.  Wave w computes rows 4w..4w+3; for each (dz, dy)
+// tap pair and K fragment q it reads the six input rows its four output rows
+// need once and applies each to up to three output rows (the dy taps).  K
+// fragments: for 32 input channels q = (dx, channel half), 6 per (dz, dy); for
+// 8 input channels q pairs two dx taps (q = 0: dx = -1 in k 0..7 and dx = 0 in
+// k 8..15; q = 1: dx = +1 and zeros).
 //
-// LDS slot layout: 16-byte chunks; for 32 channels the chunk j of voxel
-// (row ys, column xs) sits at (ys * 34 + xs) * 4 + (j ^ ((xs >> 1) & 3)), so
-// that the 8 lanes of one LDS access phase hit 8 distinct 16-byte bank groups.
+// LDS layouts.  Input slot: 16-byte chunks; for 32 channels the chunk j of
+// voxel (row ys, column xs) sits at (ys * 34 + xs) * 4 + (j ^ ((xs >> 2) & 3)),
+// so that the 16 lanes of one 128-bit LDS access phase (16 consecutive voxels,
+// one chunk each) hit 16 distinct 16-byte bank groups of the 256-byte bank
+// window.  Weights: wq[g = 3 dz + dy][q][h][n][8] (see k_prep_q), 16 lanes of
+// one phase reading 16 consecutive fragments rows.  Output staging: each wave
+// writes two output rows (32 voxels x 32 bf16 channels) into a private area,
+// voxel v at record v ^ (((v >> 2) & 1) << 1) so that the two voxels of one
+// MFMA register (v and v + 4) fall into different bank windows, and reads it
+// back in 16-byte chunks for coalesced global stores (and, for the
+// backward-data pass, coalesced ReLU-mask loads).
 constexpr int kTileRows = 16;
 constexpr int kTileCols = 32;
 constexpr int kRingRows = kTileRows + 2;
@@ -78,14 +104,15 @@ constexpr int kRingCols = kTileCols + 2;
 template <int CIN>
 struct TileGeo {
     static constexpr int kChunks = CIN / 8;                              // 16-byte chunks per voxel
-    static constexpr int kSlice = kRingRows * kRingCols * kChunks;      // chunks per ring slot
+    static constexpr int kSlice = kRingRows * kRingCols * kChunks;      // chunks per input slot
     static constexpr int kQ = CIN == 32 ? 6 : 2;                         // K fragments per (dz, dy)
+    static constexpr int kW = 9 * kQ * 64;                               // weight chunks (16 bytes)
     static constexpr int kFill = (kSlice + kCnnBlock - 1) / kCnnBlock;  // chunks per thread per slice
 };
 
 template <int CIN>
 __device__ __forceinline__ int ring_pos(int ys, int xs, int j) {
-    if constexpr (CIN == 32) return (ys * kRingCols + xs) * 4 + (j ^ ((xs >> 1) & 3));
+    if constexpr (CIN == 32) return (ys * kRingCols + xs) * 4 + (j ^ ((xs >> 2) & 3));
     else return ys * kRingCols + xs;
 }
 
@@ -96,15 +123,14 @@ __device__ __forceinline__ void tile_fetch(const ConvArgs& a, const uint16_t* in
 #pragma unroll
     for (int i = 0; i < G::kFill; ++i) {
         const int e = threadIdx.x + i * kCnnBlock;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (e < G::kSlice) {
-            const int j = e % G::kChunks, vox = e / G::kChunks;
-            const int xs = vox % kRingCols, ys = vox / kRingCols;
-            const int y = y0 - 1 + ys, x = x0 - 1 + xs;
-            if (zin >= 0 && zin < a.nz && y >= 0 && y < a.ny && x >= 0 && x < a.nx)
-                v = *reinterpret_cast<const uint4*>(in + (((long)zin * a.ny + y) * a.nx + x) * CIN + j * 8);
-        }
-        pre[i] = v;
+        const int j = e % G::kChunks, vox = e / G::kChunks;
+        const int xs = vox % kRingCols, ys = vox / kRingCols;
+        const int y = y0 - 1 + ys, x = x0 - 1 + xs;
+        const bool ok = e < G::kSlice && zin >= 0 && zin < a.nz && y >= 0 && y < a.ny && x >= 0 && x < a.nx;
+        // out-of-volume chunks read voxel 0 and are zeroed (no divergent branch around the load)
+        const long off = ok ? (((long)zin * a.ny + y) * a.nx + x) * CIN + j * 8 : 0;
+        const uint4 v = *reinterpret_cast<const uint4*>(in + off);
+        pre[i] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
     }
 }
 
@@ -121,10 +147,40 @@ __device__ __forceinline__ void tile_store(uint4* slot, const uint4 (&pre)[TileG
     }
 }
 
+// acc[r] += the taps of range offset dz (index 0..2) from the input slot.
+template <int CIN>
+__device__ __forceinline__ void conv_dz(const uint4* slot, const uint4* wsh, int dz, int wave, int m, int h,
+                                        v16f (&acc)[4]) {
+    using G = TileGeo<CIN>;
+#pragma unroll
+    for (int q = 0; q < G::kQ; ++q) {
+        int xs, j;
+        if constexpr (CIN == 32) {
+            xs = m + (q >> 1);
+            j = 2 * (q & 1) + h;
+        } else {
+            xs = m + (q == 0 ? h : 2);
+            j = 0;
+        }
+        v8bf A[6];
+#pragma unroll
+        for (int rr = 0; rr < 6; ++rr) A[rr] = __builtin_bit_cast(v8bf, slot[ring_pos<CIN>(4 * wave + rr, xs, j)]);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const v8bf B = __builtin_bit_cast(v8bf, wsh[(((dz * 3 + dy) * G::kQ + q) * 2 + h) * 32 + m]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[r + dy], B, acc[r], 0, 0, 0);
+        }
+    }
+}
+
 template <int CIN, int EPI>
 __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
     using G = TileGeo<CIN>;
-    __shared__ uint4 ring[3][G::kSlice];
+    __shared__ uint4 ring[2][G::kSlice];
+    __shared__ uint4 wsh[G::kW];
+    __shared__ uint32_t stage[4 * 2 * 32 * 16];  // per wave: 2 rows x 32 voxels x 16 dwords
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
     int b = blockIdx.x;
@@ -140,11 +196,13 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
     const long vol_off = (long)vol * a.nz * a.ny * a.nx;
     const uint16_t* in = a.in + vol_off * CIN;
 
+    for (int i = threadIdx.x; i < G::kW; i += kCnnBlock) wsh[i] = reinterpret_cast<const uint4*>(a.wq)[i];
     uint4 pre[G::kFill];
-    for (int zin = z0 - 1; zin <= z0 + 1; ++zin) {
-        tile_fetch<CIN>(a, in, zin, y0, x0, pre);
-        tile_store<CIN>(ring[(zin + 3) % 3], pre);
-    }
+    tile_fetch<CIN>(a, in, z0 - 1, y0, x0, pre);
+    tile_store<CIN>(ring[0], pre);
+    tile_fetch<CIN>(a, in, z0, y0, x0, pre);
+    tile_store<CIN>(ring[1], pre);
+    tile_fetch<CIN>(a, in, z0 + 1, y0, x0, pre);
     __syncthreads();
 
     float bias_n = 0.f, scale = 1.f;
@@ -153,65 +211,73 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
         bias_n = a.bias[0];
         if (a.scale != nullptr) scale = *a.scale;
     }
-    // weight fragment of lane (n = m, k half h): wq[(g * kQ + q) * 32 + m][8h .. 8h + 7]
-    const uint4* wq = reinterpret_cast<const uint4*>(a.wq) + m * 2 + h;
 
+    int old = 0;  // slot of input z - 1; the other slot holds input z
     for (int z = z0; z < z1; ++z) {
-        const bool next = z + 1 < z1;
-        if (next) tile_fetch<CIN>(a, in, z + 2, y0, x0, pre);
         v16f acc[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = v16f{};
-#pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-            const uint4* slot = ring[(z + dz + 2) % 3];
-#pragma unroll
-            for (int q = 0; q < G::kQ; ++q) {
-                int xs, j;
-                if constexpr (CIN == 32) {
-                    xs = m + (q >> 1);
-                    j = 2 * (q & 1) + h;
-                } else {
-                    xs = m + (q == 0 ? h : 2);
-                    j = 0;
-                }
-                v8bf A[6];
-#pragma unroll
-                for (int rr = 0; rr < 6; ++rr)
-                    A[rr] = __builtin_bit_cast(v8bf, slot[ring_pos<CIN>(4 * wave + rr, xs, j)]);
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy) {
-                    const v8bf B = __builtin_bit_cast(v8bf, wq[((dz * 3 + dy) * G::kQ + q) * 64]);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[r + dy], B, acc[r], 0, 0, 0);
-                }
-            }
-        }
+        conv_dz<CIN>(ring[old], wsh, 0, wave, m, h, acc);
+        conv_dz<CIN>(ring[old ^ 1], wsh, 1, wave, m, h, acc);
+        __syncthreads();  // every wave is done with input z - 1
+        tile_store<CIN>(ring[old], pre);
+        __syncthreads();
+        if (z + 1 < z1) tile_fetch<CIN>(a, in, z + 2, y0, x0, pre);
+        conv_dz<CIN>(ring[old], wsh, 2, wave, m, h, acc);
+        old ^= 1;
+
         // epilogue: lane holds output channel m for 16 voxels of each of its 4 rows
+        if constexpr (EPI == EPI_FINAL) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int y = y0 + 4 * wave + r;
-            if (y >= a.ny) break;
-            const long row0 = vol_off + ((long)z * a.ny + y) * a.nx + x0;
+            for (int r = 0; r < 4; ++r) {
+                const int y = y0 + 4 * wave + r;
+                if (y >= a.ny || m != 0) continue;
+                const long row0 = vol_off + ((long)z * a.ny + y) * a.nx + x0;
+                float xv[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const long v = row0 + d_row(lane, i);
-                const float val = acc[r][i];
-                if constexpr (EPI == EPI_RELU) {
-                    a.out[v * 32 + m] = f2bf(fmaxf(val + bias_n, 0.f));
-                } else if constexpr (EPI == EPI_FINAL) {
-                    if (m == 0) a.out_f32[v] = a.xin[v] + scale * (val + bias_n);
-                } else {  // EPI_DGRAD: multiply by the ReLU mask of the layer input
-                    const float keep = bf2f(a.relu_src[v * 32 + m]) > 0.f ? 1.f : 0.f;
-                    a.out[v * 32 + m] = f2bf(val * keep);
-                }
+                for (int i = 0; i < 16; ++i) xv[i] = a.xin[row0 + d_row(lane, i)];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) a.out_f32[row0 + d_row(lane, i)] = xv[i] + scale * (acc[r][i] + bias_n);
             }
-        }
-        if (next) {
-            __syncthreads();  // every wave is done with the slot of z - 1
-            tile_store<CIN>(ring[(z + 2) % 3], pre);
-            __syncthreads();
+        } else {
+            uint32_t* st = stage + wave * (2 * 32 * 16);
+            const uint4* st4 = reinterpret_cast<const uint4*>(st);
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+                for (int rp = 0; rp < 2; ++rp)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        float val = acc[2 * pass + rp][i];
+                        if constexpr (EPI == EPI_RELU) val = fmaxf(val + bias_n, 0.f);
+                        // channel m + 1 from the neighbouring lane (quad permutation 1, 0, 3, 2)
+                        const float other = __builtin_bit_cast(
+                            float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, val), 0xB1, 0xF, 0xF, false));
+                        const int vox = d_row(lane, i);
+                        if ((m & 1) == 0)
+                            st[(rp * 32 + (vox ^ (((vox >> 2) & 1) << 1))) * 16 + (m >> 1)] = pack_bf16x2(val, other);
+                    }
+                __syncthreads();
+#pragma unroll
+                for (int it = 0; it < 4; ++it) {
+                    const int e = it * 64 + lane;
+                    const int rp = e >> 7, vox = (e >> 2) & 31, c = e & 3;
+                    const int y = y0 + 4 * wave + 2 * pass + rp;
+                    if (y < a.ny) {
+                        uint4 q = st4[(rp * 32 + (vox ^ (((vox >> 2) & 1) << 1))) * 4 + c];
+                        const long v = vol_off + ((long)z * a.ny + y) * a.nx + x0 + vox;
+                        if constexpr (EPI == EPI_DGRAD) {  // multiply by the ReLU mask of the layer input
+                            const uint4 k = *reinterpret_cast<const uint4*>(a.relu_src + v * 32 + c * 8);
+                            q.x &= relu_keep2(k.x);
+                            q.y &= relu_keep2(k.y);
+                            q.z &= relu_keep2(k.z);
+                            q.w &= relu_keep2(k.w);
+                        }
+                        *reinterpret_cast<uint4*>(a.out + v * 32 + c * 8) = q;
+                    }
+                }
+                __syncthreads();
+            }
         }
     }
 }
@@ -329,18 +395,26 @@ __global__ __launch_bounds__(kCnnBlock) void k_wgrad(WgradArgs a) {
     for (int i = 0; i < 16; ++i) dst[d_row(lane, i) * 32 + ch] = acc[i];
 }
 
-// grad[W + (t * cin + ci) * cout + co] = sum over chunks of part[c][t][co][ci];
-// grad[b + co] = sum over chunks of bias partials.
+// grad[W + (t * cin + ci) * cout + co] = sum over chunks of part[c][t][co][ci]:
+// a block covers 16 consecutive positions p = t * 1024 + co * 32 + ci; thread
+// (p, l) sums chunks l, l + 16, ... in order, then the 16 partial sums are
+// added in order (a fixed summation order, so runs are bitwise repeatable).
 __global__ __launch_bounds__(kCnnBlock) void k_wgrad_reduce(const float* part, int chunks, int cin, int cout,
                                                             float* gw) {
-    const int e = blockIdx.x * kCnnBlock + threadIdx.x;
-    if (e >= 27 * cin * cout) return;
-    const int co = e % cout;
-    const int ci = (e / cout) % cin;
-    const int t = e / (cout * cin);
+    __shared__ double red[16][16];
+    const int pl = threadIdx.x & 15, l = threadIdx.x >> 4;
+    const int p = blockIdx.x * 16 + pl;
     double s = 0.0;
-    for (int c = 0; c < chunks; ++c) s += part[((long)c * 27 + t) * 1024 + co * 32 + ci];
-    gw[e] = (float)s;
+    if (p < 27 * 1024)
+        for (int c = l; c < chunks; c += 16) s += part[(long)c * 27 * 1024 + p];
+    red[l][pl] = s;
+    __syncthreads();
+    if (l == 0 && p < 27 * 1024) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += red[k][pl];
+        const int ci = p & 31, co = (p >> 5) & 31, tap = p >> 10;
+        if (ci < cin && co < cout) gw[(tap * cin + ci) * cout + co] = (float)t;
+    }
 }
 
 // Bias gradient partials: part[block][co] = sum over the block's voxels of g[v][co].
@@ -359,12 +433,20 @@ __global__ __launch_bounds__(kCnnBlock) void k_bias_partial(const uint16_t* g, l
         part[(long)blockIdx.x * 32 + threadIdx.x] = t;
     }
 }
+// Block co: thread l sums partials l, l + 256, ... in order; thread 0 adds
+// the 256 sums in order.
 __global__ __launch_bounds__(kCnnBlock) void k_bias_reduce(const float* part, int nblocks, int cout, float* gb) {
-    const int co = threadIdx.x;
-    if (co >= cout) return;
+    __shared__ double red[kCnnBlock];
+    const int co = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(long)b * 32 + co];
-    gb[co] = (float)s;
+    for (int b = threadIdx.x; b < nblocks; b += kCnnBlock) s += part[(long)b * 32 + co];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kCnnBlock; ++k) t += red[k];
+        if (co < cout) gb[co] = (float)t;
+    }
 }
 
 // Adam with bias correction on the flat parameter vector.
@@ -386,18 +468,19 @@ __global__ void k_prep_bias(const float* b, int cout, float* bias32) {
     if (e < 32) bias32[e] = e < cout ? b[e] : 0.f;
 }
 
-// Weight fragments of the tiled convolution: wq[g = 3 dz + dy][q][n][kk]
-// (bf16) for K fragment q of the input-channel count CINP (8 or 32), from the
-// fp32 W[t][cin][cout].  Forward: the effective weight is W[t][ci][co];
-// backward data (flip): W[26 - t][co][ci] with the channel roles swapped.
-// Entries beyond the real channel counts and the zero half of the last
-// 8-channel fragment are zero.
+// Weight fragments of the tiled convolution: wq[g = 3 dz + dy][q][h][n][8]
+// (bf16) holds k = 8 h .. 8 h + 7 of K fragment q for output channel n, for
+// the input-channel count CINP (8 or 32), from the fp32 W[t][cin][cout].
+// Forward: the effective weight is W[t][ci][co]; backward data (flip):
+// W[26 - t][co][ci] with the channel roles swapped.  Entries beyond the real
+// channel counts and the zero half of the last 8-channel fragment are zero.
 __global__ __launch_bounds__(kCnnBlock) void k_prep_q(const float* W, int cin, int cout, int flip, int cinp,
                                                      uint16_t* wq) {
     const int nq = cinp == 32 ? 6 : 2;
     const int e = blockIdx.x * kCnnBlock + threadIdx.x;
     if (e >= 9 * nq * 32 * 16) return;
-    const int kk = e % 16, n = (e / 16) % 32, q = (e / 512) % nq, g = e / (512 * nq);
+    const int k8 = e % 8, n = (e / 8) % 32, hh = (e / 256) % 2, q = (e / 512) % nq, g = e / (512 * nq);
+    const int kk = 8 * hh + k8;
     const int dz = g / 3, dy = g % 3;
     int dxi, ci;
     bool zero = false;
@@ -405,8 +488,7 @@ __global__ __launch_bounds__(kCnnBlock) void k_prep_q(const float* W, int cin, i
         dxi = q >> 1;
         ci = 16 * (q & 1) + kk;
     } else {
-        const int hh = kk >> 3;
-        ci = kk & 7;
+        ci = k8;
         dxi = q == 0 ? hh : 2;
         zero = q == 1 && hh == 1;
     }
@@ -489,14 +571,14 @@ hipError_t cnn_wgrad(int ca, int cg, const WgradArgs& a, int cin, int cout, floa
     else if (ca == 32 && cg == 8) LAUNCH(32, 8);
     else return hipErrorInvalidValue;
 #undef LAUNCH
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((27 * cin * cout + kCnnBlock - 1) / kCnnBlock), dim3(kCnnBlock), 0, st,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(27 * 1024 / 16), dim3(kCnnBlock), 0, st,
                        a.part, chunks, cin, cout, gw);
     const int nb = grid_for(a.nvox, 8, 2048);
     if (cg == 8)
         hipLaunchKernelGGL(k_bias_partial<8>, dim3(nb), dim3(kCnnBlock), 0, st, a.g, a.nvox, bias_part);
     else
         hipLaunchKernelGGL(k_bias_partial<32>, dim3(nb), dim3(kCnnBlock), 0, st, a.g, a.nvox, bias_part);
-    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(kCnnBlock), 0, st, bias_part, nb, cout, gb);
+    hipLaunchKernelGGL(k_bias_reduce, dim3(cout), dim3(kCnnBlock), 0, st, bias_part, nb, cout, gb);
     return hipGetLastError();
 }
 
