@@ -24,12 +24,12 @@ struct ConvArgs {
 };
 
 struct WgradArgs {
-    long nvox;                     // multiple of 8
-    int nz, ny, nx;
-    long chunk_steps;              // K-steps of 8 voxels per chunk
-    const uint16_t* act;           // bf16 [voxel][CA]
-    const uint16_t* g;             // bf16 [voxel][CG]
-    float* part;                   // fp32 [chunks][27][32][32]
+    int nvol, nz, ny, nx;          // nx a multiple of 32
+    int tiles_x, tiles_y;          // item tiles of 32 x-voxels and 8 rows (set by cnn_wgrad)
+    int zc, zchunks, items;        // range slices per item, chunks per volume, items (set by cnn_wgrad)
+    const uint16_t* act;           // bf16 [voxel][CA]: the layer input
+    const uint16_t* g;             // bf16 [voxel][CG]: the gradient of the layer output
+    float* part;                   // fp32 [2 * grid][28][32][32] partial sums (cnn_wgrad_part_bytes)
 };
 
 hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st);
@@ -40,10 +40,10 @@ int cnn_reduce_blocks(long nvox);
 hipError_t cnn_mean(const float* x, long nvox, double* part, float* mean, hipStream_t st);
 hipError_t cnn_loss(const float* out, const float* target, long nvox, uint16_t* g8, double* part, double* loss,
                     hipStream_t st);
-int cnn_wgrad_chunks(long nvox, long chunk_steps);
-int cnn_bias_blocks(long nvox);
-hipError_t cnn_wgrad(int ca, int cg, const WgradArgs& a, int cin, int cout, float* gw, float* gb, float* bias_part,
-                     hipStream_t st);
+int cnn_wgrad_grid();
+size_t cnn_wgrad_part_bytes();
+// Weight gradient gw[27][cin][cout] and bias gradient gb[cout] of one layer.
+hipError_t cnn_wgrad(int ca, int cg, WgradArgs a, int cin, int cout, float* gw, float* gb, hipStream_t st);
 hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float lr, int step, hipStream_t st);
 // Weight fragments of a layer for the forward (wq, cinp input channels) and
 // backward-data (wqd, coutp input channels; NULL to skip) convolutions and the

@@ -352,100 +352,228 @@ __global__ __launch_bounds__(kCnnBlock) void k_loss_final(const double* part, in
     if (threadIdx.x == 0) *loss = tot[0] / (double)nvox;
 }
 
-// Weight gradient of one layer: D[co][ci] = sum_v g[v][co] act[v + off(t)][ci]
-// for the tap t of each wave, over chunk `blockIdx.x / 7` of the voxels
-// (K-steps of 8 consecutive voxels along x); partials to part[chunk][t][co][ci].
-template <int CA, int CG>
-__global__ __launch_bounds__(kCnnBlock) void k_wgrad(WgradArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int chunk = blockIdx.x / 7;
-    const int t = (blockIdx.x % 7) * 4 + (threadIdx.x >> 6);
-    if (t >= 27) return;  // no barriers in this kernel
-    int dz, dy, dx;
-    tap_offset(t, dz, dy, dx);
-    const long steps = a.nvox / 8;
-    const long s0 = (long)chunk * a.chunk_steps;
-    const long s1 = s0 + a.chunk_steps < steps ? s0 + a.chunk_steps : steps;
-    const int ch = lane & 31;
-    const int kh = (lane >> 5) * 4;
-    v16f acc = {};
-    for (long s = s0; s < s1; ++s) {
-        const long v0 = s * 8 + kh;  // this lane half's 4 voxels: v0 .. v0 + 3 (same x run)
-        const int x0 = (int)(v0 % a.nx);
-        long r = v0 / a.nx;
-        const int y = (int)(r % a.ny);
-        r /= a.ny;
-        const int z = (int)(r % a.nz);
-        const long n = r / a.nz;
-        const int zz = z + dz, yy = y + dy;
-        const bool row_ok = zz >= 0 && zz < a.nz && yy >= 0 && yy < a.ny;
-        const long arow = ((n * a.nz + (row_ok ? zz : 0)) * a.ny + (row_ok ? yy : 0)) * a.nx;
-        v4s av, bv;
+// ---------------------------------------------------------------------------
+// Weight and bias gradients of one layer, tiled implicit GEMM on the 32x32x16
+// bf16 MFMA.  For every tap t: D_t[co][ci] = sum_v g[v][co] act[v + off(t)][ci]
+// (the MFMA's M = co, N = ci, K = 16 voxels along x), and the bias gradient
+// sum_v g[v][co] as an MFMA against ones.
+//
+// A persistent grid walks work items (volume, 8 output rows x 32 x-voxels,
+// chunk of range slices).  Per range slice z the block holds in LDS, channel
+// major ("transposed", x contiguous): g of the 8 x 32 output tile, and act of
+// slices z - 1, z, z + 1 over 10 rows x 48 x (x0 - 8 .. x0 + 39, a one-voxel
+// halo padded to 16-byte alignment) in a ring of three slots.  Global data is
+// channels-last; each fill unit loads 8 voxels x 8 channels and transposes
+// them in registers (byte permutes).  The dx = -1 and +1 operands come from
+// the aligned 8-voxel chunk and one neighbouring dword by byte alignment.
+// Wave (th, kh): taps 14 th .. 14 th + 13 (th = 0 also the bias), output rows
+// 4 kh .. 4 kh + 3.  Each wave writes its sums to part[2 block + kh][28][32][32]
+// (tap 27 = bias); k_wgrad_reduce adds the partial sums in a fixed order.
+// Channel planes are padded to an odd number of 16-byte chunks (61 and 33) so
+// that the 16 lanes of one 128-bit LDS phase hit distinct bank groups.
+constexpr int kWgRows = 8;
+constexpr int kActPlane4 = 61;  // uint4 per channel plane of an act slot (10 x 48 bf16 + 8 pad)
+constexpr int kGPlane4 = 33;    // uint4 per channel plane of the g tile (8 x 32 bf16 + 8 pad)
+
+// 8 x 8 bf16 transpose: in[v][k] = dword k (channels 2k, 2k + 1) of voxel v;
+// out[c][p] = dword p (voxels 2p, 2p + 1) of channel c.
+__device__ __forceinline__ void transpose8(const uint32_t (&in)[8][4], uint32_t (&out)[8][4]) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            av[j] = ch < CG ? (short)a.g[(v0 + j) * CG + ch] : (short)0;
-            const int xx = x0 + j + dx;
-            const bool ok = row_ok && xx >= 0 && xx < a.nx && ch < CA;
-            bv[j] = ok ? (short)a.act[(arow + xx) * CA + ch] : (short)0;
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const uint32_t lo = in[2 * p][k], hi = in[2 * p + 1][k];
+            out[2 * k][p] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+            out[2 * k + 1][p] = __builtin_amdgcn_perm(hi, lo, 0x07060302u);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
-    }
-    float* dst = a.part + ((long)chunk * 27 + t) * 1024;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) dst[d_row(lane, i) * 32 + ch] = acc[i];
 }
 
-// grad[W + (t * cin + ci) * cout + co] = sum over chunks of part[c][t][co][ci]:
-// a block covers 16 consecutive positions p = t * 1024 + co * 32 + ci; thread
-// (p, l) sums chunks l, l + 16, ... in order, then the 16 partial sums are
-// added in order (a fixed summation order, so runs are bitwise repeatable).
+// Loads 8 voxels (x, x + 1, .., x + 7 of one row) x 8 channels (group cg) of
+// a channels-last tensor with C stored channels; zeros where `ok` is false.
+template <int C>
+__device__ __forceinline__ void load8x8(const uint16_t* base, long vox0, int cg, bool ok, uint32_t (&v)[8][4]) {
+    ok = ok && cg * 8 < C;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const uint4 q = *reinterpret_cast<const uint4*>(base + (ok ? (vox0 + e) * C + cg * 8 : 0));
+        v[e][0] = ok ? q.x : 0u;
+        v[e][1] = ok ? q.y : 0u;
+        v[e][2] = ok ? q.z : 0u;
+        v[e][3] = ok ? q.w : 0u;
+    }
+}
+
+template <int TH, int CA, int CG>
+__device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 * kActPlane4], uint4* gt, int wave) {
+    constexpr int T0 = 14 * TH;
+    constexpr int NT = TH == 0 ? 14 : 13;
+    const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5, kh = wave >> 1;
+    const int u = threadIdx.x;
+    v16f acc[NT];
+    v16f accb = {};
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = v16f{};
+    v8bf ones;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+
+    // fill-unit coordinates: act units 0..239 on threads 0..239, g units on threads 128..255
+    const int a_xc = u % 6, a_ys = (u / 6) % 10, a_cg = u / 60;
+    const int gu = u - 128, g_xc = gu & 3, g_r = (gu >> 2) & 7, g_cg = gu >> 5;
+    uint32_t pa[8][4], pg[8][4], tr[8][4];
+
+    for (int item = blockIdx.x; item < a.items; item += gridDim.x) {
+        int b = item;
+        const int xt = b % a.tiles_x;
+        b /= a.tiles_x;
+        const int yt = b % a.tiles_y;
+        b /= a.tiles_y;
+        const int zc = b % a.zchunks;
+        const int vol = b / a.zchunks;
+        const int x0 = xt * 32, y0 = yt * kWgRows, z0 = zc * a.zc;
+        const int z1 = z0 + a.zc < a.nz ? z0 + a.zc : a.nz;
+        const long vol_off = (long)vol * a.nz * a.ny * a.nx;
+
+        auto fetch_act = [&](int zin) {
+            const int y = y0 - 1 + a_ys, x = x0 - 8 + 8 * a_xc;
+            const bool ok = u < 240 && zin >= 0 && zin < a.nz && y >= 0 && y < a.ny && x >= 0 && x < a.nx;
+            load8x8<CA>(a.act, ok ? vol_off + ((long)zin * a.ny + y) * a.nx + x : 0, a_cg, ok, pa);
+        };
+        auto fetch_g = [&](int zz) {
+            const int y = y0 + g_r, x = x0 + 8 * g_xc;
+            const bool ok = gu >= 0 && zz < a.nz && y < a.ny;
+            load8x8<CG>(a.g, ok ? vol_off + ((long)zz * a.ny + y) * a.nx + x : 0, g_cg, ok, pg);
+        };
+        auto store_act = [&](int zin) {
+            if (u < 240) {
+                transpose8(pa, tr);
+                uint4* slot = act[(zin + 3) % 3];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    slot[(a_cg * 8 + k) * kActPlane4 + a_ys * 6 + a_xc] = make_uint4(tr[k][0], tr[k][1], tr[k][2], tr[k][3]);
+            }
+        };
+        auto store_g = [&]() {
+            if (gu >= 0) {
+                transpose8(pg, tr);
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    gt[(g_cg * 8 + k) * kGPlane4 + g_r * 4 + g_xc] = make_uint4(tr[k][0], tr[k][1], tr[k][2], tr[k][3]);
+            }
+        };
+
+        __syncthreads();  // the previous item's reads are done
+        fetch_act(z0 - 1);
+        store_act(z0 - 1);
+        fetch_act(z0);
+        store_act(z0);
+        fetch_act(z0 + 1);
+        store_act(z0 + 1);
+        fetch_g(z0);
+        store_g();
+        __syncthreads();
+
+        for (int z = z0; z < z1; ++z) {
+            const bool next = z + 1 < z1;
+            if (next) {
+                fetch_act(z + 2);
+                fetch_g(z + 1);
+            }
+            const uint32_t* act32[3];
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz) act32[dz] = reinterpret_cast<const uint32_t*>(act[(z + dz + 2) % 3]);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int r = 4 * kh + rr;
+#pragma unroll
+                for (int xh = 0; xh < 2; ++xh) {
+                    const v8bf A = __builtin_bit_cast(v8bf, gt[m * kGPlane4 + r * 4 + 2 * xh + h]);
+                    if constexpr (TH == 0) accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, ones, accb, 0, 0, 0);
+#pragma unroll
+                    for (int pair = 0; pair < 9; ++pair) {
+                        const int t_lo = pair * 3;
+                        if (t_lo + 2 < T0 || t_lo >= T0 + NT) continue;  // no tap of this wave
+                        const int dz = pair / 3, dy = pair % 3;
+                        const uint32_t* pl = act32[dz] + m * (kActPlane4 * 4) + (r + dy) * 24;
+                        const uint4 c4 = *reinterpret_cast<const uint4*>(pl + 4 + 8 * xh + 4 * h);
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx) {
+                            const int t = t_lo + dx;
+                            if (t < T0 || t >= T0 + NT) continue;
+                            uint4 bq;
+                            if (dx == 1) {
+                                bq = c4;
+                            } else if (dx == 0) {  // voxels x - 1 .. x + 6
+                                const uint32_t dlo = pl[3 + 8 * xh + 4 * h];
+                                bq.x = __builtin_amdgcn_alignbyte(c4.x, dlo, 2);
+                                bq.y = __builtin_amdgcn_alignbyte(c4.y, c4.x, 2);
+                                bq.z = __builtin_amdgcn_alignbyte(c4.z, c4.y, 2);
+                                bq.w = __builtin_amdgcn_alignbyte(c4.w, c4.z, 2);
+                            } else {  // voxels x + 1 .. x + 8
+                                const uint32_t dhi = pl[8 + 8 * xh + 4 * h];
+                                bq.x = __builtin_amdgcn_alignbyte(c4.y, c4.x, 2);
+                                bq.y = __builtin_amdgcn_alignbyte(c4.z, c4.y, 2);
+                                bq.z = __builtin_amdgcn_alignbyte(c4.w, c4.z, 2);
+                                bq.w = __builtin_amdgcn_alignbyte(dhi, c4.w, 2);
+                            }
+                            acc[t - T0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, __builtin_bit_cast(v8bf, bq),
+                                                                                   acc[t - T0], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            if (next) {
+                __syncthreads();  // every wave is done with act slice z - 1 and g slice z
+                store_act(z + 2);
+                store_g();
+                __syncthreads();
+            }
+        }
+    }
+    // partial sums: D[co][ci] with co = d_row(lane, i), ci = m
+    float* dst = a.part + (long)(2 * blockIdx.x + kh) * 28 * 1024;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) dst[(T0 + t) * 1024 + d_row(lane, i) * 32 + m] = acc[t][i];
+    if constexpr (TH == 0) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) dst[27 * 1024 + d_row(lane, i) * 32 + m] = accb[i];
+    }
+}
+
+template <int CA, int CG>
+__global__ __launch_bounds__(kCnnBlock, 1) void k_wgrad(WgradArgs a) {
+    __shared__ uint4 act[3][32 * kActPlane4];
+    __shared__ uint4 gt[32 * kGPlane4];
+    const int wave = threadIdx.x >> 6;
+    if (wave & 1) wgrad_block<1, CA, CG>(a, act, gt, wave);
+    else wgrad_block<0, CA, CG>(a, act, gt, wave);
+}
+
+// gw[(t * cin + ci) * cout + co] = sum over chunks of part[c][t][co][ci] and
+// gb[co] = sum over chunks of part[c][27][co][0]: a block covers 16
+// consecutive positions p = t * 1024 + co * 32 + ci; thread (p, l) sums
+// chunks l, l + 16, ... in order, then the 16 partial sums are added in order
+// (a fixed summation order, so runs are bitwise repeatable).
 __global__ __launch_bounds__(kCnnBlock) void k_wgrad_reduce(const float* part, int chunks, int cin, int cout,
-                                                            float* gw) {
+                                                            float* gw, float* gb) {
     __shared__ double red[16][16];
     const int pl = threadIdx.x & 15, l = threadIdx.x >> 4;
     const int p = blockIdx.x * 16 + pl;
     double s = 0.0;
-    if (p < 27 * 1024)
-        for (int c = l; c < chunks; c += 16) s += part[(long)c * 27 * 1024 + p];
+    for (int c = l; c < chunks; c += 16) s += part[(long)c * 28 * 1024 + p];
     red[l][pl] = s;
     __syncthreads();
-    if (l == 0 && p < 27 * 1024) {
+    if (l == 0) {
         double t = 0.0;
         for (int k = 0; k < 16; ++k) t += red[k][pl];
         const int ci = p & 31, co = (p >> 5) & 31, tap = p >> 10;
-        if (ci < cin && co < cout) gw[(tap * cin + ci) * cout + co] = (float)t;
-    }
-}
-
-// Bias gradient partials: part[block][co] = sum over the block's voxels of g[v][co].
-template <int CG>
-__global__ __launch_bounds__(kCnnBlock) void k_bias_partial(const uint16_t* g, long nvox, float* part) {
-    __shared__ float red[kCnnBlock];
-    const int co = threadIdx.x % 32, lane_v = threadIdx.x / 32;
-    float s = 0.f;
-    if (co < CG)
-        for (long v = (long)blockIdx.x * 8 + lane_v; v < nvox; v += (long)gridDim.x * 8) s += bf2f(g[v * CG + co]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < 32) {
-        float t = 0.f;
-        for (int k = 0; k < 8; ++k) t += red[k * 32 + threadIdx.x];
-        part[(long)blockIdx.x * 32 + threadIdx.x] = t;
-    }
-}
-// Block co: thread l sums partials l, l + 256, ... in order; thread 0 adds
-// the 256 sums in order.
-__global__ __launch_bounds__(kCnnBlock) void k_bias_reduce(const float* part, int nblocks, int cout, float* gb) {
-    __shared__ double red[kCnnBlock];
-    const int co = blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kCnnBlock) s += part[(long)b * 32 + co];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < kCnnBlock; ++k) t += red[k];
-        if (co < cout) gb[co] = (float)t;
+        if (tap < 27) {
+            if (ci < cin && co < cout) gw[(tap * cin + ci) * cout + co] = (float)t;
+        } else if (ci == 0 && co < cout) {
+            gb[co] = (float)t;
+        }
     }
 }
 
@@ -559,30 +687,41 @@ hipError_t cnn_loss(const float* out, const float* target, long nvox, uint16_t* 
     return hipGetLastError();
 }
 
-int cnn_wgrad_chunks(long nvox, long chunk_steps) { return (int)((nvox / 8 + chunk_steps - 1) / chunk_steps); }
+int cnn_wgrad_grid() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+        cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    }
+    return cus;
+}
 
-hipError_t cnn_wgrad(int ca, int cg, const WgradArgs& a, int cin, int cout, float* gw, float* gb, float* bias_part,
-                     hipStream_t st) {
-    const int chunks = cnn_wgrad_chunks(a.nvox, a.chunk_steps);
-    const dim3 grid((unsigned)chunks * 7);
-#define LAUNCH(A, G) hipLaunchKernelGGL((k_wgrad<A, G>), grid, dim3(kCnnBlock), 0, st, a)
+size_t cnn_wgrad_part_bytes() { return (size_t)2 * cnn_wgrad_grid() * 28 * 1024 * sizeof(float); }
+
+hipError_t cnn_wgrad(int ca, int cg, WgradArgs a, int cin, int cout, float* gw, float* gb, hipStream_t st) {
+    a.tiles_x = a.nx / 32;
+    a.tiles_y = (a.ny + kWgRows - 1) / kWgRows;
+    const long tiles = (long)a.nvol * a.tiles_x * a.tiles_y;
+    const int grid_max = cnn_wgrad_grid();
+    a.zc = 16;
+    while (a.zc > 2 && tiles * ((a.nz + a.zc - 1) / a.zc) < 2L * grid_max) a.zc /= 2;
+    a.zchunks = (a.nz + a.zc - 1) / a.zc;
+    const long items = tiles * a.zchunks;
+    if (items >= (1L << 31)) return hipErrorInvalidValue;
+    a.items = (int)items;
+    const int grid = (int)(items < grid_max ? items : grid_max);
+#define LAUNCH(A, G) hipLaunchKernelGGL((k_wgrad<A, G>), dim3(grid), dim3(kCnnBlock), 0, st, a)
     if (ca == 8 && cg == 32) LAUNCH(8, 32);
     else if (ca == 32 && cg == 32) LAUNCH(32, 32);
     else if (ca == 32 && cg == 8) LAUNCH(32, 8);
     else return hipErrorInvalidValue;
 #undef LAUNCH
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(27 * 1024 / 16), dim3(kCnnBlock), 0, st,
-                       a.part, chunks, cin, cout, gw);
-    const int nb = grid_for(a.nvox, 8, 2048);
-    if (cg == 8)
-        hipLaunchKernelGGL(k_bias_partial<8>, dim3(nb), dim3(kCnnBlock), 0, st, a.g, a.nvox, bias_part);
-    else
-        hipLaunchKernelGGL(k_bias_partial<32>, dim3(nb), dim3(kCnnBlock), 0, st, a.g, a.nvox, bias_part);
-    hipLaunchKernelGGL(k_bias_reduce, dim3(cout), dim3(kCnnBlock), 0, st, bias_part, nb, cout, gb);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(28 * 1024 / 16), dim3(kCnnBlock), 0, st, a.part, 2 * grid, cin, cout, gw,
+                       gb);
     return hipGetLastError();
 }
-
-int cnn_bias_blocks(long nvox) { return grid_for(nvox, 8, 2048); }
 
 hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float lr, int step, hipStream_t st) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;

@@ -24,7 +24,6 @@ using clampk::WgradArgs;
 
 constexpr int kLayers = 8;
 constexpr int kWidth = 32;
-constexpr long kChunkSteps = 512;  // weight-gradient chunk: 4096 voxels
 
 int cin_of(int l) { return l == 0 ? 1 : kWidth; }
 int cout_of(int l) { return l == kLayers - 1 ? 1 : kWidth; }
@@ -55,7 +54,7 @@ clamp_status hip_check(hipError_t e, const char* what) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t x8, act[kLayers], out, g8, ga, gb, mean, part, wpart, bpart, total;
+    size_t x8, act[kLayers], out, g8, ga, gb, mean, part, wpart, total;
 };
 
 Layout layout(long nvox, bool train) {
@@ -73,8 +72,7 @@ Layout layout(long nvox, bool train) {
         L.g8 = take(nvox * 16);
         L.ga = take(nvox * 64);
         L.gb = take(nvox * 64);
-        L.wpart = take((size_t)clampk::cnn_wgrad_chunks(nvox, kChunkSteps) * 27 * 1024 * 4);
-        L.bpart = take((size_t)clampk::cnn_bias_blocks(nvox) * 32 * 4);
+        L.wpart = take(clampk::cnn_wgrad_part_bytes());
     } else {
         L.act[1] = take(nvox * 64);
         L.act[2] = take(nvox * 64);
@@ -285,16 +283,14 @@ clamp_status clamp_cnn_grad(clamp_cnn* cnn, const float* x, const float* target,
     uint16_t* gbuf[2] = {at<uint16_t>(workspace, L.ga), at<uint16_t>(workspace, L.gb)};
     for (int l = kLayers - 1; l >= 0 && e == hipSuccess; --l) {
         WgradArgs wa{};
-        wa.nvox = nvox;
+        wa.nvol = nvol;
         wa.nz = nz;
         wa.ny = ny;
         wa.nx = nx;
-        wa.chunk_steps = kChunkSteps;
         wa.act = acts[l];
         wa.g = gl;
         wa.part = at<float>(workspace, L.wpart);
-        e = clampk::cnn_wgrad(cinp_of(l), coutp_of(l), wa, cin_of(l), cout_of(l), g + w_offset(l), g + b_offset(l),
-                              at<float>(workspace, L.bpart), s);
+        e = clampk::cnn_wgrad(cinp_of(l), coutp_of(l), wa, cin_of(l), cout_of(l), g + w_offset(l), g + b_offset(l), s);
         if (e == hipSuccess && l > 0) {
             ConvArgs a = conv_args(nvol, nz, ny, nx);
             a.in = gl;
