@@ -13,7 +13,8 @@ Pinned against closed forms, brute force and invariants (tests/test_oracle_*):
 operator (brute-force DFT, Parseval, adjoint, projector), gradient (finite
 differences), step size (numerical line search, exact decrement), aperture
 ablation (one-step closed form), r-update (exact-prox cubic, sigma^2 -> inf
-limit, monotone on downward moves), Mann iteration (quadratic-agent consensus
+limit, monotone on downward moves), exact surrogate prox (global minimum on a
+dense grid, stationarity, sigma^2 limits), Mann iteration (quadratic-agent consensus
 optimum), Gaussian prior (dense circular convolution).  The full trajectory of
 Algorithm 2 on a synthetic scene has no printed value in the paper: parity
 unpinned beyond those invariants and the vanishing consensus error.
@@ -24,7 +25,7 @@ from .operator import (  # noqa: F401
 )
 from .agent import (  # noqa: F401
     noise_floor_weight, h_objective, neg_grad_h, exact_step, cov_diag,
-    qs_prox, forward_agent, beta_schedule,
+    qs_prox, forward_agent, beta_schedule, exact_prox, surrogate_prox_objective,
 )
 from .prior import gaussian_taps, gaussian_smooth  # noqa: F401
 from .mace import (  # noqa: F401

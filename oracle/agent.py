@@ -94,10 +94,51 @@ def qs_prox(r_anchor, s, v, sigma2, beta):
     return np.clip(r_new, lo, hi)
 
 
-def forward_agent(mu, y, r_anchor, v, mask, sigma_w2, sigma2, alpha, beta):
+def surrogate_prox_objective(r, s, v, sigma2):
+    """phi_j(r) = log r + s_j / r + (r - v_j)^2 / (2 sigma^2): the voxel term of
+    the EM surrogate plus the proximal term (eq. surrogate-prox)."""
+    return np.log(r) + s / r + (r - v) ** 2 / (2.0 * sigma2)
+
+
+def exact_prox(s, v, sigma2):
+    """Exact proximal map of the EM surrogate (eq. surrogate-prox), voxel by
+    voxel: argmin over r > 0 of phi(r) = log r + s/r + (r - v)^2/(2 sigma^2).
+
+    phi'(r) = 1/r - s/r^2 + (r - v)/sigma^2; multiplied by sigma^2 r^2 it is
+    the cubic r^3 - v r^2 + sigma^2 r - sigma^2 s, whose value at 0 is
+    -sigma^2 s < 0, so it has a positive root.  The roots are the eigenvalues
+    of the cubic's companion matrix; phi is not convex for r > 2 s, so when
+    there are several positive roots the one with the smallest phi is kept."""
+    s, v = np.broadcast_arrays(np.asarray(s, dtype=np.float64), np.asarray(v, dtype=np.float64))
+    shape = s.shape
+    s = s.ravel()
+    v = v.ravel()
+    comp = np.zeros((s.size, 3, 3))
+    comp[:, 0, 0] = v                  # companion matrix of r^3 + c2 r^2 + c1 r + c0
+    comp[:, 0, 1] = -sigma2            # with c2 = -v, c1 = sigma^2, c0 = -sigma^2 s
+    comp[:, 0, 2] = sigma2 * s
+    comp[:, 1, 0] = 1.0
+    comp[:, 2, 1] = 1.0
+    roots = np.linalg.eigvals(comp)
+    scale = np.maximum(np.abs(roots), 1e-300)
+    real = (np.abs(roots.imag) <= 1e-7 * scale) & (roots.real > 0.0)
+    cand = np.where(real, roots.real, np.nan)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        phi = surrogate_prox_objective(cand, s[:, None], v[:, None], sigma2)
+    phi = np.where(real, phi, np.inf)
+    best = np.argmin(phi, axis=1)
+    out = cand[np.arange(s.size), best]
+    return out.reshape(shape)
+
+
+def forward_agent(mu, y, r_anchor, v, mask, sigma_w2, sigma2, alpha, beta, r_update="quadratic"):
     """One application of the CLAMP forward agent for one look (Alg. 2, the
     body of the per-look loop): covariance diagonal, one exact steepest-descent
     step on mu, and the surrogate proximal update of r at v.
+
+    r_update selects the r-update: "quadratic" is the quadratic surrogate of
+    App. A (the paper's choice), "exact" the exact proximal map of the EM
+    surrogate (eq. surrogate-prox, a cubic per voxel).
 
     Returns (mu_new, r_new, info) with info holding gamma, ||d||^2, ||A d||^2,
     sum omega |d|^2 and h before and after the mu step."""
@@ -108,7 +149,10 @@ def forward_agent(mu, y, r_anchor, v, mask, sigma_w2, sigma2, alpha, beta):
     mu_new = mu + gamma * d
     h1 = h_objective(mu_new, y, r_anchor, mask, sigma_w2, alpha)
     s = c + np.abs(mu_new) ** 2
-    r_new = qs_prox(r_anchor, s, v, sigma2, beta)
+    if r_update == "exact":
+        r_new = exact_prox(s, v, sigma2)
+    else:
+        r_new = qs_prox(r_anchor, s, v, sigma2, beta)
     info = {"gamma": gamma, "dd": dd, "ad": ad, "wd": wd, "h0": h0, "h1": h1,
             "d": d}
     return mu_new, r_new, info

@@ -48,9 +48,10 @@ def clamp_init(y, mask, looks_with_prior=True, mu_scale=1.0):
 
 
 def clamp_iteration(state, y, mask, sigma_w2, sigma2, rho=0.5, prior=None,
-                    beta=None):
+                    beta=None, r_update="quadratic"):
     """One pass of the Alg. 2 loop body.  `prior` is a callable H(w_{L+1}) or
-    None for forward-only runs.  Returns a dict of diagnostics."""
+    None for forward-only runs; `r_update` is "quadratic" (App. A) or "exact"
+    (eq. surrogate-prox).  Returns a dict of diagnostics."""
     y = np.asarray(y, dtype=np.complex128)
     L = y.shape[0]
     alpha = aperture_fraction(mask)
@@ -62,7 +63,7 @@ def clamp_iteration(state, y, mask, sigma_w2, sigma2, rho=0.5, prior=None,
     mu_new = state.mu.copy()
     for l in range(L):
         mu_l, r_l, info = forward_agent(state.mu[l], y[l], state.r[l], state.w[l],
-                                        mask, sigma_w2, sigma2, alpha, beta)
+                                        mask, sigma_w2, sigma2, alpha, beta, r_update)
         mu_new[l] = mu_l
         r_new[l] = r_l
         infos.append(info)
@@ -84,7 +85,7 @@ def clamp_iteration(state, y, mask, sigma_w2, sigma2, rho=0.5, prior=None,
 
 
 def clamp_run(y, radius, sigma_w2, sigma2, iters, rho=0.5, with_prior=True,
-              mu_scale=1.0, prior_sigma=1.0, mask=None):
+              mu_scale=1.0, prior_sigma=1.0, mask=None, r_update="quadratic"):
     """Alg. 2 for `iters` iterations; returns (state, list of diagnostics)."""
     y = np.asarray(y)
     if mask is None:
@@ -93,5 +94,5 @@ def clamp_run(y, radius, sigma_w2, sigma2, iters, rho=0.5, with_prior=True,
     prior = (lambda x: gaussian_smooth(x, prior_sigma)) if with_prior else None
     hist = []
     for _ in range(iters):
-        hist.append(clamp_iteration(state, y, mask, sigma_w2, sigma2, rho, prior))
+        hist.append(clamp_iteration(state, y, mask, sigma_w2, sigma2, rho, prior, r_update=r_update))
     return state, hist

@@ -170,3 +170,82 @@ def test_qs_prox_tie_returns_anchor():
     # choose v so that rho'(r') = 0 exactly
     v = rp + sigma2 * (1 / rp - s / rp ** 2)
     assert np.isclose(oracle.qs_prox(np.array([rp]), np.array([s]), np.array([v]), sigma2, 2.0)[0], rp)
+
+
+# ---------------------------------------------------------------------------
+# Exact proximal map of the EM surrogate (eq. surrogate-prox)
+
+def _grid_minimum(s, v, sigma2):
+    """Global minimum of phi over r > 0 by a dense log grid refined with a
+    bounded scalar minimisation around the best grid point (brute force)."""
+    from scipy.optimize import minimize_scalar
+    grid = np.geomspace(1e-8, 1e3, 200001)
+    phi = oracle.surrogate_prox_objective(grid, s, v, sigma2)
+    k = int(np.argmin(phi))
+    lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, grid.size - 1)]
+    res = minimize_scalar(lambda r: oracle.surrogate_prox_objective(r, s, v, sigma2), bounds=(lo, hi),
+                          method="bounded", options={"xatol": 1e-14 * hi})
+    return res.x
+
+
+def test_exact_prox_is_the_global_minimum(rng):
+    for _ in range(60):
+        s = float(rng.uniform(0.01, 2.0))
+        v = float(rng.uniform(0.01, 3.0))
+        sigma2 = float(10 ** rng.uniform(-3, 0.5))
+        r = float(oracle.exact_prox(s, v, sigma2))
+        rb = _grid_minimum(s, v, sigma2)
+        phi = oracle.surrogate_prox_objective
+        assert phi(r, s, v, sigma2) <= phi(rb, s, v, sigma2) + 1e-12 * max(1.0, abs(phi(rb, s, v, sigma2)))
+        assert abs(r - rb) <= 1e-6 * max(r, rb) + 1e-12
+
+
+def test_exact_prox_is_stationary_and_vectorised(rng):
+    s = rng.uniform(0.01, 2.0, (7, 9))
+    v = rng.uniform(0.01, 3.0, (7, 9))
+    sigma2 = 0.05
+    r = oracle.exact_prox(s, v, sigma2)
+    assert r.shape == s.shape and np.all(r > 0)
+    dphi = 1.0 / r - s / r ** 2 + (r - v) / sigma2
+    assert np.max(np.abs(dphi) * r ** 2 * sigma2) <= 1e-10
+    for i in (0, 3, 6):
+        assert r[i, 2] == oracle.exact_prox(s[i, 2], v[i, 2], sigma2)
+
+
+def test_exact_prox_limits():
+    s = np.array([0.3, 1.2, 0.05])
+    v = np.array([0.7, 0.1, 2.0])
+    # a vanishing proximal term leaves the EM M-step r = s
+    np.testing.assert_allclose(oracle.exact_prox(s, v, 1e9), s, rtol=1e-6)
+    # a dominant proximal term keeps r at v, to first order in sigma^2:
+    # r = v - sigma^2 (1/v - s/v^2) + O(sigma^4)
+    sig = 1e-9
+    np.testing.assert_allclose(oracle.exact_prox(s, v, sig), v - sig * (1.0 / v - s / v ** 2), rtol=1e-10)
+
+
+def test_exact_prox_picks_the_lower_of_two_minima():
+    # phi is not convex for r > 2 s: a small s with v far above it gives two
+    # local minima, one near s and one near v
+    s, v, sigma2 = 0.01, 1.0, 0.1
+    r = float(oracle.exact_prox(s, v, sigma2))
+    roots = np.roots([1.0, -v, sigma2, -sigma2 * s])
+    pos = np.sort(roots[np.abs(roots.imag) < 1e-12].real)
+    pos = pos[pos > 0]
+    assert pos.size == 3  # two minima and the maximum between them
+    phi = oracle.surrogate_prox_objective
+    best = min(pos[[0, 2]], key=lambda x: phi(x, s, v, sigma2))
+    assert abs(r - best) <= 1e-9 * best
+
+
+def test_forward_agent_exact_r_update_uses_the_same_mu_step(rng):
+    mask = oracle.pupil_mask(8, 8, 2.5)
+    alpha = oracle.aperture_fraction(mask)
+    y = rng.standard_normal((2, 8, 8)) + 1j * rng.standard_normal((2, 8, 8))
+    mu = oracle.apply_AH(y, mask)
+    rp = rng.uniform(0.2, 1.0, (2, 8, 8))
+    w = rng.uniform(0.2, 1.0, (2, 8, 8))
+    m_q, r_q, _ = oracle.forward_agent(mu, y, rp, w, mask, 0.1, 0.05, alpha, 2.0)
+    m_e, r_e, info = oracle.forward_agent(mu, y, rp, w, mask, 0.1, 0.05, alpha, 2.0, r_update="exact")
+    np.testing.assert_array_equal(m_q, m_e)
+    s = oracle.cov_diag(rp, 0.1, alpha) + np.abs(m_e) ** 2
+    np.testing.assert_allclose(r_e, oracle.exact_prox(s, w, 0.05))
