@@ -449,6 +449,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="full")
     ap.add_argument("--sigma2", type=float, default=1e-3)
+    ap.add_argument("--r-update", default="quadratic", choices=("quadratic", "exact"),
+                    help="forward-agent r-update: the quadratic surrogate (App. A) or the exact surrogate prox")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-cap", type=float, default=2.5e9,
                     help="largest total voxel-looks of the uneven batch draw (--workload batch)")
@@ -490,7 +492,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     g = G.ClampGPU(spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, args.sigma2, with_prior=True,
-                   device=dev)
+                   device=dev, r_update=args.r_update)
     yt = torch.from_numpy(y).to(dev)
     g.init(yt)
     if args.copy_probe > 0:
@@ -538,7 +540,8 @@ def main():
     dom_avg_ms = stages[dom][0] / stages[dom][1]
     achieved = sb[dom] / (dom_avg_ms * 1e-3) / 1e9
     traffic = None
-    rec = counter_traffic("clamp_iteration_256x256x64_L16", "fwd") if args.workload == "full" else None
+    rec = (counter_traffic("clamp_iteration_256x256x64_L16", "fwd")
+           if args.workload == "full" and args.r_update == "quadratic" else None)
     if rec is not None and dom in rec["stages"]:
         traffic = round(rec["stages"][dom]["read_bytes"] + rec["stages"][dom]["write_bytes"])
     agent_stage_names = ("col_inv", "row_grad", "col_fwd", "gamma", "row_update", "resid_update", "diag_after")
@@ -562,7 +565,7 @@ def main():
                                "%d looks, pupil radius %g, SNR %g dB" % (spec.nx, spec.ny, spec.nz, spec.looks,
                                                                          spec.radius, spec.snr_db),
                    "nx": spec.nx, "ny": spec.ny, "nz": spec.nz, "looks": spec.looks, "pupil_radius": spec.radius,
-                   "sigma2": args.sigma2, "parallelism": "single GPU"},
+                   "sigma2": args.sigma2, "r_update": args.r_update, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "iters_per_s": args.steps / elapsed,

@@ -97,7 +97,17 @@ typedef struct {
     float mu_init_scale;  /* s_mu: mu_l starts at s_mu A^H y_l (> 0)         */
     const float* upsilon; /* HOST [n_agents] agent weights, summing to 1     */
     int32_t n_agents;     /* L (forward agents only) or L + 1 (with prior)   */
+    int32_t r_update;     /* CLAMP_R_QUADRATIC or CLAMP_R_EXACT               */
 } clamp_params;
+
+/* r-update of the forward agent.  CLAMP_R_QUADRATIC: the quadratic surrogate
+ * of App. A (r' anchored, clipped to [r', xi], uses beta).  CLAMP_R_EXACT: the
+ * exact proximal map of the EM surrogate (eq. surrogate-prox, Sec. III-B),
+ * argmin_{r>0} log r + s/r + (r - v)^2 / (2 sigma^2) per voxel: the positive
+ * root of r^3 - v r^2 + sigma^2 r - sigma^2 s with the smallest objective,
+ * solved in float64 (beta unused). */
+#define CLAMP_R_QUADRATIC 0
+#define CLAMP_R_EXACT 1
 
 /* Per-look state of the forward agents (device memory, caller-owned).
  *   mu    complex64 [L][n]   posterior means mu_l (eq. mu2).
@@ -160,7 +170,8 @@ clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene,
  *   d = A^H resid / sigma_w^2 - omega mu, omega = 1/(r' + sigma_w^2/alpha);
  *   gamma = ||d||^2 / (||A d||^2 / sigma_w^2 + sum omega |d|^2) (0 if d = 0);
  *   mu += gamma d;  resid -= gamma D(a) F d;
- *   r[l] = quadratic-surrogate prox at v = w[l] with s = c + |mu|^2, beta.
+ *   r[l] = surrogate prox at v = w[l] with s = c + |mu|^2 (params->r_update:
+ *   the quadratic surrogate of App. A with beta, or the exact prox).
  * w: float32 [L][n] (the forward agents' slices of the Mann state).
  * diag: device double [L][8] = {gamma, ||d||^2, ||A d||^2, sum omega|d|^2,
  *   ||resid||^2 before, sum omega|mu|^2 before, ||resid||^2 after,
@@ -204,7 +215,8 @@ typedef struct clamp_batch clamp_batch;
 /* One scene of a batch (device pointers, caller-owned; the same arrays the
  * single-scene calls take).  params.beta is ignored (see above). */
 typedef struct {
-    clamp_params params;    /* n_agents = L or L + 1, at most 40 in a batch   */
+    clamp_params params;    /* n_agents = L or L + 1, at most 40 in a batch;  */
+                            /* r_update CLAMP_R_QUADRATIC (else EUNSUPPORTED) */
     clamp_fwd_state state;  /* mu, resid, r (r: float32 [n_agents][n])        */
     float* w;               /* float32 [n_agents][n]                          */
     float* wbar;            /* float32 [n]                                    */

@@ -53,7 +53,13 @@ class clamp_scene(ctypes.Structure):
 class clamp_params(ctypes.Structure):
     _fields_ = [("sigma_w2", ctypes.c_float), ("sigma2", ctypes.c_float), ("rho", ctypes.c_float),
                 ("beta", ctypes.c_float), ("mu_init_scale", ctypes.c_float),
-                ("upsilon", ctypes.POINTER(ctypes.c_float)), ("n_agents", ctypes.c_int32)]
+                ("upsilon", ctypes.POINTER(ctypes.c_float)), ("n_agents", ctypes.c_int32),
+                ("r_update", ctypes.c_int32)]
+
+
+CLAMP_R_QUADRATIC = 0
+CLAMP_R_EXACT = 1
+R_UPDATES = {"quadratic": CLAMP_R_QUADRATIC, "exact": CLAMP_R_EXACT}
 
 
 class clamp_fwd_state(ctypes.Structure):
@@ -226,10 +232,12 @@ def clamp_aperture_op(plan, scene, direction, x, out, nbatch, workspace, stream=
                                                    "workspace"), _stream(stream)))
 
 
-def make_params(sigma_w2, sigma2, rho, beta, mu_init_scale, upsilon):
+def make_params(sigma_w2, sigma2, rho, beta, mu_init_scale, upsilon, r_update="quadratic"):
+    """clamp_params; r_update is "quadratic" (App. A) or "exact" (the exact surrogate prox)."""
     ups = (ctypes.c_float * len(upsilon))(*[float(u) for u in upsilon])
+    code = R_UPDATES[r_update] if isinstance(r_update, str) else int(r_update)
     p = clamp_params(float(sigma_w2), float(sigma2), float(rho), float(beta), float(mu_init_scale),
-                     ctypes.cast(ups, ctypes.POINTER(ctypes.c_float)), len(upsilon))
+                     ctypes.cast(ups, ctypes.POINTER(ctypes.c_float)), len(upsilon), code)
     p._keep = ups
     return p
 

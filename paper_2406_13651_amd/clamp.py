@@ -32,7 +32,7 @@ class ClampGPU:
     """State and loop of one CLAMP reconstruction on the current GPU."""
 
     def __init__(self, nx, ny, nz, looks, radius, sigma_w2, sigma2, with_prior=True, rho=0.5,
-                 mu_scale=1.0, prior_sigma=1.0, mask=None, device="cuda"):
+                 mu_scale=1.0, prior_sigma=1.0, mask=None, device="cuda", r_update="quadratic"):
         self.scene = C.Scene(nx, ny, nz, looks, radius, mask)
         self.plan = C.clamp_plan_create([self.scene])
         self.info = self.plan.info[0]
@@ -47,6 +47,7 @@ class ClampGPU:
         self.rho = float(rho)
         self.mu_scale = float(mu_scale)
         self.prior_sigma = float(prior_sigma)
+        self.r_update = r_update
         self.upsilon = agent_weights(looks, with_prior)
         f = dict(device=self.dev)
         self.mu = torch.zeros(looks, nz, ny, nx, dtype=torch.complex64, **f)
@@ -61,7 +62,7 @@ class ClampGPU:
         self.k = 0
 
     def params(self, beta=2.0):
-        return C.make_params(self.sigma_w2, self.sigma2, self.rho, beta, self.mu_scale, self.upsilon)
+        return C.make_params(self.sigma_w2, self.sigma2, self.rho, beta, self.mu_scale, self.upsilon, self.r_update)
 
     def init(self, y):
         """Alg. 2 initialisation from looks y (complex64 [L, nz, ny, nx], on the GPU)."""
@@ -150,7 +151,7 @@ class ClampBatchGPU:
                 "prior_sigma": float(sc.get("prior_sigma", 1.0)),
             }
             st["params"] = C.make_params(sc["sigma_w2"], sc["sigma2"], sc.get("rho", 0.5), 2.0,
-                                         sc.get("mu_scale", 1.0), st["ups"])
+                                         sc.get("mu_scale", 1.0), st["ups"], sc.get("r_update", "quadratic"))
             self.states.append(st)
         self.batch = C.clamp_batch_create(self.plan, self.states, self.fault, self.conv, self.ws)
         self.k = 0
@@ -180,7 +181,8 @@ class ClampBatchGPU:
         beta = beta_schedule(self.k)
         for i, st in enumerate(self.states):
             p = C.make_params(self.specs[i]["sigma_w2"], self.specs[i]["sigma2"], self.specs[i].get("rho", 0.5),
-                              beta, self.specs[i].get("mu_scale", 1.0), st["ups"])
+                              beta, self.specs[i].get("mu_scale", 1.0), st["ups"],
+                              self.specs[i].get("r_update", "quadratic"))
             C.clamp_fwd_agent(self.plan, i, p, st["mu"], st["resid"], st["r"], st["w"], st["diag"], self.fault,
                               self.ws)
             L = self.specs[i]["looks"]

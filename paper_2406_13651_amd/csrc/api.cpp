@@ -256,6 +256,8 @@ clamp_status check_params(const Scene& s, const clamp_params* p, bool need_prox)
     }
     if (!(p->rho > 0.f && p->rho < 1.f)) return fail(CLAMP_EINVAL, "rho must lie in (0, 1)");
     if (!finite_pos(p->mu_init_scale)) return fail(CLAMP_EINVAL, "mu_init_scale must be finite and > 0");
+    if (p->r_update != CLAMP_R_QUADRATIC && p->r_update != CLAMP_R_EXACT)
+        return fail(CLAMP_EINVAL, "r_update must be CLAMP_R_QUADRATIC or CLAMP_R_EXACT");
     const int L = s.sc.looks;
     if (p->n_agents != L && p->n_agents != L + 1)
         return fail(CLAMP_EINVAL, "n_agents must be looks (%d) or looks + 1", L);
@@ -542,6 +544,7 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_
     ra.inv_beta = (float)(1.0 / beta);
     ra.k_up = (float)((1.0 + beta) / (beta * beta));
     ra.k_dn = (float)(beta * (1.0 + beta));
+    const int upd_mode = params->r_update == CLAMP_R_EXACT ? clampk::ROW_UPDATE_EXACT : clampk::ROW_UPDATE;
 
     ColArgs ci = col_args(s, L);
     ci.cmp_in = resid;
@@ -569,7 +572,7 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_
         RowArgs u = ra;
         u.band_in = T;
         u.part = pupd;
-        e = timed(plan, ST_ROW_UPDATE, stream, [&] { return clampk::launch_row(clampk::ROW_UPDATE, u, stream); });
+        e = timed(plan, ST_ROW_UPDATE, stream, [&] { return clampk::launch_row(upd_mode, u, stream); });
     }
     if (e == hipSuccess)
         e = timed(plan, ST_RESID, stream,
@@ -781,6 +784,8 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         const clamp_batch_scene& bs = scenes[i];
         if ((st = check_params(s, &bs.params, true)) != CLAMP_OK) return fail(st, "scene %d: %s", i, g_err.c_str());
         if (bs.params.n_agents > 40) return fail(CLAMP_EUNSUPPORTED, "scene %d: a batch holds at most 40 agents", i);
+        if (bs.params.r_update != CLAMP_R_QUADRATIC)
+            return fail(CLAMP_EUNSUPPORTED, "scene %d: batches use the quadratic-surrogate r-update", i);
         if (bs.state.mu == nullptr || bs.state.resid == nullptr || bs.state.r == nullptr || bs.w == nullptr ||
             bs.wbar == nullptr || bs.diag == nullptr)
             return fail(CLAMP_EINVAL, "scene %d: NULL array", i);

@@ -50,7 +50,7 @@ int resid_blocks(const SceneTables& s);
 int mace_blocks(size_t n);
 
 enum ColMode { COL_INV_COMPACT = 0, COL_INV_FULL = 1, COL_INV_INIT = 2, COL_FWD_COMPACT = 3 };
-enum RowMode { ROW_INV = 0, ROW_FWD = 1, ROW_GRAD = 2, ROW_UPDATE = 3 };
+enum RowMode { ROW_INV = 0, ROW_FWD = 1, ROW_GRAD = 2, ROW_UPDATE = 3, ROW_UPDATE_EXACT = 4 };
 
 struct ColArgs {
     SceneTables s;

@@ -374,6 +374,7 @@ hipError_t launch_row(int mode, const RowArgs& a, hipStream_t st) {
         case ROW_FWD: return row_dispatch<ROW_FWD>(a, st);
         case ROW_GRAD: return row_dispatch<ROW_GRAD>(a, st);
         case ROW_UPDATE: return row_dispatch<ROW_UPDATE>(a, st);
+        case ROW_UPDATE_EXACT: return row_dispatch<ROW_UPDATE_EXACT>(a, st);
         default: return hipErrorInvalidValue;
     }
 }

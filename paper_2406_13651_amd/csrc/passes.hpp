@@ -106,6 +106,60 @@ __host__ __device__ inline BetaVals beta_vals(double beta) {
     return b;
 }
 
+// Exact proximal map of the EM surrogate for one voxel (eq. surrogate-prox):
+// argmin over r > 0 of log r + s/r + (r - v)^2 / (2 sigma^2).  Its stationary
+// points are the positive roots of r^3 - v r^2 + sigma^2 r - sigma^2 s (the
+// derivative times sigma^2 r^2, negative at r = 0, so a positive root exists).
+// With r = t + v/3 the cubic is t^3 + p t + q; its roots come from the
+// trigonometric form when it has three real roots and from Cardano's form
+// (the cube root taken on the side without cancellation) when it has one,
+// each polished by two Newton steps, all in float64.  The positive root with
+// the smallest objective is returned (the objective is not convex for r > 2 s
+// and can have two local minima).
+__device__ __forceinline__ float exact_prox(float sf, float vf, float s2f) {
+    const double s = sf, v = vf, q2 = s2f;
+    const double sh = v / 3.0;
+    const double p = q2 - v * v / 3.0;
+    const double q = -2.0 * v * v * v / 27.0 + v * q2 / 3.0 - q2 * s;
+    const double disc = 0.25 * q * q + p * p * p / 27.0;
+    double root[3];
+    int nr;
+    if (disc > 0.0) {
+        const double a = -0.5 * q;
+        const double u = cbrt(a + copysign(sqrt(disc), a));
+        root[0] = (u != 0.0 ? u - p / (3.0 * u) : 0.0) + sh;
+        nr = 1;
+    } else {
+        const double m = 2.0 * sqrt(fmax(-p / 3.0, 0.0));
+        const double c = m > 0.0 ? fmin(fmax(3.0 * q / (p * m), -1.0), 1.0) : 0.0;
+        const double th = acos(c) / 3.0;
+        const double third = 2.0943951023931954923;  // 2 pi / 3
+        root[0] = m * cos(th) + sh;
+        root[1] = m * cos(th - third) + sh;
+        root[2] = m * cos(th - 2.0 * third) + sh;
+        nr = 3;
+    }
+    double best = 0.0, best_phi = 0.0;
+    bool found = false;
+    for (int k = 0; k < nr; ++k) {
+        double r = root[k];
+        for (int it = 0; it < 2; ++it) {
+            const double f = ((r - v) * r + q2) * r - q2 * s;
+            const double df = (3.0 * r - 2.0 * v) * r + q2;
+            if (df != 0.0) r -= f / df;
+        }
+        if (r > 0.0) {
+            const double phi = log(r) + s / r + (r - v) * (r - v) / (2.0 * q2);
+            if (!found || phi < best_phi) {
+                best = r;
+                best_phi = phi;
+                found = true;
+            }
+        }
+    }
+    return (float)best;  // 0 (flagged by the caller) only if no positive root was found
+}
+
 // LDS buffers of a row item: twiddles, band position and band column tables
 // (length NX each) and the padded row buffers.
 struct RowLds {
@@ -128,7 +182,11 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
     constexpr int S1 = (MODE == ROW_FWD) ? -1 : +1;
     constexpr int PAD = kRowPad;
     constexpr int RS = lds_len<NX, PAD>();          // padded row length in LDS
-    constexpr bool FUSED = (MODE == ROW_GRAD || MODE == ROW_UPDATE);
+    // ROW_UPDATE_EXACT is the update pass with the exact surrogate prox in
+    // place of the quadratic surrogate (a separate instantiation, so that the
+    // float64 root solve does not raise the register count of the other)
+    constexpr bool UPD = (MODE == ROW_UPDATE || MODE == ROW_UPDATE_EXACT);
+    constexpr bool FUSED = (MODE == ROW_GRAD || UPD);
     // Stream prefetch pays off for the gradient pass; the update pass already
     // runs near the read/write bandwidth ceiling and loads its streams late.
     constexpr bool PREFETCH = (MODE == ROW_GRAD);
@@ -143,7 +201,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
 
     float2 m[FUSED ? PX : 1];
     float rp[FUSED ? PX : 1];
-    float wv[MODE == ROW_UPDATE ? PX : 1];
+    float wv[UPD ? PX : 1];
     auto load_streams = [&]() {
         if (active) {
 #pragma unroll
@@ -152,7 +210,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
                 if (NX % TR == 0 || x < NX) {
                     m[k] = a.mu[img + x];
                     rp[k] = a.r[img + x];
-                    if constexpr (MODE == ROW_UPDATE) wv[k] = a.w[img + x];
+                    if constexpr (UPD) wv[k] = a.w[img + x];
                 }
             }
         }
@@ -230,20 +288,26 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
                     // covariance diagonal with A^H A ~ alpha I, and s = c + |mu|^2
                     const float c = a.s2w * r0 / (a.alpha * r0 + a.s2w);
                     const float sv = c + cabs2(m1);
-                    // quadratic surrogate of r/r' + s/r, interpolating its
-                    // derivative at r' and xi; written with s/r' first so that
-                    // small anchors stay in float32 range
-                    const float inv = 1.f / r0;
-                    const float sr = sv * inv;
-                    const float dq = inv * (1.f - sr);                  // q'(r')
-                    const float D = dq + (r0 - v) * a.inv_sigma2;       // rho'(r')
-                    const bool down = D > 0.f;
-                    const float xi = down ? r0 * bv.inv_beta : r0 * bv.beta;
-                    const float qa = sr * inv * inv * (down ? bv.k_dn : bv.k_up);
-                    const float qb = dq - qa * r0;
-                    float rn = (v - a.sigma2 * qb) / (1.f + a.sigma2 * qa);
-                    if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
-                    rn = fminf(fmaxf(rn, fminf(r0, xi)), fmaxf(r0, xi));
+                    float rn;
+                    if constexpr (MODE == ROW_UPDATE_EXACT) {
+                        rn = exact_prox(sv, v, a.sigma2);
+                        if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
+                    } else {
+                        // quadratic surrogate of r/r' + s/r, interpolating its
+                        // derivative at r' and xi; written with s/r' first so that
+                        // small anchors stay in float32 range
+                        const float inv = 1.f / r0;
+                        const float sr = sv * inv;
+                        const float dq = inv * (1.f - sr);                  // q'(r')
+                        const float D = dq + (r0 - v) * a.inv_sigma2;       // rho'(r')
+                        const bool down = D > 0.f;
+                        const float xi = down ? r0 * bv.inv_beta : r0 * bv.beta;
+                        const float qa = sr * inv * inv * (down ? bv.k_dn : bv.k_up);
+                        const float qb = dq - qa * r0;
+                        rn = (v - a.sigma2 * qb) / (1.f + a.sigma2 * qa);
+                        if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
+                        rn = fminf(fmaxf(rn, fminf(r0, xi)), fmaxf(r0, xi));
+                    }
                     if (!(rn > 0.f)) fb |= 2u;
                     a.r[img + x] = rn;
                     wm1 += om * cabs2(m1);

@@ -57,11 +57,13 @@ def _state(spec, seed=3):
     synth.SceneSpec("m", 128, 64, 6, 3, 20.0, 10.0, 8, 0.05),
     synth.SceneSpec("k", 192, 192, 3, 2, 48.0, 10.0, 8, 0.05),
 ], ids=lambda s: "%dx%dx%d" % (s.nx, s.ny, s.nz))
-def test_one_agent_application_matches_oracle(G, spec):
+@pytest.mark.parametrize("r_update", ["quadratic", "exact"])
+def test_one_agent_application_matches_oracle(G, spec, r_update):
     import torch
     r_true, y, s2w, mask, mu, rp, w = _state(spec)
     sigma2, beta = 0.0625, 2.0
-    g = G.ClampGPU(spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, sigma2, with_prior=False)
+    g = G.ClampGPU(spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, sigma2, with_prior=False,
+                   r_update=r_update)
     idx = G.clamp_plan_pupil_index(g.plan, 0)
     y64 = y.astype(np.complex128)
     mu64 = mu.astype(np.complex128)
@@ -79,8 +81,8 @@ def test_one_agent_application_matches_oracle(G, spec):
     s2w32 = f32(s2w)
     for l in range(spec.looks):
         m1, r1, info = oracle.forward_agent(mu64[l], y64[l], rp[l].astype(np.float64), w[l].astype(np.float64),
-                                            mask, s2w32, sigma2, alpha, beta)
-        tag = "%dx%dx%d look %d" % (spec.nx, spec.ny, spec.nz, l)
+                                            mask, s2w32, sigma2, alpha, beta, r_update)
+        tag = "%dx%dx%d look %d %s" % (spec.nx, spec.ny, spec.nz, l, r_update)
         assert report("agent mu " + tag, rel_l2(mu_g[l], m1), TOL_OP) <= TOL_OP
         assert report("agent r " + tag, rel_l2(r_g[l], r1), TOL_OP) <= TOL_OP
         res1 = compact(y64[l] - oracle.apply_A(m1, mask), idx)
@@ -140,10 +142,11 @@ def test_prior_and_mann_step_match_oracle(G):
     assert abs(g.conv_err() - ce) <= 1e-5 * ce
 
 
-def _run_pair(G, spec, sigma2, iters, with_prior):
+def _run_pair(G, spec, sigma2, iters, with_prior, r_update="quadratic"):
     import torch
     r_true, y, s2w = synth.make_problem(spec, 0)
-    g = G.ClampGPU(spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, sigma2, with_prior=with_prior)
+    g = G.ClampGPU(spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, sigma2, with_prior=with_prior,
+                   r_update=r_update)
     g.init(to_gpu(y))
     errs = []
     for _ in range(iters):
@@ -151,7 +154,8 @@ def _run_pair(G, spec, sigma2, iters, with_prior):
         errs.append(g.conv_err())
     torch.cuda.synchronize()
     assert int(g.fault.item()) == 0
-    st, hist = oracle.clamp_run(y, spec.radius, f32(s2w), f32(sigma2), iters, with_prior=with_prior)
+    st, hist = oracle.clamp_run(y, spec.radius, f32(s2w), f32(sigma2), iters, with_prior=with_prior,
+                                r_update=r_update)
     return g, st, hist, errs
 
 
@@ -163,6 +167,23 @@ def test_tiny_forward_only_20_iterations(G):
     assert report("tiny 20 it mu", rel_l2(g.mu.cpu().numpy(), st.mu), TOL_RUN) <= TOL_RUN
     ref = np.array([h["conv_err"] for h in hist])
     assert report("tiny 20 it conv_err", rel_l2(np.array(errs), ref), TOL_RUN) <= TOL_RUN
+
+
+def test_tiny_forward_only_20_iterations_exact_prox(G):
+    """The exact surrogate prox in place of the quadratic surrogate: 20
+    forward-only iterations against the oracle run with the same r-update."""
+    spec = synth.CONFIGS["tiny"]
+    g, st, hist, errs = _run_pair(G, spec, 2e-4, 20, False, r_update="exact")
+    assert report("tiny 20 it exact wbar", rel_l2(g.wbar.cpu().numpy(), hist[-1]["wbar"]), TOL_RUN) <= TOL_RUN
+    assert report("tiny 20 it exact r", rel_l2(g.r.cpu().numpy(), st.r), TOL_RUN) <= TOL_RUN
+    assert report("tiny 20 it exact mu", rel_l2(g.mu.cpu().numpy(), st.mu), TOL_RUN) <= TOL_RUN
+
+
+def test_exact_prox_run_with_prior(G):
+    spec = synth.SceneSpec("r", 64, 64, 16, 4, 16.0, 10.0, 8, 0.05, 1, 1)
+    g, st, hist, errs = _run_pair(G, spec, 1e-3, 20, True, r_update="exact")
+    assert report("64x64x16 20 it exact w", rel_l2(g.w.cpu().numpy(), st.w), TOL_RUN) <= TOL_RUN
+    assert report("64x64x16 20 it exact mu", rel_l2(g.mu.cpu().numpy(), st.mu), TOL_RUN) <= TOL_RUN
 
 
 def test_reduced_full_recipe_50_iterations_with_prior(G):

@@ -122,3 +122,13 @@ def test_autotuned_grids_give_identical_results(G):
     for sa, sb in zip(a.states, b.states):
         assert np.array_equal(sa["w"].cpu().numpy(), sb["w"].cpu().numpy())
         assert np.array_equal(sa["mu"].cpu().numpy(), sb["mu"].cpu().numpy())
+
+
+def test_batch_rejects_the_exact_prox():
+    import torch
+    import paper_2406_13651_amd as G
+    from paper_2406_13651_amd import _clamp as C
+    sc = dict(nx=32, ny=32, nz=4, looks=2, radius=8.0, sigma_w2=0.01, sigma2=1e-3, with_prior=True,
+              r_update="exact")
+    with pytest.raises(C.ClampError):
+        G.ClampBatchGPU([sc])
