@@ -10,7 +10,8 @@ Buzzard, Bouman).  numpy's FFT serves as the DFT primitive; everything else is
 written out in the paper's order and notation.
 
 Pinned against closed forms, brute force and invariants (tests/test_oracle_*):
-operator (brute-force DFT, Parseval, adjoint, projector), gradient (finite
+operator (brute-force 2D and 3D DFT, Parseval, adjoint, projector, the 3D
+form with a full range box against the per-slice form), gradient (finite
 differences), step size (numerical line search, exact decrement), aperture
 ablation (one-step closed form), r-update (exact-prox cubic, sigma^2 -> inf
 limit, monotone on downward moves), exact surrogate prox (global minimum on a
@@ -22,6 +23,7 @@ unpinned beyond those invariants and the vanishing consensus error.
 
 from .operator import (  # noqa: F401
     pupil_mask, aperture_fraction, dft2, idft2, apply_A, apply_AH, apply_AHA,
+    range_box, cylinder_mask, dft3, idft3,
 )
 from .agent import (  # noqa: F401
     noise_floor_weight, h_objective, neg_grad_h, exact_step, cov_diag,

@@ -132,14 +132,27 @@ def noise_variance(r: np.ndarray, snr_db: float) -> float:
     return float(np.mean(r)) * 10.0 ** (-float(snr_db) / 10.0)
 
 
+def synth_range_support(nz: int, k: int) -> np.ndarray:
+    """Range frequencies that hold data after zero-padding in range: the k
+    samples nearest DC (signed index -floor(k/2) .. ceil(k/2) - 1)."""
+    w = np.arange(nz)
+    sw = np.where(2 * w >= nz, w - nz, w)
+    return (sw >= -(k // 2)) & (sw <= (k + 1) // 2 - 1)
+
+
 def measure_looks(r: np.ndarray, looks: int, radius: float, sigma_eta2: float,
-                  rngs, out: np.ndarray | None = None, workers: int = 1) -> np.ndarray:
+                  rngs, out: np.ndarray | None = None, workers: int = 1, range_support: int = 0) -> np.ndarray:
     """y[l] = D(a) F (sqrt(r) z_l) + eta_l as complex64 [looks, nz, ny, nx].
 
-    Each look draws from its own stream, so `workers` threads give the same
-    looks as one."""
+    range_support = 0: F is the orthonormal 2D DFT of each range slice and a
+    the pupil.  range_support = k > 0: F is the orthonormal 3D DFT and a the
+    pupil on the k range frequencies nearest DC (zero-padding in range, Sec.
+    II-A).  Each look draws from its own stream, so `workers` threads give the
+    same looks as one."""
     nz, ny, nx = r.shape
     pupil = synth_pupil(ny, nx, radius)
+    if range_support > 0:
+        pupil = synth_range_support(nz, range_support)[:, None, None] & pupil[None]
     if out is None:
         out = np.empty((looks, nz, ny, nx), dtype=np.complex64)
     amp = np.sqrt(r)
@@ -148,7 +161,10 @@ def measure_looks(r: np.ndarray, looks: int, radius: float, sigma_eta2: float,
     def one(ell):
         rng = rngs[ell]
         z = (rng.standard_normal(r.shape) + 1j * rng.standard_normal(r.shape)) / math.sqrt(2.0)
-        field = np.fft.fft2(amp * z, axes=(-2, -1), norm="ortho")
+        if range_support > 0:
+            field = np.fft.fftn(amp * z, axes=(-3, -2, -1), norm="ortho")
+        else:
+            field = np.fft.fft2(amp * z, axes=(-2, -1), norm="ortho")
         field *= pupil
         field += s_noise * (rng.standard_normal(r.shape) + 1j * rng.standard_normal(r.shape))
         out[ell] = field.astype(np.complex64)
@@ -163,8 +179,9 @@ def measure_looks(r: np.ndarray, looks: int, radius: float, sigma_eta2: float,
     return out
 
 
-def make_problem(spec: SceneSpec, scene_id: int = 0, workers: int = 1):
-    """Scene, looks and noise variance for one seeded workload.
+def make_problem(spec: SceneSpec, scene_id: int = 0, workers: int = 1, range_support: int = 0):
+    """Scene, looks and noise variance for one seeded workload (range_support:
+    see measure_looks).
 
     Returns (r_true float64 [nz,ny,nx], y complex64 [L,nz,ny,nx], sigma_eta2).
     """
@@ -173,7 +190,7 @@ def make_problem(spec: SceneSpec, scene_id: int = 0, workers: int = 1):
     r = facet_scene(spec, np.random.Generator(np.random.PCG64(children[0])))
     s2 = noise_variance(r, spec.snr_db)
     rngs = [np.random.Generator(np.random.PCG64(c)) for c in children[1:]]
-    y = measure_looks(r, spec.looks, spec.radius, s2, rngs, workers=workers)
+    y = measure_looks(r, spec.looks, spec.radius, s2, rngs, workers=workers, range_support=range_support)
     return r, y, s2
 
 

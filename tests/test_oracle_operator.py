@@ -116,3 +116,72 @@ def test_A_AH_is_pupil_restriction(rng):
     for s in (1.0, 0.5, 1.0 / oracle.aperture_fraction(mask)):
         res = mask * (y - oracle.apply_A(s * oracle.apply_AH(y, mask), mask))
         np.testing.assert_allclose(res, (1 - s) * mask * y, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# The 3D operator with a zero-padded (cylinder) aperture
+
+def test_dft3_matches_brute_force(rng):
+    nz, ny, nx = 4, 3, 5
+    x = rng.standard_normal((nz, ny, nx)) + 1j * rng.standard_normal((nz, ny, nx))
+    want = np.zeros_like(x)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for w in range(nz):
+        for u in range(ny):
+            for v in range(nx):
+                ph = np.exp(-2j * np.pi * (w * zz / nz + u * yy / ny + v * xx / nx))
+                want[w, u, v] = np.sum(x * ph) / np.sqrt(nz * ny * nx)
+    np.testing.assert_allclose(oracle.dft3(x), want, atol=1e-12)
+    np.testing.assert_allclose(oracle.idft3(oracle.dft3(x)), x, atol=1e-12)
+
+
+def test_range_box_counts_and_centre():
+    for nz, k in ((8, 8), (8, 5), (12, 8), (9, 4), (16, 1)):
+        box = oracle.range_box(nz, k)
+        assert box.sum() == k and box[0]
+        sw = np.fft.fftfreq(nz) * nz
+        assert sw[box].min() == -(k // 2) and sw[box].max() == (k + 1) // 2 - 1
+
+
+def test_cylinder_operator_adjoint_projector_and_alpha(rng):
+    nz, ny, nx = 12, 16, 16
+    m = oracle.cylinder_mask(nz, ny, nx, 5.0, 8)
+    x = rng.standard_normal((nz, ny, nx)) + 1j * rng.standard_normal((nz, ny, nx))
+    y = rng.standard_normal((nz, ny, nx)) + 1j * rng.standard_normal((nz, ny, nx))
+    lhs = np.vdot(oracle.apply_A(x, m), y)
+    rhs = np.vdot(x, oracle.apply_AH(y, m))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    p1 = oracle.apply_AHA(x, m)
+    np.testing.assert_allclose(oracle.apply_AHA(p1, m), p1, atol=1e-12)
+    disk = oracle.pupil_mask(ny, nx, 5.0).sum()
+    assert oracle.aperture_fraction(m) == disk * 8 / (nz * ny * nx)
+    # trace of the projector
+    assert abs(np.count_nonzero(m) - disk * 8) == 0
+
+
+def test_full_range_box_equals_per_slice_operator(rng):
+    """With every range frequency passed, the 3D operator is the per-slice
+    operator followed by a unitary range DFT: same A^H A, same norms."""
+    nz, ny, nx = 6, 16, 8
+    m2 = oracle.pupil_mask(ny, nx, 4.0)
+    m3 = oracle.cylinder_mask(nz, ny, nx, 4.0, nz)
+    x = rng.standard_normal((nz, ny, nx)) + 1j * rng.standard_normal((nz, ny, nx))
+    np.testing.assert_allclose(oracle.apply_AHA(x, m3), oracle.apply_AHA(x, m2), atol=1e-12)
+    np.testing.assert_allclose(oracle.apply_A(x, m3), np.fft.fft(oracle.apply_A(x, m2), axis=0, norm="ortho"),
+                               atol=1e-12)
+
+
+def test_full_range_box_clamp_run_equals_per_slice_run(rng):
+    """A CLAMP run on 3D data with a full range box reproduces the per-slice
+    run on the same looks (the 3D data are the range DFT of the 2D data)."""
+    nz, ny, nx, L = 4, 16, 16, 2
+    m2 = oracle.pupil_mask(ny, nx, 4.0)
+    m3 = oracle.cylinder_mask(nz, ny, nx, 4.0, nz)
+    r = rng.uniform(0.1, 1.0, (nz, ny, nx))
+    g = np.sqrt(r) * (rng.standard_normal((L, nz, ny, nx)) + 1j * rng.standard_normal((L, nz, ny, nx))) / np.sqrt(2)
+    y2 = oracle.apply_A(g, m2) + 0.01 * m2 * (rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape))
+    y3 = np.fft.fft(y2, axis=1, norm="ortho")
+    s2, _ = oracle.clamp_run(y2, 4.0, 0.01, 1e-3, 5, with_prior=False, mask=m2)
+    s3, _ = oracle.clamp_run(y3, 4.0, 0.01, 1e-3, 5, with_prior=False, mask=m3)
+    np.testing.assert_allclose(s3.r, s2.r, rtol=1e-9)
+    np.testing.assert_allclose(s3.mu, s2.mu, atol=1e-9 * np.abs(s2.mu).max())
