@@ -86,7 +86,23 @@ typedef struct {
     int32_t looks;        /* L, number of looks (>= 1)                      */
     float pupil_radius;   /* R of the circular pupil, in DFT samples (> 0)  */
     const uint8_t* pupil_mask;
+    int32_t range_support; /* 0: per-slice 2D operator; K in [1, nz]: 3D     */
 } clamp_scene;
+
+/* Operator form (clamp_scene.range_support).
+ * 0: A = D(a) F with F the orthonormal 2D DFT of each range slice and a the
+ *    pupil on every slice (equal to the paper's operator whenever its range
+ *    aperture passes every range frequency).
+ * K >= 1: the paper's A = D(a) F with F the orthonormal 3D DFT (Sec. II-B,
+ *    eq. A) and a the zero-padded aperture (Sec. II-A: only the K range
+ *    frequencies nearest DC hold data): the pupil disk times the range
+ *    frequencies of signed index -floor(K/2) .. ceil(K/2) - 1.  Looks,
+ *    y_full and operator outputs are then 3D frequency grids (range
+ *    frequency w, u, v).  The residual and every "compact" pupil array hold
+ *    [K][P] per look: box index k (range frequency k for k < ceil(K/2), else
+ *    nz - K + k) outer, pupil sample inner.  alpha = P K / (nx ny nz).
+ *    nz must be 16, 32, 48, 64, 96, 128, 192 or 256 (CLAMP_EUNSUPPORTED
+ *    otherwise); batches do not accept K >= 1. */
 
 /* Scalars of Alg. 2 and App. A (host memory). */
 typedef struct {
@@ -311,7 +327,7 @@ clamp_status clamp_cnn_adam_step(clamp_cnn* cnn, float lr, void* hip_stream);
  * (HOST arrays of CLAMP_STAGES entries, see clamp_stage_name) and forgets
  * the records.  Enabling timing makes the plan unsafe to share between
  * threads.  Creating events can fail with CLAMP_EDEVICE. */
-#define CLAMP_STAGES 12
+#define CLAMP_STAGES 14
 clamp_status clamp_plan_set_timing(clamp_plan* plan, int32_t enable);
 clamp_status clamp_plan_get_timing(clamp_plan* plan, double* total_ms, int32_t* launches);
 /* Name of a timing stage ("" outside [0, CLAMP_STAGES)). */

@@ -35,7 +35,7 @@ FAULT_RNONPOS = 2
 FAULT_GAMMA = 4
 
 DIAG = 8  # doubles of diagnostics per look
-STAGES = 12  # timing stages
+STAGES = 14  # timing stages
 
 
 class ClampError(RuntimeError):
@@ -47,7 +47,7 @@ class ClampError(RuntimeError):
 class clamp_scene(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("looks", ctypes.c_int32), ("pupil_radius", ctypes.c_float),
-                ("pupil_mask", ctypes.c_void_p)]
+                ("pupil_mask", ctypes.c_void_p), ("range_support", ctypes.c_int32)]
 
 
 class clamp_params(ctypes.Structure):
@@ -154,9 +154,10 @@ def _ptr(t, dtype, numel, name):
 class Scene:
     """Host description of one scene (mirrors clamp_scene)."""
 
-    def __init__(self, nx, ny, nz, looks, radius=0.0, mask=None):
+    def __init__(self, nx, ny, nz, looks, radius=0.0, mask=None, range_support=0):
         self.nx, self.ny, self.nz, self.looks = int(nx), int(ny), int(nz), int(looks)
         self.radius = float(radius)
+        self.range_support = int(range_support)  # 0: per-slice 2D operator; K: 3D operator, K range samples
         self.mask = None
         if mask is not None:
             import numpy as np
@@ -196,6 +197,7 @@ def clamp_plan_create(scenes):
         arr[i].nx, arr[i].ny, arr[i].nz, arr[i].looks = s.nx, s.ny, s.nz, s.looks
         arr[i].pupil_radius = s.radius
         arr[i].pupil_mask = s.mask.ctypes.data if s.mask is not None else None
+        arr[i].range_support = getattr(s, "range_support", 0)
     h = ctypes.c_void_p()
     _check(lib.clamp_plan_create(arr, len(scenes), ctypes.byref(h)))
     return Plan(h, scenes)
@@ -246,7 +248,9 @@ def _state(plan, scene, mu, resid, r, n_agents):
     s = plan.scenes[scene]
     P = plan.info[scene]["P"]
     st = clamp_fwd_state(_ptr(mu, torch.complex64, s.looks * s.n, "mu").value,
-                         _ptr(resid, torch.complex64, s.looks * s.nz * P, "resid").value,
+                         _ptr(resid, torch.complex64,
+                              s.looks * (s.range_support if getattr(s, "range_support", 0) > 0 else s.nz) * P,
+                              "resid").value,
                          _ptr(r, torch.float32, n_agents * s.n, "r").value)
     return st
 

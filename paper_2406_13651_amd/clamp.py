@@ -32,8 +32,10 @@ class ClampGPU:
     """State and loop of one CLAMP reconstruction on the current GPU."""
 
     def __init__(self, nx, ny, nz, looks, radius, sigma_w2, sigma2, with_prior=True, rho=0.5,
-                 mu_scale=1.0, prior_sigma=1.0, mask=None, device="cuda", r_update="quadratic"):
-        self.scene = C.Scene(nx, ny, nz, looks, radius, mask)
+                 mu_scale=1.0, prior_sigma=1.0, mask=None, device="cuda", r_update="quadratic", range_support=0):
+        """range_support = 0: per-slice 2D operator; K >= 1: the 3D operator
+        with the K range frequencies nearest DC (looks are 3D frequency grids)."""
+        self.scene = C.Scene(nx, ny, nz, looks, radius, mask, range_support)
         self.plan = C.clamp_plan_create([self.scene])
         self.info = self.plan.info[0]
         self.dev = torch.device(device)
@@ -51,7 +53,8 @@ class ClampGPU:
         self.upsilon = agent_weights(looks, with_prior)
         f = dict(device=self.dev)
         self.mu = torch.zeros(looks, nz, ny, nx, dtype=torch.complex64, **f)
-        self.resid = torch.zeros(looks, nz, self.info["P"], dtype=torch.complex64, **f)
+        self.resid = torch.zeros(looks, range_support if range_support > 0 else nz, self.info["P"],
+                                 dtype=torch.complex64, **f)
         self.r = torch.zeros(self.N, nz, ny, nx, dtype=torch.float32, **f)
         self.w = torch.zeros(self.N, nz, ny, nx, dtype=torch.float32, **f)
         self.wbar = torch.zeros(nz, ny, nx, dtype=torch.float32, **f)
@@ -124,8 +127,8 @@ class ClampBatchGPU:
         prior_sigma."""
         self.dev = torch.device(device)
         self.specs = [dict(sc) for sc in scenes]
-        self.plan = C.clamp_plan_create([C.Scene(sc["nx"], sc["ny"], sc["nz"], sc["looks"], sc["radius"])
-                                         for sc in scenes])
+        self.plan = C.clamp_plan_create([C.Scene(sc["nx"], sc["ny"], sc["nz"], sc["looks"], sc["radius"], None,
+                                                 sc.get("range_support", 0)) for sc in scenes])
         self.ws = torch.empty(max(C.clamp_batch_workspace_size(self.plan), 256), dtype=torch.uint8,
                               device=self.dev)
         self.fault = torch.zeros(1, dtype=torch.int32, device=self.dev)

@@ -2,6 +2,7 @@
 // tables, workspace layout and the launch sequences of each call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -61,12 +62,14 @@ bool size_supported(int n) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t T, T2, dfd, prow, pcf, pci, pupd, pres, pmace, scal, g0, g1, total;
+    size_t T, T2, dfd, prow, pcf, pci, pupd, pres, pmace, scal, g0, g1;
+    size_t dfdb, pzi, pzf;  // 3D operator: box data [L][K][P], range-pass partial sums
+    size_t total;
 };
 
 struct Scene {
     clamp_scene sc{};
-    int P = 0, B = 0, Bs = 0, tiles = 0;
+    int P = 0, B = 0, Bs = 0, tiles = 0, K = 0;
     double alpha = 0.0;
     std::vector<int> band_cols, band_pos, col_off, row_idx, pidx;
     std::vector<void*> dev;  // device allocations owned by this scene
@@ -80,11 +83,11 @@ struct Scene {
 // Timing stages; the names are returned by clamp_stage_name.
 enum Stage {
     ST_COL_INV = 0, ST_ROW_GRAD, ST_COL_FWD, ST_GAMMA, ST_ROW_UPDATE, ST_RESID, ST_DIAG,
-    ST_PRIOR, ST_MACE, ST_INIT, ST_OPERATOR, ST_OTHER
+    ST_PRIOR, ST_MACE, ST_INIT, ST_OPERATOR, ST_OTHER, ST_RANGE_INV, ST_RANGE_FWD
 };
 const char* const kStageNames[CLAMP_STAGES] = {
     "col_inv", "row_grad", "col_fwd", "gamma", "row_update", "resid_update", "diag_after",
-    "prior_gauss", "mace_step", "init", "aperture_op", "other"};
+    "prior_gauss", "mace_step", "init", "aperture_op", "other", "range_inv", "range_fwd"};
 
 struct TimingRecord {
     int stage;
@@ -178,7 +181,8 @@ clamp_status build_scene(const clamp_scene& in, Scene& s) {
     if (s.P == 0) return fail(CLAMP_EINVAL, "pupil passes no DFT sample");
     s.Bs = (s.B + 15) / 16 * 16;
     s.tiles = (s.B + clampk::col_tile_cols(ny) - 1) / clampk::col_tile_cols(ny);
-    s.alpha = (double)s.P / ((double)nx * ny);
+    s.K = in.range_support;
+    s.alpha = s.K > 0 ? (double)s.P * s.K / ((double)nx * ny * in.nz) : (double)s.P / ((double)nx * ny);
     return CLAMP_OK;
 }
 
@@ -199,6 +203,16 @@ clamp_status upload_scene(Scene& s) {
     if ((st = upload(s, s.col_off, &t.col_off)) != CLAMP_OK) return st;
     if ((st = upload(s, s.row_idx, &t.row_idx)) != CLAMP_OK) return st;
     if ((st = upload(s, s.pidx, &t.pidx)) != CLAMP_OK) return st;
+    t.K = s.K;
+    t.tw_z = nullptr;
+    t.cpos = nullptr;
+    if (s.K > 0) {
+        std::vector<int> cpos(s.P);
+        for (int c = 0; c < s.B; ++c)
+            for (int p = s.col_off[c]; p < s.col_off[c + 1]; ++p) cpos[p] = s.row_idx[p] * s.sc.nx + s.band_cols[c];
+        if ((st = upload(s, twiddles(s.sc.nz), &t.tw_z)) != CLAMP_OK) return st;
+        if ((st = upload(s, cpos, &t.cpos)) != CLAMP_OK) return st;
+    }
     return CLAMP_OK;
 }
 
@@ -224,6 +238,12 @@ void layout_scene(Scene& s) {
     w.scal = take(64 * sizeof(double));
     w.g0 = take(s.n() * sizeof(float));
     w.g1 = take(s.n() * sizeof(float));
+    if (s.K > 0) {
+        const size_t nz_blocks = (size_t)std::max(clampk::zpass_blocks(s.tab), clampk::gather_blocks(s.tab));
+        w.dfdb = take(L * s.K * (size_t)s.P * sizeof(float2));
+        w.pzi = take(L * nz_blocks * sizeof(double));
+        w.pzf = take(L * nz_blocks * sizeof(double));
+    }
     w.total = o;
 }
 
@@ -335,6 +355,10 @@ clamp_status clamp_plan_create(const clamp_scene* scenes, int32_t nscenes, clamp
                         c.nx, c.ny);
         if (c.pupil_mask == nullptr && !(std::isfinite(c.pupil_radius) && c.pupil_radius > 0.f))
             return fail(CLAMP_EINVAL, "scene %d: pupil_radius must be > 0 without a mask", i);
+        if (c.range_support < 0 || c.range_support > c.nz)
+            return fail(CLAMP_EINVAL, "scene %d: range_support must lie in [0, nz]", i);
+        if (c.range_support > 0 && !clampk::range_size_ok(c.nz))
+            return fail(CLAMP_EUNSUPPORTED, "scene %d: the 3D operator needs nz in 16 32 48 64 96 128 192 256", i);
         if ((size_t)c.nx * c.ny * c.nz * (size_t)c.looks > ((size_t)1 << 40))
             return fail(CLAMP_ESHAPE, "scene %d too large", i);
     }
@@ -420,11 +444,49 @@ clamp_status clamp_aperture_op(const clamp_plan* plan, int32_t scene, int32_t di
     float2* dfd = at<float2>(workspace, s.ws.dfd);
     const float2* src = static_cast<const float2*>(in);
     float2* dst = static_cast<float2*>(out);
+    const bool range = s.K > 0;
     for (int b0 = 0; b0 < nbatch; b0 += s.sc.looks) {
         const int nb = (nbatch - b0 < s.sc.looks) ? nbatch - b0 : s.sc.looks;
         const float2* x = src + (size_t)b0 * n;
         float2* y = dst + (size_t)b0 * n;
         hipError_t e = hipSuccess;
+        if (range) {
+            // 3D operator: per-slice passes plus range passes on the pupil samples
+            float2* box = at<float2>(workspace, s.ws.dfdb);
+            double* pz = at<double>(workspace, s.ws.pzi);
+            if (dir == CLAMP_FWD || dir == CLAMP_NORMAL) {
+                RowArgs ra = row_args(s, nb);
+                ra.img_in = x;
+                ra.band_out = T2;
+                e = clampk::launch_row(clampk::ROW_FWD, ra, stream);
+                if (e == hipSuccess) {
+                    ColArgs ca = col_args(s, nb);
+                    ca.band_in = T2;
+                    ca.cmp_out = dfd;
+                    e = clampk::launch_col(clampk::COL_FWD_COMPACT, ca, stream);
+                }
+                clampk::ZArgs za{s.tab, nb, dfd, box, pz};
+                if (e == hipSuccess) e = clampk::launch_zpass(-1, za, stream);
+                if (e == hipSuccess && dir == CLAMP_FWD) e = clampk::launch_range_scatter(s.tab, nb, box, y, stream);
+            }
+            if (e == hipSuccess && (dir == CLAMP_ADJ || dir == CLAMP_NORMAL)) {
+                if (dir == CLAMP_ADJ) e = clampk::launch_range_gather(s.tab, nb, x, box, nullptr, 1.f, pz, stream);
+                clampk::ZArgs za{s.tab, nb, box, dfd, pz};
+                if (e == hipSuccess) e = clampk::launch_zpass(+1, za, stream);
+                ColArgs ca = col_args(s, nb);
+                ca.cmp_in = dfd;
+                ca.band_out = T;
+                if (e == hipSuccess) e = clampk::launch_col(clampk::COL_INV_COMPACT, ca, stream);
+                if (e == hipSuccess) {
+                    RowArgs ra = row_args(s, nb);
+                    ra.band_in = T;
+                    ra.img_out = y;
+                    e = clampk::launch_row(clampk::ROW_INV, ra, stream);
+                }
+            }
+            if ((st = hip_check(e, "clamp_aperture_op launch")) != CLAMP_OK) return st;
+            continue;
+        }
         if (dir == CLAMP_FWD || dir == CLAMP_NORMAL) {
             RowArgs ra = row_args(s, nb);
             ra.img_in = x;
@@ -481,20 +543,37 @@ clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene, const clamp_p
     double* scal = at<double>(workspace, s.ws.scal);
     float2* mu = static_cast<float2*>(state->mu);
 
-    ColArgs ca = col_args(s, L);
-    ca.full_in = static_cast<const float2*>(y_full);
-    ca.band_out = T;
-    ca.cmp_out = static_cast<float2*>(state->resid);
-    ca.part = pci;
-    ca.init_keep = 1.f - params->mu_init_scale;
-    hipError_t e = clampk::launch_col(clampk::COL_INV_INIT, ca, stream);
+    hipError_t e = hipSuccess;
+    if (s.K > 0) {
+        // 3D operator: D(a) y on the cylinder, then A^H y = F2^H F_z^H (zero-filled box)
+        float2* box = at<float2>(workspace, s.ws.dfdb);
+        double* pg = at<double>(workspace, s.ws.pzi);
+        e = clampk::launch_range_gather(s.tab, L, static_cast<const float2*>(y_full), box,
+                                        static_cast<float2*>(state->resid), 1.f - params->mu_init_scale, pg, stream);
+        if (e == hipSuccess) e = clampk::launch_sum(pg, clampk::gather_blocks(s.tab), L, 1.0, ahy2, stream);
+        clampk::ZArgs za{s.tab, L, box, at<float2>(workspace, s.ws.dfd), at<double>(workspace, s.ws.pzf)};
+        if (e == hipSuccess) e = clampk::launch_zpass(+1, za, stream);
+        ColArgs ca = col_args(s, L);
+        ca.cmp_in = at<float2>(workspace, s.ws.dfd);
+        ca.band_out = T;
+        ca.part = pci;
+        if (e == hipSuccess) e = clampk::launch_col(clampk::COL_INV_COMPACT, ca, stream);
+    } else {
+        ColArgs ca = col_args(s, L);
+        ca.full_in = static_cast<const float2*>(y_full);
+        ca.band_out = T;
+        ca.cmp_out = static_cast<float2*>(state->resid);
+        ca.part = pci;
+        ca.init_keep = 1.f - params->mu_init_scale;
+        e = clampk::launch_col(clampk::COL_INV_INIT, ca, stream);
+    }
     if (e == hipSuccess) {
         RowArgs ra = row_args(s, L);
         ra.band_in = T;
         ra.img_out = mu;
         e = clampk::launch_row(clampk::ROW_INV, ra, stream);
     }
-    if (e == hipSuccess) e = clampk::launch_sum(pci, clampk::col_blocks(s.tab), L, 1.0, ahy2, stream);
+    if (e == hipSuccess && s.K == 0) e = clampk::launch_sum(pci, clampk::col_blocks(s.tab), L, 1.0, ahy2, stream);
     if (e == hipSuccess) e = clampk::launch_init_r0(n, L, mu, params->mu_init_scale, state->r, pm, stream);
     if (e == hipSuccess) e = clampk::launch_sum(pm, clampk::mace_blocks(n), 1, 1.0 / (double)n, scal, stream);
     if (e == hipSuccess) e = clampk::launch_init_floor(n, params->n_agents, scal, state->r, w, stream);
@@ -546,11 +625,25 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_
     ra.k_dn = (float)(beta * (1.0 + beta));
     const int upd_mode = params->r_update == CLAMP_R_EXACT ? clampk::ROW_UPDATE_EXACT : clampk::ROW_UPDATE;
 
+    // 3D operator: the residual lives on the cylinder [K][P]; a range pass
+    // spreads it over every slice first, and one after the forward column
+    // pass crops A d back to the box.  The gamma and residual sums then come
+    // from the range passes.
+    const bool range = s.K > 0;
+    float2* dfd_box = range ? at<float2>(workspace, s.ws.dfdb) : dfd;
+    double* pz_inv = range ? at<double>(workspace, s.ws.pzi) : pci;
+    double* pz_fwd = range ? at<double>(workspace, s.ws.pzf) : pcf;
+    hipError_t e = hipSuccess;
+    if (range) {
+        clampk::ZArgs za{s.tab, L, resid, dfd, pz_inv};
+        e = timed(plan, ST_RANGE_INV, stream, [&] { return clampk::launch_zpass(+1, za, stream); });
+    }
     ColArgs ci = col_args(s, L);
-    ci.cmp_in = resid;
+    ci.cmp_in = range ? dfd : resid;
     ci.band_out = T;
     ci.part = pci;
-    hipError_t e = timed(plan, ST_COL_INV, stream, [&] { return clampk::launch_col(clampk::COL_INV_COMPACT, ci, stream); });
+    if (e == hipSuccess)
+        e = timed(plan, ST_COL_INV, stream, [&] { return clampk::launch_col(clampk::COL_INV_COMPACT, ci, stream); });
     if (e == hipSuccess) {
         RowArgs g = ra;
         g.band_in = T;
@@ -565,9 +658,13 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_
         cf.part = pcf;
         e = timed(plan, ST_COL_FWD, stream, [&] { return clampk::launch_col(clampk::COL_FWD_COMPACT, cf, stream); });
     }
+    if (e == hipSuccess && range) {
+        clampk::ZArgs za{s.tab, L, dfd, dfd_box, pz_fwd};
+        e = timed(plan, ST_RANGE_FWD, stream, [&] { return clampk::launch_zpass(-1, za, stream); });
+    }
     if (e == hipSuccess)
         e = timed(plan, ST_GAMMA, stream,
-                  [&] { return clampk::launch_gamma(s.tab, L, prow, pcf, pci, 1.0 / s2w, diag, fault, stream); });
+                  [&] { return clampk::launch_gamma(s.tab, L, prow, pz_fwd, pz_inv, 1.0 / s2w, diag, fault, stream); });
     if (e == hipSuccess) {
         RowArgs u = ra;
         u.band_in = T;
@@ -576,7 +673,7 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_
     }
     if (e == hipSuccess)
         e = timed(plan, ST_RESID, stream,
-                  [&] { return clampk::launch_resid_update(s.tab, L, resid, dfd, diag, pres, stream); });
+                  [&] { return clampk::launch_resid_update(s.tab, L, resid, dfd_box, diag, pres, stream); });
     if (e == hipSuccess)
         e = timed(plan, ST_DIAG, stream, [&] { return clampk::launch_diag_after(s.tab, L, pupd, pres, diag, stream); });
     return hip_check(e, "clamp_fwd_agent launch");
@@ -786,6 +883,7 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         if (bs.params.n_agents > 40) return fail(CLAMP_EUNSUPPORTED, "scene %d: a batch holds at most 40 agents", i);
         if (bs.params.r_update != CLAMP_R_QUADRATIC)
             return fail(CLAMP_EUNSUPPORTED, "scene %d: batches use the quadratic-surrogate r-update", i);
+        if (s.K > 0) return fail(CLAMP_EUNSUPPORTED, "scene %d: batches use the per-slice operator", i);
         if (bs.state.mu == nullptr || bs.state.resid == nullptr || bs.state.r == nullptr || bs.w == nullptr ||
             bs.wbar == nullptr || bs.diag == nullptr)
             return fail(CLAMP_EINVAL, "scene %d: NULL array", i);

@@ -29,7 +29,36 @@ struct SceneTables {
     const int* col_off;     // [B + 1] compact offset of each band column
     const int* row_idx;     // [P] row of each compact entry
     const int* pidx;        // [ny * nx] compact index of a sample, -1 off-pupil
+    int K;                  // range frequencies of the 3D aperture (0: per-slice 2D operator)
+    const float2* tw_z;     // [nz] (3D operator only)
+    const int* cpos;        // [P] u * nx + v of each compact entry (3D operator only)
 };
+
+// Range lengths of the 3D operator's range pass.
+#define CLAMP_RANGE_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+__host__ __device__ constexpr bool range_size_ok(int n) {
+    return n == 16 || n == 32 || n == 48 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256;
+}
+
+// Range pass of the 3D operator (range.hip): dir +1 inverse (box [K][P] ->
+// [nz][P], part = sum |in|^2), -1 forward ([nz][P] -> box, part = sum |out|^2);
+// part has zpass_blocks(s) entries per look.
+struct ZArgs {
+    SceneTables s;
+    int looks;
+    const float2* in;
+    float2* out;
+    double* part;
+};
+int zpass_blocks(const SceneTables& s);
+int gather_blocks(const SceneTables& s);
+hipError_t launch_zpass(int dir, const ZArgs& a, hipStream_t st);
+// out[l][k][p] = y[l][w_k][pupil position p] (and keep times that into
+// out_keep if non-null); part has gather_blocks(s) entries per look.
+hipError_t launch_range_gather(const SceneTables& s, int looks, const float2* y, float2* out, float2* out_keep,
+                               float keep, double* part, hipStream_t st);
+// Full 3D frequency grids from box data (zero off the support).
+hipError_t launch_range_scatter(const SceneTables& s, int looks, const float2* cmp, float2* full, hipStream_t st);
 
 // Threads per row of a row-pass block (the power of two >= n/8) and rows per
 // block.

@@ -390,15 +390,18 @@ hipError_t launch_scatter_full(const SceneTables& s, int looks, const float2* cm
 hipError_t launch_gamma(const SceneTables& s, int looks, const double* part_row, const double* part_colfwd,
                           const double* part_colinv, double inv_s2w, double* diag, uint32_t* fault,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_gamma, dim3(looks), dim3(kBlock), 0, st, row_blocks(s), col_blocks(s), part_row,
-                       part_colfwd, part_colinv, inv_s2w, diag, fault);
+    // with the 3D operator the column-side sums come from the range passes
+    const int ncol = s.K > 0 ? zpass_blocks(s) : col_blocks(s);
+    hipLaunchKernelGGL(k_gamma, dim3(looks), dim3(kBlock), 0, st, row_blocks(s), ncol, part_row, part_colfwd,
+                       part_colinv, inv_s2w, diag, fault);
     return hipGetLastError();
 }
 
 hipError_t launch_resid_update(const SceneTables& s, int looks, float2* resid, const float2* dfd,
                                const double* diag, double* part, hipStream_t st) {
-    hipLaunchKernelGGL(k_resid, dim3(resid_blocks(s), looks), dim3(kBlock), 0, st, (size_t)s.nz * s.P, resid,
-                       dfd, diag, part);
+    const size_t per_look = (size_t)(s.K > 0 ? s.K : s.nz) * s.P;  // box [K][P] with the 3D operator
+    hipLaunchKernelGGL(k_resid, dim3(resid_blocks(s), looks), dim3(kBlock), 0, st, per_look, resid, dfd, diag,
+                       part);
     return hipGetLastError();
 }
 

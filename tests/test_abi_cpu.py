@@ -14,7 +14,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libclamp.so not
 class Scene(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("looks", ctypes.c_int32), ("pupil_radius", ctypes.c_float),
-                ("pupil_mask", ctypes.c_void_p)]
+                ("pupil_mask", ctypes.c_void_p), ("range_support", ctypes.c_int32)]
 
 
 @pytest.fixture(scope="module")
