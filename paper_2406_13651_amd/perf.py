@@ -6,12 +6,22 @@ measured launch duration.  Sizes: complex64 = 8 bytes, float32 = 4 bytes.
 """
 
 
-def stage_bytes(nx, ny, nz, looks, P, B, n_agents):
-    """Bytes per launch of each timing stage of one CLAMP iteration."""
+def stage_bytes(nx, ny, nz, looks, P, B, n_agents, K=0):
+    """Bytes per launch of each timing stage of one CLAMP iteration (K > 0:
+    the 3D operator with K range frequencies, adding the two range passes and
+    keeping the residual on the K x P cylinder)."""
     L = looks
     n = nx * ny * nz
     band = 8 * ny * B          # one slice's band rows (complex64)
-    return {
+    extra = {}
+    if K > 0:
+        extra = {
+            # box [K][P] in, every slice [nz][P] out
+            "range_inv": L * 8 * P * (K + nz),
+            # every slice in, box out
+            "range_fwd": L * 8 * P * (nz + K),
+        }
+    out = {
         # resid (compact) in, band rows out
         "col_inv": L * nz * (8 * P + band),
         # band rows in, mu and the anchor in, band rows out
@@ -21,12 +31,14 @@ def stage_bytes(nx, ny, nz, looks, P, B, n_agents):
         # band rows, mu, anchor and w in; mu and r out
         "row_update": L * nz * (band + ny * nx * (8 + 4 + 4 + 8 + 4)),
         # resid and D(a) F d in, resid out
-        "resid_update": L * nz * P * 24,
+        "resid_update": L * (K if K > 0 else nz) * P * 24,
         # three separable passes, each float32 in and out
         "prior_gauss": 3 * n * 8,
         # every agent's w and r in, w out, and w_bar out
         "mace_step": n * (12 * n_agents + 4),
     }
+    out.update(extra)
+    return out
 
 
 def agent_bytes_min(nx, ny, nz, looks, P):
