@@ -6,19 +6,13 @@
 // m = mean(w) and returns w + m N(w / m).
 //
 // Storage: activations and gradients are channels-last bfloat16, [voxel][C]
-// with C = 8 for one-channel tensors (channel 0 used) and 32 otherwise.
-// Every convolution is an implicit GEMM on the 32x32x8 bf16 MFMA with fp32
-// accumulation: a wave owns 32 consecutive voxels along x and 32 output
-// channels, and walks K = 27 taps x (C / 8) input-channel groups, loading the
-// A fragment (4 channels of one shifted voxel per lane) and the B fragment
-// (4 input channels of one output channel per lane) as 8-byte loads.  The
-// backward data pass is the same kernel with tap-flipped, channel-swapped
-// weights; the weight gradient is a per-tap GEMM over voxel chunks with
-// per-chunk partial sums reduced in a fixed order.
-//
-// MFMA 32x32x8 bf16 lane layout (64 lanes, l = lane): A[m][k] in lane
-// m + 32 (k / 4), element k % 4; B[k][n] in lane n + 32 (k / 4), element
-// k % 4; D[m][n] in lane n + 32 ((m / 4) % 2), register (m / 8) 4 + m % 4.
+// with C = 8 for one-channel tensors (channel 0 used) and 32 otherwise;
+// weights are fp32 masters with bf16 copies laid out per MFMA fragment.
+// Every convolution (forward, backward data, weight gradient) is an implicit
+// GEMM on gfx950's 32x32x16 bf16 MFMA with fp32 accumulation; the kernels
+// below describe their tilings.  Lane layout (64 lanes, l = lane): A[m][k] in
+// lane m + 32 (k / 8), element k % 8; B[k][n] in lane n + 32 (k / 8), element
+// k % 8; D[m][n] in lane n + 32 ((m / 4) % 2), register (m / 8) 4 + m % 4.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -27,7 +21,6 @@
 
 namespace clampk {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
