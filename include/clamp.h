@@ -296,14 +296,22 @@ clamp_status clamp_batch_replay(clamp_batch* batch, int32_t iters, void* hip_str
 #define CLAMP_CNN_PARAMS 167841
 typedef struct clamp_cnn clamp_cnn;
 
-/* Allocates device parameters (zero), Adam moments and BF16 copies. */
+/* Allocates device parameters (zero), Adam moments and BF16 copies on the
+ * current device (CLAMP_EDEVICE without one, CLAMP_ENOMEM when allocation
+ * fails).  Destroy frees them; call it only after every call using the
+ * object has completed on the device. */
 clamp_status clamp_cnn_create(clamp_cnn** out);
 clamp_status clamp_cnn_destroy(clamp_cnn* cnn);
-/* Copies HOST parameters in (and resets the Adam state) or out.  Synchronous. */
+/* Copies HOST parameters in (and resets the Adam state and step count) or
+ * out.  Both are synchronous device copies: finish the work of other streams
+ * that uses the object first.  set_params rejects non-finite values with
+ * CLAMP_EINVAL (nothing is changed). */
 clamp_status clamp_cnn_set_params(clamp_cnn* cnn, const float* params);
 clamp_status clamp_cnn_get_params(const clamp_cnn* cnn, float* params);
 /* Workspace bytes for apply (train = 0) or gradient (train = 1) calls on
- * nvol volumes of nz x ny x nx. */
+ * nvol volumes of nz x ny x nx.  Errors shared by the sized calls:
+ * CLAMP_EINVAL for non-positive sizes or NULL arguments, CLAMP_ESHAPE when nx
+ * is not a multiple of 32 or nvol nz ny nx >= 2^31. */
 clamp_status clamp_cnn_workspace_size(int32_t nvol, int32_t nz, int32_t ny, int32_t nx, int32_t train,
                                       size_t* bytes);
 /* out = H(x) per volume (device float32 arrays).  normalize != 0 applies the
