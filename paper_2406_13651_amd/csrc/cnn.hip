@@ -8,9 +8,11 @@
 // Storage: activations and gradients are channels-last bfloat16, [voxel][C]
 // with C = 8 for one-channel tensors (channel 0 used) and 32 otherwise;
 // weights are fp32 masters with bf16 copies laid out per MFMA fragment.
-// Every convolution (forward, backward data, weight gradient) is an implicit
-// GEMM on gfx950's 32x32x16 bf16 MFMA with fp32 accumulation; the kernels
-// below describe their tilings.  Lane layout (64 lanes, l = lane): A[m][k] in
+// Every convolution with 32 output channels (forward, backward data, weight
+// gradient) is an implicit GEMM on gfx950's 32x32x16 bf16 MFMA with fp32
+// accumulation; the one-channel output layer of the forward pass uses bf16
+// dot products on the vector ALUs instead.  The kernels below describe their
+// tilings.  Lane layout (64 lanes, l = lane): A[m][k] in
 // lane m + 32 (k / 8), element k % 8; B[k][n] in lane n + 32 (k / 8), element
 // k % 8; D[m][n] in lane n + 32 ((m / 4) % 2), register (m / 8) 4 + m % 4.
 #include <hip/hip_runtime.h>
@@ -170,6 +172,7 @@ __device__ __forceinline__ void conv_dz(const uint4* slot, const uint4* wsh, int
 
 template <int CIN, int EPI>
 __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
+    static_assert(EPI == EPI_RELU || EPI == EPI_DGRAD, "the final layer runs in k_conv_final");
     using G = TileGeo<CIN>;
     __shared__ uint4 ring[2][G::kSlice];
     __shared__ uint4 wsh[G::kW];
@@ -198,12 +201,8 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
     tile_fetch<CIN>(a, in, z0 + 1, y0, x0, pre);
     __syncthreads();
 
-    float bias_n = 0.f, scale = 1.f;
+    float bias_n = 0.f;
     if constexpr (EPI == EPI_RELU) bias_n = a.bias[m];
-    if constexpr (EPI == EPI_FINAL) {
-        bias_n = a.bias[0];
-        if (a.scale != nullptr) scale = *a.scale;
-    }
 
     int old = 0;  // slot of input z - 1; the other slot holds input z
     for (int z = z0; z < z1; ++z) {
@@ -220,19 +219,7 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
         old ^= 1;
 
         // epilogue: lane holds output channel m for 16 voxels of each of its 4 rows
-        if constexpr (EPI == EPI_FINAL) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int y = y0 + 4 * wave + r;
-                if (y >= a.ny || m != 0) continue;
-                const long row0 = vol_off + ((long)z * a.ny + y) * a.nx + x0;
-                float xv[16];
-#pragma unroll
-                for (int i = 0; i < 16; ++i) xv[i] = a.xin[row0 + d_row(lane, i)];
-#pragma unroll
-                for (int i = 0; i < 16; ++i) a.out_f32[row0 + d_row(lane, i)] = xv[i] + scale * (acc[r][i] + bias_n);
-            }
-        } else {
+        {
             uint32_t* st = stage + wave * (2 * 32 * 16);
             const uint4* st4 = reinterpret_cast<const uint4*>(st);
 #pragma unroll
@@ -270,6 +257,99 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
                     }
                 }
                 __syncthreads();
+            }
+        }
+    }
+}
+
+// Final layer of the forward pass (32 input channels, one output channel):
+// out[v] = xin[v] + scale (b + sum_t sum_ci x[v + off(t)][ci] W[t][ci]).  A
+// matrix-core tile would spend 31 of its 32 output columns on nothing, so
+// each thread computes whole output voxels with bf16 dot products (fp32
+// accumulation), two voxels per thread (rows r and r + 8 of the tile, x =
+// lane), reading the input rows from the same two-slot LDS window and block
+// tiling as k_conv and the 27 x 32 weights, broadcast, from LDS.
+__device__ __forceinline__ float dot8(uint4 a, const uint32_t* w, float acc) {
+    typedef __bf16 v2b __attribute__((ext_vector_type(2)));
+    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2b, a.x), __builtin_bit_cast(v2b, w[0]), acc, false);
+    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2b, a.y), __builtin_bit_cast(v2b, w[1]), acc, false);
+    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2b, a.z), __builtin_bit_cast(v2b, w[2]), acc, false);
+    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2b, a.w), __builtin_bit_cast(v2b, w[3]), acc, false);
+    return acc;
+}
+
+__device__ __forceinline__ void conv_final_dz(const uint4* slot, const uint32_t* wsh, int dz, int r0, int x,
+                                              float (&acc)[2]) {
+#pragma unroll 1
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const uint32_t* wt = wsh + (9 * dz + 3 * dy + dx) * 16;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint4 a0 = slot[ring_pos<32>(r0 + dy, x + dx, j)];
+                const uint4 a1 = slot[ring_pos<32>(r0 + 8 + dy, x + dx, j)];
+                acc[0] = dot8(a0, wt + 4 * j, acc[0]);
+                acc[1] = dot8(a1, wt + 4 * j, acc[1]);
+            }
+        }
+}
+
+__global__ __launch_bounds__(kCnnBlock) void k_conv_final(ConvArgs a) {
+    static_assert(kCnnBlock == 8 * kTileCols && kTileRows == 16, "two output rows per thread");
+    using G = TileGeo<32>;
+    __shared__ uint4 ring[2][G::kSlice];
+    __shared__ uint32_t wsh[27 * 16];  // W[t][ci] as bf16 pairs
+    const int tid = threadIdx.x;
+    const int x = tid & 31, r0 = tid >> 5;  // output rows r0 and r0 + 8 of the tile
+    int b = blockIdx.x;
+    const int xt = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int yt = b % a.tiles_y;
+    b /= a.tiles_y;
+    const int zc = b % a.zchunks;
+    const int vol = b / a.zchunks;
+    const int x0 = xt * kTileCols, y0 = yt * kTileRows;
+    const int z0 = zc * a.zc;
+    const int z1 = z0 + a.zc < a.nz ? z0 + a.zc : a.nz;
+    const long vol_off = (long)vol * a.nz * a.ny * a.nx;
+    const uint16_t* in = a.in + vol_off * 32;
+
+    // weights of output channel 0 from the fragment layout wq[g][q][h][n][8]
+    // (q = 2 dx + channel half, k = 8 h + k8)
+    uint16_t* w16 = reinterpret_cast<uint16_t*>(wsh);
+    for (int i = tid; i < 27 * 32; i += kCnnBlock) {
+        const int t = i / 32, ci = i % 32;
+        const int g = t / 3, dxi = t % 3, c = ci / 16, h = (ci / 8) % 2, k8 = ci % 8;
+        w16[i] = a.wq[(((g * 6 + 2 * dxi + c) * 2 + h) * 32 + 0) * 8 + k8];
+    }
+    uint4 pre[G::kFill];
+    tile_fetch<32>(a, in, z0 - 1, y0, x0, pre);
+    tile_store<32>(ring[0], pre);
+    tile_fetch<32>(a, in, z0, y0, x0, pre);
+    tile_store<32>(ring[1], pre);
+    tile_fetch<32>(a, in, z0 + 1, y0, x0, pre);
+    __syncthreads();
+    const float bias = a.bias[0];
+    const float scale = a.scale != nullptr ? *a.scale : 1.f;
+
+    int old = 0;
+    for (int z = z0; z < z1; ++z) {
+        float acc[2] = {0.f, 0.f};
+        conv_final_dz(ring[old], wsh, 0, r0, x, acc);
+        conv_final_dz(ring[old ^ 1], wsh, 1, r0, x, acc);
+        __syncthreads();
+        tile_store<32>(ring[old], pre);
+        __syncthreads();
+        if (z + 1 < z1) tile_fetch<32>(a, in, z + 2, y0, x0, pre);
+        conv_final_dz(ring[old], wsh, 2, r0, x, acc);
+        old ^= 1;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int y = y0 + r0 + 8 * k;
+            if (y < a.ny) {
+                const long v = vol_off + ((long)z * a.ny + y) * a.nx + x0 + x;
+                a.out_f32[v] = a.xin[v] + scale * (acc[k] + bias);
             }
         }
     }
@@ -641,7 +721,7 @@ hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st) {
 #define LAUNCH(CI, EP) hipLaunchKernelGGL((k_conv<CI, EP>), grid, dim3(kCnnBlock), 0, st, a)
     if (cin == 8 && epi == EPI_RELU) LAUNCH(8, EPI_RELU);
     else if (cin == 32 && epi == EPI_RELU) LAUNCH(32, EPI_RELU);
-    else if (cin == 32 && epi == EPI_FINAL) LAUNCH(32, EPI_FINAL);
+    else if (cin == 32 && epi == EPI_FINAL) hipLaunchKernelGGL(k_conv_final, grid, dim3(kCnnBlock), 0, st, a);
     else if (cin == 8 && epi == EPI_DGRAD) LAUNCH(8, EPI_DGRAD);
     else if (cin == 32 && epi == EPI_DGRAD) LAUNCH(32, EPI_DGRAD);
     else return hipErrorInvalidValue;
