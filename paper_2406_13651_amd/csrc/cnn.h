@@ -12,7 +12,7 @@ enum ConvEpi { EPI_RELU = 0, EPI_FINAL = 1, EPI_DGRAD = 2 };
 struct ConvArgs {
     int nvol, nz, ny, nx;          // nx a multiple of 32
     int tiles_x, tiles_y;          // output tiles of 32 x-voxels and 16 rows (set by cnn_conv)
-    int zc, zchunks;               // range slices per block and chunks per volume (set by cnn_conv)
+    int span;                      // output tile-slices per block (set by cnn_conv)
     const uint16_t* in;            // bf16 [voxel][CIN]
     const uint16_t* wq;            // bf16 weight fragments [9][kQ][2][32][8] (cnn_prep_q)
     const float* bias;             // fp32 [32] (EPI_RELU, EPI_FINAL)

@@ -78,19 +78,18 @@ __device__ __forceinline__ int d_row(int l, int i) { return (l / 32) * 4 + (i / 
 // need once and applies each to up to three output rows (the dy taps).  K
 // fragments: for 32 input channels q = (dx, channel half), 6 per (dz, dy); for
 // 8 input channels q pairs two dx taps (q = 0: dx = -1 in k 0..7 and dx = 0 in
-// k 8..15; q = 1: dx = +1 and zeros).
+// k 8..15; q = 1: dx = +1 and zeros).  The product is formed transposed,
+// D[channel][voxel] = W^T X^T (weights as the A operand, inputs as B), so that
+// each lane ends with 16 output channels of one voxel in runs of four
+// consecutive channels and stores them, after bias and ReLU, straight to the
+// channels-last output as 8-byte runs.
 //
 // LDS layouts.  Input slot: 16-byte chunks; for 32 channels the chunk j of
 // voxel (row ys, column xs) sits at (ys * 34 + xs) * 4 + (j ^ ((xs >> 2) & 3)),
 // so that the 16 lanes of one 128-bit LDS access phase (16 consecutive voxels,
 // one chunk each) hit 16 distinct 16-byte bank groups of the 256-byte bank
 // window.  Weights: wq[g = 3 dz + dy][q][h][n][8] (see k_prep_q), 16 lanes of
-// one phase reading 16 consecutive fragments rows.  Output staging: each wave
-// writes two output rows (32 voxels x 32 bf16 channels) into a private area,
-// voxel v at record v ^ (((v >> 2) & 1) << 1) so that the two voxels of one
-// MFMA register (v and v + 4) fall into different bank windows, and reads it
-// back in 16-byte chunks for coalesced global stores (and, for the
-// backward-data pass, coalesced ReLU-mask loads).
+// one phase reading 16 consecutive fragments rows.
 constexpr int kTileRows = 16;
 constexpr int kTileCols = 32;
 constexpr int kRingRows = kTileRows + 2;
@@ -142,31 +141,95 @@ __device__ __forceinline__ void tile_store(uint4* slot, const uint4 (&pre)[TileG
     }
 }
 
-// acc[r] += the taps of range offset dz (index 0..2) from the input slot.
+// Persistent work split of the convolutions: output tile-slices, numbered
+// t = ((vol tiles_y + yt) tiles_x + xt) nz + z (z fastest), go to blocks in
+// contiguous runs of a.span, and a block walks its run in range order,
+// starting a new segment (with its two-slice halo prologue) only where the
+// run crosses into the next tile.
+struct ConvSeg {
+    int xt, yt, vol, z0, z1;
+};
+
+__device__ __forceinline__ bool next_seg(const ConvArgs& a, long& t, long tend, ConvSeg& g) {
+    if (t >= tend) return false;
+    const long col = t / a.nz;
+    g.z0 = (int)(t - col * a.nz);
+    const long rem = tend - t;
+    g.z1 = rem < a.nz - g.z0 ? g.z0 + (int)rem : a.nz;
+    g.xt = (int)(col % a.tiles_x);
+    g.yt = (int)((col / a.tiles_x) % a.tiles_y);
+    g.vol = (int)(col / ((long)a.tiles_x * a.tiles_y));
+    t += g.z1 - g.z0;
+    return true;
+}
+
+// Segment prologue: inputs z0 - 1 and z0 into the two slots (fetched
+// together), input z0 + 1 into registers.  The leading barrier keeps the
+// previous segment's readers away from the slots.
 template <int CIN>
-__device__ __forceinline__ void conv_dz(const uint4* slot, const uint4* wsh, int dz, int wave, int m, int h,
-                                        v16f (&acc)[4]) {
+__device__ __forceinline__ void seg_prologue(const ConvArgs& a, const uint16_t* in, int z0, int y0, int x0,
+                                             uint4 (*ring)[TileGeo<CIN>::kSlice], uint4 (&pre)[TileGeo<CIN>::kFill]) {
+    uint4 pre0[TileGeo<CIN>::kFill];
+    tile_fetch<CIN>(a, in, z0 - 1, y0, x0, pre0);
+    tile_fetch<CIN>(a, in, z0, y0, x0, pre);
+    __syncthreads();
+    tile_store<CIN>(ring[0], pre0);
+    tile_store<CIN>(ring[1], pre);
+    tile_fetch<CIN>(a, in, z0 + 1, y0, x0, pre);
+    __syncthreads();
+}
+
+// One stage of a convolution step: the MFMA operands of range offset dz
+// (index 0..2) and K fragment q -- six input rows of the wave (X) and the
+// weights of the three row offsets dy (W) -- and the twelve products they
+// feed: acc[r] += W[dy]^T X[r + dy]^T.  Operands of the next stage are loaded
+// while the current stage's products run, so that LDS latency overlaps the
+// matrix cores with a single wave per SIMD.
+struct ConvFrag {
+    v8bf X[6];
+    v8bf W[3];
+};
+
+template <int CIN>
+__device__ __forceinline__ void frag_load(const uint4* slot, const uint4* wsh, int dz, int q, int wave, int m, int h,
+                                          ConvFrag& f) {
     using G = TileGeo<CIN>;
+    int xs, j;
+    if constexpr (CIN == 32) {
+        xs = m + (q >> 1);
+        j = 2 * (q & 1) + h;
+    } else {
+        xs = m + (q == 0 ? h : 2);
+        j = 0;
+    }
 #pragma unroll
-    for (int q = 0; q < G::kQ; ++q) {
-        int xs, j;
-        if constexpr (CIN == 32) {
-            xs = m + (q >> 1);
-            j = 2 * (q & 1) + h;
-        } else {
-            xs = m + (q == 0 ? h : 2);
-            j = 0;
+    for (int rr = 0; rr < 6; ++rr) f.X[rr] = __builtin_bit_cast(v8bf, slot[ring_pos<CIN>(4 * wave + rr, xs, j)]);
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+        f.W[dy] = __builtin_bit_cast(v8bf, wsh[(((dz * 3 + dy) * G::kQ + q) * 2 + h) * 32 + m]);
+}
+
+__device__ __forceinline__ void frag_mma(const ConvFrag& f, v16f (&acc)[4]) {
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.W[dy], f.X[r + dy], acc[r], 0, 0, 0);
+}
+
+// Instruction order of one pipelined stage: each of the next stage's nine LDS
+// reads issues beside one of the current stage's MFMAs (mask 0x100: LDS
+// reads, 0x8: MFMA), so that they complete long before they are waited on.
+template <bool LOADS>
+__device__ __forceinline__ void sched_stage() {
+    if constexpr (LOADS) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x8, 1, 0);
         }
-        v8bf A[6];
-#pragma unroll
-        for (int rr = 0; rr < 6; ++rr) A[rr] = __builtin_bit_cast(v8bf, slot[ring_pos<CIN>(4 * wave + rr, xs, j)]);
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            const v8bf B = __builtin_bit_cast(v8bf, wsh[(((dz * 3 + dy) * G::kQ + q) * 2 + h) * 32 + m]);
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[r + dy], B, acc[r], 0, 0, 0);
-        }
+        __builtin_amdgcn_sched_group_barrier(0x8, 3, 0);
+    } else {
+        __builtin_amdgcn_sched_group_barrier(0x8, 12, 0);
     }
 }
 
@@ -176,87 +239,125 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
     using G = TileGeo<CIN>;
     __shared__ uint4 ring[2][G::kSlice];
     __shared__ uint4 wsh[G::kW];
-    __shared__ uint32_t stage[4 * 2 * 32 * 16];  // per wave: 2 rows x 32 voxels x 16 dwords
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
-    int b = blockIdx.x;
-    const int xt = b % a.tiles_x;
-    b /= a.tiles_x;
-    const int yt = b % a.tiles_y;
-    b /= a.tiles_y;
-    const int zc = b % a.zchunks;
-    const int vol = b / a.zchunks;
-    const int x0 = xt * kTileCols, y0 = yt * kTileRows;
-    const int z0 = zc * a.zc;
-    const int z1 = z0 + a.zc < a.nz ? z0 + a.zc : a.nz;
-    const long vol_off = (long)vol * a.nz * a.ny * a.nx;
-    const uint16_t* in = a.in + vol_off * CIN;
 
-    for (int i = threadIdx.x; i < G::kW; i += kCnnBlock) wsh[i] = reinterpret_cast<const uint4*>(a.wq)[i];
-    uint4 pre[G::kFill];
-    tile_fetch<CIN>(a, in, z0 - 1, y0, x0, pre);
-    tile_store<CIN>(ring[0], pre);
-    tile_fetch<CIN>(a, in, z0, y0, x0, pre);
-    tile_store<CIN>(ring[1], pre);
-    tile_fetch<CIN>(a, in, z0 + 1, y0, x0, pre);
-    __syncthreads();
+    // weight fragments, once per block: every load in flight, then into LDS
+    {
+        constexpr int kWl = (G::kW + kCnnBlock - 1) / kCnnBlock;
+        const uint4* wq4 = reinterpret_cast<const uint4*>(a.wq);
+        uint4 w[kWl];
+#pragma unroll
+        for (int i = 0; i < kWl; ++i) {
+            const int e = threadIdx.x + i * kCnnBlock;
+            w[i] = e < G::kW ? wq4[e] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < kWl; ++i) {
+            const int e = threadIdx.x + i * kCnnBlock;
+            if (e < G::kW) wsh[e] = w[i];
+        }
+    }
+    // output channel of accumulator register i: (i / 4) 8 + 4 h + i % 4
+    float bias_r[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) bias_r[i] = EPI == EPI_RELU ? a.bias[(i >> 2) * 8 + 4 * h + (i & 3)] : 0.f;
 
-    float bias_n = 0.f;
-    if constexpr (EPI == EPI_RELU) bias_n = a.bias[m];
+    long t = (long)blockIdx.x * a.span;
+    const long total = (long)a.nvol * a.tiles_x * a.tiles_y * a.nz;
+    const long tend = t + a.span < total ? t + a.span : total;
+    ConvSeg sg;
+    while (next_seg(a, t, tend, sg)) {
+        const int x0 = sg.xt * kTileCols, y0 = sg.yt * kTileRows;
+        const int z0 = sg.z0, z1 = sg.z1;
+        const long vol_off = (long)sg.vol * a.nz * a.ny * a.nx;
+        const uint16_t* in = a.in + vol_off * CIN;
+        uint4 pre[G::kFill];
+        seg_prologue<CIN>(a, in, z0, y0, x0, ring, pre);
 
-    int old = 0;  // slot of input z - 1; the other slot holds input z
-    for (int z = z0; z < z1; ++z) {
-        v16f acc[4];
+        int old = 0;  // slot of input z - 1; the other slot holds input z
+        for (int z = z0; z < z1; ++z) {
+            v16f acc[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = v16f{};
-        conv_dz<CIN>(ring[old], wsh, 0, wave, m, h, acc);
-        conv_dz<CIN>(ring[old ^ 1], wsh, 1, wave, m, h, acc);
-        __syncthreads();  // every wave is done with input z - 1
-        tile_store<CIN>(ring[old], pre);
-        __syncthreads();
-        if (z + 1 < z1) tile_fetch<CIN>(a, in, z + 2, y0, x0, pre);
-        conv_dz<CIN>(ring[old], wsh, 2, wave, m, h, acc);
-        old ^= 1;
+            for (int r = 0; r < 4; ++r) acc[r] = v16f{};
+            constexpr int S = G::kQ;  // stages per range offset
+            ConvFrag f[2];
+            // dz = 0 (input z - 1) and dz = 1 (input z): one pipelined run of 2 S stages
+            frag_load<CIN>(ring[old], wsh, 0, 0, wave, m, h, f[0]);
+            __builtin_amdgcn_sched_group_barrier(0x100, 9, 0);
+#pragma unroll
+            for (int s = 0; s < 2 * S; ++s) {
+                if (s + 1 < 2 * S) {
+                    frag_load<CIN>(ring[old ^ ((s + 1) / S)], wsh, (s + 1) / S, (s + 1) % S, wave, m, h, f[(s + 1) & 1]);
+                    frag_mma(f[s & 1], acc);
+                    sched_stage<true>();
+                } else {
+                    frag_mma(f[s & 1], acc);
+                    sched_stage<false>();
+                }
+            }
+            __syncthreads();  // every wave is done with input z - 1
+            tile_store<CIN>(ring[old], pre);
+            __syncthreads();
+            if (z + 1 < z1) tile_fetch<CIN>(a, in, z + 2, y0, x0, pre);
+            // dz = 2: input z + 1, now in the slot that held z - 1
+            frag_load<CIN>(ring[old], wsh, 2, 0, wave, m, h, f[0]);
+            __builtin_amdgcn_sched_group_barrier(0x100, 9, 0);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                if (q + 1 < S) {
+                    frag_load<CIN>(ring[old], wsh, 2, q + 1, wave, m, h, f[(q + 1) & 1]);
+                    frag_mma(f[q & 1], acc);
+                    sched_stage<true>();
+                } else {
+                    frag_mma(f[q & 1], acc);
+                    sched_stage<false>();
+                }
+            }
+            old ^= 1;
 
-        // epilogue: lane holds output channel m for 16 voxels of each of its 4 rows
-        {
-            uint32_t* st = stage + wave * (2 * 32 * 16);
-            const uint4* st4 = reinterpret_cast<const uint4*>(st);
+            // epilogue: lane (voxel x0 + m, half h) of output row 4 wave + r holds
+            // channels 8 g + 4 h + 0..3 (g = 0..3); a swap between the lane halves
+            // turns the pairs of groups (2 p, 2 p + 1) into 8 consecutive channels
+            // 16 p + 8 h + 0..7 per lane, stored as one 16-byte run
 #pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
+            for (int r = 0; r < 4; ++r) {
+                const int y = y0 + 4 * wave + r;
+                if (y < a.ny) {
+                    const long v = vol_off + ((long)z * a.ny + y) * a.nx + x0 + m;
+                    uint4 keep[2];
+                    if constexpr (EPI == EPI_DGRAD) {  // ReLU mask of the layer input
 #pragma unroll
-                for (int rp = 0; rp < 2; ++rp)
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        float val = acc[2 * pass + rp][i];
-                        if constexpr (EPI == EPI_RELU) val = fmaxf(val + bias_n, 0.f);
-                        // channel m + 1 from the neighbouring lane (quad permutation 1, 0, 3, 2)
-                        const float other = __builtin_bit_cast(
-                            float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, val), 0xB1, 0xF, 0xF, false));
-                        const int vox = d_row(lane, i);
-                        if ((m & 1) == 0)
-                            st[(rp * 32 + (vox ^ (((vox >> 2) & 1) << 1))) * 16 + (m >> 1)] = pack_bf16x2(val, other);
+                        for (int p = 0; p < 2; ++p)
+                            keep[p] = *reinterpret_cast<const uint4*>(a.relu_src + v * 32 + 16 * p + 8 * h);
                     }
-                __syncthreads();
 #pragma unroll
-                for (int it = 0; it < 4; ++it) {
-                    const int e = it * 64 + lane;
-                    const int rp = e >> 7, vox = (e >> 2) & 31, c = e & 3;
-                    const int y = y0 + 4 * wave + 2 * pass + rp;
-                    if (y < a.ny) {
-                        uint4 q = st4[(rp * 32 + (vox ^ (((vox >> 2) & 1) << 1))) * 4 + c];
-                        const long v = vol_off + ((long)z * a.ny + y) * a.nx + x0 + vox;
-                        if constexpr (EPI == EPI_DGRAD) {  // multiply by the ReLU mask of the layer input
-                            const uint4 k = *reinterpret_cast<const uint4*>(a.relu_src + v * 32 + c * 8);
-                            q.x &= relu_keep2(k.x);
-                            q.y &= relu_keep2(k.y);
-                            q.z &= relu_keep2(k.z);
-                            q.w &= relu_keep2(k.w);
+                    for (int p = 0; p < 2; ++p) {
+                        uint32_t d[2][2];  // [group 2 p + e][channel pair]
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+#pragma unroll
+                            for (int c = 0; c < 2; ++c) {
+                                const int i = 4 * (2 * p + e) + 2 * c;
+                                float lo = acc[r][i], hi = acc[r][i + 1];
+                                if constexpr (EPI == EPI_RELU) {
+                                    lo = fmaxf(lo + bias_r[i], 0.f);
+                                    hi = fmaxf(hi + bias_r[i + 1], 0.f);
+                                }
+                                d[e][c] = pack_bf16x2(lo, hi);
+                            }
+                        const auto s0 = __builtin_amdgcn_permlane32_swap(d[0][0], d[1][0], false, false);
+                        const auto s1 = __builtin_amdgcn_permlane32_swap(d[0][1], d[1][1], false, false);
+                        uint4 q = make_uint4(s0[0], s1[0], s0[1], s1[1]);
+                        if constexpr (EPI == EPI_DGRAD) {
+                            q.x &= relu_keep2(keep[p].x);
+                            q.y &= relu_keep2(keep[p].y);
+                            q.z &= relu_keep2(keep[p].z);
+                            q.w &= relu_keep2(keep[p].w);
                         }
-                        *reinterpret_cast<uint4*>(a.out + v * 32 + c * 8) = q;
+                        *reinterpret_cast<uint4*>(a.out + v * 32 + 16 * p + 8 * h) = q;
                     }
                 }
-                __syncthreads();
             }
         }
     }
@@ -302,18 +403,6 @@ __global__ __launch_bounds__(kCnnBlock) void k_conv_final(ConvArgs a) {
     __shared__ uint32_t wsh[27 * 16];  // W[t][ci] as bf16 pairs
     const int tid = threadIdx.x;
     const int x = tid & 31, r0 = tid >> 5;  // output rows r0 and r0 + 8 of the tile
-    int b = blockIdx.x;
-    const int xt = b % a.tiles_x;
-    b /= a.tiles_x;
-    const int yt = b % a.tiles_y;
-    b /= a.tiles_y;
-    const int zc = b % a.zchunks;
-    const int vol = b / a.zchunks;
-    const int x0 = xt * kTileCols, y0 = yt * kTileRows;
-    const int z0 = zc * a.zc;
-    const int z1 = z0 + a.zc < a.nz ? z0 + a.zc : a.nz;
-    const long vol_off = (long)vol * a.nz * a.ny * a.nx;
-    const uint16_t* in = a.in + vol_off * 32;
 
     // weights of output channel 0 from the fragment layout wq[g][q][h][n][8]
     // (q = 2 dx + channel half, k = 8 h + k8)
@@ -323,35 +412,41 @@ __global__ __launch_bounds__(kCnnBlock) void k_conv_final(ConvArgs a) {
         const int g = t / 3, dxi = t % 3, c = ci / 16, h = (ci / 8) % 2, k8 = ci % 8;
         w16[i] = a.wq[(((g * 6 + 2 * dxi + c) * 2 + h) * 32 + 0) * 8 + k8];
     }
-    uint4 pre[G::kFill];
-    tile_fetch<32>(a, in, z0 - 1, y0, x0, pre);
-    tile_store<32>(ring[0], pre);
-    tile_fetch<32>(a, in, z0, y0, x0, pre);
-    tile_store<32>(ring[1], pre);
-    tile_fetch<32>(a, in, z0 + 1, y0, x0, pre);
-    __syncthreads();
     const float bias = a.bias[0];
     const float scale = a.scale != nullptr ? *a.scale : 1.f;
 
-    int old = 0;
-    for (int z = z0; z < z1; ++z) {
-        float acc[2] = {0.f, 0.f};
-        conv_final_dz(ring[old], wsh, 0, r0, x, acc);
-        conv_final_dz(ring[old ^ 1], wsh, 1, r0, x, acc);
-        __syncthreads();
-        tile_store<32>(ring[old], pre);
-        __syncthreads();
-        if (z + 1 < z1) tile_fetch<32>(a, in, z + 2, y0, x0, pre);
-        conv_final_dz(ring[old], wsh, 2, r0, x, acc);
-        old ^= 1;
+    long t = (long)blockIdx.x * a.span;
+    const long total = (long)a.nvol * a.tiles_x * a.tiles_y * a.nz;
+    const long tend = t + a.span < total ? t + a.span : total;
+    ConvSeg sg;
+    while (next_seg(a, t, tend, sg)) {
+        const int x0 = sg.xt * kTileCols, y0 = sg.yt * kTileRows;
+        const int z0 = sg.z0, z1 = sg.z1;
+        const long vol_off = (long)sg.vol * a.nz * a.ny * a.nx;
+        const uint16_t* in = a.in + vol_off * 32;
+        uint4 pre[G::kFill];
+        seg_prologue<32>(a, in, z0, y0, x0, ring, pre);
+
+        int old = 0;
+        for (int z = z0; z < z1; ++z) {
+            float acc[2] = {0.f, 0.f};
+            conv_final_dz(ring[old], wsh, 0, r0, x, acc);
+            conv_final_dz(ring[old ^ 1], wsh, 1, r0, x, acc);
+            __syncthreads();
+            tile_store<32>(ring[old], pre);
+            __syncthreads();
+            if (z + 1 < z1) tile_fetch<32>(a, in, z + 2, y0, x0, pre);
+            conv_final_dz(ring[old], wsh, 2, r0, x, acc);
+            old ^= 1;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int y = y0 + r0 + 8 * k;
-            if (y < a.ny) {
-                const long v = vol_off + ((long)z * a.ny + y) * a.nx + x0 + x;
-                a.out_f32[v] = a.xin[v] + scale * (acc[k] + bias);
+            for (int k = 0; k < 2; ++k) {
+                const int y = y0 + r0 + 8 * k;
+                if (y < a.ny) {
+                    const long v = vol_off + ((long)z * a.ny + y) * a.nx + x0 + x;
+                    a.out_f32[v] = a.xin[v] + scale * (acc[k] + bias);
+                }
             }
-        }
+    }
     }
 }
 
@@ -709,24 +804,36 @@ static int grid_for(long work, int per_block, int cap) {
     return (int)(g < cap ? g : cap);
 }
 
+// Launch of a persistent convolution: as many blocks as fit on the chip at
+// once (resident blocks per CU, which the kernel's LDS and registers decide,
+// times the CU count; computed once per kernel), each with a contiguous run
+// of output tile-slices.
+template <void (*K)(ConvArgs)>
+static hipError_t launch_conv(ConvArgs a, long total, hipStream_t st) {
+    static int cap = 0;
+    if (cap == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K, kCnnBlock, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        cap = per_cu * cnn_wgrad_grid();
+    }
+    a.span = (int)((total + cap - 1) / cap);
+    const unsigned grid = (unsigned)((total + a.span - 1) / a.span);
+    hipLaunchKernelGGL(K, dim3(grid), dim3(kCnnBlock), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st) {
     a.tiles_x = a.nx / kTileCols;
     a.tiles_y = (a.ny + kTileRows - 1) / kTileRows;
-    // range slices per block: fewer when the volume gives too few tiles to fill the chip
-    const long tiles = (long)a.nvol * a.tiles_x * a.tiles_y;
-    a.zc = 8;
-    while (a.zc > 2 && tiles * ((a.nz + a.zc - 1) / a.zc) < 1024) a.zc /= 2;
-    a.zchunks = (a.nz + a.zc - 1) / a.zc;
-    const dim3 grid((unsigned)(tiles * a.zchunks));
-#define LAUNCH(CI, EP) hipLaunchKernelGGL((k_conv<CI, EP>), grid, dim3(kCnnBlock), 0, st, a)
-    if (cin == 8 && epi == EPI_RELU) LAUNCH(8, EPI_RELU);
-    else if (cin == 32 && epi == EPI_RELU) LAUNCH(32, EPI_RELU);
-    else if (cin == 32 && epi == EPI_FINAL) hipLaunchKernelGGL(k_conv_final, grid, dim3(kCnnBlock), 0, st, a);
-    else if (cin == 8 && epi == EPI_DGRAD) LAUNCH(8, EPI_DGRAD);
-    else if (cin == 32 && epi == EPI_DGRAD) LAUNCH(32, EPI_DGRAD);
-    else return hipErrorInvalidValue;
-#undef LAUNCH
-    return hipGetLastError();
+    const long total = (long)a.nvol * a.tiles_x * a.tiles_y * a.nz;
+    if (total <= 0) return hipSuccess;
+    if (cin == 8 && epi == EPI_RELU) return launch_conv<k_conv<8, EPI_RELU>>(a, total, st);
+    if (cin == 32 && epi == EPI_RELU) return launch_conv<k_conv<32, EPI_RELU>>(a, total, st);
+    if (cin == 32 && epi == EPI_FINAL) return launch_conv<k_conv_final>(a, total, st);
+    if (cin == 8 && epi == EPI_DGRAD) return launch_conv<k_conv<8, EPI_DGRAD>>(a, total, st);
+    if (cin == 32 && epi == EPI_DGRAD) return launch_conv<k_conv<32, EPI_DGRAD>>(a, total, st);
+    return hipErrorInvalidValue;
 }
 
 size_t cnn_wq_elems(int cinp) { return (size_t)9 * (cinp == 32 ? 6 : 2) * 32 * 16; }
