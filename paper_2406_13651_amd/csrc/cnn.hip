@@ -25,6 +25,13 @@ namespace clampk {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+// Word 3 of a raw buffer resource (32-bit data, no format conversion) and a
+// byte offset that lies outside every buffer the kernels address (at most
+// one output slice, < 2^31 bytes): stores there are dropped, loads read 0.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr uint32_t kBufferOutside = 0x80000000u;
 
 constexpr int kCnnBlock = 256;
 
@@ -102,6 +109,7 @@ struct TileGeo {
     static constexpr int kQ = CIN == 32 ? 6 : 2;                         // K fragments per (dz, dy)
     static constexpr int kW = 9 * kQ * 64;                               // weight chunks (16 bytes)
     static constexpr int kFill = (kSlice + kCnnBlock - 1) / kCnnBlock;  // chunks per thread per slice
+    static constexpr int kSlot = kFill * kCnnBlock;                      // slot size, padded for branch-free stores
 };
 
 template <int CIN>
@@ -110,36 +118,49 @@ __device__ __forceinline__ int ring_pos(int ys, int xs, int j) {
     else return ys * kRingCols + xs;
 }
 
+// Loads of input slice zin of the block's tile (with halo) into registers,
+// branch-free: buffer loads relative to the slice, whose size is 0 when the
+// slice lies outside the volume or is not wanted (live = false), and an
+// offset outside it for halo voxels outside the volume -- those read 0.
 template <int CIN>
 __device__ __forceinline__ void tile_fetch(const ConvArgs& a, const uint16_t* in, int zin, int y0, int x0,
-                                           uint4 (&pre)[TileGeo<CIN>::kFill]) {
+                                           uint4 (&pre)[TileGeo<CIN>::kFill], bool live = true) {
     using G = TileGeo<CIN>;
+    const bool zok = live && zin >= 0 && zin < a.nz;
+    const long plane = (long)a.ny * a.nx;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint16_t*>(in) + (zok ? zin : 0) * plane * CIN, 0, zok ? (uint32_t)(plane * CIN * 2) : 0u,
+        kBufferWord3);
 #pragma unroll
     for (int i = 0; i < G::kFill; ++i) {
         const int e = threadIdx.x + i * kCnnBlock;
         const int j = e % G::kChunks, vox = e / G::kChunks;
         const int xs = vox % kRingCols, ys = vox / kRingCols;
         const int y = y0 - 1 + ys, x = x0 - 1 + xs;
-        const bool ok = e < G::kSlice && zin >= 0 && zin < a.nz && y >= 0 && y < a.ny && x >= 0 && x < a.nx;
-        // out-of-volume chunks read voxel 0 and are zeroed (no divergent branch around the load)
-        const long off = ok ? (((long)zin * a.ny + y) * a.nx + x) * CIN + j * 8 : 0;
-        const uint4 v = *reinterpret_cast<const uint4*>(in + off);
-        pre[i] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+        const bool ok = e < G::kSlice && y >= 0 && y < a.ny && x >= 0 && x < a.nx;
+        const uint32_t off = ok ? (uint32_t)(((y * a.nx + x) * CIN + j * 8) * 2) : kBufferOutside;
+        const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        pre[i] = make_uint4(v[0], v[1], v[2], v[3]);
     }
 }
 
-template <int CIN>
+// Store of a fetched slice into an LDS slot.  PAD: the slot has kSlot chunks
+// and the chunks past the slice (e >= kSlice) are stored unguarded into the
+// padding -- ring_pos maps them to e itself, up to a permutation of its four
+// chunks -- which keeps the store free of branches.
+template <int CIN, bool PAD>
 __device__ __forceinline__ void tile_store(uint4* slot, const uint4 (&pre)[TileGeo<CIN>::kFill]) {
     using G = TileGeo<CIN>;
 #pragma unroll
     for (int i = 0; i < G::kFill; ++i) {
         const int e = threadIdx.x + i * kCnnBlock;
-        if (e < G::kSlice) {
-            const int j = e % G::kChunks, vox = e / G::kChunks;
-            slot[ring_pos<CIN>(vox / kRingCols, vox % kRingCols, j)] = pre[i];
-        }
+        const int j = e % G::kChunks, vox = e / G::kChunks;
+        if (PAD || e < G::kSlice) slot[ring_pos<CIN>(vox / kRingCols, vox % kRingCols, j)] = pre[i];
     }
 }
+
+template <int CIN, bool PAD>
+using RingSlots = uint4[2][PAD ? TileGeo<CIN>::kSlot : TileGeo<CIN>::kSlice];
 
 // Persistent work split of the convolutions: output tile-slices, numbered
 // t = ((vol tiles_y + yt) tiles_x + xt) nz + z (z fastest), go to blocks in
@@ -166,15 +187,15 @@ __device__ __forceinline__ bool next_seg(const ConvArgs& a, long& t, long tend, 
 // Segment prologue: inputs z0 - 1 and z0 into the two slots (fetched
 // together), input z0 + 1 into registers.  The leading barrier keeps the
 // previous segment's readers away from the slots.
-template <int CIN>
+template <int CIN, bool PAD>
 __device__ __forceinline__ void seg_prologue(const ConvArgs& a, const uint16_t* in, int z0, int y0, int x0,
-                                             uint4 (*ring)[TileGeo<CIN>::kSlice], uint4 (&pre)[TileGeo<CIN>::kFill]) {
+                                             RingSlots<CIN, PAD>& ring, uint4 (&pre)[TileGeo<CIN>::kFill]) {
     uint4 pre0[TileGeo<CIN>::kFill];
     tile_fetch<CIN>(a, in, z0 - 1, y0, x0, pre0);
     tile_fetch<CIN>(a, in, z0, y0, x0, pre);
     __syncthreads();
-    tile_store<CIN>(ring[0], pre0);
-    tile_store<CIN>(ring[1], pre);
+    tile_store<CIN, PAD>(ring[0], pre0);
+    tile_store<CIN, PAD>(ring[1], pre);
     tile_fetch<CIN>(a, in, z0 + 1, y0, x0, pre);
     __syncthreads();
 }
@@ -216,28 +237,41 @@ __device__ __forceinline__ void frag_mma(const ConvFrag& f, v16f (&acc)[4]) {
         for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.W[dy], f.X[r + dy], acc[r], 0, 0, 0);
 }
 
-// Instruction order of one pipelined stage: each of the next stage's nine LDS
-// reads issues beside one of the current stage's MFMAs (mask 0x100: LDS
-// reads, 0x8: MFMA), so that they complete long before they are waited on.
-template <bool LOADS>
-__device__ __forceinline__ void sched_stage() {
-    if constexpr (LOADS) {
+// Instruction order of one pipelined stage (mask 0x100: LDS reads, 0x200: LDS
+// writes, 0x8: MFMA): each of the next stage's nine LDS reads issues beside
+// one of the current stage's MFMAs, so that they complete long before they
+// are waited on, and up to three LDS writes of a slice refill ride on the
+// stage's last three MFMAs.
+// (The arguments are constants once the stage loops are unrolled.)
+__device__ __forceinline__ void sched_stage(bool loads, int writes) {
+    if (loads) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x8, 1, 0);
         }
-        __builtin_amdgcn_sched_group_barrier(0x8, 3, 0);
     } else {
-        __builtin_amdgcn_sched_group_barrier(0x8, 12, 0);
+        __builtin_amdgcn_sched_group_barrier(0x8, 9, 0);
     }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (i < writes) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x8, 1, 0);
+    }
+}
+
+// LDS writes of the slice refill carried by stage q (three per stage).
+template <int CIN>
+__device__ constexpr int store_share(int q) {
+    const int left = TileGeo<CIN>::kFill - 3 * q;
+    return left <= 0 ? 0 : left < 3 ? left : 3;
 }
 
 template <int CIN, int EPI>
 __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
     static_assert(EPI == EPI_RELU || EPI == EPI_DGRAD, "the final layer runs in k_conv_final");
     using G = TileGeo<CIN>;
-    __shared__ uint4 ring[2][G::kSlice];
+    __shared__ RingSlots<CIN, true> ring;
     __shared__ uint4 wsh[G::kW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
@@ -273,7 +307,7 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
         const long vol_off = (long)sg.vol * a.nz * a.ny * a.nx;
         const uint16_t* in = a.in + vol_off * CIN;
         uint4 pre[G::kFill];
-        seg_prologue<CIN>(a, in, z0, y0, x0, ring, pre);
+        seg_prologue<CIN, true>(a, in, z0, y0, x0, ring, pre);
 
         int old = 0;  // slot of input z - 1; the other slot holds input z
         for (int z = z0; z < z1; ++z) {
@@ -281,26 +315,58 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[r] = v16f{};
             constexpr int S = G::kQ;  // stages per range offset
+            // output slice z: its byte size, element offset, and the byte offset of
+            // lane (m, h)'s 16-byte run p of row r of the wave (outside the slice for
+            // rows past the volume)
+            const uint32_t slice_bytes = (uint32_t)(a.ny * a.nx) * 64u;
+            const long slice_off = vol_off + (long)z * a.ny * a.nx;
+            auto out_off = [&](int r, int p) {
+                const int y = y0 + 4 * wave + r;
+                return y < a.ny ? (uint32_t)((y * a.nx + x0 + m) * 64 + 16 * h + 32 * p) : kBufferOutside;
+            };
+            v4u keep[4][2];  // backward-data pass: ReLU mask of the layer input at the outputs
             ConvFrag f[2];
-            // dz = 0 (input z - 1) and dz = 1 (input z): one pipelined run of 2 S stages
+            // dz = 0: input z - 1
             frag_load<CIN>(ring[old], wsh, 0, 0, wave, m, h, f[0]);
             __builtin_amdgcn_sched_group_barrier(0x100, 9, 0);
 #pragma unroll
-            for (int s = 0; s < 2 * S; ++s) {
-                if (s + 1 < 2 * S) {
-                    frag_load<CIN>(ring[old ^ ((s + 1) / S)], wsh, (s + 1) / S, (s + 1) % S, wave, m, h, f[(s + 1) & 1]);
-                    frag_mma(f[s & 1], acc);
-                    sched_stage<true>();
+            for (int q = 0; q < S; ++q) {
+                if (q + 1 < S) {
+                    frag_load<CIN>(ring[old], wsh, 0, q + 1, wave, m, h, f[(q + 1) & 1]);
+                    frag_mma(f[q & 1], acc);
+                    sched_stage(true, 0);
                 } else {
-                    frag_mma(f[s & 1], acc);
-                    sched_stage<false>();
+                    frag_mma(f[q & 1], acc);
+                    sched_stage(false, 0);
                 }
             }
             __syncthreads();  // every wave is done with input z - 1
-            tile_store<CIN>(ring[old], pre);
-            __syncthreads();
-            if (z + 1 < z1) tile_fetch<CIN>(a, in, z + 2, y0, x0, pre);
-            // dz = 2: input z + 1, now in the slot that held z - 1
+            // dz = 1: input z; meanwhile input z + 1 replaces z - 1 and z + 2 is fetched
+            frag_load<CIN>(ring[old ^ 1], wsh, 1, 0, wave, m, h, f[0]);
+            tile_store<CIN, true>(ring[old], pre);
+            tile_fetch<CIN>(a, in, z + 2, y0, x0, pre, z + 1 < z1);
+            if constexpr (EPI == EPI_DGRAD) {
+                const __amdgpu_buffer_rsrc_t keep_rs = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<uint16_t*>(a.relu_src) + slice_off * 32, 0, slice_bytes, kBufferWord3);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) keep[r][p] = __builtin_amdgcn_raw_buffer_load_b128(keep_rs, out_off(r, p), 0, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x100, 9, 0);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                if (q + 1 < S) {
+                    frag_load<CIN>(ring[old ^ 1], wsh, 1, q + 1, wave, m, h, f[(q + 1) & 1]);
+                    frag_mma(f[q & 1], acc);
+                    sched_stage(true, store_share<CIN>(q));
+                } else {
+                    frag_mma(f[q & 1], acc);
+                    sched_stage(false, store_share<CIN>(q));
+                }
+            }
+            __syncthreads();  // input z + 1 is in place
+            // dz = 2: input z + 1
             frag_load<CIN>(ring[old], wsh, 2, 0, wave, m, h, f[0]);
             __builtin_amdgcn_sched_group_barrier(0x100, 9, 0);
 #pragma unroll
@@ -308,10 +374,10 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
                 if (q + 1 < S) {
                     frag_load<CIN>(ring[old], wsh, 2, q + 1, wave, m, h, f[(q + 1) & 1]);
                     frag_mma(f[q & 1], acc);
-                    sched_stage<true>();
+                    sched_stage(true, 0);
                 } else {
                     frag_mma(f[q & 1], acc);
-                    sched_stage<false>();
+                    sched_stage(false, 0);
                 }
             }
             old ^= 1;
@@ -319,44 +385,39 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
             // epilogue: lane (voxel x0 + m, half h) of output row 4 wave + r holds
             // channels 8 g + 4 h + 0..3 (g = 0..3); a swap between the lane halves
             // turns the pairs of groups (2 p, 2 p + 1) into 8 consecutive channels
-            // 16 p + 8 h + 0..7 per lane, stored as one 16-byte run
+            // 16 p + 8 h + 0..7 per lane, stored as one 16-byte run.  Buffer
+            // stores relative to the output slice: rows past the volume get an
+            // offset beyond its size, which the hardware drops -- no branch, so
+            // that the number of stores in flight is fixed and the next step's
+            // wait for its prefetched slice need not wait for them.
+            const __amdgpu_buffer_rsrc_t out_rs =
+                __builtin_amdgcn_make_buffer_rsrc(a.out + slice_off * 32, 0, slice_bytes, kBufferWord3);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int y = y0 + 4 * wave + r;
-                if (y < a.ny) {
-                    const long v = vol_off + ((long)z * a.ny + y) * a.nx + x0 + m;
-                    uint4 keep[2];
-                    if constexpr (EPI == EPI_DGRAD) {  // ReLU mask of the layer input
 #pragma unroll
-                        for (int p = 0; p < 2; ++p)
-                            keep[p] = *reinterpret_cast<const uint4*>(a.relu_src + v * 32 + 16 * p + 8 * h);
-                    }
+                for (int p = 0; p < 2; ++p) {
+                    const uint32_t off = out_off(r, p);
+                    uint32_t d[2][2];  // [group 2 p + e][channel pair]
 #pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        uint32_t d[2][2];  // [group 2 p + e][channel pair]
+                    for (int e = 0; e < 2; ++e)
 #pragma unroll
-                        for (int e = 0; e < 2; ++e)
-#pragma unroll
-                            for (int c = 0; c < 2; ++c) {
-                                const int i = 4 * (2 * p + e) + 2 * c;
-                                float lo = acc[r][i], hi = acc[r][i + 1];
-                                if constexpr (EPI == EPI_RELU) {
-                                    lo = fmaxf(lo + bias_r[i], 0.f);
-                                    hi = fmaxf(hi + bias_r[i + 1], 0.f);
-                                }
-                                d[e][c] = pack_bf16x2(lo, hi);
+                        for (int c = 0; c < 2; ++c) {
+                            const int i = 4 * (2 * p + e) + 2 * c;
+                            float lo = acc[r][i], hi = acc[r][i + 1];
+                            if constexpr (EPI == EPI_RELU) {
+                                lo = fmaxf(lo + bias_r[i], 0.f);
+                                hi = fmaxf(hi + bias_r[i + 1], 0.f);
                             }
-                        const auto s0 = __builtin_amdgcn_permlane32_swap(d[0][0], d[1][0], false, false);
-                        const auto s1 = __builtin_amdgcn_permlane32_swap(d[0][1], d[1][1], false, false);
-                        uint4 q = make_uint4(s0[0], s1[0], s0[1], s1[1]);
-                        if constexpr (EPI == EPI_DGRAD) {
-                            q.x &= relu_keep2(keep[p].x);
-                            q.y &= relu_keep2(keep[p].y);
-                            q.z &= relu_keep2(keep[p].z);
-                            q.w &= relu_keep2(keep[p].w);
+                            d[e][c] = pack_bf16x2(lo, hi);
                         }
-                        *reinterpret_cast<uint4*>(a.out + v * 32 + 16 * p + 8 * h) = q;
+                    const auto s0 = __builtin_amdgcn_permlane32_swap(d[0][0], d[1][0], false, false);
+                    const auto s1 = __builtin_amdgcn_permlane32_swap(d[0][1], d[1][1], false, false);
+                    v4u q = {s0[0], s1[0], s0[1], s1[1]};
+                    if constexpr (EPI == EPI_DGRAD) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) q[k] &= relu_keep2(keep[r][p][k]);
                     }
+                    __builtin_amdgcn_raw_buffer_store_b128(q, out_rs, off, 0, 0);
                 }
             }
         }
@@ -399,7 +460,7 @@ __device__ __forceinline__ void conv_final_dz(const uint4* slot, const uint32_t*
 __global__ __launch_bounds__(kCnnBlock) void k_conv_final(ConvArgs a) {
     static_assert(kCnnBlock == 8 * kTileCols && kTileRows == 16, "two output rows per thread");
     using G = TileGeo<32>;
-    __shared__ uint4 ring[2][G::kSlice];
+    __shared__ RingSlots<32, false> ring;
     __shared__ uint32_t wsh[27 * 16];  // W[t][ci] as bf16 pairs
     const int tid = threadIdx.x;
     const int x = tid & 31, r0 = tid >> 5;  // output rows r0 and r0 + 8 of the tile
@@ -425,7 +486,7 @@ __global__ __launch_bounds__(kCnnBlock) void k_conv_final(ConvArgs a) {
         const long vol_off = (long)sg.vol * a.nz * a.ny * a.nx;
         const uint16_t* in = a.in + vol_off * 32;
         uint4 pre[G::kFill];
-        seg_prologue<32>(a, in, z0, y0, x0, ring, pre);
+        seg_prologue<32, false>(a, in, z0, y0, x0, ring, pre);
 
         int old = 0;
         for (int z = z0; z < z1; ++z) {
@@ -433,7 +494,7 @@ __global__ __launch_bounds__(kCnnBlock) void k_conv_final(ConvArgs a) {
             conv_final_dz(ring[old], wsh, 0, r0, x, acc);
             conv_final_dz(ring[old ^ 1], wsh, 1, r0, x, acc);
             __syncthreads();
-            tile_store<32>(ring[old], pre);
+            tile_store<32, false>(ring[old], pre);
             __syncthreads();
             if (z + 1 < z1) tile_fetch<32>(a, in, z + 2, y0, x0, pre);
             conv_final_dz(ring[old], wsh, 2, r0, x, acc);
@@ -824,6 +885,8 @@ static hipError_t launch_conv(ConvArgs a, long total, hipStream_t st) {
 }
 
 hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st) {
+    // one slice of a 32-channel tensor must stay below the buffer offset that marks "outside"
+    if ((long)a.ny * a.nx * 64 >= (long)kBufferOutside) return hipErrorInvalidValue;
     a.tiles_x = a.nx / kTileCols;
     a.tiles_y = (a.ny + kTileRows - 1) / kTileRows;
     const long total = (long)a.nvol * a.tiles_x * a.tiles_y * a.nz;
