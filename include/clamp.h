@@ -325,7 +325,13 @@ clamp_status clamp_cnn_apply(clamp_cnn* cnn, const float* x, float* out, int32_t
 clamp_status clamp_cnn_grad(clamp_cnn* cnn, const float* x, const float* target, int32_t nvol, int32_t nz,
                             int32_t ny, int32_t nx, double* loss, float* grad, void* workspace, void* hip_stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
- * gradient of the last clamp_cnn_grad call that kept it inside the object. */
+ * gradient of the last clamp_cnn_grad call that kept it inside the object.
+ * The gradient is first clipped in norm to 3 times a running average of the
+ * past (clipped) norms (weight 0.05 per step; the first step is not clipped),
+ * and a gradient with a non-finite norm leaves parameters, moments and the
+ * running norm unchanged (the step count of the bias correction still
+ * advances).  clamp_cnn_set_params resets the running norm and the Adam
+ * state. */
 clamp_status clamp_cnn_adam_step(clamp_cnn* cnn, float lr, void* hip_stream);
 
 /* Optional per-stage timing (for benchmarks).  While enabled, every call

@@ -44,7 +44,10 @@ int cnn_wgrad_grid();
 size_t cnn_wgrad_part_bytes();
 // Weight gradient gw[27][cin][cout] and bias gradient gb[cout] of one layer.
 hipError_t cnn_wgrad(int ca, int cg, WgradArgs a, int cin, int cout, float* gw, float* gb, hipStream_t st);
-hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float lr, int step, hipStream_t st);
+// Adam step with gradient-norm clipping; clip: device float[2] state (zeroed
+// with the parameters), see k_grad_clip.
+hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float lr, int step, float* clip,
+                    hipStream_t st);
 // Weight fragments of a layer for the forward (wq, cinp input channels) and
 // backward-data (wqd, coutp input channels; NULL to skip) convolutions and the
 // padded bias.

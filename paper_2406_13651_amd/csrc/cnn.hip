@@ -144,23 +144,23 @@ __device__ __forceinline__ void tile_fetch(const ConvArgs& a, const uint16_t* in
     }
 }
 
-// Store of a fetched slice into an LDS slot.  PAD: the slot has kSlot chunks
-// and the chunks past the slice (e >= kSlice) are stored unguarded into the
-// padding -- ring_pos maps them to e itself, up to a permutation of its four
-// chunks -- which keeps the store free of branches.
-template <int CIN, bool PAD>
+// Store of a fetched slice into an LDS slot of kSlot chunks.  The chunks past
+// the slice (e >= kSlice) are stored unguarded into the padding -- ring_pos
+// maps them to e itself, up to a permutation of its four chunks -- which
+// keeps the store free of branches.
+template <int CIN>
 __device__ __forceinline__ void tile_store(uint4* slot, const uint4 (&pre)[TileGeo<CIN>::kFill]) {
     using G = TileGeo<CIN>;
 #pragma unroll
     for (int i = 0; i < G::kFill; ++i) {
         const int e = threadIdx.x + i * kCnnBlock;
         const int j = e % G::kChunks, vox = e / G::kChunks;
-        if (PAD || e < G::kSlice) slot[ring_pos<CIN>(vox / kRingCols, vox % kRingCols, j)] = pre[i];
+        slot[ring_pos<CIN>(vox / kRingCols, vox % kRingCols, j)] = pre[i];
     }
 }
 
-template <int CIN, bool PAD>
-using RingSlots = uint4[2][PAD ? TileGeo<CIN>::kSlot : TileGeo<CIN>::kSlice];
+template <int CIN>
+using RingSlots = uint4[2][TileGeo<CIN>::kSlot];
 
 // Persistent work split of the convolutions: output tile-slices, numbered
 // t = ((vol tiles_y + yt) tiles_x + xt) nz + z (z fastest), go to blocks in
@@ -187,15 +187,15 @@ __device__ __forceinline__ bool next_seg(const ConvArgs& a, long& t, long tend, 
 // Segment prologue: inputs z0 - 1 and z0 into the two slots (fetched
 // together), input z0 + 1 into registers.  The leading barrier keeps the
 // previous segment's readers away from the slots.
-template <int CIN, bool PAD>
+template <int CIN>
 __device__ __forceinline__ void seg_prologue(const ConvArgs& a, const uint16_t* in, int z0, int y0, int x0,
-                                             RingSlots<CIN, PAD>& ring, uint4 (&pre)[TileGeo<CIN>::kFill]) {
+                                             RingSlots<CIN>& ring, uint4 (&pre)[TileGeo<CIN>::kFill]) {
     uint4 pre0[TileGeo<CIN>::kFill];
     tile_fetch<CIN>(a, in, z0 - 1, y0, x0, pre0);
     tile_fetch<CIN>(a, in, z0, y0, x0, pre);
     __syncthreads();
-    tile_store<CIN, PAD>(ring[0], pre0);
-    tile_store<CIN, PAD>(ring[1], pre);
+    tile_store<CIN>(ring[0], pre0);
+    tile_store<CIN>(ring[1], pre);
     tile_fetch<CIN>(a, in, z0 + 1, y0, x0, pre);
     __syncthreads();
 }
@@ -271,7 +271,7 @@ template <int CIN, int EPI>
 __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
     static_assert(EPI == EPI_RELU || EPI == EPI_DGRAD, "the final layer runs in k_conv_final");
     using G = TileGeo<CIN>;
-    __shared__ RingSlots<CIN, true> ring;
+    __shared__ RingSlots<CIN> ring;
     __shared__ uint4 wsh[G::kW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
         const long vol_off = (long)sg.vol * a.nz * a.ny * a.nx;
         const uint16_t* in = a.in + vol_off * CIN;
         uint4 pre[G::kFill];
-        seg_prologue<CIN, true>(a, in, z0, y0, x0, ring, pre);
+        seg_prologue<CIN>(a, in, z0, y0, x0, ring, pre);
 
         int old = 0;  // slot of input z - 1; the other slot holds input z
         for (int z = z0; z < z1; ++z) {
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
             __syncthreads();  // every wave is done with input z - 1
             // dz = 1: input z; meanwhile input z + 1 replaces z - 1 and z + 2 is fetched
             frag_load<CIN>(ring[old ^ 1], wsh, 1, 0, wave, m, h, f[0]);
-            tile_store<CIN, true>(ring[old], pre);
+            tile_store<CIN>(ring[old], pre);
             tile_fetch<CIN>(a, in, z + 2, y0, x0, pre, z + 1 < z1);
             if constexpr (EPI == EPI_DGRAD) {
                 const __amdgpu_buffer_rsrc_t keep_rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -425,53 +425,64 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
 }
 
 // Final layer of the forward pass (32 input channels, one output channel):
-// out[v] = xin[v] + scale (b + sum_t sum_ci x[v + off(t)][ci] W[t][ci]).  A
-// matrix-core tile would spend 31 of its 32 output columns on nothing, so
-// each thread computes whole output voxels with bf16 dot products (fp32
-// accumulation), two voxels per thread (rows r and r + 8 of the tile, x =
-// lane), reading the input rows from the same two-slot LDS window and block
-// tiling as k_conv and the 27 x 32 weights, broadcast, from LDS.
-__device__ __forceinline__ float dot8(uint4 a, const uint32_t* w, float acc) {
-    typedef __bf16 v2b __attribute__((ext_vector_type(2)));
-    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2b, a.x), __builtin_bit_cast(v2b, w[0]), acc, false);
-    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2b, a.y), __builtin_bit_cast(v2b, w[1]), acc, false);
-    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2b, a.z), __builtin_bit_cast(v2b, w[2]), acc, false);
-    acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2b, a.w), __builtin_bit_cast(v2b, w[3]), acc, false);
-    return acc;
-}
+// out[v] = xin[v] + scale (b + sum_t P_t[v + off(t)]) with the tap partials
+// P_t[u] = sum_ci x[u][ci] W[t][ci] of every input voxel u.  A direct
+// convolution would read 27 x 64 bytes of input per output from LDS for one
+// output channel; instead the matrix cores form all 27 partials of each input
+// voxel at once (D[t][u] = W^T X^T on the 32x32x16 MFMA, taps padded to 32),
+// they go to LDS as fp32 P[t][u], and each output gathers its 27 partials
+// (108 bytes).  Per input slice z' of the block's tile (18 x 34 voxels with
+// the halo, flattened to u = ys 34 + xs and cut into 20 chunks of 32), each
+// wave computes 5 chunks straight from global memory (operands in MFMA
+// layout, prefetched one slice ahead), then each thread adds the partials of
+// its two outputs (x = lane, rows r and r + 8) into three rolling sums, for
+// output slices z' + 1, z' and z' - 1 (range taps dz = 0, 1, 2); after input
+// z' the sum of output z' - 1 is complete and is stored.
+constexpr int kFinHalo = kRingRows * kRingCols;      // voxels of an input slice with halo
+constexpr int kFinChunks = (kFinHalo + 31) / 32;     // chunks of 32 voxels
+constexpr int kFinCols = kFinChunks * 32;             // voxel columns of P
+constexpr int kFinPerWave = (kFinChunks + 3) / 4;    // chunks per wave
 
-__device__ __forceinline__ void conv_final_dz(const uint4* slot, const uint32_t* wsh, int dz, int r0, int x,
-                                              float (&acc)[2]) {
-#pragma unroll 1
-    for (int dy = 0; dy < 3; ++dy)
+// MFMA operands of input slice zin: for chunk k of this wave (c = wave + 4 k)
+// and channel half e, lane (n, hh) gets channels 16 e + 8 hh .. + 7 of voxel
+// u = 32 c + n (zero outside the volume, the halo or the slice).
+__device__ __forceinline__ void final_fetch(const ConvArgs& a, const uint16_t* in, int zin, int y0, int x0, int wave,
+                                           int n, int hh, v4u (&xb)[kFinPerWave][2]) {
+    const bool zok = zin >= 0 && zin < a.nz;
+    const long plane = (long)a.ny * a.nx;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint16_t*>(in) + (zok ? zin : 0) * plane * 32, 0, zok ? (uint32_t)(plane * 64) : 0u, kBufferWord3);
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-            const uint32_t* wt = wsh + (9 * dz + 3 * dy + dx) * 16;
+    for (int k = 0; k < kFinPerWave; ++k) {
+        const int u = 32 * (wave + 4 * k) + n;
+        const int ys = u / kRingCols, xs = u % kRingCols;
+        const int y = y0 - 1 + ys, x = x0 - 1 + xs;
+        const bool ok = u < kFinHalo && y >= 0 && y < a.ny && x >= 0 && x < a.nx;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint4 a0 = slot[ring_pos<32>(r0 + dy, x + dx, j)];
-                const uint4 a1 = slot[ring_pos<32>(r0 + 8 + dy, x + dx, j)];
-                acc[0] = dot8(a0, wt + 4 * j, acc[0]);
-                acc[1] = dot8(a1, wt + 4 * j, acc[1]);
-            }
+        for (int e = 0; e < 2; ++e) {
+            const uint32_t off = ok ? (uint32_t)((y * a.nx + x) * 64 + 32 * e + 16 * hh) : kBufferOutside;
+            xb[k][e] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
         }
+    }
 }
 
 __global__ __launch_bounds__(kCnnBlock) void k_conv_final(ConvArgs a) {
     static_assert(kCnnBlock == 8 * kTileCols && kTileRows == 16, "two output rows per thread");
-    using G = TileGeo<32>;
-    __shared__ RingSlots<32, false> ring;
-    __shared__ uint32_t wsh[27 * 16];  // W[t][ci] as bf16 pairs
-    const int tid = threadIdx.x;
-    const int x = tid & 31, r0 = tid >> 5;  // output rows r0 and r0 + 8 of the tile
+    static_assert(4 * kFinPerWave >= kFinChunks, "four waves cover the chunks");
+    __shared__ float P[27][kFinCols];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 31, hh = lane >> 5;
+    const int x = tid & 31, r0 = tid >> 5;  // gather: output rows r0 and r0 + 8 of the tile
 
-    // weights of output channel 0 from the fragment layout wq[g][q][h][n][8]
-    // (q = 2 dx + channel half, k = 8 h + k8)
-    uint16_t* w16 = reinterpret_cast<uint16_t*>(wsh);
-    for (int i = tid; i < 27 * 32; i += kCnnBlock) {
-        const int t = i / 32, ci = i % 32;
-        const int g = t / 3, dxi = t % 3, c = ci / 16, h = (ci / 8) % 2, k8 = ci % 8;
-        w16[i] = a.wq[(((g * 6 + 2 * dxi + c) * 2 + h) * 32 + 0) * 8 + k8];
+    // A operand W^T: lane (t, hh), channel half e holds W[t][16 e + 8 hh + 0..7]
+    // (zero for the padding taps t >= 27), from the fragment layout
+    // wq[g][q][h][n][8] at output channel 0 (g = t / 3, q = 2 (t % 3) + e)
+    v8bf wa[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+        if (n < 27) w = *reinterpret_cast<const uint4*>(a.wq + ((((n / 3) * 6 + 2 * (n % 3) + e) * 2 + hh) * 32) * 8);
+        wa[e] = __builtin_bit_cast(v8bf, w);
     }
     const float bias = a.bias[0];
     const float scale = a.scale != nullptr ? *a.scale : 1.f;
@@ -485,29 +496,67 @@ __global__ __launch_bounds__(kCnnBlock) void k_conv_final(ConvArgs a) {
         const int z0 = sg.z0, z1 = sg.z1;
         const long vol_off = (long)sg.vol * a.nz * a.ny * a.nx;
         const uint16_t* in = a.in + vol_off * 32;
-        uint4 pre[G::kFill];
-        seg_prologue<32, false>(a, in, z0, y0, x0, ring, pre);
-
-        int old = 0;
-        for (int z = z0; z < z1; ++z) {
-            float acc[2] = {0.f, 0.f};
-            conv_final_dz(ring[old], wsh, 0, r0, x, acc);
-            conv_final_dz(ring[old ^ 1], wsh, 1, r0, x, acc);
-            __syncthreads();
-            tile_store<32, false>(ring[old], pre);
-            __syncthreads();
-            if (z + 1 < z1) tile_fetch<32>(a, in, z + 2, y0, x0, pre);
-            conv_final_dz(ring[old], wsh, 2, r0, x, acc);
-            old ^= 1;
+        v4u xb[kFinPerWave][2];
+        final_fetch(a, in, z0 - 1, y0, x0, wave, n, hh, xb);
+        // rolling sums of outputs z' - 1, z', z' + 1 for the two rows
+        float s_lo[2] = {0.f, 0.f}, s_mid[2] = {0.f, 0.f}, s_hi[2] = {0.f, 0.f};
+        for (int zi = z0 - 1; zi <= z1; ++zi) {
+            // tap partials of input slice zi into P, chunk by chunk
+            __syncthreads();  // the previous slice's gathers are done with P
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int y = y0 + r0 + 8 * k;
-                if (y < a.ny) {
-                    const long v = vol_off + ((long)z * a.ny + y) * a.nx + x0 + x;
-                    a.out_f32[v] = a.xin[v] + scale * (acc[k] + bias);
+            for (int k = 0; k < kFinPerWave; ++k) {
+                const int c = wave + 4 * k;
+                v16f d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[0], __builtin_bit_cast(v8bf, xb[k][0]), v16f{}, 0,
+                                                                 0, 0);
+                d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[1], __builtin_bit_cast(v8bf, xb[k][1]), d, 0, 0, 0);
+                if (c < kFinChunks) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int tap = (i / 4) * 8 + 4 * hh + (i % 4);  // D row of register i
+                        if (tap < 27) P[tap][32 * c + n] = d[i];
+                    }
                 }
             }
-    }
+            if (zi < z1) final_fetch(a, in, zi + 1, y0, x0, wave, n, hh, xb);
+            __syncthreads();
+            // gather: input zi feeds output zi + 1 - dz through the taps of range offset dz
+            float g[3][2];
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx)
+                            acc += P[9 * dz + 3 * dy + dx][(r0 + 8 * k + dy) * kRingCols + x + dx];
+                    g[dz][k] = acc;
+                }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                s_lo[k] += g[2][k];   // output zi - 1
+                s_mid[k] += g[1][k];  // output zi
+                s_hi[k] += g[0][k];   // output zi + 1
+            }
+            const int zo = zi - 1;
+            if (zo >= z0) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int y = y0 + r0 + 8 * k;
+                    if (y < a.ny) {
+                        const long v = vol_off + ((long)zo * a.ny + y) * a.nx + x0 + x;
+                        a.out_f32[v] = a.xin[v] + scale * (s_lo[k] + bias);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                s_lo[k] = s_mid[k];
+                s_mid[k] = s_hi[k];
+                s_hi[k] = 0.f;
+            }
+        }
     }
 }
 
@@ -806,12 +855,51 @@ __global__ __launch_bounds__(kCnnBlock) void k_wgrad_reduce(const float* part, i
     }
 }
 
-// Adam with bias correction on the flat parameter vector.
+// Gradient-norm clipping state: clip[0] the running norm of the (clipped)
+// gradients, clip[1] the factor for the coming step -- min(1, kClipRatio x
+// running norm / norm), 1 on the first step, 0 for a non-finite norm (the
+// step is skipped).  One block of 1024 threads, fixed reduction order.
+constexpr int kClipBlock = 1024;
+constexpr float kClipRatio = 3.f;
+constexpr float kClipDecay = 0.95f;
+
+__global__ __launch_bounds__(kClipBlock) void k_grad_clip(const float* g, int n, float* clip) {
+    __shared__ double part[kClipBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kClipBlock) acc += (double)g[i] * g[i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kClipBlock / 2; w > 0; w /= 2) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float norm = (float)sqrt(part[0]);
+        const float run = clip[0];
+        float c;
+        if (!isfinite(norm)) {
+            c = 0.f;
+        } else if (run <= 0.f) {
+            c = 1.f;
+            clip[0] = norm;
+        } else {
+            const float cap = kClipRatio * run;
+            c = norm > cap ? cap / norm : 1.f;
+            clip[0] = kClipDecay * run + (1.f - kClipDecay) * fminf(norm, cap);
+        }
+        clip[1] = c;
+    }
+}
+
+// Adam with bias correction on the flat parameter vector, with the gradient
+// scaled by the clipping factor (factor 0: no update at all).
 __global__ __launch_bounds__(kCnnBlock) void k_adam(float* p, float* m, float* v, const float* g, int n, float lr,
-                                                    float b1, float b2, float eps, float c1, float c2) {
+                                                    float b1, float b2, float eps, float c1, float c2,
+                                                    const float* clip) {
     const int i = blockIdx.x * kCnnBlock + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
+    const float c = clip[1];
+    if (i >= n || !(c > 0.f)) return;
+    const float gi = c * g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
@@ -966,11 +1054,13 @@ hipError_t cnn_wgrad(int ca, int cg, WgradArgs a, int cin, int cout, float* gw, 
     return hipGetLastError();
 }
 
-hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float lr, int step, hipStream_t st) {
+hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float lr, int step, float* clip,
+                    hipStream_t st) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = (float)(1.0 - std::pow(0.9, step)), c2 = (float)(1.0 - std::pow(0.999, step));
+    hipLaunchKernelGGL(k_grad_clip, dim3(1), dim3(kClipBlock), 0, st, g, n, clip);
     hipLaunchKernelGGL(k_adam, dim3((n + kCnnBlock - 1) / kCnnBlock), dim3(kCnnBlock), 0, st, p, m, v, g, n, lr, b1, b2,
-                       eps, c1, c2);
+                       eps, c1, c2, (const float*)clip);
     return hipGetLastError();
 }
 

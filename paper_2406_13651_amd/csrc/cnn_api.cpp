@@ -102,6 +102,7 @@ struct clamp_cnn {
     float* m = nullptr;
     float* v = nullptr;
     float* grad = nullptr;
+    float* clip = nullptr;        // gradient-norm clipping state [2]
     uint16_t* wq[kLayers] = {};   // forward weight fragments
     uint16_t* wqd[kLayers] = {};  // backward-data weight fragments
     float* bias32[kLayers] = {};
@@ -184,6 +185,7 @@ clamp_status clamp_cnn_create(clamp_cnn** out) {
     if (st == CLAMP_OK) st = alloc(c, CLAMP_CNN_PARAMS, &c->m);
     if (st == CLAMP_OK) st = alloc(c, CLAMP_CNN_PARAMS, &c->v);
     if (st == CLAMP_OK) st = alloc(c, CLAMP_CNN_PARAMS, &c->grad);
+    if (st == CLAMP_OK) st = alloc(c, 2, &c->clip);
     for (int l = 0; l < kLayers && st == CLAMP_OK; ++l) {
         st = alloc(c, clampk::cnn_wq_elems(cinp_of(l)), &c->wq[l]);
         if (st == CLAMP_OK) st = alloc(c, clampk::cnn_wq_elems(coutp_of(l)), &c->wqd[l]);
@@ -218,6 +220,7 @@ clamp_status clamp_cnn_set_params(clamp_cnn* cnn, const float* params) {
     if (e == hipSuccess) e = hipMemcpy(cnn->m, zero.data(), bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(cnn->v, zero.data(), bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(cnn->grad, zero.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(cnn->clip, zero.data(), 2 * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = prep_all(cnn, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     cnn->step = 0;
@@ -309,7 +312,8 @@ clamp_status clamp_cnn_adam_step(clamp_cnn* cnn, float lr, void* hip_stream) {
     if (!(std::isfinite(lr) && lr > 0.f)) return fail(CLAMP_EINVAL, "lr must be finite and > 0");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     cnn->step += 1;
-    hipError_t e = clampk::cnn_adam(cnn->params, cnn->m, cnn->v, cnn->grad, CLAMP_CNN_PARAMS, lr, cnn->step, s);
+    hipError_t e =
+        clampk::cnn_adam(cnn->params, cnn->m, cnn->v, cnn->grad, CLAMP_CNN_PARAMS, lr, cnn->step, cnn->clip, s);
     if (e == hipSuccess) e = prep_all(cnn, s);
     return hip_check(e, "clamp_cnn_adam_step launch");
 }

@@ -135,6 +135,61 @@ def test_adam_steps_reduce_loss(C):
     assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 * losses[0]
 
 
+def test_adam_gradient_clipping_matches_model(C):
+    """Adam steps with gradient-norm clipping against a float64 model of the
+    documented rule, fed with the gradients the library computes: five
+    ordinary steps, one with the target scaled by 100 (its gradient norm far
+    above 3 times the running norm: clipped), two more."""
+    net, params, x, t, torch = _setup(C, seed=5, shape=(2, 4, 8, 32))
+    xt = torch.from_numpy(x).cuda()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(C.clamp_cnn_workspace_size(*x.shape, True), dtype=torch.uint8, device="cuda")
+    g = torch.empty(C.CNN_PARAMS, dtype=torch.float32, device="cuda")
+    p = C.clamp_cnn_get_params(net).astype(np.float64)
+    m, v, run, lr = np.zeros_like(p), np.zeros_like(p), 0.0, 1e-3
+    clipped = []
+    for k, sc in enumerate([1, 1, 1, 1, 1, 100, 1, 1], start=1):
+        tt = torch.from_numpy((t * sc).astype(np.float32)).cuda()
+        C.clamp_cnn_grad(net, xt, tt, loss, ws, grad=g)  # read out
+        gk = g.cpu().numpy().astype(np.float64)
+        C.clamp_cnn_grad(net, xt, tt, loss, ws)  # kept for the step
+        C.clamp_cnn_adam_step(net, lr)
+        norm = np.sqrt(np.sum(gk * gk))
+        if run == 0.0:
+            c, run = 1.0, norm
+        else:
+            cap = 3.0 * run
+            c = min(1.0, cap / norm)
+            run = 0.95 * run + 0.05 * min(norm, cap)
+        clipped.append(c < 1.0)
+        ge = c * gk
+        m = 0.9 * m + 0.1 * ge
+        v = 0.999 * v + 0.001 * ge * ge
+        p = p - lr * (m / (1 - 0.9 ** k)) / (np.sqrt(v / (1 - 0.999 ** k)) + 1e-8)
+        np.testing.assert_allclose(C.clamp_cnn_get_params(net), p, rtol=1e-5, atol=1e-7)
+    print("clipped steps", clipped)
+    assert clipped[5]
+
+
+def test_adam_skips_non_finite_gradient(C):
+    """A gradient with a non-finite norm leaves the parameters unchanged; the
+    next finite step updates them."""
+    net, params, x, t, torch = _setup(C, seed=6, shape=(1, 4, 8, 32))
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(C.clamp_cnn_workspace_size(*x.shape, True), dtype=torch.uint8, device="cuda")
+    tt = torch.from_numpy(t).cuda()
+    before = C.clamp_cnn_get_params(net)
+    xn = x.copy()
+    xn[0, 1, 2, 3] = np.nan
+    C.clamp_cnn_grad(net, torch.from_numpy(xn).cuda(), tt, loss, ws)
+    C.clamp_cnn_adam_step(net, 1e-3)
+    np.testing.assert_array_equal(C.clamp_cnn_get_params(net), before)
+    C.clamp_cnn_grad(net, torch.from_numpy(x).cuda(), tt, loss, ws)
+    C.clamp_cnn_adam_step(net, 1e-3)
+    after = C.clamp_cnn_get_params(net)
+    assert np.all(np.isfinite(after)) and not np.array_equal(after, before)
+
+
 def test_forward_full_size_sampled(C):
     """At the full evaluation size (64 x 256 x 256, the launch configuration of
     the learned-form benchmark) sampled outputs match the oracle run on the
