@@ -218,9 +218,10 @@ def run_learned(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log("training pairs: %d volumes of 64x64x32 (%s inputs)" % (args.train_pairs, args.train_mode))
+    log("training pairs: %d volumes of 64x64x32 (%s inputs, noise %g)" % (args.train_pairs, args.train_mode,
+                                                                          args.train_noise))
     t0 = time.perf_counter()
-    X, T = Lm.make_pairs(args.train_pairs, seed=0, mode=args.train_mode)
+    X, T = Lm.make_pairs(args.train_pairs, seed=0, mode=args.train_mode, noise=args.train_noise)
     t_pairs = time.perf_counter() - t0
     prior = Lm.CnnPrior(Lm.init_params(0), device=dev)
     log("training %d epochs, lr %g" % (args.train_epochs, args.lr))
@@ -321,7 +322,7 @@ def run_learned(args):
                                % (spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, spec.snr_db,
                                   args.train_pairs),
                    "sigma2": args.sigma2, "train_epochs": args.train_epochs, "lr": args.lr,
-                   "train_mode": args.train_mode},
+                   "train_mode": args.train_mode, "train_noise": args.train_noise},
         "roofline": {"bound": "mfma", "kernel": "cnn_apply (8 convolutions)", "achieved": round(cnn_tflops, 2),
                      "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(cnn_tflops / BF16_PEAK_TFLOPS, 4),
                      "traffic": cnn_traffic},
@@ -353,7 +354,7 @@ def run_large(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log("training pairs: %d volumes of 64x64x32" % args.train_pairs)
-    X, T = Lm.make_pairs(args.train_pairs, seed=0, mode=args.train_mode)
+    X, T = Lm.make_pairs(args.train_pairs, seed=0, mode=args.train_mode, noise=args.train_noise)
     prior = Lm.CnnPrior(Lm.init_params(0), device=dev)
     hist = Lm.train(prior, X, T, epochs=args.train_epochs, lr=args.lr)
     del X, T
@@ -552,6 +553,8 @@ def main():
     ap.add_argument("--train-pairs", type=int, default=2000, help="training volumes (--workload learned)")
     ap.add_argument("--train-epochs", type=int, default=30)
     ap.add_argument("--train-mode", default="awgn", choices=("awgn", "speckle"))
+    ap.add_argument("--train-noise", type=float, default=0.3,
+                    help="awgn pairs: noise standard deviation U[0, train_noise] max(target)")
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--eval-iters", type=int, default=50)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

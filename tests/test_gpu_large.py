@@ -82,6 +82,12 @@ def test_large_prior_and_mann_step_on_slabs(large):
 
 
 def test_large_cnn_sampled_voxels(large):
+    """Sampled outputs of the CNN at 128 x 512 x 512 against the oracle run on
+    each sample's receptive field, with the same bf16-rounded weights and
+    activations.  The fp32 sums of the kernels and the float64 sums of the
+    oracle round a few activations to neighbouring bf16 values, which moves
+    an output by ~1e-4..2e-3 whatever its size, so the error is measured
+    against the RMS of the sampled residuals N(x), not per sample."""
     torch = large["torch"]
     from paper_2406_13651_amd import _clamp as C
     spec = large["spec"]
@@ -94,14 +100,19 @@ def test_large_cnn_sampled_voxels(large):
     flat = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
     net = C.clamp_cnn_create()
     C.clamp_cnn_set_params(net, flat)
-    x = torch.rand(shape, device="cuda") * 0.95 + 0.05
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    x = torch.rand(shape, device="cuda", generator=gen) * 0.95 + 0.05
     out = torch.empty_like(x)
     ws = torch.empty(C.clamp_cnn_workspace_size(*shape, False), dtype=torch.uint8, device="cuda")
     C.clamp_cnn_apply(net, x, out, False, ws)
     torch.cuda.synchronize()
     p16 = [(ocnn.bf16_round(w), b) for w, b in params]
-    samples = [(0, 0, 0), (127, 511, 511), (64, 200, 300), (5, 17, 255), (100, 480, 31)]
-    errs = []
+    # corners, edges and tile borders (16-row, 32-column tiles) and interior points
+    samples = [(0, 0, 0), (127, 511, 511), (64, 200, 300), (5, 17, 255), (100, 480, 31), (64, 256, 256),
+               (64, 255, 255), (1, 1, 1), (126, 510, 510), (64, 511, 0), (0, 511, 256), (64, 16, 32), (64, 15, 31),
+               (64, 300, 480), (127, 0, 100)]
+    diffs, resid = [], []
     for c in samples:
         lo = [max(0, c[d] - 8) for d in range(3)]
         hi = [min(shape[1 + d], c[d] + 9) for d in range(3)]
@@ -109,8 +120,10 @@ def test_large_cnn_sampled_voxels(large):
         ref, _ = ocnn.forward(crop, p16, act_round=True)
         xc = float(x[0][c].item())
         r = ref[c[0] - lo[0], c[1] - lo[1], c[2] - lo[2]] - xc
-        errs.append(abs(float(out[0][c].item()) - xc - r) / max(abs(r), 1e-3))
-    assert report("large cnn sampled voxels", max(errs), 2e-2) <= 2e-2
+        diffs.append(float(out[0][c].item()) - xc - r)
+        resid.append(r)
+    err = float(np.max(np.abs(diffs)) / np.sqrt(np.mean(np.square(resid))))
+    assert report("large cnn sampled voxels", err, 2e-2) <= 2e-2
 
 
 def test_large_learned_run_through_fallback_driver(large):
