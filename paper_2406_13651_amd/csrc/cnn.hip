@@ -866,7 +866,17 @@ constexpr float kClipDecay = 0.95f;
 __global__ __launch_bounds__(kClipBlock) void k_grad_clip(const float* g, int n, float* clip) {
     __shared__ double part[kClipBlock];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += kClipBlock) acc += (double)g[i] * g[i];
+    // eight independent loads in flight per thread, then summed in a fixed order
+    for (int i0 = threadIdx.x; i0 < n; i0 += 8 * kClipBlock) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * kClipBlock;
+            v[u] = i < n ? g[i] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (double)v[u] * v[u];
+    }
     part[threadIdx.x] = acc;
     __syncthreads();
     for (int w = kClipBlock / 2; w > 0; w /= 2) {
