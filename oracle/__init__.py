@@ -16,7 +16,10 @@ differences), step size (numerical line search, exact decrement), aperture
 ablation (one-step closed form), r-update (exact-prox cubic, sigma^2 -> inf
 limit, monotone on downward moves), exact surrogate prox (global minimum on a
 dense grid, stationarity, sigma^2 limits), Mann iteration (quadratic-agent consensus
-optimum), Gaussian prior (dense circular convolution).  The full trajectory of
+optimum), Gaussian prior (dense circular convolution), U-Net prior (brute-force
+pooling and transposed convolution, adjoint and linearity identities, batch
+normalisation closed forms and finite differences, folded against unfolded
+evaluation, whole-network loss gradient by finite differences).  The full trajectory of
 Algorithm 2 on a synthetic scene has no printed value in the paper: parity
 unpinned beyond those invariants and the vanishing consensus error.
 """
