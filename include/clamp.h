@@ -334,6 +334,59 @@ clamp_status clamp_cnn_grad(clamp_cnn* cnn, const float* x, const float* target,
  * state. */
 clamp_status clamp_cnn_adam_step(clamp_cnn* cnn, float lr, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * U-Net prior agent (the paper's deep prior architecture, Sec. III-C): three
+ * encoder blocks of two 3x3x3 convolutions, each followed by batch
+ * normalisation and ReLU, with 2x2x2 max pooling after each block; three
+ * decoder blocks, each opening with a 2x2x2 stride-2 transposed convolution
+ * whose output is added to the encoder output of the same level, then two
+ * convolutions with batch normalisation and ReLU; a final 3x3x3 convolution
+ * to one channel; output H(x) = x + N(x).  Every level is 32 channels wide.
+ * The convolutions followed by batch normalisation have no bias.  BF16
+ * weights and activations with FP32 accumulation on the matrix cores.
+ *
+ * Parameters (float32, CLAMP_UNET_PARAMS values): for each of the 12
+ * batch-normalised convolutions (encoder blocks 1, 2, 3, then decoder blocks
+ * 3, 2, 1, two each) W[27][Cin][32] (Cin = 1 for the first, else 32; taps as
+ * for the CNN), gamma[32], beta[32]; for each transposed convolution
+ * (decoder blocks 3, 2, 1) W[8][32][32] with sub-position s = 4a + 2b + c of
+ * output voxel (2z+a, 2y+b, 2x+c), then b[32]; the final W[27][32][1], b[1].
+ * Running statistics (float32, CLAMP_UNET_STATS values): per batch
+ * normalisation mean[32] then variance[32].  Apply uses evaluation mode: the
+ * running statistics, folded into the convolutions (eps 1e-5).
+ * Volumes are float32 [nvol][nz][ny][nx] with nz and ny multiples of 8 and
+ * nx a multiple of 128 (the third level's rows are 32-voxel tiles).
+ * ------------------------------------------------------------------------ */
+#define CLAMP_UNET_PARAMS 331297
+#define CLAMP_UNET_STATS (12 * 2 * 32)
+typedef struct clamp_unet clamp_unet;
+
+/* Allocates device parameters (zero), running statistics (mean 0, variance
+ * 1) and evaluation weights on the current device (CLAMP_EDEVICE without
+ * one, CLAMP_ENOMEM when allocation fails).  Destroy frees them; call it
+ * only after every call using the object has completed on the device. */
+clamp_status clamp_unet_create(clamp_unet** out);
+clamp_status clamp_unet_destroy(clamp_unet* unet);
+/* Copies HOST parameters and running statistics (NULL: mean 0, variance 1)
+ * in, and rebuilds the evaluation weights, or copies either out (NULL skips
+ * it).  Synchronous device copies: finish the work of other streams that
+ * uses the object first.  set_params rejects non-finite values and negative
+ * variances with CLAMP_EINVAL (nothing is changed). */
+clamp_status clamp_unet_set_params(clamp_unet* unet, const float* params, const float* stats);
+clamp_status clamp_unet_get_params(const clamp_unet* unet, float* params, float* stats);
+/* Workspace bytes for apply (train = 0) on nvol volumes of nz x ny x nx.
+ * Errors shared by the sized calls: CLAMP_EINVAL for non-positive sizes or
+ * NULL arguments, CLAMP_ESHAPE when nz or ny is not a multiple of 8, nx not
+ * a multiple of 128, or nvol nz ny nx >= 2^31; CLAMP_EUNSUPPORTED for train
+ * != 0 where training is not available. */
+clamp_status clamp_unet_workspace_size(int32_t nvol, int32_t nz, int32_t ny, int32_t nx, int32_t train,
+                                       size_t* bytes);
+/* out = H(x) per volume (device float32 arrays), evaluation mode.
+ * normalize != 0 applies the scale-free form out = x + m N(x / m) with m the
+ * mean of all nvol volumes.  x and out must not overlap (CLAMP_EINVAL). */
+clamp_status clamp_unet_apply(clamp_unet* unet, const float* x, float* out, int32_t nvol, int32_t nz, int32_t ny,
+                              int32_t nx, int32_t normalize, void* workspace, void* hip_stream);
+
 /* Optional per-stage timing (for benchmarks).  While enabled, every call
  * that takes a stream records a pair of HIP events on that stream around
  * each of its stages; clamp_plan_get_timing waits for the recorded events,

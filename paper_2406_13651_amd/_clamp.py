@@ -110,6 +110,12 @@ def _load():
         "clamp_cnn_apply": [P, P, P, i32, i32, i32, i32, i32, P, P],
         "clamp_cnn_grad": [P, P, P, i32, i32, i32, i32, P, P, P, P],
         "clamp_cnn_adam_step": [P, ctypes.c_float, P],
+        "clamp_unet_create": [ctypes.POINTER(P)],
+        "clamp_unet_destroy": [P],
+        "clamp_unet_set_params": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+        "clamp_unet_get_params": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+        "clamp_unet_workspace_size": [i32, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "clamp_unet_apply": [P, P, P, i32, i32, i32, i32, i32, P, P],
         "clamp_plan_get_timing": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
@@ -449,3 +455,69 @@ def clamp_cnn_grad(cnn, x, target, loss, workspace, grad=None, stream=None):
 
 def clamp_cnn_adam_step(cnn, lr, stream=None):
     _check(lib.clamp_cnn_adam_step(cnn.handle, float(lr), _stream(stream)))
+
+
+# -- U-Net prior --------------------------------------------------------------
+
+UNET_PARAMS = 331297
+UNET_STATS = 12 * 2 * 32
+
+
+class Unet:
+    """Owns a clamp_unet*; released with clamp_unet_destroy."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib.clamp_unet_create(ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self, _finalizing=sys.is_finalizing, _destroy=lib.clamp_unet_destroy):
+        h = getattr(self, "handle", None)
+        if h and not _finalizing():  # at interpreter exit the process releases everything
+            _destroy(h)
+            self.handle = None
+
+
+def clamp_unet_create():
+    return Unet()
+
+
+def clamp_unet_set_params(unet, params, stats=None):
+    import numpy as np
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    if p.size != UNET_PARAMS:
+        raise ValueError("expected %d parameters" % UNET_PARAMS)
+    sp = None
+    if stats is not None:
+        st = np.ascontiguousarray(np.asarray(stats, dtype=np.float32))
+        if st.size != UNET_STATS:
+            raise ValueError("expected %d running statistics" % UNET_STATS)
+        sp = st.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    _check(lib.clamp_unet_set_params(unet.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), sp))
+
+
+def clamp_unet_get_params(unet):
+    """(parameters, running statistics) as float32 numpy arrays."""
+    import numpy as np
+    p = np.empty(UNET_PARAMS, dtype=np.float32)
+    st = np.empty(UNET_STATS, dtype=np.float32)
+    _check(lib.clamp_unet_get_params(unet.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                     st.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return p, st
+
+
+def clamp_unet_workspace_size(nvol, nz, ny, nx, train):
+    b = ctypes.c_size_t()
+    _check(lib.clamp_unet_workspace_size(int(nvol), int(nz), int(ny), int(nx), 1 if train else 0, ctypes.byref(b)))
+    return b.value
+
+
+def clamp_unet_apply(unet, x, out, normalize, workspace, stream=None):
+    """x, out: float32 [nvol, nz, ny, nx] (or [nz, ny, nx]) on the GPU."""
+    shape = tuple(x.shape) if x.dim() == 4 else (1,) + tuple(x.shape)
+    nvol, nz, ny, nx = shape
+    n = nvol * nz * ny * nx
+    _check(lib.clamp_unet_apply(unet.handle, _ptr(x, torch.float32, n, "x"), _ptr(out, torch.float32, n, "out"),
+                                nvol, nz, ny, nx, 1 if normalize else 0,
+                                _ptr(workspace, torch.uint8, clamp_unet_workspace_size(nvol, nz, ny, nx, False),
+                                     "workspace"), _stream(stream)))

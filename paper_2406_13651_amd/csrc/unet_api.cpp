@@ -1,0 +1,330 @@
+// C ABI of the U-Net prior agent (include/clamp.h, clamp_unet_*): parameter
+// and running-statistics storage, the evaluation-mode weights (batch
+// normalisation folded into the convolutions), workspace layout and the
+// launch sequence of the forward pass.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/clamp.h"
+#include "cnn.h"
+#include "unet.h"
+
+namespace clampk {
+clamp_status set_error(clamp_status st, const char* msg);
+}
+
+namespace {
+
+using clampk::ConvArgs;
+
+constexpr int kWidth = 32;
+constexpr int kLevels = 3;
+constexpr int kConvs = 4 * kLevels;  // encoder blocks 1, 2, 3, then decoder blocks 3, 2, 1; two each
+
+int cin_of(int l) { return l == 0 ? 1 : kWidth; }
+int cinp_of(int l) { return l == 0 ? 8 : kWidth; }  // stored channels of the convolution input
+
+// flat parameter layout: per convolution W [27][cin][32], gamma [32], beta
+// [32]; per transposed convolution W [8][32][32], b [32]; final W [27][32][1], b [1]
+long conv_w(int l) {
+    long o = 0;
+    for (int i = 0; i < l; ++i) o += 27L * cin_of(i) * kWidth + 2 * kWidth;
+    return o;
+}
+long conv_gamma(int l) { return conv_w(l) + 27L * cin_of(l) * kWidth; }
+long conv_beta(int l) { return conv_gamma(l) + kWidth; }
+long up_w(int j) { return conv_w(kConvs) + j * (8L * kWidth * kWidth + kWidth); }
+long up_b(int j) { return up_w(j) + 8L * kWidth * kWidth; }
+long final_w() { return up_w(kLevels); }
+long final_b() { return final_w() + 27L * kWidth; }
+
+clamp_status fail(clamp_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return clampk::set_error(st, buf);
+}
+
+clamp_status hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return CLAMP_OK;
+    return fail(CLAMP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of the evaluation pass (V voxels at level 0, V / 8^k at level k):
+// level 0: packed input, e1 and two buffers; levels 1 and 2: e and two
+// buffers; level 3: the pooled bottom.
+struct Layout {
+    size_t x8, e[kLevels], t[kLevels][2], p3, mean, part, total;
+};
+
+Layout layout(long nvox) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.x8 = take(nvox * 16);
+    long v = nvox;
+    for (int k = 0; k < kLevels; ++k, v /= 8) {
+        L.e[k] = take(v * 64);
+        L.t[k][0] = take(v * 64);
+        L.t[k][1] = take(v * 64);
+    }
+    L.p3 = take(v * 64);
+    L.mean = take(16);
+    L.part = take((size_t)clampk::cnn_reduce_blocks(nvox) * 8);
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+clamp_status check_dims(int32_t nvol, int32_t nz, int32_t ny, int32_t nx) {
+    if (nvol <= 0 || nz <= 0 || ny <= 0 || nx <= 0) return fail(CLAMP_EINVAL, "sizes must be positive");
+    if (nz % 8 != 0 || ny % 8 != 0) return fail(CLAMP_ESHAPE, "nz and ny must be multiples of 8");
+    if (nx % 128 != 0) return fail(CLAMP_ESHAPE, "nx must be a multiple of 128");
+    if ((long)nvol * nz * ny * nx >= (1L << 31)) return fail(CLAMP_ESHAPE, "at most 2^31 voxels per call");
+    return CLAMP_OK;
+}
+
+}  // namespace
+
+struct clamp_unet {
+    float* params = nullptr;  // CLAMP_UNET_PARAMS
+    float* stats = nullptr;   // CLAMP_UNET_STATS: per BN layer mean [32], variance [32]
+    // evaluation-mode weights
+    float* wfold = nullptr;             // fp32 scratch [27][32][32] of one folded convolution
+    float* bfold = nullptr;             // fp32 scratch [32]
+    uint16_t* wq[kConvs + 1] = {};      // forward fragments of the 12 convolutions and the final one
+    float* bias32[kConvs + 1] = {};     // padded biases (folded for the 12)
+    uint16_t* wup[kLevels] = {};        // transposed-convolution fragments
+    bool eval_ready = false;
+    std::vector<void*> dev;
+};
+
+namespace {
+
+template <typename T>
+clamp_status alloc(clamp_unet* u, size_t count, T** out) {
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? CLAMP_ENOMEM : CLAMP_EDEVICE, "hipMalloc: %s",
+                                     hipGetErrorString(e));
+    u->dev.push_back(p);
+    *out = static_cast<T*>(p);
+    return CLAMP_OK;
+}
+
+// Evaluation-mode weights from the parameters and running statistics.
+hipError_t prep_eval(clamp_unet* u, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < kConvs && e == hipSuccess; ++l) {
+        const float* mean = u->stats + l * 2 * kWidth;
+        e = clampk::unet_fold_bn(u->params + conv_w(l), u->params + conv_gamma(l), u->params + conv_beta(l), mean,
+                                 mean + kWidth, cin_of(l), u->wfold, u->bfold, st);
+        if (e == hipSuccess)
+            e = clampk::cnn_prep(u->wfold, u->bfold, cin_of(l), kWidth, cinp_of(l), kWidth, u->wq[l], nullptr,
+                                 u->bias32[l], st);
+    }
+    for (int j = 0; j < kLevels && e == hipSuccess; ++j) e = clampk::unet_prep_up(u->params + up_w(j), u->wup[j], st);
+    if (e == hipSuccess)
+        e = clampk::cnn_prep(u->params + final_w(), u->params + final_b(), kWidth, 1, kWidth, 8, u->wq[kConvs],
+                             nullptr, u->bias32[kConvs], st);
+    return e;
+}
+
+ConvArgs conv_args(int32_t nvol, int32_t nz, int32_t ny, int32_t nx) {
+    ConvArgs a{};
+    a.nvol = nvol;
+    a.nz = nz;
+    a.ny = ny;
+    a.nx = nx;
+    return a;
+}
+
+// Evaluation-mode forward pass.
+hipError_t forward_eval(clamp_unet* u, const float* x, float* out, const float* scale, int32_t nvol, int32_t nz,
+                        int32_t ny, int32_t nx, void* ws, const Layout& L, hipStream_t st) {
+    const long nvox = (long)nvol * nz * ny * nx;
+    int dz[kLevels + 1], dy[kLevels + 1], dx[kLevels + 1];
+    for (int k = 0; k <= kLevels; ++k) {
+        dz[k] = nz >> k;
+        dy[k] = ny >> k;
+        dx[k] = nx >> k;
+    }
+    auto conv = [&](int l, int k, const uint16_t* in, uint16_t* o) {
+        ConvArgs a = conv_args(nvol, dz[k], dy[k], dx[k]);
+        a.in = in;
+        a.wq = u->wq[l];
+        a.bias = u->bias32[l];
+        a.out = o;
+        return clampk::cnn_conv(cinp_of(l), clampk::EPI_RELU, a, st);
+    };
+    uint16_t* x8 = at<uint16_t>(ws, L.x8);
+    uint16_t* e_[kLevels];
+    uint16_t* t[kLevels][2];
+    for (int k = 0; k < kLevels; ++k) {
+        e_[k] = at<uint16_t>(ws, L.e[k]);
+        t[k][0] = at<uint16_t>(ws, L.t[k][0]);
+        t[k][1] = at<uint16_t>(ws, L.t[k][1]);
+    }
+    uint16_t* p3 = at<uint16_t>(ws, L.p3);
+    hipError_t e = clampk::cnn_pack(x, scale, nvox, x8, st);
+    // encoder: block k reads the pooled output of block k - 1 (held in t[k][1])
+    const uint16_t* in = x8;
+    for (int k = 0; k < kLevels && e == hipSuccess; ++k) {
+        e = conv(2 * k, k, in, t[k][0]);
+        if (e == hipSuccess) e = conv(2 * k + 1, k, t[k][0], e_[k]);
+        uint16_t* pooled = k + 1 < kLevels ? t[k + 1][1] : p3;
+        if (e == hipSuccess) e = clampk::unet_pool(e_[k], pooled, nvol, dz[k], dy[k], dx[k], st);
+        in = pooled;
+    }
+    // decoder: block of level k = 2, 1, 0 (transposed convolution j = 2 - k)
+    for (int j = 0; j < kLevels && e == hipSuccess; ++j) {
+        const int k = kLevels - 1 - j;
+        clampk::UpArgs a{};
+        a.nvol = nvol;
+        a.nz = dz[k + 1];
+        a.ny = dy[k + 1];
+        a.nx = dx[k + 1];
+        a.in = in;
+        a.wf = u->wup[j];
+        a.bias = u->params + up_b(j);
+        a.skip = e_[k];
+        a.out = t[k][0];
+        e = clampk::unet_upconv(a, st);
+        const int l = 2 * kLevels + 2 * j;
+        if (e == hipSuccess) e = conv(l, k, t[k][0], t[k][1]);
+        if (e == hipSuccess) e = conv(l + 1, k, t[k][1], t[k][0]);
+        in = t[k][0];
+    }
+    if (e == hipSuccess) {
+        ConvArgs a = conv_args(nvol, nz, ny, nx);
+        a.in = in;
+        a.wq = u->wq[kConvs];
+        a.bias = u->bias32[kConvs];
+        a.out_f32 = out;
+        a.xin = x;
+        a.scale = scale;
+        e = clampk::cnn_conv(kWidth, clampk::EPI_FINAL, a, st);
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+clamp_status clamp_unet_create(clamp_unet** out) {
+    if (out == nullptr) return fail(CLAMP_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(CLAMP_EDEVICE, "no HIP device available");
+    clamp_unet* u = new clamp_unet();
+    clamp_status st = alloc(u, CLAMP_UNET_PARAMS, &u->params);
+    if (st == CLAMP_OK) st = alloc(u, CLAMP_UNET_STATS, &u->stats);
+    if (st == CLAMP_OK) st = alloc(u, 27 * kWidth * kWidth, &u->wfold);
+    if (st == CLAMP_OK) st = alloc(u, kWidth, &u->bfold);
+    for (int l = 0; l <= kConvs && st == CLAMP_OK; ++l) {
+        st = alloc(u, clampk::cnn_wq_elems(l == kConvs ? kWidth : cinp_of(l)), &u->wq[l]);
+        if (st == CLAMP_OK) st = alloc(u, 32, &u->bias32[l]);
+    }
+    for (int j = 0; j < kLevels && st == CLAMP_OK; ++j) st = alloc(u, 8 * 2 * 64 * 8, &u->wup[j]);
+    if (st == CLAMP_OK) {
+        std::vector<float> zero(CLAMP_UNET_PARAMS, 0.f);
+        st = clamp_unet_set_params(u, zero.data(), nullptr);
+    }
+    if (st != CLAMP_OK) {
+        clamp_unet_destroy(u);
+        return st;
+    }
+    *out = u;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_unet_destroy(clamp_unet* u) {
+    if (u == nullptr) return CLAMP_OK;
+    for (void* p : u->dev) (void)hipFree(p);
+    delete u;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_unet_set_params(clamp_unet* u, const float* params, const float* stats) {
+    if (u == nullptr || params == nullptr) return fail(CLAMP_EINVAL, "NULL argument");
+    for (long i = 0; i < CLAMP_UNET_PARAMS; ++i)
+        if (!std::isfinite(params[i])) return fail(CLAMP_EINVAL, "parameter %ld is not finite", i);
+    std::vector<float> s(CLAMP_UNET_STATS);
+    for (int l = 0; l < kConvs; ++l)
+        for (int c = 0; c < kWidth; ++c) {
+            const float m = stats ? stats[l * 2 * kWidth + c] : 0.f;
+            const float v = stats ? stats[l * 2 * kWidth + kWidth + c] : 1.f;
+            if (!std::isfinite(m) || !(v >= 0.f) || !std::isfinite(v))
+                return fail(CLAMP_EINVAL, "running statistics of layer %d channel %d are invalid", l, c);
+            s[l * 2 * kWidth + c] = m;
+            s[l * 2 * kWidth + kWidth + c] = v;
+        }
+    hipError_t e = hipMemcpy(u->params, params, sizeof(float) * CLAMP_UNET_PARAMS, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(u->stats, s.data(), sizeof(float) * CLAMP_UNET_STATS, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = prep_eval(u, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    u->eval_ready = e == hipSuccess;
+    return hip_check(e, "clamp_unet_set_params");
+}
+
+clamp_status clamp_unet_get_params(const clamp_unet* u, float* params, float* stats) {
+    if (u == nullptr) return fail(CLAMP_EINVAL, "NULL argument");
+    hipError_t e = hipSuccess;
+    if (params != nullptr) e = hipMemcpy(params, u->params, sizeof(float) * CLAMP_UNET_PARAMS, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && stats != nullptr)
+        e = hipMemcpy(stats, u->stats, sizeof(float) * CLAMP_UNET_STATS, hipMemcpyDeviceToHost);
+    return hip_check(e, "clamp_unet_get_params");
+}
+
+clamp_status clamp_unet_workspace_size(int32_t nvol, int32_t nz, int32_t ny, int32_t nx, int32_t train,
+                                       size_t* bytes) {
+    if (bytes == nullptr) return fail(CLAMP_EINVAL, "bytes is NULL");
+    clamp_status st = check_dims(nvol, nz, ny, nx);
+    if (st != CLAMP_OK) return st;
+    if (train != 0) return fail(CLAMP_EUNSUPPORTED, "training workspaces are not available");
+    *bytes = layout((long)nvol * nz * ny * nx).total;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_unet_apply(clamp_unet* u, const float* x, float* out, int32_t nvol, int32_t nz, int32_t ny,
+                              int32_t nx, int32_t normalize, void* workspace, void* hip_stream) {
+    if (u == nullptr || x == nullptr || out == nullptr || workspace == nullptr)
+        return fail(CLAMP_EINVAL, "NULL argument");
+    if (x == out) return fail(CLAMP_EINVAL, "x and out must not overlap");
+    clamp_status st = check_dims(nvol, nz, ny, nx);
+    if (st != CLAMP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const long nvox = (long)nvol * nz * ny * nx;
+    const Layout L = layout(nvox);
+    hipError_t e = hipSuccess;
+    if (!u->eval_ready) {
+        e = prep_eval(u, s);
+        u->eval_ready = e == hipSuccess;
+    }
+    float* mean = nullptr;
+    if (e == hipSuccess && normalize) {
+        mean = at<float>(workspace, L.mean);
+        e = clampk::cnn_mean(x, nvox, at<double>(workspace, L.part), mean, s);
+    }
+    if (e == hipSuccess) e = forward_eval(u, x, out, mean, nvol, nz, ny, nx, workspace, L, s);
+    return hip_check(e, "clamp_unet_apply launch");
+}
+
+}  // extern "C"

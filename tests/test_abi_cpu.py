@@ -81,3 +81,11 @@ def test_valid_plan_without_gpu_reports_device_error(lib):
         pytest.skip("a GPU is present")
     st, h = _create(lib, Scene(64, 64, 4, 2, 16.0, None))
     assert st == -4 and not h.value
+
+
+def test_unet_workspace_size_checks_shapes(lib):
+    b = ctypes.c_size_t()
+    ok = lib.clamp_unet_workspace_size(1, 8, 16, 128, 0, ctypes.byref(b))
+    assert ok == 0 and b.value > 0
+    for dims in ((1, 12, 16, 128), (1, 8, 20, 128), (1, 8, 16, 96), (0, 8, 16, 128)):
+        assert lib.clamp_unet_workspace_size(*dims, 0, ctypes.byref(b)) != 0
