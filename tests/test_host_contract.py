@@ -28,3 +28,17 @@ def test_package_import_fails_without_library(tmp_path):
                        env={**os.environ, "PYTHONPATH": str(tmp_path)})
     assert p.returncode != 0
     assert "libclamp.so is not built" in p.stderr
+
+
+def test_build_script_loads_without_the_library(tmp_path):
+    """build() must work in a fresh checkout, where libclamp.so does not exist
+    yet: the build script is loaded without importing the package."""
+    import shutil
+    shutil.copytree(os.path.join(ROOT, "paper_2406_13651_amd"), tmp_path / "paper_2406_13651_amd",
+                    ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__"))
+    shutil.copy(os.path.join(ROOT, "__graft_entry__.py"), tmp_path)
+    code = ("import sys, __graft_entry__ as g; m = g._build_module(); "
+            "assert callable(m.build) and 'paper_2406_13651_amd' not in sys.modules")
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=tmp_path,
+                       env={**os.environ, "PYTHONPATH": str(tmp_path)})
+    assert p.returncode == 0, p.stderr
