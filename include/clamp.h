@@ -374,11 +374,11 @@ clamp_status clamp_unet_destroy(clamp_unet* unet);
  * variances with CLAMP_EINVAL (nothing is changed). */
 clamp_status clamp_unet_set_params(clamp_unet* unet, const float* params, const float* stats);
 clamp_status clamp_unet_get_params(const clamp_unet* unet, float* params, float* stats);
-/* Workspace bytes for apply (train = 0) on nvol volumes of nz x ny x nx.
- * Errors shared by the sized calls: CLAMP_EINVAL for non-positive sizes or
- * NULL arguments, CLAMP_ESHAPE when nz or ny is not a multiple of 8, nx not
- * a multiple of 128, or nvol nz ny nx >= 2^31; CLAMP_EUNSUPPORTED for train
- * != 0 where training is not available. */
+/* Workspace bytes for apply (train = 0) or gradient (train = 1) calls on
+ * nvol volumes of nz x ny x nx.  Errors shared by the sized calls:
+ * CLAMP_EINVAL for non-positive sizes or NULL arguments, CLAMP_ESHAPE when nz
+ * or ny is not a multiple of 8, nx not a multiple of 128, or nvol nz ny nx >=
+ * 2^31. */
 clamp_status clamp_unet_workspace_size(int32_t nvol, int32_t nz, int32_t ny, int32_t nx, int32_t train,
                                        size_t* bytes);
 /* out = H(x) per volume (device float32 arrays), evaluation mode.
@@ -386,6 +386,18 @@ clamp_status clamp_unet_workspace_size(int32_t nvol, int32_t nz, int32_t ny, int
  * mean of all nvol volumes.  x and out must not overlap (CLAMP_EINVAL). */
 clamp_status clamp_unet_apply(clamp_unet* unet, const float* x, float* out, int32_t nvol, int32_t nz, int32_t ny,
                               int32_t nx, int32_t normalize, void* workspace, void* hip_stream);
+/* Training mode: mean squared error of H(x) against target over the batch
+ * into *loss (device double), with batch normalisation on the batch
+ * statistics (biased variance), and its gradient with respect to every
+ * parameter into grad (device float32 [CLAMP_UNET_PARAMS]; NULL keeps it
+ * inside the object for clamp_unet_adam_step).  Updates the running
+ * statistics (momentum 0.1, unbiased variance). */
+clamp_status clamp_unet_grad(clamp_unet* unet, const float* x, const float* target, int32_t nvol, int32_t nz,
+                             int32_t ny, int32_t nx, double* loss, float* grad, void* workspace, void* hip_stream);
+/* One Adam step with gradient-norm clipping, as clamp_cnn_adam_step, with
+ * the gradient of the last clamp_unet_grad call that kept it inside the
+ * object.  clamp_unet_set_params resets the Adam state. */
+clamp_status clamp_unet_adam_step(clamp_unet* unet, float lr, void* hip_stream);
 
 /* Optional per-stage timing (for benchmarks).  While enabled, every call
  * that takes a stream records a pair of HIP events on that stream around

@@ -116,6 +116,8 @@ def _load():
         "clamp_unet_get_params": [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
         "clamp_unet_workspace_size": [i32, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
         "clamp_unet_apply": [P, P, P, i32, i32, i32, i32, i32, P, P],
+        "clamp_unet_grad": [P, P, P, i32, i32, i32, i32, P, P, P, P],
+        "clamp_unet_adam_step": [P, ctypes.c_float, P],
         "clamp_plan_get_timing": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
@@ -521,3 +523,17 @@ def clamp_unet_apply(unet, x, out, normalize, workspace, stream=None):
                                 nvol, nz, ny, nx, 1 if normalize else 0,
                                 _ptr(workspace, torch.uint8, clamp_unet_workspace_size(nvol, nz, ny, nx, False),
                                      "workspace"), _stream(stream)))
+
+
+def clamp_unet_grad(unet, x, target, loss, workspace, grad=None, stream=None):
+    nvol, nz, ny, nx = x.shape
+    n = nvol * nz * ny * nx
+    g = _ptr(grad, torch.float32, UNET_PARAMS, "grad") if grad is not None else None
+    _check(lib.clamp_unet_grad(unet.handle, _ptr(x, torch.float32, n, "x"), _ptr(target, torch.float32, n, "target"),
+                               nvol, nz, ny, nx, _ptr(loss, torch.float64, 1, "loss"), g,
+                               _ptr(workspace, torch.uint8, clamp_unet_workspace_size(nvol, nz, ny, nx, True),
+                                    "workspace"), _stream(stream)))
+
+
+def clamp_unet_adam_step(unet, lr, stream=None):
+    _check(lib.clamp_unet_adam_step(unet.handle, float(lr), _stream(stream)))

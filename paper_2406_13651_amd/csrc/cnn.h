@@ -7,7 +7,12 @@
 
 namespace clampk {
 
-enum ConvEpi { EPI_RELU = 0, EPI_FINAL = 1, EPI_DGRAD = 2 };
+// Epilogues of the convolution: RELU stores ReLU(y + b); FINAL the one-channel
+// output layer x + m (y + b) in fp32; DGRAD the backward-data product masked
+// by the ReLU pattern of relu_src; RAW stores y unchanged (pre-activations
+// before batch normalisation, or a backward-data product through a layer
+// input that is no ReLU output).
+enum ConvEpi { EPI_RELU = 0, EPI_FINAL = 1, EPI_DGRAD = 2, EPI_RAW = 3 };
 
 struct ConvArgs {
     int nvol, nz, ny, nx;          // nx a multiple of 32

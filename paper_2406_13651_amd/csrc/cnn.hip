@@ -269,7 +269,7 @@ __device__ constexpr int store_share(int q) {
 
 template <int CIN, int EPI>
 __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
-    static_assert(EPI == EPI_RELU || EPI == EPI_DGRAD, "the final layer runs in k_conv_final");
+    static_assert(EPI == EPI_RELU || EPI == EPI_DGRAD || EPI == EPI_RAW, "the final layer runs in k_conv_final");
     using G = TileGeo<CIN>;
     __shared__ RingSlots<CIN> ring;
     __shared__ uint4 wsh[G::kW];
@@ -994,6 +994,8 @@ hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st) {
     if (cin == 32 && epi == EPI_FINAL) return launch_conv<k_conv_final>(a, total, st);
     if (cin == 8 && epi == EPI_DGRAD) return launch_conv<k_conv<8, EPI_DGRAD>>(a, total, st);
     if (cin == 32 && epi == EPI_DGRAD) return launch_conv<k_conv<32, EPI_DGRAD>>(a, total, st);
+    if (cin == 8 && epi == EPI_RAW) return launch_conv<k_conv<8, EPI_RAW>>(a, total, st);
+    if (cin == 32 && epi == EPI_RAW) return launch_conv<k_conv<32, EPI_RAW>>(a, total, st);
     return hipErrorInvalidValue;
 }
 

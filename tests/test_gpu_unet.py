@@ -172,3 +172,71 @@ def test_errors(C):
     bad[5] = np.nan
     with pytest.raises(RuntimeError):
         C.clamp_unet_set_params(net, bad)
+
+
+def _grad_groups(v):
+    """Gradient vector split by parameter group (flat layout of the oracle)."""
+    q = U.unflatten(np.asarray(v, dtype=np.float64))
+    out = {}
+    for i in range(U.CONVS):
+        out["conv%d" % i] = q["conv"][i]
+        out["gamma%d" % i] = q["gamma"][i]
+        out["beta%d" % i] = q["beta"][i]
+    for j in range(U.LEVELS):
+        out["up_w%d" % j] = q["up_w"][j]
+        out["up_b%d" % j] = q["up_b"][j]
+    out["final_w"] = q["final_w"]
+    out["final_b"] = q["final_b"]
+    return out
+
+
+@pytest.mark.parametrize("shape", [(2, 8, 8, 128)])
+def test_training_gradients_and_running_statistics(C, shape):
+    """Training mode (batch statistics) against the oracle's backward pass
+    with the same bf16 roundings: the loss, every parameter group's gradient,
+    and the running statistics after the call."""
+    import torch
+    p, _ = _params(9, last_scale=1.0)
+    p16 = U.unflatten(U.flatten(p))
+    for i in range(U.CONVS):
+        p16["conv"][i] = ocnn.bf16_round(p16["conv"][i])
+    for j in range(U.LEVELS):
+        p16["up_w"][j] = ocnn.bf16_round(p16["up_w"][j])
+    p16["final_w"] = ocnn.bf16_round(p16["final_w"])
+    net = C.clamp_unet_create()
+    C.clamp_unet_set_params(net, U.flatten(p))
+    rng = np.random.default_rng(10)
+    x = rng.uniform(0.05, 1.0, shape).astype(np.float32).astype(np.float64)
+    t = rng.uniform(0.05, 1.0, shape).astype(np.float32).astype(np.float64)
+    xt, tt = torch.from_numpy(x.astype(np.float32)).cuda(), torch.from_numpy(t.astype(np.float32)).cuda()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = torch.zeros(C.UNET_PARAMS, dtype=torch.float32, device="cuda")
+    ws = torch.empty(C.clamp_unet_workspace_size(*shape, True), dtype=torch.uint8, device="cuda")
+    C.clamp_unet_grad(net, xt, tt, loss, ws, grad=g)
+    torch.cuda.synchronize()
+    ref_loss, ref = U.loss_and_grads(x, t, p16, act_round=True)
+    _, ref64 = U.loss_and_grads(x, t, p16, act_round=False)
+    assert abs(loss.item() - ref_loss) <= 1e-2 * ref_loss
+    got = _grad_groups(g.cpu().numpy())
+    rnd = _grad_groups(U.flatten(ref))
+    unr = _grad_groups(U.flatten(ref64))
+    # bf16 storage of the gradients, amplified by the batch normalisation
+    # backward (dy - mean(dy) - xhat mean(dy xhat) cancels), moves the rounded
+    # oracle's gradients from the unrounded ones by 1e-3 (output layer) to
+    # ~0.3 (first encoder block); the kernels round at the same points from
+    # fp32 sums.  Per parameter group, the GPU must be no farther from the
+    # unrounded oracle than 1.5 times the rounded oracle is, plus 1e-3.
+    worst = 0.0
+    for k in got:
+        budget = rel_l2(rnd[k], unr[k])
+        err = rel_l2(got[k], unr[k])
+        print("grad %-8s vs unrounded %.3e budget %.3e vs rounded %.3e" % (k, err, budget, rel_l2(got[k], rnd[k])))
+        worst = max(worst, err / (1.5 * budget + 1e-3))
+    assert report("unet training gradients (worst group / its bound)", worst, 1.0) <= 1.0
+    # running statistics: momentum 0.1 from (0, 1) towards the batch statistics
+    stats = U.init_stats()
+    U.forward(x, p16, True, stats, act_round=True)
+    _, got_s = C.clamp_unet_get_params(net)
+    ref_s = _stats_vector(stats)
+    err = rel_l2(got_s.astype(np.float64), ref_s.astype(np.float64))
+    assert report("unet running statistics after one step", err, 1e-3) <= 1e-3
