@@ -201,6 +201,13 @@ def run_batch(args):
 
 CNN_FWD_FLOP = 335_232      # per voxel: 2 * 27 * (1*32 + 6*32*32 + 32*1)
 CNN_TRAIN_FLOP = 1_003_968  # forward + input gradients of layers 2-8 + weight gradients of all 8
+# U-Net forward, algorithmic flop per full-resolution voxel: 3x3x3
+# convolutions (1 -> 32: 1,728; 32 -> 32: 55,296) at level k cost 1/8^k per
+# voxel (level 0: 1 + 3 of 32 -> 32, levels 1 and 2: 4 each), transposed
+# convolutions 2,048 per output voxel at levels 0, 1, 2, the output layer 1,728
+UNET_FWD_FLOP = 1728 + 3 * 55296 + 4 * 55296 // 8 + 4 * 55296 // 64 + 2048 + 2048 // 8 + 2048 // 64 + 1728
+# training: forward, input gradients (none for the first layer) and weight gradients
+UNET_TRAIN_FLOP = 3 * UNET_FWD_FLOP - 1728
 BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -218,17 +225,21 @@ def run_learned(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log("training pairs: %d volumes of 64x64x32 (%s inputs, noise %g)" % (args.train_pairs, args.train_mode,
-                                                                          args.train_noise))
+    unet = args.prior == "unet"
+    # U-Net patches: nx a multiple of 128 (32-voxel tiles at the third level)
+    pz, py, px = (32, 32, 128) if unet else (32, 64, 64)
+    log("training pairs: %d volumes of %dx%dx%d (%s inputs, noise %g)" % (args.train_pairs, px, py, pz,
+                                                                         args.train_mode, args.train_noise))
     t0 = time.perf_counter()
-    X, T = Lm.make_pairs(args.train_pairs, seed=0, mode=args.train_mode, noise=args.train_noise)
+    X, T = Lm.make_pairs(args.train_pairs, seed=0, nz=pz, ny=py, nx=px, mode=args.train_mode, noise=args.train_noise)
     t_pairs = time.perf_counter() - t0
-    prior = Lm.CnnPrior(Lm.init_params(0), device=dev)
+    prior = (Lm.UnetPrior(Lm.unet_init_params(0), device=dev) if unet else Lm.CnnPrior(Lm.init_params(0), device=dev))
+    fwd_flop, train_flop = (UNET_FWD_FLOP, UNET_TRAIN_FLOP) if unet else (CNN_FWD_FLOP, CNN_TRAIN_FLOP)
     log("training %d epochs, lr %g" % (args.train_epochs, args.lr))
     hist = Lm.train(prior, X, T, epochs=args.train_epochs, lr=args.lr,
                     log=lambda m: log("  " + m))
     del X, T
-    train_tflops = hist["voxels"] * CNN_TRAIN_FLOP / hist["seconds"] / 1e12
+    train_tflops = hist["voxels"] * train_flop / hist["seconds"] / 1e12
 
     spec = synth.CONFIGS["learned"]
     log("evaluation scene %dx%dx%d, %d looks" % (spec.nx, spec.ny, spec.nz, spec.looks))
@@ -282,9 +293,9 @@ def run_learned(args):
     ev1.record()
     torch.cuda.synchronize()
     cnn_ms = ev0.elapsed_time(ev1) / reps
-    cnn_tflops = spec.n * CNN_FWD_FLOP / (cnn_ms * 1e-3) / 1e12
+    cnn_tflops = spec.n * fwd_flop / (cnn_ms * 1e-3) / 1e12
 
-    rec = counter_traffic("cnn_apply_64x256x256", "cnn")
+    rec = None if unet else counter_traffic("cnn_apply_64x256x256", "cnn")
     cnn_traffic = round(rec["read_bytes"] + rec["write_bytes"]) if rec is not None else None
     target = out["plain"]["nrmse"][min(50, iters)]
     equal = {"target_nrmse": target, "target": "NRMSE of the plain form (Gaussian prior) at iteration %d"
@@ -315,18 +326,21 @@ def run_learned(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (forward agents), bf16 with f32 accumulation (CNN)",
+        "dtype": "f32 (forward agents), bf16 with f32 accumulation (%s)" % ("U-Net" if unet else "CNN"),
         "data": "synthetic",
-        "config": {"workload": "learned form: CLAMP iteration with the CNN prior agent, %dx%dx%d, %d looks, "
-                               "pupil radius %g, SNR %g dB; CNN trained on %d seeded 64x64x32 denoising pairs"
-                               % (spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, spec.snr_db,
-                                  args.train_pairs),
-                   "sigma2": args.sigma2, "train_epochs": args.train_epochs, "lr": args.lr,
+        "config": {"workload": "learned form: CLAMP iteration with the %s prior agent, %dx%dx%d, %d looks, "
+                               "pupil radius %g, SNR %g dB; trained on %d seeded %dx%dx%d denoising pairs"
+                               % ("U-Net" if unet else "CNN", spec.nx, spec.ny, spec.nz, spec.looks, spec.radius,
+                                  spec.snr_db, args.train_pairs, px, py, pz),
+                   "prior": args.prior, "sigma2": args.sigma2, "train_epochs": args.train_epochs, "lr": args.lr,
                    "train_mode": args.train_mode, "train_noise": args.train_noise},
-        "roofline": {"bound": "mfma", "kernel": "cnn_apply (8 convolutions)", "achieved": round(cnn_tflops, 2),
-                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(cnn_tflops / BF16_PEAK_TFLOPS, 4),
-                     "traffic": cnn_traffic},
-        "cnn_apply_ms": round(cnn_ms, 3),
+        "roofline": {"bound": "mfma",
+                     "kernel": ("unet_apply (13 convolutions, 3 transposed)" if unet
+                                else "cnn_apply (8 convolutions)"),
+                     "achieved": round(cnn_tflops, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(cnn_tflops / BF16_PEAK_TFLOPS, 4), "traffic": cnn_traffic},
+        "prior_apply_ms": round(cnn_ms, 3),
+        "cnn_apply_ms": None if unet else round(cnn_ms, 3),
         "training": {"pairs": args.train_pairs, "pair_synthesis_s": round(t_pairs, 2), "steps": hist["steps"],
                      "seconds": round(hist["seconds"], 2), "voxels_per_s": hist["voxels"] / hist["seconds"],
                      "tflops": round(train_tflops, 2), "frac_bf16_peak": round(train_tflops / BF16_PEAK_TFLOPS, 4),
@@ -552,6 +566,8 @@ def main():
                     help="largest total voxel-looks of the uneven batch draw (--workload batch)")
     ap.add_argument("--train-pairs", type=int, default=2000, help="training volumes (--workload learned)")
     ap.add_argument("--train-epochs", type=int, default=30)
+    ap.add_argument("--prior", default="cnn", choices=("cnn", "unet"),
+                    help="learned workload: the 8-layer CNN or the U-Net prior")
     ap.add_argument("--train-mode", default="awgn", choices=("awgn", "speckle"))
     ap.add_argument("--train-noise", type=float, default=0.3,
                     help="awgn pairs: noise standard deviation U[0, train_noise] max(target)")

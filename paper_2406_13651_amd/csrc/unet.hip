@@ -262,15 +262,38 @@ __global__ __launch_bounds__(kBlock) void k_chan_sums(const uint16_t* X, const u
 // FIN_SUM: sum x into out (a bias gradient).
 enum FinMode { FIN_STATS = 0, FIN_BWD = 1, FIN_SUM = 2 };
 
-__global__ void k_chan_finalize(int mode, const double* part, int blocks, long m, const float* gamma,
-                                const float* beta, float* mean, float* rstd, float* A, float* B, float* Cc,
-                                float* run_mean, float* run_var, float* out0, float* out1) {
-    const int c = threadIdx.x;
-    if (c >= 32) return;
+// 1024 threads: lane k of channel c (thread 32 k + c) sums the partials of
+// blocks k, k + 32, ... in order, then thread c adds the 32 lane sums in order.
+__global__ __launch_bounds__(1024) void k_chan_finalize(int mode, const double* part, int blocks, long m,
+                                                        const float* gamma, const float* beta, float* mean,
+                                                        float* rstd, float* A, float* B, float* Cc, float* run_mean,
+                                                        float* run_var, float* out0, float* out1) {
+    __shared__ double lanes[32][32][2];
+    const int c = threadIdx.x & 31, k = threadIdx.x >> 5;
+    double a1 = 0.0, a2 = 0.0;
+    int b = k;
+    for (; b + 96 < blocks; b += 128) {  // four independent loads in flight
+        double2 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = *reinterpret_cast<const double2*>(part + ((long)(b + 32 * u) * 32 + c) * 2);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a1 += q[u].x;
+            a2 += q[u].y;
+        }
+    }
+    for (; b < blocks; b += 32) {
+        a1 += part[((long)b * 32 + c) * 2 + 0];
+        a2 += part[((long)b * 32 + c) * 2 + 1];
+    }
+    lanes[k][c][0] = a1;
+    lanes[k][c][1] = a2;
+    __syncthreads();
+    if (k != 0) return;
     double s1 = 0.0, s2 = 0.0;
-    for (int b = 0; b < blocks; ++b) {
-        s1 += part[((long)b * 32 + c) * 2 + 0];
-        s2 += part[((long)b * 32 + c) * 2 + 1];
+    for (int j = 0; j < 32; ++j) {
+        s1 += lanes[j][c][0];
+        s2 += lanes[j][c][1];
     }
     if (mode == FIN_STATS) {
         const double mu = s1 / (double)m;
@@ -590,8 +613,8 @@ hipError_t unet_chan_sums(int mode, const uint16_t* X, const uint16_t* Y, const 
 hipError_t unet_chan_finalize(int mode, const double* part, int blocks, long m, const float* gamma, const float* beta,
                               float* mean, float* rstd, float* A, float* B, float* C, float* run_mean,
                               float* run_var, float* out0, float* out1, hipStream_t st) {
-    hipLaunchKernelGGL(k_chan_finalize, dim3(1), dim3(32), 0, st, mode, part, blocks, m, gamma, beta, mean, rstd, A, B,
-                       C, run_mean, run_var, out0, out1);
+    hipLaunchKernelGGL(k_chan_finalize, dim3(1), dim3(1024), 0, st, mode, part, blocks, m, gamma, beta, mean, rstd, A,
+                       B, C, run_mean, run_var, out0, out1);
     return hipGetLastError();
 }
 

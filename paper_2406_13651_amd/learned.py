@@ -73,6 +73,81 @@ class CnnPrior:
         shape = tuple(x.shape) if x.dim() == 4 else (1,) + tuple(x.shape)
         C.clamp_cnn_apply(self.net, x, out, normalize, self.workspace(shape, False))
 
+    def grad(self, x, t, loss, ws, grad=None):
+        C.clamp_cnn_grad(self.net, x, t, loss, ws, grad=grad)
+
+    def adam_step(self, lr):
+        C.clamp_cnn_adam_step(self.net, lr)
+
+    def val_loss(self, x, t, ws, vgrad):
+        loss = torch.zeros(1, dtype=torch.float64, device=x.device)
+        C.clamp_cnn_grad(self.net, x, t, loss, ws, grad=vgrad)
+        return float(loss.item())
+
+    n_params = C.CNN_PARAMS
+
+
+class UnetPrior:
+    """The U-Net prior (Sec. III-C's architecture) on the GPU, evaluation mode
+    for apply, training mode (batch statistics) for grad; workspaces cached
+    per shape.  params() and set_params() carry the parameters together with
+    the running statistics of its batch normalisation."""
+
+    n_params = C.UNET_PARAMS
+
+    def __init__(self, params=None, device="cuda"):
+        self.dev = torch.device(device)
+        self.net = C.clamp_unet_create()
+        C.clamp_unet_set_params(self.net, unet_init_params() if params is None else params)
+        self._ws = {}
+
+    def params(self):
+        return C.clamp_unet_get_params(self.net)
+
+    def set_params(self, p):
+        params, stats = p if isinstance(p, tuple) else (p, None)
+        C.clamp_unet_set_params(self.net, params, stats)
+
+    def workspace(self, shape, train):
+        key = (tuple(shape), bool(train))
+        if key not in self._ws:
+            self._ws[key] = torch.empty(max(C.clamp_unet_workspace_size(*shape, train), 256), dtype=torch.uint8,
+                                        device=self.dev)
+        return self._ws[key]
+
+    def apply(self, x, out, normalize=True):
+        shape = tuple(x.shape) if x.dim() == 4 else (1,) + tuple(x.shape)
+        C.clamp_unet_apply(self.net, x, out, normalize, self.workspace(shape, False))
+
+    def grad(self, x, t, loss, ws, grad=None):
+        C.clamp_unet_grad(self.net, x, t, loss, ws, grad=grad)
+
+    def adam_step(self, lr):
+        C.clamp_unet_adam_step(self.net, lr)
+
+    def val_loss(self, x, t, ws, vgrad):
+        """Evaluation mode (running statistics; the training-mode gradient pass
+        would move them): mean squared error of H(x)."""
+        out = torch.empty_like(x)
+        self.apply(x, out, normalize=False)
+        return float(torch.mean((out.double() - t.double()) ** 2).item())
+
+
+def unet_init_params(seed=0, last_scale=0.0, width=32, levels=3):
+    """He-normal convolution and transposed-convolution weights, BN gamma 1
+    and beta 0, zero biases, as one flat float32 vector in the library's
+    parameter order; the output layer scaled by last_scale."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for i in range(4 * levels):
+        ci = 1 if i == 0 else width
+        parts += [(rng.standard_normal((27, ci, width)) * math.sqrt(2.0 / (27 * ci))).ravel(), np.ones(width),
+                  np.zeros(width)]
+    for _ in range(levels):
+        parts += [(rng.standard_normal((8, width, width)) * math.sqrt(1.0 / width)).ravel(), np.zeros(width)]
+    parts += [(rng.standard_normal((27, width, 1)) * math.sqrt(2.0 / (27 * width)) * last_scale).ravel(), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
 
 def make_pairs(n, seed=0, nz=32, ny=64, nx=64, looks=(4, 8, 16), snr_db=10.0, mode="awgn", noise=0.1,
                device="cuda", workers=16):
@@ -121,7 +196,7 @@ def train(prior, X, T, epochs=10, batch=24, lr=1e-3, decay=0.975, decay_every=30
     shape = (batch,) + tuple(X.shape[1:])
     ws = prior.workspace(shape, True)
     loss = torch.zeros(1, dtype=torch.float64, device=X.device)
-    vgrad = torch.empty(C.CNN_PARAMS, dtype=torch.float32, device=X.device)
+    vgrad = torch.empty(prior.n_params, dtype=torch.float32, device=X.device)
     rng = np.random.Generator(np.random.PCG64(seed))
     best = (math.inf, prior.params())
     hist = {"train": [], "val": [], "seconds": 0.0, "steps": 0, "voxels": 0}
@@ -133,21 +208,19 @@ def train(prior, X, T, epochs=10, batch=24, lr=1e-3, decay=0.975, decay_every=30
         for b0 in range(0, n_tr - batch + 1, batch):
             idx = torch.from_numpy(order[b0:b0 + batch]).to(X.device)
             xb, tb = X.index_select(0, idx).contiguous(), T.index_select(0, idx).contiguous()
-            C.clamp_cnn_grad(prior.net, xb, tb, loss, ws)
-            C.clamp_cnn_adam_step(prior.net, lr * decay ** (step // decay_every))
+            prior.grad(xb, tb, loss, ws)
+            prior.adam_step(lr * decay ** (step // decay_every))
             step += 1
             tl.append(loss)
             loss = torch.zeros(1, dtype=torch.float64, device=X.device)
         vl = []
         for b0 in range(n_tr, n - batch + 1, batch):
             xb, tb = X[b0:b0 + batch].contiguous(), T[b0:b0 + batch].contiguous()
-            C.clamp_cnn_grad(prior.net, xb, tb, loss, ws, grad=vgrad)
-            vl.append(float(loss.item()))
+            vl.append(prior.val_loss(xb, tb, ws, vgrad))
         if not vl:  # fewer validation volumes than a batch: evaluate them padded with training volumes
             xb = torch.cat([X[n_tr:], X[:batch - n_val]]).contiguous()
             tb = torch.cat([T[n_tr:], T[:batch - n_val]]).contiguous()
-            C.clamp_cnn_grad(prior.net, xb, tb, loss, ws, grad=vgrad)
-            vl.append(float(loss.item()))
+            vl.append(prior.val_loss(xb, tb, ws, vgrad))
         tr = float(np.mean([x.item() for x in tl])) if tl else math.nan
         va = float(np.mean(vl))
         hist["train"].append(tr)

@@ -240,3 +240,26 @@ def test_training_gradients_and_running_statistics(C, shape):
     ref_s = _stats_vector(stats)
     err = rel_l2(got_s.astype(np.float64), ref_s.astype(np.float64))
     assert report("unet running statistics after one step", err, 1e-3) <= 1e-3
+
+
+def test_adam_steps_reduce_loss(C):
+    """Training-mode steps through clamp_unet_grad and clamp_unet_adam_step
+    towards a target the output bias alone can reach (H(x) = x + 0.1)."""
+    import torch
+    p, _ = _params(11, last_scale=0.1)
+    net = _make(C, p, {"mean": [np.zeros(32)] * U.CONVS, "var": [np.ones(32)] * U.CONVS})
+    rng = np.random.default_rng(12)
+    x = rng.uniform(0.05, 1.0, (4, 8, 16, 128)).astype(np.float32)
+    xt, tt = torch.from_numpy(x).cuda(), torch.from_numpy(x + 0.1).cuda()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(C.clamp_unet_workspace_size(*x.shape, True), dtype=torch.uint8, device="cuda")
+    losses = []
+    for _ in range(30):
+        C.clamp_unet_grad(net, xt, tt, loss, ws)
+        C.clamp_unet_adam_step(net, 1e-2)
+        torch.cuda.synchronize()
+        losses.append(loss.item())
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 * losses[0]
+    # the running statistics moved away from (0, 1) and stay finite
+    _, stats = C.clamp_unet_get_params(net)
+    assert np.all(np.isfinite(stats)) and not np.allclose(stats[32:64], 1.0)
