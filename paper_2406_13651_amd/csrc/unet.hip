@@ -548,12 +548,21 @@ __global__ __launch_bounds__(kBlock) void k_upconv_wgrad(UpBwdArgs a, float* par
     }
 }
 
-// out[e] = sum over blocks of part[block][e] (fixed order), e < n.
+// out[e] = sum over blocks of part[block][e] (fixed order), e < n; eight
+// independent loads in flight per step.
 __global__ __launch_bounds__(kBlock) void k_sum_blocks(const float* part, int blocks, int n, float* out) {
     const int e = blockIdx.x * kBlock + threadIdx.x;
     if (e >= n) return;
     float acc = 0.f;
-    for (int b = 0; b < blocks; ++b) acc += part[(long)b * n + e];
+    int b = 0;
+    for (; b + 8 <= blocks; b += 8) {
+        float q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = part[(long)(b + u) * n + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += q[u];
+    }
+    for (; b < blocks; ++b) acc += part[(long)b * n + e];
     out[e] = acc;
 }
 
