@@ -3,6 +3,8 @@ reconstruction object (no GPU)."""
 
 import math
 
+import numpy as np
+
 import torch
 
 from paper_2406_13651_amd import learned as Lm
@@ -60,3 +62,21 @@ def test_nrmse_is_scale_free():
     assert Lm.nrmse(7.0 * r, r) < 1e-6  # float32 rounding of 7 r
     noisy = r + 0.01 * torch.randn(3, 4, 5)
     assert abs(Lm.nrmse(3.0 * noisy, r) - Lm.nrmse(noisy, r)) < 1e-6
+
+
+def test_unet_initial_parameters_follow_the_library_layout():
+    """unet_init_params lays out the flat vector in the order of the C
+    interface (the oracle's flatten order): gamma 1, beta 0, zero biases and
+    a zero output layer where that order puts them."""
+    from oracle import unet as U
+    from paper_2406_13651_amd import _clamp as C
+    from paper_2406_13651_amd.learned import unet_init_params
+    p = unet_init_params(0)
+    assert p.size == C.UNET_PARAMS == U.param_count()
+    q = U.unflatten(p.astype(np.float64))
+    for i in range(U.CONVS):
+        assert np.all(q["gamma"][i] == 1.0) and np.all(q["beta"][i] == 0.0)
+        assert np.std(q["conv"][i]) > 0.0
+    for j in range(U.LEVELS):
+        assert np.all(q["up_b"][j] == 0.0) and np.std(q["up_w"][j]) > 0.0
+    assert np.all(q["final_w"] == 0.0) and np.all(q["final_b"] == 0.0)
