@@ -215,39 +215,46 @@ __global__ __launch_bounds__(kBlock) void k_init_floor(size_t n, int n_agents, c
 
 // ---------------------------------------------------------------------------
 // Mann step: two adjacent voxels per thread, every agent's w and r held in
-// registers (NA >= n_agents, a multiple of 8).  Each agent's slice is
-// addressed from a wave-uniform base pointer plus a 32-bit voxel offset.
+// registers (NA >= n_agents, a multiple of 4).  Every load is unconditional so
+// that all 2 NA of them are in flight at once: the NA - n_agents padding
+// agents re-read the last agent, with weight 0 in the averages, and store
+// nothing.  Each agent's slice is addressed from a wave-uniform base pointer
+// plus a 32-bit byte offset (n <= 2^30).
 template <int NA>
 __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
     const unsigned n = (unsigned)a.n;
     const unsigned n2 = n / 2;
+    const int na = a.n_agents;
     double num = 0.0, den = 0.0;
     for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n2; i += gridDim.x * kBlock) {
+        const unsigned off = i * 8u;
         float2 wv[NA], rv[NA];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            const size_t base = (size_t)(j < na ? j : na - 1) * n;
+            wv[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.w + base) + off);
+            rv[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.r + base) + off);
+        }
         float2 wb = make_float2(0.f, 0.f), rb = make_float2(0.f, 0.f);
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-            if (j < a.n_agents) {
-                wv[j] = reinterpret_cast<const float2*>(a.w + (size_t)j * n)[i];
-                rv[j] = reinterpret_cast<const float2*>(a.r + (size_t)j * n)[i];
-                const float u = a.ups[j];
-                wb.x += u * wv[j].x;
-                wb.y += u * wv[j].y;
-                rb.x += u * rv[j].x;
-                rb.y += u * rv[j].y;
-            }
+            const float u = a.ups[j];
+            wb.x += u * wv[j].x;
+            wb.y += u * wv[j].y;
+            rb.x += u * rv[j].x;
+            rb.y += u * rv[j].y;
         }
         const float2 xb = make_float2(2.f * rb.x - wb.x, 2.f * rb.y - wb.y);
         float2 wbn = make_float2(0.f, 0.f);
         float nm = 0.f;
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
-            if (j < a.n_agents) {
+            if (j < na) {
                 const float dx = rv[j].x - wb.x, dy = rv[j].y - wb.y;
                 nm += dx * dx + dy * dy;
                 const float2 wn = make_float2(wv[j].x + a.two_rho * (xb.x - rv[j].x),
                                               wv[j].y + a.two_rho * (xb.y - rv[j].y));
-                reinterpret_cast<float2*>(a.w + (size_t)j * n)[i] = wn;
+                *reinterpret_cast<float2*>(reinterpret_cast<char*>(a.w + (size_t)j * n) + off) = wn;
                 const float u = a.ups[j];
                 wbn.x += u * wn.x;
                 wbn.y += u * wn.y;
@@ -255,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
         }
         reinterpret_cast<float2*>(a.wbar)[i] = wbn;
         num += nm;
-        den += (double)a.n_agents * ((double)wb.x * wb.x + (double)wb.y * wb.y);
+        den += (double)na * ((double)wb.x * wb.x + (double)wb.y * wb.y);
     }
     double v[2] = {num, den};
     block_sum_store<2>(v, a.part + (size_t)blockIdx.x * 2);
@@ -430,14 +437,15 @@ hipError_t launch_init_floor(size_t n, int n_agents, const double* mean_r0, floa
 }
 
 hipError_t launch_mace(const MaceArgs& a, hipStream_t st) {
-    if (a.n % 2 != 0) return hipErrorInvalidValue;
+    if (a.n % 2 != 0 || a.n > ((size_t)1 << 30) || a.n_agents < 1) return hipErrorInvalidValue;
     const dim3 grid(mace_blocks(a.n));
-    switch ((a.n_agents + 7) / 8) {
+    switch ((a.n_agents + 3) / 4) {
 #define CASE(K)                                                              \
     case K:                                                                  \
-        hipLaunchKernelGGL(k_mace<8 * K>, grid, dim3(kBlock), 0, st, a);     \
+        hipLaunchKernelGGL(k_mace<4 * K>, grid, dim3(kBlock), 0, st, a);     \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE
         default:
             return hipErrorInvalidValue;

@@ -536,20 +536,24 @@ __device__ __forceinline__ void diag_after_item(int look, int nrow, int nres, co
 }
 
 // Mann step of voxel i with every agent's w and r in registers (NA >=
-// n_agents); returns (sum_j (r_j - w_bar)^2, n_agents w_bar^2).
+// n_agents); returns (sum_j (r_j - w_bar)^2, n_agents w_bar^2).  The loads
+// are unconditional so that all of them are in flight at once: padding agents
+// re-read the last agent and carry weight 0 (ups[j] = 0 for j >= n_agents).
 template <int NA>
 __device__ __forceinline__ void mace_voxel(const MaceArgs& a, const float* ups, unsigned n, unsigned i, double& num,
                                            double& den) {
     float wv[NA], rv[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        const size_t base = (size_t)(j < a.n_agents ? j : a.n_agents - 1) * n;
+        wv[j] = (a.w + base)[i];
+        rv[j] = (a.r + base)[i];
+    }
     float wb = 0.f, rb = 0.f;
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-        if (j < a.n_agents) {
-            wv[j] = (a.w + (size_t)j * n)[i];
-            rv[j] = (a.r + (size_t)j * n)[i];
-            wb += ups[j] * wv[j];
-            rb += ups[j] * rv[j];
-        }
+        wb += ups[j] * wv[j];
+        rb += ups[j] * rv[j];
     }
     const float xb = 2.f * rb - wb;
     float wbn = 0.f, nm = 0.f;

@@ -142,6 +142,31 @@ def test_prior_and_mann_step_match_oracle(G):
     assert abs(g.conv_err() - ce) <= 1e-5 * ce
 
 
+@pytest.mark.parametrize("L,with_prior", [(3, False), (6, True), (16, True), (40, False)])
+def test_mann_step_agent_counts(G, L, with_prior):
+    """Agent counts that are and are not multiples of the kernel's register
+    block (padding agents must neither contribute nor be written)."""
+    import torch
+    rng = np.random.default_rng(10 + L)
+    nx, ny, nz = 64, 32, 4
+    g = G.ClampGPU(nx, ny, nz, L, 8.0, 0.01, 1e-3, with_prior=with_prior)
+    na = L + int(with_prior)
+    w = rng.uniform(0.05, 1.0, (na, nz, ny, nx)).astype(np.float32)
+    r = rng.uniform(0.05, 1.0, (na, nz, ny, nx)).astype(np.float32)
+    g.w.copy_(to_gpu(w))
+    g.r.copy_(to_gpu(r))
+    g.mace()
+    torch.cuda.synchronize()
+    ups = oracle.agent_weights(L, with_prior)
+    w64, r64 = w.astype(np.float64), r.astype(np.float64)
+    wn = oracle.mann_step(w64, r64, ups, 0.5)
+    assert report("mann w, %d agents" % na, rel_l2(g.w.cpu().numpy(), wn), 1e-6) <= 1e-6
+    assert rel_l2(g.wbar.cpu().numpy(), oracle.weighted_average(wn, ups)) <= 1e-6
+    np.testing.assert_array_equal(g.r.cpu().numpy(), r)
+    ce = oracle.convergence_error(r64, w64, ups)
+    assert abs(g.conv_err() - ce) <= 1e-5 * ce
+
+
 def _run_pair(G, spec, sigma2, iters, with_prior, r_update="quadratic"):
     import torch
     r_true, y, s2w = synth.make_problem(spec, 0)
