@@ -215,13 +215,13 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
             }
         }
     };
-    if constexpr (PREFETCH) load_streams();
     __syncthreads();  // the previous item's readers of the LDS buffers are done
     if (load_tables) {
         for (int i = tid; i < NX; i += kBlock) {
             L.tw[i] = s.tw_x[i];
             L.bpos[i] = s.band_pos[i];
-            L.bcol[i] = i < s.B ? s.band_cols[i] : 0;
+            const int bc = s.band_cols[i < s.B ? i : 0];  // unconditional: one wait for all three tables
+            L.bcol[i] = i < s.B ? bc : 0;
         }
         __syncthreads();
     }
@@ -231,11 +231,28 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
         if (active)
             for (int x = t; x < NX; x += TR) rb[lds_pos<PAD>(x)] = a.img_in[img + x];
     } else {
-        if (active)
-            for (int x = t; x < NX; x += TR) {
-                const int bp = L.bpos[x];
-                rb[lds_pos<PAD>(x)] = bp >= 0 ? a.band_in[band + bp] : make_float2(0.f, 0.f);
+        // The row's band samples: all PX loads are issued before the first
+        // is used (samples off the band read the row's first band sample and
+        // are replaced by zero), then the pointwise streams are prefetched
+        // behind them.
+        float2 bin[PX];
+        int bp[PX];
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                bp[k] = (NX % TR == 0 || x < NX) ? L.bpos[x] : -1;
+                bin[k] = a.band_in[band + (bp[k] >= 0 ? bp[k] : 0)];
             }
+        }
+        if constexpr (PREFETCH) load_streams();
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) rb[lds_pos<PAD>(x)] = bp[k] >= 0 ? bin[k] : make_float2(0.f, 0.f);
+            }
+        }
     }
     fft_lds<NX, TR, S1, PAD>(rb, 1, t, L.tw);
 
