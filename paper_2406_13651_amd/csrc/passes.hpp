@@ -352,6 +352,32 @@ __device__ __forceinline__ void col_inv_item(const ColArgs& a, int item, float2*
     const int tile_i = item % s.tiles;
     const int zl = item / s.tiles;  // look * nz + z
     const int c0 = tile_i * TC;
+    // Scatter of column bc's pupil samples p in [p0, p1): lane l takes p0 + l,
+    // p0 + l + TPC, ..., in chunks of CH whose loads are all issued before the
+    // first is used (positions past p1 re-read the column's last sample and
+    // are dropped).  The first chunk is loaded before the tile is cleared.
+    constexpr int CH = 8;
+    const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
+    const bool col = bc < s.B;
+    const float2* src = a.cmp_in + (size_t)zl * s.P;
+    int p0 = 0, p1 = 0;
+    if (col) {
+        p0 = s.col_off[bc];
+        p1 = s.col_off[bc + 1];
+    }
+    float2 v[CH];
+    int ry[CH];
+    auto load_chunk = [&](int base) {
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int p = base + k * TPC;
+            const int pc = p < p1 ? p : p1 - 1;
+            v[k] = src[pc];
+            ry[k] = s.row_idx[pc];
+        }
+    };
+    int base = p0 + lane;
+    if (base < p1) load_chunk(base);
     __syncthreads();  // the previous item's readers of the LDS buffers are done
     if (load_tables)
         for (int i = tid; i < NY; i += kBlock) tw[i] = s.tw_y[i];
@@ -359,25 +385,26 @@ __device__ __forceinline__ void col_inv_item(const ColArgs& a, int item, float2*
     __syncthreads();
     double acc[1] = {0.0};
     {
-        const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
-        if (bc < s.B) {
-            const float2* src = a.cmp_in + (size_t)zl * s.P;
-            const int p1 = s.col_off[bc + 1];
-            float f = 0.f;
-            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
-                const float2 val = src[p];
-                tile[s.row_idx[p] * TC + c] = val;
-                f += cabs2(val);
+        float f = 0.f;
+        while (base < p1) {
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                if (base + k * TPC < p1) {
+                    tile[ry[k] * TC + c] = v[k];
+                    f += cabs2(v[k]);
+                }
             }
-            acc[0] = f;
+            base += CH * TPC;
+            if (base < p1) load_chunk(base);
         }
+        acc[0] = f;
     }
     fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
     {
-        const int c = tid % TC, bc = c0 + c;
-        if (bc < s.B) {
-            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bc;
-            for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + c], a.scale);
+        const int co = tid % TC, bo = c0 + co;
+        if (bo < s.B) {
+            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bo;
+            for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + co], a.scale);
         }
     }
     if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
