@@ -110,21 +110,27 @@ __device__ __forceinline__ void col_dense_inv(const ColArgs& a, float2* tw, floa
     }
 }
 
-// Persistent dense column passes: the forward pass from band rows (items
-// pipelined by col_fwd_stream) and the inverse passes from full grids.
+// Persistent dense column passes: the inverse passes from full grids.
 template <int NY, int MODE>
 __global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
     __shared__ float2 tw[NY];
     __shared__ float2 tile[NY * col_tile_cols(NY)];
-    if constexpr (MODE == COL_FWD_COMPACT) {
-        for (int i = threadIdx.x; i < NY; i += kBlock) tw[i] = a.s.tw_y[i];
-        __syncthreads();
-        const ColArgs* ap = &a;
-        col_fwd_stream<NY>(blockIdx.x, a.looks * a.s.nz * a.s.tiles, gridDim.x,
-                           [ap](int pos) { return ColItemRef{ap, pos}; }, tw, tile);
-    } else {
-        col_dense_inv<NY, MODE>(a, tw, tile);
-    }
+    col_dense_inv<NY, MODE>(a, tw, tile);
+}
+
+// Persistent forward column pass from band rows, items pipelined by
+// col_fwd_stream.  Three waves per SIMD: the LDS tile allows three or four
+// blocks per CU, and the prefetched band rows plus the item's pupil rows
+// would otherwise take the register count just past the three-wave limit.
+template <int NY>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_col_fwd(ColArgs a) {
+    __shared__ float2 tw[NY];
+    __shared__ float2 tile[NY * col_tile_cols(NY)];
+    for (int i = threadIdx.x; i < NY; i += kBlock) tw[i] = a.s.tw_y[i];
+    __syncthreads();
+    const ColArgs* ap = &a;
+    col_fwd_stream<NY>(blockIdx.x, a.looks * a.s.nz * a.s.tiles, gridDim.x,
+                       [ap](int pos) { return ColItemRef{ap, pos}; }, tw, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,6 +342,8 @@ static hipError_t col_dispatch(const ColArgs& a, hipStream_t st) {
     case N:                                                                              \
         if constexpr (MODE == COL_INV_COMPACT)                                           \
             hipLaunchKernelGGL((k_col_inv_compact<N>), grid, dim3(kBlock), 0, st, a);    \
+        else if constexpr (MODE == COL_FWD_COMPACT)                                      \
+            hipLaunchKernelGGL((k_col_fwd<N>), grid, dim3(kBlock), 0, st, a);            \
         else                                                                             \
             hipLaunchKernelGGL((k_col<N, MODE>), grid, dim3(kBlock), 0, st, a);          \
         break;

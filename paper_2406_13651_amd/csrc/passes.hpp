@@ -355,8 +355,9 @@ __device__ __forceinline__ void col_inv_item(const ColArgs& a, int item, float2*
     // Scatter of column bc's pupil samples p in [p0, p1): lane l takes p0 + l,
     // p0 + l + TPC, ..., in chunks of CH whose loads are all issued before the
     // first is used (positions past p1 re-read the column's last sample and
-    // are dropped).  The first chunk is loaded before the tile is cleared.
-    constexpr int CH = 8;
+    // are dropped).  A column holds at most NY = CH * TPC samples, so one
+    // chunk, loaded before the tile is cleared, covers it.
+    constexpr int CH = NY / TPC;
     const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
     const bool col = bc < s.B;
     const float2* src = a.cmp_in + (size_t)zl * s.P;
@@ -446,18 +447,36 @@ __device__ __forceinline__ void col_fwd_stream(int first, int count, int stride,
         __syncthreads();  // the previous item's readers of `tile` are done
 #pragma unroll
         for (int k = 0; k < PT; ++k) tile[(y_ld + k * TPC) * TC + c_ld] = pre[k];
+        // Rows of column bc's pupil samples p0 + lane + k TPC (at most NY =
+        // PT * TPC of them), loaded before the next item's prefetch so that
+        // waiting for them does not wait for it; positions past p1 re-read
+        // the column's last row and are not stored.
+        const int c = tid / TPC, lane = tid % TPC, bc = tile_i * TC + c;
+        int p0 = 0, p1 = 0;
+        int ry[PT];
+        if (bc < s.B) {
+            p0 = s.col_off[bc];
+            p1 = s.col_off[bc + 1];
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int p = p0 + lane + k * TPC;
+                ry[k] = s.row_idx[p < p1 ? p : p1 - 1];
+            }
+        }
         if (pos + stride < count) load(pos + stride);
         fft_lds<NY, TPC, -1>(tile + c_ld, TC, y_ld, tw);
         double acc[1] = {0.0};
-        const int c = tid / TPC, lane = tid % TPC, bc = tile_i * TC + c;
         if (bc < s.B) {
             float2* dst = a.cmp_out + (size_t)zl * s.P;
-            const int p1 = s.col_off[bc + 1];
             float f = 0.f;
-            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
-                const float2 val = cscale(tile[s.row_idx[p] * TC + c], a.scale);
-                dst[p] = val;
-                f += cabs2(val);
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int p = p0 + lane + k * TPC;
+                if (p < p1) {
+                    const float2 val = cscale(tile[ry[k] * TC + c], a.scale);
+                    dst[p] = val;
+                    f += cabs2(val);
+                }
             }
             acc[0] = f;
         }
