@@ -224,8 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_init_floor(size_t n, int n_agents, c
 // registers (NA >= n_agents, a multiple of 4).  Every load is unconditional so
 // that all 2 NA of them are in flight at once: the NA - n_agents padding
 // agents re-read the last agent, with weight 0 in the averages, and store
-// nothing.  Each agent's slice is addressed from a wave-uniform base pointer
-// plus a 32-bit byte offset (n <= 2^30).
+// nothing.
 template <int NA>
 __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
     const unsigned n = (unsigned)a.n;
@@ -233,13 +232,12 @@ __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
     const int na = a.n_agents;
     double num = 0.0, den = 0.0;
     for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n2; i += gridDim.x * kBlock) {
-        const unsigned off = i * 8u;
         float2 wv[NA], rv[NA];
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
             const size_t base = (size_t)(j < na ? j : na - 1) * n;
-            wv[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.w + base) + off);
-            rv[j] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(a.r + base) + off);
+            wv[j] = reinterpret_cast<const float2*>(a.w + base)[i];
+            rv[j] = reinterpret_cast<const float2*>(a.r + base)[i];
         }
         float2 wb = make_float2(0.f, 0.f), rb = make_float2(0.f, 0.f);
 #pragma unroll
@@ -260,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
                 nm += dx * dx + dy * dy;
                 const float2 wn = make_float2(wv[j].x + a.two_rho * (xb.x - rv[j].x),
                                               wv[j].y + a.two_rho * (xb.y - rv[j].y));
-                *reinterpret_cast<float2*>(reinterpret_cast<char*>(a.w + (size_t)j * n) + off) = wn;
+                reinterpret_cast<float2*>(a.w + (size_t)j * n)[i] = wn;
                 const float u = a.ups[j];
                 wbn.x += u * wn.x;
                 wbn.y += u * wn.y;
@@ -445,7 +443,7 @@ hipError_t launch_init_floor(size_t n, int n_agents, const double* mean_r0, floa
 }
 
 hipError_t launch_mace(const MaceArgs& a, hipStream_t st) {
-    if (a.n % 2 != 0 || a.n > ((size_t)1 << 30) || a.n_agents < 1) return hipErrorInvalidValue;
+    if (a.n % 2 != 0 || a.n_agents < 1) return hipErrorInvalidValue;
     const dim3 grid(mace_blocks(a.n));
     switch ((a.n_agents + 3) / 4) {
 #define CASE(K)                                                              \

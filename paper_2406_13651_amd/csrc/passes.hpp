@@ -639,13 +639,19 @@ struct Taps7 {
     float g[7];
 };
 
-// Periodic 7-tap filter along x of voxel i.
+// Periodic 7-tap filter along x of voxel i (i < 2^31, nx >= 4): 32-bit index
+// arithmetic and the wrap as a compare, no 64-bit division.
 __device__ __forceinline__ float gauss_x_voxel(int nx, const float* g, const float* in, size_t i) {
-    const int x = (int)(i % nx);
-    const size_t row = i - x;
+    const unsigned ii = (unsigned)i;
+    const int x = (int)(ii % (unsigned)nx);
+    const float* row = in + (ii - (unsigned)x);
     float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) acc += g[k] * in[row + (size_t)((x + k - 3 + nx) % nx)];
+    for (int k = 0; k < 7; ++k) {
+        int xx = x + k - 3;
+        xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+        acc += g[k] * row[xx];
+    }
     return acc;
 }
 
@@ -656,16 +662,18 @@ __device__ __forceinline__ float gauss_x_voxel(int nx, const float* g, const flo
 template <int CH>
 __device__ __forceinline__ void gauss_strided_unit(int len, size_t inner, size_t outer, const float* g,
                                                    const float* in, float* out, size_t idx) {
-    const size_t o = idx % outer;
-    const int c = (int)(idx / outer);
-    const size_t base = (o / inner) * inner * (size_t)len + (o % inner);
+    // every index is below 2^31 (a volume holds fewer voxels): 32-bit division
+    const unsigned in32 = (unsigned)inner, out32 = (unsigned)outer, id = (unsigned)idx;
+    const unsigned o = id % out32;
+    const int c = (int)(id / out32);
+    const unsigned base = (o / in32) * in32 * (unsigned)len + (o % in32);
     const int y0 = c * CH;
     float win[CH + 6];
 #pragma unroll
     for (int k = 0; k < CH + 6; ++k) {
         int yy = (y0 + k - 3) % len;
         if (yy < 0) yy += len;
-        win[k] = in[base + (size_t)yy * inner];
+        win[k] = in[base + (unsigned)yy * in32];
     }
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
@@ -673,7 +681,7 @@ __device__ __forceinline__ void gauss_strided_unit(int len, size_t inner, size_t
             float acc = 0.f;
 #pragma unroll
             for (int q = 0; q < 7; ++q) acc += g[q] * win[k + q];
-            out[base + (size_t)(y0 + k) * inner] = acc;
+            out[base + (unsigned)(y0 + k) * in32] = acc;
         }
     }
 }
