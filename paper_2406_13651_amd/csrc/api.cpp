@@ -925,9 +925,9 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         sb.cfwd.part = at<double>(w0, s.ws.pcf);
         sb.gam = GammaArgs{row_blocks(s.tab), col_blocks(s.tab), at<double>(w0, s.ws.prow), at<double>(w0, s.ws.pcf),
                            at<double>(w0, s.ws.pci), 1.0 / s2w, bs.diag, fault};
-        sb.res = ResidArgs{(size_t)s.sc.nz * s.P, resid_blocks(s.tab), static_cast<float2*>(bs.state.resid),
+        sb.res = ResidArgs{(size_t)s.sc.nz * s.P, resid_chunks(s.tab), static_cast<float2*>(bs.state.resid),
                            at<float2>(w0, s.ws.dfd), bs.diag, at<double>(w0, s.ws.pres)};
-        sb.dia = DiagArgs{row_blocks(s.tab), resid_blocks(s.tab), at<double>(w0, s.ws.pupd), at<double>(w0, s.ws.pres),
+        sb.dia = DiagArgs{row_blocks(s.tab), resid_chunks(s.tab), at<double>(w0, s.ws.pupd), at<double>(w0, s.ws.pres),
                           bs.diag};
         MaceArgs m{};
         m.n = n;
@@ -939,7 +939,7 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         m.wbar = bs.wbar;
         m.part = at<double>(w0, s.ws.pmace);
         sb.mace = m;
-        sb.mace_chunks = mace_blocks(n);
+        sb.mace_chunks = mace_chunks(n);
         sb.with_prior = with_prior ? 1 : 0;
         sb.conv = conv_err + i;
         PriorArgs pr{};
@@ -971,7 +971,7 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         for (int it = 0; it < L * s.sc.nz * s.tiles; ++it) cols_by_len[ci].push_back(BatchItem{i, it, 0, 0});
         for (int l = 0; l < L; ++l) {
             q[Q_LOOK].push_back(BatchItem{i, l, 0, 0});
-            for (int c = 0; c < resid_blocks(s.tab); ++c) q[Q_RESID].push_back(BatchItem{i, l, c, 0});
+            for (int c = 0; c < resid_chunks(s.tab); ++c) q[Q_RESID].push_back(BatchItem{i, l, c, 0});
         }
         for (int c = 0; c < sb.mace_chunks; ++c) q[Q_VOX].push_back(BatchItem{i, 0, c, 0});
         q[Q_SCENE].push_back(BatchItem{i, 0, 0, 0});
