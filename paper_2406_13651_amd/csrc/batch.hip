@@ -146,10 +146,7 @@ __global__ __launch_bounds__(kBlock) void kb_mace_final(BatchLaunch b) {
     for (int it = blockIdx.x; it < b.count[Q_SCENE]; it += gridDim.x) {
         const SceneBatch& sb = b.scenes[q[it].scene];
         double v[2] = {0.0, 0.0};
-        for (int i = threadIdx.x; i < sb.mace_chunks; i += kBlock) {
-            v[0] += sb.mace.part[(size_t)i * 2];
-            v[1] += sb.mace.part[(size_t)i * 2 + 1];
-        }
+        strided_sums<2>(sb.mace.part, sb.mace_chunks, 2, v);
         __shared__ double tot[2];
         block_sum_store<2>(v, tot);
         if (threadIdx.x == 0) sb.conv[0] = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : 0.0;

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_init_r0(size_t n, int looks, float2*
 __global__ __launch_bounds__(kBlock) void k_sum(const double* part, int count, double scale, double* out) {
     const int look = blockIdx.x;
     double v[1] = {0.0};
-    for (int i = threadIdx.x; i < count; i += kBlock) v[0] += part[(size_t)look * count + i];
+    strided_sums<1>(part + (size_t)look * count, count, 1, v);
     __shared__ double tot[1];
     block_sum_store<1>(v, tot);
     if (threadIdx.x == 0) out[look] = tot[0] * scale;
@@ -276,10 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_mace_final(const double* part, int blocks, double* conv) {
     double v[2] = {0.0, 0.0};
-    for (int i = threadIdx.x; i < blocks; i += kBlock) {
-        v[0] += part[(size_t)i * 2];
-        v[1] += part[(size_t)i * 2 + 1];
-    }
+    strided_sums<2>(part, blocks, 2, v);
     __shared__ double tot[2];
     block_sum_store<2>(v, tot);
     if (threadIdx.x == 0) conv[0] = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : 0.0;

@@ -73,6 +73,31 @@ __device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
     __syncthreads();  // red may be reused by the next item
 }
 
+// v[k] += p[i * stride + k] (k < K) for i = threadIdx.x, + kBlock, ... below
+// count, with eight rows of loads in flight per thread (rows past count
+// re-read the last one and are not added).  The order of the additions is
+// fixed, so the sums are deterministic.
+template <int K>
+__device__ __forceinline__ void strided_sums(const double* p, int count, int stride, double* v) {
+    for (int i0 = threadIdx.x; i0 < count; i0 += 8 * kBlock) {
+        double x[8][K];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * kBlock;
+            const double* q = p + (size_t)(i < count ? i : count - 1) * stride;
+#pragma unroll
+            for (int k = 0; k < K; ++k) x[u][k] = q[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (i0 + u * kBlock < count) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) v[k] += x[u][k];
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ void wave_or_fault(uint32_t bits, uint32_t* fault) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
@@ -542,16 +567,9 @@ __device__ __forceinline__ void col_fwd_item(const ColArgs& a, int item, float2*
 __device__ __forceinline__ void gamma_item(int look, int nrow, int ncol, const double* prow, const double* pcf,
                                            const double* pci, double inv_s2w, double* diag, uint32_t* fault) {
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < nrow; i += kBlock) {
-        const double* p = prow + ((size_t)look * nrow + i) * 3;
-        v[0] += p[0];
-        v[1] += p[1];
-        v[2] += p[2];
-    }
-    for (int i = threadIdx.x; i < ncol; i += kBlock) {
-        v[3] += pcf[(size_t)look * ncol + i];
-        v[4] += pci[(size_t)look * ncol + i];
-    }
+    strided_sums<3>(prow + (size_t)look * nrow * 3, nrow, 3, v);
+    strided_sums<1>(pcf + (size_t)look * ncol, ncol, 1, v + 3);
+    strided_sums<1>(pci + (size_t)look * ncol, ncol, 1, v + 4);
     __shared__ double tot[5];
     block_sum_store<5>(v, tot);
     if (threadIdx.x == 0) {
@@ -588,8 +606,8 @@ __device__ __forceinline__ float resid_range(float2* R, const float2* D, float g
 __device__ __forceinline__ void diag_after_item(int look, int nrow, int nres, const double* pupd,
                                                 const double* pres, double* diag) {
     double v[2] = {0.0, 0.0};
-    for (int i = threadIdx.x; i < nrow; i += kBlock) v[0] += pupd[(size_t)look * nrow + i];
-    for (int i = threadIdx.x; i < nres; i += kBlock) v[1] += pres[(size_t)look * nres + i];
+    strided_sums<1>(pupd + (size_t)look * nrow, nrow, 1, v);
+    strided_sums<1>(pres + (size_t)look * nres, nres, 1, v + 1);
     __shared__ double tot[2];
     block_sum_store<2>(v, tot);
     if (threadIdx.x == 0) {
