@@ -194,6 +194,29 @@ struct RowLds {
     float2* buf;
 };
 
+// Pointwise step of the gradient pass on one row held in rb (the inverse row
+// FFT of the band already applied): d = A^H r / sigma_w^2 - omega mu with
+// omega = 1 / (r' + sigma_w^2 / alpha), written back into rb, plus the
+// thread's shares of ||d||^2, sum omega |d|^2 and sum omega |mu|^2.
+template <int NX, int TR, int PX, int PAD>
+__device__ __forceinline__ void row_grad_pointwise(const RowArgs& a, float2* rb, int t, const float2 (&m)[PX],
+                                                   const float (&rp)[PX], float& dd, float& wd, float& wm) {
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+        const int x = t + k * TR;
+        if (NX % TR == 0 || x < NX) {
+            const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
+            const float om = 1.f / (rp[k] + a.floor_w);
+            const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
+            rb[lds_pos<PAD>(x)] = d;
+            const float d2 = cabs2(d);
+            dd += d2;
+            wd += om * d2;
+            wm += om * cabs2(m[k]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Row pass over rows [rgroup * RPB, rgroup * RPB + RPB) of look `look`;
 // `slot` indexes the look's partial-sum slots.  `load_tables` reloads the
@@ -289,22 +312,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
             for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale);
     } else if constexpr (MODE == ROW_GRAD) {
         float dd = 0.f, wd = 0.f, wm = 0.f;
-        if (active) {
-#pragma unroll
-            for (int k = 0; k < PX; ++k) {
-                const int x = t + k * TR;
-                if (NX % TR == 0 || x < NX) {
-                    const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
-                    const float om = 1.f / (rp[k] + a.floor_w);
-                    const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
-                    rb[lds_pos<PAD>(x)] = d;
-                    const float d2 = cabs2(d);
-                    dd += d2;
-                    wd += om * d2;
-                    wm += om * cabs2(m[k]);
-                }
-            }
-        }
+        if (active) row_grad_pointwise<NX, TR, PX, PAD>(a, rb, t, m, rp, dd, wd, wm);
         fft_lds<NX, TR, -1, PAD>(rb, 1, t, L.tw);
         if (active)
             for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale);
