@@ -149,6 +149,19 @@ __global__ __launch_bounds__(kBlock) void k_row(RowArgs a) {
     row_item<NX, MODE>(a, blockIdx.y, blockIdx.x, (size_t)blockIdx.y * gridDim.x + blockIdx.x, L, true, bv);
 }
 
+// The gradient row pass as its own kernel, held to six waves per SIMD (its
+// LDS allows seven blocks per CU; the register count otherwise allows five).
+template <int NX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_row_grad(RowArgs a) {
+    __shared__ float2 tw[NX];
+    __shared__ int bpos[NX];
+    __shared__ int bcol[NX];
+    __shared__ float2 buf[row_lds_floats2<NX>()];
+    const RowLds L{tw, bpos, bcol, buf};
+    const BetaVals bv{a.beta, a.inv_beta, a.k_up, a.k_dn};
+    row_item<NX, ROW_GRAD>(a, blockIdx.y, blockIdx.x, (size_t)blockIdx.y * gridDim.x + blockIdx.x, L, true, bv);
+}
+
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_scatter_full(SceneTables s, size_t total,
                                                          const float2* cmp, float2* full) {
@@ -369,7 +382,10 @@ static hipError_t row_dispatch(const RowArgs& a, hipStream_t st) {
     switch (a.s.nx) {
 #define CASE(N)                                                                  \
     case N:                                                                      \
-        hipLaunchKernelGGL((k_row<N, MODE>), grid, dim3(kBlock), 0, st, a);      \
+        if constexpr (MODE == ROW_GRAD)                                          \
+            hipLaunchKernelGGL((k_row_grad<N>), grid, dim3(kBlock), 0, st, a);   \
+        else                                                                     \
+            hipLaunchKernelGGL((k_row<N, MODE>), grid, dim3(kBlock), 0, st, a);  \
         break;
         CLAMP_SIZES(CASE)
 #undef CASE
