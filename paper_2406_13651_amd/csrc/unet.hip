@@ -40,21 +40,23 @@ __device__ __forceinline__ uint32_t max2(uint32_t a, uint32_t b) {
 
 __global__ __launch_bounds__(kBlock) void k_pool2(const uint16_t* in, uint16_t* out, int nvol, int nz, int ny,
                                                   int nx) {
-    const int cz = nz / 2, cy = ny / 2, cx = nx / 2;
-    const long total = (long)nvol * cz * cy * cx * 4;
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < total; i += (long)gridDim.x * kBlock) {
-        const int j = (int)(i & 3);
-        long v = i >> 2;
-        const int x = (int)(v % cx);
+    // a volume holds fewer than 2^31 voxels (checked by the caller): 32-bit
+    // index arithmetic
+    const unsigned cz = nz / 2, cy = ny / 2, cx = nx / 2;
+    const unsigned total = (unsigned)nvol * cz * cy * cx * 4u;
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+        const unsigned j = i & 3u;
+        unsigned v = i >> 2;
+        const unsigned x = v % cx;
         v /= cx;
-        const int y = (int)(v % cy);
+        const unsigned y = v % cy;
         v /= cy;
-        const int z = (int)(v % cz);
-        const long vol = v / cz;
+        const unsigned z = v % cz;
+        const unsigned vol = v / cz;
         uint4 m;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const long f = ((vol * nz + 2 * z + (s >> 2)) * ny + 2 * y + ((s >> 1) & 1)) * nx + 2 * x + (s & 1);
+            const long f = (((long)vol * nz + 2 * z + (s >> 2)) * ny + 2 * y + ((s >> 1) & 1)) * nx + 2 * x + (s & 1);
             const uint4 q = *reinterpret_cast<const uint4*>(in + f * 32 + j * 8);
             if (s == 0) {
                 m = q;
@@ -65,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_pool2(const uint16_t* in, uint16_t* 
                 m.w = max2(m.w, q.w);
             }
         }
-        *reinterpret_cast<uint4*>(out + (i >> 2) * 32 + j * 8) = m;
+        *reinterpret_cast<uint4*>(out + (long)(i >> 2) * 32 + j * 8) = m;
     }
 }
 
@@ -212,9 +214,9 @@ __global__ __launch_bounds__(kBlock) void k_chan_sums(const uint16_t* X, const u
         mu[c] = MODE == 1 ? mean[8 * j + c] : 0.f;
         rs[c] = MODE == 1 ? rstd[8 * j + c] : 0.f;
     }
-    for (long v = (long)blockIdx.x * 64 + vl; v < nvox; v += (long)gridDim.x * 64) {
+    auto add = [&](uint4 xq, uint4 yq) {
         float x[8];
-        unpack8(*reinterpret_cast<const uint4*>(X + v * 32 + 8 * j), x);
+        unpack8(xq, x);
         if constexpr (MODE == 0) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
@@ -223,13 +225,30 @@ __global__ __launch_bounds__(kBlock) void k_chan_sums(const uint16_t* X, const u
             }
         } else {
             float z[8];
-            unpack8(*reinterpret_cast<const uint4*>(Y + v * 32 + 8 * j), z);
+            unpack8(yq, z);
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 s1[c] += x[c];
                 s2[c] += (double)x[c] * ((z[c] - mu[c]) * rs[c]);
             }
         }
+    };
+    // voxels v, v + stride, ... in order; four loads in flight per step
+    const long stride = (long)gridDim.x * 64;
+    long v = (long)blockIdx.x * 64 + vl;
+    for (; v + 3 * stride < nvox; v += 4 * stride) {
+        uint4 xq[4], yq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xq[u] = *reinterpret_cast<const uint4*>(X + (v + u * stride) * 32 + 8 * j);
+            yq[u] = MODE == 1 ? *reinterpret_cast<const uint4*>(Y + (v + u * stride) * 32 + 8 * j) : xq[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add(xq[u], yq[u]);
+    }
+    for (; v < nvox; v += stride) {
+        const uint4 xq = *reinterpret_cast<const uint4*>(X + v * 32 + 8 * j);
+        add(xq, MODE == 1 ? *reinterpret_cast<const uint4*>(Y + v * 32 + 8 * j) : xq);
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -326,15 +345,23 @@ template <bool HAS_Y, bool RELU>
 __global__ __launch_bounds__(kBlock) void k_affine(const uint16_t* X, const uint16_t* Y, const float* A,
                                                    const float* B, const float* Cc, long nvox, uint16_t* out) {
     const long n = nvox * 4;
+    // the grid stride is a multiple of 4, so each thread keeps one channel group
+    const int j = (int)(threadIdx.x & 3);
+    float a8[8], b8[8], c8[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        a8[c] = A[8 * j + c];
+        b8[c] = HAS_Y ? B[8 * j + c] : 0.f;
+        c8[c] = Cc[8 * j + c];
+    }
     for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
-        const int j = (int)(i & 3);
         float x[8], y[8], o[8];
         unpack8(*reinterpret_cast<const uint4*>(X + i * 8), x);
         if constexpr (HAS_Y) unpack8(*reinterpret_cast<const uint4*>(Y + i * 8), y);
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            float v = A[8 * j + c] * x[c] + Cc[8 * j + c];
-            if constexpr (HAS_Y) v += B[8 * j + c] * y[c];
+            float v = a8[c] * x[c] + c8[c];
+            if constexpr (HAS_Y) v += b8[c] * y[c];
             o[c] = RELU ? fmaxf(v, 0.f) : v;
         }
         *reinterpret_cast<uint4*>(out + i * 8) = pack8(o);
@@ -345,26 +372,36 @@ __global__ __launch_bounds__(kBlock) void k_affine(const uint16_t* X, const uint
 // first maximum of each window + dskip), per fine voxel (fine sizes given).
 __global__ __launch_bounds__(kBlock) void k_pool2_bwd(const uint16_t* e, const uint16_t* dp, const uint16_t* dskip,
                                                       uint16_t* de, int nvol, int nz, int ny, int nx) {
-    const int cz = nz / 2, cy = ny / 2, cx = nx / 2;
-    const long total = (long)nvol * cz * cy * cx * 4;
-    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < total; i += (long)gridDim.x * kBlock) {
-        const int j = (int)(i & 3);
-        long v = i >> 2;
-        const int x = (int)(v % cx);
+    // a volume holds fewer than 2^31 voxels (checked by the caller): 32-bit
+    // index arithmetic
+    const unsigned cz = nz / 2, cy = ny / 2, cx = nx / 2;
+    const unsigned total = (unsigned)nvol * cz * cy * cx * 4u;
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+        const unsigned j = i & 3u;
+        unsigned v = i >> 2;
+        const unsigned x = v % cx;
         v /= cx;
-        const int y = (int)(v % cy);
+        const unsigned y = v % cy;
         v /= cy;
-        const int z = (int)(v % cz);
-        const long vol = v / cz;
+        const unsigned z = v % cz;
+        const unsigned vol = v / cz;
         long f[8];
         float ev[8][8];
+        uint4 kq[8];
+        // every load of the window is issued before the first is used
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            f[s] = ((vol * nz + 2 * z + (s >> 2)) * ny + 2 * y + ((s >> 1) & 1)) * nx + 2 * x + (s & 1);
-            unpack8(*reinterpret_cast<const uint4*>(e + f[s] * 32 + 8 * j), ev[s]);
-        }
+        for (int s = 0; s < 8; ++s)
+            f[s] = (((long)vol * nz + 2 * z + (s >> 2)) * ny + 2 * y + ((s >> 1) & 1)) * nx + 2 * x + (s & 1);
+        uint4 eq[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) eq[s] = *reinterpret_cast<const uint4*>(e + f[s] * 32 + 8 * j);
+        const uint4 gq = *reinterpret_cast<const uint4*>(dp + (long)(i >> 2) * 32 + 8 * j);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) kq[s] = *reinterpret_cast<const uint4*>(dskip + f[s] * 32 + 8 * j);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) unpack8(eq[s], ev[s]);
         float g[8];
-        unpack8(*reinterpret_cast<const uint4*>(dp + (i >> 2) * 32 + 8 * j), g);
+        unpack8(gq, g);
         int arg[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
@@ -377,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_pool2_bwd(const uint16_t* e, const u
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             float k[8], o[8];
-            unpack8(*reinterpret_cast<const uint4*>(dskip + f[s] * 32 + 8 * j), k);
+            unpack8(kq[s], k);
 #pragma unroll
             for (int c = 0; c < 8; ++c) o[c] = ev[s][c] > 0.f ? (arg[c] == s ? g[c] : 0.f) + k[c] : 0.f;
             *reinterpret_cast<uint4*>(de + f[s] * 32 + 8 * j) = pack8(o);
@@ -629,7 +666,7 @@ hipError_t unet_chan_finalize(int mode, const double* part, int blocks, long m, 
 
 hipError_t unet_affine(const uint16_t* X, const uint16_t* Y, const float* A, const float* B, const float* C, int relu,
                        long nvox, uint16_t* out, hipStream_t st) {
-    const dim3 g(grid_of(nvox * 4, 16384)), b(kBlock);
+    const dim3 g(grid_of(nvox * 4, 1 << 20)), b(kBlock);
     if (Y != nullptr && relu) hipLaunchKernelGGL((k_affine<true, true>), g, b, 0, st, X, Y, A, B, C, nvox, out);
     else if (Y != nullptr) hipLaunchKernelGGL((k_affine<true, false>), g, b, 0, st, X, Y, A, B, C, nvox, out);
     else if (relu) hipLaunchKernelGGL((k_affine<false, true>), g, b, 0, st, X, Y, A, B, C, nvox, out);
