@@ -251,8 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
 #pragma unroll
         for (int j = 0; j < NA; ++j) {
             const size_t base = (size_t)(j < na ? j : na - 1) * n;
-            wv[j] = reinterpret_cast<const float2*>(a.w + base)[i];
-            rv[j] = reinterpret_cast<const float2*>(a.r + base)[i];
+            wv[j] = ld_stream(reinterpret_cast<const float2*>(a.w + base) + i);
+            rv[j] = ld_stream(reinterpret_cast<const float2*>(a.r + base) + i);
         }
         float2 wb = make_float2(0.f, 0.f), rb = make_float2(0.f, 0.f);
 #pragma unroll
@@ -273,13 +273,13 @@ __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
                 nm += dx * dx + dy * dy;
                 const float2 wn = make_float2(wv[j].x + a.two_rho * (xb.x - rv[j].x),
                                               wv[j].y + a.two_rho * (xb.y - rv[j].y));
-                reinterpret_cast<float2*>(a.w + (size_t)j * n)[i] = wn;
+                st_stream(reinterpret_cast<float2*>(a.w + (size_t)j * n) + i, wn);
                 const float u = a.ups[j];
                 wbn.x += u * wn.x;
                 wbn.y += u * wn.y;
             }
         }
-        reinterpret_cast<float2*>(a.wbar)[i] = wbn;
+        st_stream(reinterpret_cast<float2*>(a.wbar) + i, wbn);
         num += nm;
         den += (double)na * ((double)wb.x * wb.x + (double)wb.y * wb.y);
     }
