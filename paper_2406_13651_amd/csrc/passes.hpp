@@ -17,9 +17,12 @@ namespace clampk {
 
 constexpr int kRowPad = 4;  // one float2 of LDS padding per 16 row samples
 
-// Loads and stores of streams that a pass touches once: non-temporal, so
-// they do not displace cached data that other passes of the iteration reuse
-// (measured: the fused update pass 428 -> 355 us at 256x256x64, 16 looks).
+// Non-temporal loads and stores, for streams that do not fit the caches
+// between their writer and reader anyway: the pointwise streams of the update
+// pass and the Mann step, the residual update, and the band buffers between
+// the column and row passes.  They then do not displace cached data that the
+// other passes reuse (measured at 256x256x64, 16 looks: update pass 428 ->
+// 355 us, whole iteration 1.30 -> 1.16 ms).
 __device__ __forceinline__ float ld_stream(const float* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ float2 ld_stream(const float2* p) {
     return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
@@ -308,7 +311,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
             for (int k = 0; k < PX; ++k) {
                 const int x = t + k * TR;
                 bp[k] = (NX % TR == 0 || x < NX) ? L.bpos[x] : -1;
-                bin[k] = a.band_in[band + (bp[k] >= 0 ? bp[k] : 0)];
+                bin[k] = ld_stream(a.band_in + band + (bp[k] >= 0 ? bp[k] : 0));
             }
         }
         if constexpr (PREFETCH) load_streams();
@@ -333,7 +336,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
         if (active) row_grad_pointwise<NX, TR, PX, PAD>(a, rb, t, m, rp, dd, wd, wm);
         fft_lds<NX, TR, -1, PAD>(rb, 1, t, L.tw);
         if (active)
-            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale);
+            for (int b = t; b < s.B; b += TR) st_stream(a.band_out + band + b, cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale));
         double acc[3] = {dd, wd, wm};
         block_sum_store<3>(acc, a.part + slot * 3);
     } else {  // ROW_UPDATE
@@ -456,7 +459,7 @@ __device__ __forceinline__ void col_inv_item(const ColArgs& a, int item, float2*
         const int co = tid % TC, bo = c0 + co;
         if (bo < s.B) {
             float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bo;
-            for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + co], a.scale);
+            for (int y = tid / TC; y < NY; y += TPC) st_stream(dst + (size_t)y * s.Bs, cscale(tile[y * TC + co], a.scale));
         }
     }
     if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
