@@ -32,6 +32,10 @@ typedef unsigned v4u __attribute__((ext_vector_type(4)));
 // one output slice, < 2^31 bytes): stores there are dropped, loads read 0.
 constexpr int kBufferWord3 = 0x00020000;
 constexpr uint32_t kBufferOutside = 0x80000000u;
+// Cache policy of the input-slice loads: non-temporal (the slices stream
+// through once per layer; measured faster for both the forward layers and
+// training).  Output stores stay cached: the next layer reads them.
+constexpr int kNonTemporal = 2;
 
 constexpr int kCnnBlock = 256;
 
@@ -139,7 +143,7 @@ __device__ __forceinline__ void tile_fetch(const ConvArgs& a, const uint16_t* in
         const int y = y0 - 1 + ys, x = x0 - 1 + xs;
         const bool ok = e < G::kSlice && y >= 0 && y < a.ny && x >= 0 && x < a.nx;
         const uint32_t off = ok ? (uint32_t)(((y * a.nx + x) * CIN + j * 8) * 2) : kBufferOutside;
-        const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kNonTemporal);
         pre[i] = make_uint4(v[0], v[1], v[2], v[3]);
     }
 }
