@@ -121,11 +121,25 @@ __host__ __device__ constexpr int lds_len() {
     return lds_pos<PADSH>(N - 1) + 1;
 }
 
+// Synchronisation of the threads that share one transform: the block
+// (__syncthreads), or, when each group lies inside one wave (WAVE), the wave
+// alone.  A wave's LDS operations execute in issue order, so the wave-local
+// form only has to keep the compiler from moving LDS accesses across it.
+template <bool WAVE>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // One Stockham stage and the ones after it.  buf[lds_pos(i) * stride] is
 // element i of this group's vector; t in [0, T) is the thread's rank in the
-// group.  Every thread of the block must call this (it contains block
-// barriers).
-template <int N, int T, int S, int PADSH, int STAGE, int NS>
+// group.  Every thread of the block (of the wave, for WAVE) must call this.
+template <int N, int T, int S, int PADSH, int STAGE, int NS, bool WAVE>
 __device__ __forceinline__ void fft_stages(float2* buf, int stride, int t, const float2* tw) {
     if constexpr (STAGE < num_stages(N)) {
         constexpr int R = radix_at(N, STAGE);
@@ -141,7 +155,7 @@ __device__ __forceinline__ void fft_stages(float2* buf, int stride, int t, const
                 for (int r = 0; r < R; ++r) v[p][r] = buf[lds_pos<PADSH>(j + r * NB) * stride];
             }
         }
-        __syncthreads();
+        group_sync<WAVE>();
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int j = t + p * T;
@@ -161,19 +175,22 @@ __device__ __forceinline__ void fft_stages(float2* buf, int stride, int t, const
                 for (int r = 0; r < R; ++r) buf[lds_pos<PADSH>(base + r * NS) * stride] = v[p][r];
             }
         }
-        __syncthreads();
-        fft_stages<N, T, S, PADSH, STAGE + 1, NS * R>(buf, stride, t, tw);
+        group_sync<WAVE>();
+        fft_stages<N, T, S, PADSH, STAGE + 1, NS * R, WAVE>(buf, stride, t, tw);
     }
 }
 
 // Unnormalised length-N DFT of buf (S = -1 forward, +1 inverse), in place.
-// Starts with a block barrier, so writes made to buf before the call are
-// visible, and ends with one, so the result is visible to the whole block.
-template <int N, int T, int S, int PADSH = 0>
+// Starts with a group synchronisation, so writes made to buf before the call
+// are visible, and ends with one, so the result is visible to the group (the
+// block, or with WAVE the wave, which must then hold every thread of the
+// group: T divides 64 and groups start at multiples of T).
+template <int N, int T, int S, int PADSH = 0, bool WAVE = false>
 __device__ __forceinline__ void fft_lds(float2* buf, int stride, int t, const float2* tw) {
     static_assert(fft_len_ok(N), "FFT length must be 2^a 3^b");
-    __syncthreads();
-    fft_stages<N, T, S, PADSH, 0, 1>(buf, stride, t, tw);
+    static_assert(!WAVE || (T <= 64 && 64 % T == 0), "a wave-local transform must lie inside one wave");
+    group_sync<WAVE>();
+    fft_stages<N, T, S, PADSH, 0, 1, WAVE>(buf, stride, t, tw);
 }
 
 }  // namespace clampk

@@ -323,7 +323,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
             }
         }
     }
-    fft_lds<NX, TR, S1, PAD>(rb, 1, t, L.tw);
+    fft_lds<NX, TR, S1, PAD, true>(rb, 1, t, L.tw);
 
     if constexpr (MODE == ROW_INV) {
         if (active)
@@ -334,7 +334,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
     } else if constexpr (MODE == ROW_GRAD) {
         float dd = 0.f, wd = 0.f, wm = 0.f;
         if (active) row_grad_pointwise<NX, TR, PX, PAD>(a, rb, t, m, rp, dd, wd, wm);
-        fft_lds<NX, TR, -1, PAD>(rb, 1, t, L.tw);
+        fft_lds<NX, TR, -1, PAD, true>(rb, 1, t, L.tw);
         if (active)
             for (int b = t; b < s.B; b += TR) st_stream(a.band_out + band + b, cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale));
         double acc[3] = {dd, wd, wm};
