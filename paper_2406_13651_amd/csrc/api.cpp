@@ -939,7 +939,7 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         m.wbar = bs.wbar;
         m.part = at<double>(w0, s.ws.pmace);
         sb.mace = m;
-        sb.mace_chunks = mace_chunks(n);
+        sb.mace_chunks = mace_blocks(n);
         sb.with_prior = with_prior ? 1 : 0;
         sb.conv = conv_err + i;
         PriorArgs pr{};

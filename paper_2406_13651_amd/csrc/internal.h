@@ -75,15 +75,14 @@ __host__ __device__ inline int row_blocks(const SceneTables& s) {
     return (s.nz * s.ny + rpb - 1) / rpb;
 }
 __host__ __device__ inline int col_blocks(const SceneTables& s) { return s.nz * s.tiles; }
-// Single-scene launches of the residual update and the Mann step take one
-// element (pair) per thread: many short blocks stream HBM faster on this chip
-// than a capped grid that loops.  The batched passes keep fewer, longer work
-// items (resid_chunks, mace_chunks <= the block counts, which size the
-// partial-sum workspace).
+// Launches of the residual update and the Mann step take one element (pair)
+// per thread: many short blocks stream HBM faster on this chip than a capped
+// grid that loops.  The batched Mann step uses the same work items; the
+// batched residual update keeps fewer, longer ones (resid_chunks <=
+// resid_blocks, which sizes the partial-sum workspace), measured faster there.
 int resid_blocks(const SceneTables& s);
 int mace_blocks(size_t n);
 int resid_chunks(const SceneTables& s);
-int mace_chunks(size_t n);
 
 enum ColMode { COL_INV_COMPACT = 0, COL_INV_FULL = 1, COL_INV_INIT = 2, COL_FWD_COMPACT = 3 };
 enum RowMode { ROW_INV = 0, ROW_FWD = 1, ROW_GRAD = 2, ROW_UPDATE = 3, ROW_UPDATE_EXACT = 4 };

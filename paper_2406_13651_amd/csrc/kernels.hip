@@ -28,7 +28,6 @@ static int grid_cap(size_t work, int cap) {
 int resid_blocks(const SceneTables& s) { return grid_cap((size_t)s.nz * s.P, 1 << 20); }
 int mace_blocks(size_t n) { return grid_cap(n / 2, 1 << 22); }
 int resid_chunks(const SceneTables& s) { return grid_cap((size_t)s.nz * s.P, 512); }
-int mace_chunks(size_t n) { return grid_cap(n / 2, 2048); }
 
 // ---------------------------------------------------------------------------
 // Column passes.  A work item is a tile of TC band columns of one slice of one
