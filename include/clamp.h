@@ -201,7 +201,10 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene,
 
 /* Fixed prior agent: out = periodic separable 3D Gaussian smoothing of in
  * (float32 [n] each; standard deviation sigma_vox voxels, 7 taps per axis,
- * taps normalised to sum 1).  in and out must not overlap. */
+ * taps normalised to sum 1).  in and out must not overlap; in must be
+ * 16-byte aligned (the x pass reads it in float4 units), as any device
+ * allocation and any agent slice w + j n of a stack is; CLAMP_EINVAL
+ * otherwise. */
 clamp_status clamp_prior_gauss(const clamp_plan* plan, int32_t scene, float sigma_vox,
                                const float* in, float* out,
                                void* workspace, void* hip_stream);

@@ -686,6 +686,7 @@ clamp_status clamp_prior_gauss(const clamp_plan* plan, int32_t scene, float sigm
     if (!finite_pos(sigma_vox)) return fail(CLAMP_EINVAL, "sigma_vox must be finite and > 0");
     if (in == nullptr || out == nullptr) return fail(CLAMP_EINVAL, "in/out is NULL");
     if (in == out) return fail(CLAMP_EINVAL, "in and out must not overlap");
+    if (reinterpret_cast<uintptr_t>(in) % 16 != 0) return fail(CLAMP_EINVAL, "in must be 16-byte aligned");
     if ((st = check_ws(workspace)) != CLAMP_OK) return st;
     const Scene& s = plan->scenes[scene];
     double g[7], sum = 0.0;

@@ -296,9 +296,11 @@ __global__ __launch_bounds__(kBlock) void k_mace_final(const double* part, int b
 
 // ---------------------------------------------------------------------------
 // Periodic 7-tap filter along x (contiguous).
+// x pass: four voxels per thread (n and nx multiples of 4), one per thread
+// block-wise rather than a looping capped grid.
 __global__ __launch_bounds__(kBlock) void k_gauss_x(int nx, size_t n, Taps7 t, const float* in, float* out) {
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
-        out[i] = gauss_x_voxel(nx, t.g, in, i);
+    const unsigned q = blockIdx.x * kBlock + threadIdx.x;
+    if (q < n / 4) reinterpret_cast<float4*>(out)[q] = gauss_x_quad(nx, t.g, in, q);
 }
 
 // Periodic 7-tap filter along a strided axis, CH samples per work unit.
@@ -483,7 +485,8 @@ hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float*
     Taps7 t;
     for (int k = 0; k < 7; ++k) t.g[k] = taps7[k];
     const size_t n = (size_t)nx * ny * nz;
-    hipLaunchKernelGGL(k_gauss_x, dim3(grid_cap(n, 8192)), dim3(kBlock), 0, st, nx, n, t, in, tmp0);
+    hipLaunchKernelGGL(k_gauss_x, dim3((unsigned)((n / 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nx, n, t, in,
+                       tmp0);
     // y: stride nx, outer index runs over (z, x); z: stride nx*ny, outer over (y, x)
     gauss_axis(ny, (size_t)nx, (size_t)nz * nx, t, tmp0, tmp1, st);
     gauss_axis(nz, (size_t)nx * ny, (size_t)nx * ny, t, tmp1, out, st);

@@ -702,6 +702,27 @@ __device__ __forceinline__ float gauss_x_voxel(int nx, const float* g, const flo
     return acc;
 }
 
+// The same filter for the four voxels 4 q .. 4 q + 3 of a row (nx a multiple
+// of 4): three float4 loads cover taps x - 4 .. x + 7, wrapped whole at the
+// row ends; each output sums its taps in the same order as gauss_x_voxel.
+__device__ __forceinline__ float4 gauss_x_quad(int nx, const float* g, const float* in, unsigned q) {
+    const unsigned i = 4u * q;
+    const int x = (int)(i % (unsigned)nx);
+    const float4* row = reinterpret_cast<const float4*>(in + (i - (unsigned)x));
+    const int c = x >> 2, nq = nx >> 2;
+    const float4 l = row[c == 0 ? nq - 1 : c - 1], m = row[c], r = row[c + 1 == nq ? 0 : c + 1];
+    const float v[12] = {l.x, l.y, l.z, l.w, m.x, m.y, m.z, m.w, r.x, r.y, r.z, r.w};
+    float o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < 7; ++t) acc += g[t] * v[e + t + 1];
+        o[e] = acc;
+    }
+    return make_float4(o[0], o[1], o[2], o[3]);
+}
+
 // Periodic 7-tap filter along a strided axis of length len (stride `inner`
 // elements) for work unit idx = chunk * outer + o: the thread slides a
 // register window down CH samples, reading each input once plus a 6-sample

@@ -119,3 +119,19 @@ def test_zero_batch_and_errors(C):
         C.clamp_aperture_op(plan, 0, 7, x, x.clone(), 1, ws)
     with pytest.raises(C.ClampError):
         C.clamp_aperture_op(plan, 0, C.CLAMP_FWD, x, x, 1, ws)  # in and out overlap
+
+
+def test_prior_rejects_misaligned_input(C):
+    """The prior's x pass reads its input in float4 units: a pointer that is
+    not 16-byte aligned is an argument error, not a fault."""
+    import torch
+    scene = C.Scene(64, 32, 4, 2, 8.0)
+    plan = C.clamp_plan_create([scene])
+    ws = plan.workspace()
+    n = 64 * 32 * 4
+    buf = torch.zeros(n + 4, dtype=torch.float32, device="cuda")
+    out = torch.zeros(n, dtype=torch.float32, device="cuda")
+    C.clamp_prior_gauss(plan, 0, 1.0, buf[4:], out, ws)  # 16-byte offset: accepted
+    with pytest.raises(C.ClampError, match="aligned"):
+        C.clamp_prior_gauss(plan, 0, 1.0, buf[1:n + 1], out, ws)
+    torch.cuda.synchronize()
