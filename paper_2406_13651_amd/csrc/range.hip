@@ -50,21 +50,34 @@ __global__ __launch_bounds__(kBlock) void k_zpass(ZArgs a) {
     const int tid = threadIdx.x, c = tid % kZCols, t = tid / kZCols;
     const int p = tile_i * kZCols + c;
     const bool col_ok = p < P;
-    for (int i = tid; i < NZ; i += kBlock) tw[i] = s.tw_z[i];
     const float scale = rsqrtf((float)NZ);
     float acc = 0.f;
+    // every load of the column first (positions outside the box or past P
+    // read a valid sample and are replaced by zero), then the tile stores
+    const int pc = col_ok ? p : P - 1;
+    float2 vin[NZ / TPC];
+#pragma unroll
+    for (int j = 0; j < NZ / TPC; ++j) {
+        const int z = t + j * TPC;
+        if constexpr (S > 0) {
+            const int k = box_index(z, NZ, K);
+            vin[j] = a.in[((size_t)look * K + (k >= 0 ? k : 0)) * P + pc];
+        } else {
+            vin[j] = a.in[((size_t)look * NZ + z) * P + pc];
+        }
+    }
+    for (int i = tid; i < NZ; i += kBlock) tw[i] = s.tw_z[i];
 #pragma unroll
     for (int j = 0; j < NZ / TPC; ++j) {
         const int z = t + j * TPC;
         float2 v = make_float2(0.f, 0.f);
         if constexpr (S > 0) {
-            const int k = box_index(z, NZ, K);
-            if (col_ok && k >= 0) {
-                v = a.in[((size_t)look * K + k) * P + p];
+            if (col_ok && box_index(z, NZ, K) >= 0) {
+                v = vin[j];
                 acc += cabs2(v);
             }
         } else {
-            if (col_ok) v = a.in[((size_t)look * NZ + z) * P + p];
+            if (col_ok) v = vin[j];
         }
         tile[z * kZCols + c] = v;
     }
