@@ -844,7 +844,16 @@ __global__ __launch_bounds__(kCnnBlock) void k_wgrad_reduce(const float* part, i
     const int pl = threadIdx.x & 15, l = threadIdx.x >> 4;
     const int p = blockIdx.x * 16 + pl;
     double s = 0.0;
-    for (int c = l; c < chunks; c += 16) s += part[(long)c * 28 * 1024 + p];
+    // chunks l, l + 16, ... in order, eight loads in flight
+    int c = l;
+    for (; c + 7 * 16 < chunks; c += 8 * 16) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(long)(c + 16 * u) * 28 * 1024 + p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < chunks; c += 16) s += part[(long)c * 28 * 1024 + p];
     red[l][pl] = s;
     __syncthreads();
     if (l == 0) {
