@@ -46,7 +46,6 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // Two floats as packed bf16 (lo in bits 0..15), round to nearest even: one
 // hardware conversion instruction on gfx950.
@@ -62,12 +61,6 @@ __device__ __forceinline__ uint32_t relu_keep2(uint32_t k) {
     const uint32_t lo = ((k & 0x8000u) == 0u && (k & 0x7fffu) != 0u) ? 0x0000ffffu : 0u;
     const uint32_t hi = ((k & 0x80000000u) == 0u && (k & 0x7fff0000u) != 0u) ? 0xffff0000u : 0u;
     return lo | hi;
-}
-
-__device__ __forceinline__ void tap_offset(int t, int& dz, int& dy, int& dx) {
-    dz = t / 9 - 1;
-    dy = (t / 3) % 3 - 1;
-    dx = t % 3 - 1;
 }
 
 // Row index of the MFMA output register i of lane l (the column is l % 32).

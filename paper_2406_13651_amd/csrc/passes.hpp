@@ -38,28 +38,6 @@ __host__ __device__ constexpr int row_lds_floats2() {
     return rows_per_block(N) * lds_len<N, kRowPad>();
 }
 
-// Largest row-pass and column-pass LDS buffers over the supported lengths.
-__host__ __device__ constexpr int max_row_lds() {
-    int m = 0;
-    m = m > row_lds_floats2<32>() ? m : row_lds_floats2<32>();
-    m = m > row_lds_floats2<64>() ? m : row_lds_floats2<64>();
-    m = m > row_lds_floats2<128>() ? m : row_lds_floats2<128>();
-    m = m > row_lds_floats2<192>() ? m : row_lds_floats2<192>();
-    m = m > row_lds_floats2<256>() ? m : row_lds_floats2<256>();
-    m = m > row_lds_floats2<384>() ? m : row_lds_floats2<384>();
-    m = m > row_lds_floats2<512>() ? m : row_lds_floats2<512>();
-    return m;
-}
-__host__ __device__ constexpr int max_col_lds() {
-    int m = 0;
-    const int ns[7] = {32, 64, 128, 192, 256, 384, 512};
-    for (int i = 0; i < 7; ++i) {
-        const int v = ns[i] * col_tile_cols(ns[i]);
-        m = m > v ? m : v;
-    }
-    return m;
-}
-
 // Sum of K doubles over the block, written by thread 0 to out[0..K).
 template <int K>
 __device__ __forceinline__ void block_sum_store(double (&v)[K], double* out) {
@@ -550,46 +528,6 @@ struct ColItemVal {
     int item;
     __device__ const ColArgs& get() const { return args; }
 };
-
-// Forward column pass of one tile from band rows to the compact layout,
-// without pipelining.
-template <int NY>
-__device__ __forceinline__ void col_fwd_item(const ColArgs& a, int item, float2* tw, float2* tile,
-                                             bool load_tables) {
-    constexpr int TC = col_tile_cols(NY);
-    constexpr int TPC = kBlock / TC;
-    const SceneTables& s = a.s;
-    const int tid = threadIdx.x;
-    const int tile_i = item % s.tiles;
-    const int zl = item / s.tiles;
-    const int c0 = tile_i * TC;
-    __syncthreads();
-    if (load_tables)
-        for (int i = tid; i < NY; i += kBlock) tw[i] = s.tw_y[i];
-    {
-        const int c = tid % TC, bc = c0 + c;
-        const float2* src = a.band_in + (size_t)zl * s.ny * s.Bs + bc;
-        for (int y = tid / TC; y < NY; y += TPC)
-            tile[y * TC + c] = bc < s.B ? src[(size_t)y * s.Bs] : make_float2(0.f, 0.f);
-    }
-    fft_lds<NY, TPC, -1>(tile + tid % TC, TC, tid / TC, tw);
-    double acc[1] = {0.0};
-    {
-        const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
-        if (bc < s.B) {
-            float2* dst = a.cmp_out + (size_t)zl * s.P;
-            const int p1 = s.col_off[bc + 1];
-            float f = 0.f;
-            for (int p = s.col_off[bc] + lane; p < p1; p += TPC) {
-                const float2 val = cscale(tile[s.row_idx[p] * TC + c], a.scale);
-                dst[p] = val;
-                f += cabs2(val);
-            }
-            acc[0] = f;
-        }
-    }
-    if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
-}
 
 // ---------------------------------------------------------------------------
 // Exact step size of one look from the partial sums of the three passes.
