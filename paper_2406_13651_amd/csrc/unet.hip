@@ -405,10 +405,16 @@ __global__ __launch_bounds__(kBlock) void k_pool2_bwd(const uint16_t* e, const u
         int arg[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
+            // first maximum, tracked by value (no run-time index into ev,
+            // which would put the array in scratch memory)
             int best = 0;
+            float bv = ev[0][c];
 #pragma unroll
-            for (int s = 1; s < 8; ++s)
-                if (ev[s][c] > ev[best][c]) best = s;
+            for (int s = 1; s < 8; ++s) {
+                const bool gt = ev[s][c] > bv;
+                best = gt ? s : best;
+                bv = gt ? ev[s][c] : bv;
+            }
             arg[c] = best;
         }
 #pragma unroll
