@@ -188,21 +188,46 @@ struct RowLds {
     float2* buf;
 };
 
-// Pointwise step of the gradient pass on one row held in rb (the inverse row
+// Row transform of h (h[k] = element t + k TR of the row): in registers where
+// fft_regs applies (power-of-two rows), else through rb with fft_lds.  With
+// OUT_REGS the result returns to h; otherwise it is left in rb in natural
+// order, for gathers across the row by the row's own wave.
+template <int NX, int TR, int S, int PAD, bool OUT_REGS, int PX>
+__device__ __forceinline__ void row_fft(float2 (&h)[PX], float2* rb, int t, const float2* tw) {
+    if constexpr (NX % TR == 0 && fft_regs_ok<NX, TR>()) {
+        fft_regs<NX, TR, S, PAD, OUT_REGS>(h, rb, t, tw);
+    } else {
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+            const int x = t + k * TR;
+            if (NX % TR == 0 || x < NX) rb[lds_pos<PAD>(x)] = h[k];
+        }
+        fft_lds<NX, TR, S, PAD, true>(rb, 1, t, tw);
+        if constexpr (OUT_REGS) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) h[k] = rb[lds_pos<PAD>(x)];
+            }
+        }
+    }
+}
+
+// Pointwise step of the gradient pass on one row held in h (the inverse row
 // FFT of the band already applied): d = A^H r / sigma_w^2 - omega mu with
-// omega = 1 / (r' + sigma_w^2 / alpha), written back into rb, plus the
+// omega = 1 / (r' + sigma_w^2 / alpha), written back into h, plus the
 // thread's shares of ||d||^2, sum omega |d|^2 and sum omega |mu|^2.
-template <int NX, int TR, int PX, int PAD>
-__device__ __forceinline__ void row_grad_pointwise(const RowArgs& a, float2* rb, int t, const float2 (&m)[PX],
+template <int NX, int TR, int PX>
+__device__ __forceinline__ void row_grad_pointwise(const RowArgs& a, float2 (&h)[PX], int t, const float2 (&m)[PX],
                                                    const float (&rp)[PX], float& dd, float& wd, float& wm) {
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
         const int x = t + k * TR;
         if (NX % TR == 0 || x < NX) {
-            const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
+            const float2 ahr = cscale(h[k], a.scale);
             const float om = 1.f / (rp[k] + a.floor_w);
             const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
-            rb[lds_pos<PAD>(x)] = d;
+            h[k] = d;
             const float d2 = cabs2(d);
             dd += d2;
             wd += om * d2;
@@ -221,7 +246,6 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
     constexpr int TR = row_threads(NX);
     constexpr int RPB = rows_per_block(NX);
     constexpr int PX = (NX + TR - 1) / TR;          // row samples per thread
-    constexpr int S1 = (MODE == ROW_FWD) ? -1 : +1;
     constexpr int PAD = kRowPad;
     constexpr int RS = lds_len<NX, PAD>();          // padded row length in LDS
     // ROW_UPDATE_EXACT is the update pass with the exact surrogate prox in
@@ -274,9 +298,14 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
     }
     float2* rb = L.buf + ri * RS;
 
+    // the row in registers: h[k] = element t + k TR (zero for inactive rows)
+    float2 h[PX];
     if constexpr (MODE == ROW_FWD) {
-        if (active)
-            for (int x = t; x < NX; x += TR) rb[lds_pos<PAD>(x)] = a.img_in[img + x];
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+            const int x = t + k * TR;
+            h[k] = (active && (NX % TR == 0 || x < NX)) ? a.img_in[img + x] : make_float2(0.f, 0.f);
+        }
     } else {
         // The row's band samples: all PX loads are issued before the first
         // is used (samples off the band read the row's first band sample and
@@ -284,40 +313,41 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
         // behind them.
         float2 bin[PX];
         int bp[PX];
-        if (active) {
 #pragma unroll
-            for (int k = 0; k < PX; ++k) {
-                const int x = t + k * TR;
-                bp[k] = (NX % TR == 0 || x < NX) ? L.bpos[x] : -1;
-                bin[k] = ld_stream(a.band_in + band + (bp[k] >= 0 ? bp[k] : 0));
-            }
+        for (int k = 0; k < PX; ++k) {
+            const int x = t + k * TR;
+            bp[k] = (active && (NX % TR == 0 || x < NX)) ? L.bpos[x] : -1;
+            bin[k] = ld_stream(a.band_in + band + (bp[k] >= 0 ? bp[k] : 0));  // inactive rows read row 0
         }
         if constexpr (PREFETCH) load_streams();
+#pragma unroll
+        for (int k = 0; k < PX; ++k) h[k] = bp[k] >= 0 ? bin[k] : make_float2(0.f, 0.f);
+    }
+
+    if constexpr (MODE == ROW_INV) {
+        row_fft<NX, TR, +1, PAD, true>(h, rb, t, L.tw);
         if (active) {
 #pragma unroll
             for (int k = 0; k < PX; ++k) {
                 const int x = t + k * TR;
-                if (NX % TR == 0 || x < NX) rb[lds_pos<PAD>(x)] = bp[k] >= 0 ? bin[k] : make_float2(0.f, 0.f);
+                if (NX % TR == 0 || x < NX) a.img_out[img + x] = cscale(h[k], a.scale);
             }
         }
-    }
-    fft_lds<NX, TR, S1, PAD, true>(rb, 1, t, L.tw);
-
-    if constexpr (MODE == ROW_INV) {
-        if (active)
-            for (int x = t; x < NX; x += TR) a.img_out[img + x] = cscale(rb[lds_pos<PAD>(x)], a.scale);
     } else if constexpr (MODE == ROW_FWD) {
+        row_fft<NX, TR, -1, PAD, false>(h, rb, t, L.tw);
         if (active)
             for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale);
     } else if constexpr (MODE == ROW_GRAD) {
+        row_fft<NX, TR, +1, PAD, true>(h, rb, t, L.tw);
         float dd = 0.f, wd = 0.f, wm = 0.f;
-        if (active) row_grad_pointwise<NX, TR, PX, PAD>(a, rb, t, m, rp, dd, wd, wm);
-        fft_lds<NX, TR, -1, PAD, true>(rb, 1, t, L.tw);
+        if (active) row_grad_pointwise<NX, TR>(a, h, t, m, rp, dd, wd, wm);
+        row_fft<NX, TR, -1, PAD, false>(h, rb, t, L.tw);
         if (active)
             for (int b = t; b < s.B; b += TR) st_stream(a.band_out + band + b, cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale));
         double acc[3] = {dd, wd, wm};
         block_sum_store<3>(acc, a.part + slot * 3);
     } else {  // ROW_UPDATE
+        row_fft<NX, TR, +1, PAD, true>(h, rb, t, L.tw);
         if constexpr (!PREFETCH) load_streams();
         const float gamma = (float)a.diag[(size_t)look * kDiag];
         float wm1 = 0.f;
@@ -327,7 +357,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
             for (int k = 0; k < PX; ++k) {
                 const int x = t + k * TR;
                 if (NX % TR == 0 || x < NX) {
-                    const float2 ahr = cscale(rb[lds_pos<PAD>(x)], a.scale);
+                    const float2 ahr = cscale(h[k], a.scale);
                     const float r0 = rp[k];
                     const float v = wv[k];
                     const float om = 1.f / (r0 + a.floor_w);
