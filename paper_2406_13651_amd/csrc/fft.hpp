@@ -193,38 +193,43 @@ __device__ __forceinline__ void fft_lds(float2* buf, int stride, int t, const fl
     fft_stages<N, T, S, PADSH, 0, 1, WAVE>(buf, stride, t, tw);
 }
 
-// Row transforms with the row in registers: the T threads of a wave-local
-// group hold h[k] = element t + k T.  This applies when the first radix R0
-// gives N = R0 T (stage 0 then takes its butterfly inputs straight from h)
-// and the last radix RL gives (N / RL) % T == 0 (the last stage's outputs
-// then land on element t + k T of their own thread).  The stages between
-// go through buf as in fft_lds, with wave synchronisation.
+// Transforms with the data in registers: the T threads of a group hold h[k] =
+// element t + k T.  This applies when every stage's N / R butterflies divide
+// evenly among the T threads: the first stage can then take its inputs
+// j + r N / R0 (j = t + p T) from h[p + r N / (R0 T)], and the last stage can
+// write its outputs j + r N / RL to h[p + r N / (RL T)], each on the thread
+// that holds it.  The stages between go through buf as in fft_lds; the group
+// synchronises as a block, or (WAVE) as a wave when it lies inside one.
 template <int N, int T>
 __host__ __device__ constexpr bool fft_regs_ok() {
-    return T <= 64 && 64 % T == 0 && radix_at(N, 0) * T == N &&
-           (N / radix_at(N, num_stages(N) - 1)) % T == 0;
+    for (int st = 0; st < num_stages(N); ++st)
+        if ((N / radix_at(N, st)) % T != 0) return false;
+    return true;
 }
 
-template <int N, int T, int S, int PADSH, int STAGE, int NS, bool OUT_REGS>
-__device__ __forceinline__ void fft_regs_stages(float2 (&h)[N / T], float2* buf, int t, const float2* tw) {
+template <int N, int T, int S, int PADSH, int STAGE, int NS, bool IN_REGS, bool OUT_REGS, bool WAVE>
+__device__ __forceinline__ void fft_regs_stages(float2 (&h)[N / T], float2* buf, int stride, int t,
+                                                const float2* tw) {
     constexpr int NST = num_stages(N);
     if constexpr (STAGE < NST) {
         constexpr int R = radix_at(N, STAGE);
         constexpr int NB = N / R;
         constexpr int PER = NB / T;
         constexpr int TWSTEP = N / (NS * R);
+        constexpr bool FIRST_FROM_REGS = IN_REGS && STAGE == 0;
         constexpr bool LAST_IN_REGS = OUT_REGS && STAGE == NST - 1;
-        static_assert(NB % T == 0, "every stage must give each thread whole butterflies");
         float2 v[PER][R];
-        if constexpr (STAGE == 0) {
+        if constexpr (FIRST_FROM_REGS) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[0][r] = h[r];  // element t + r NB, NB = T
+            for (int p = 0; p < PER; ++p)
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[p][r] = h[p + r * PER];
         } else {
 #pragma unroll
             for (int p = 0; p < PER; ++p)
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[p][r] = buf[lds_pos<PADSH>(t + p * T + r * NB)];
-            group_sync<true>();
+                for (int r = 0; r < R; ++r) v[p][r] = buf[lds_pos<PADSH>(t + p * T + r * NB) * stride];
+            group_sync<WAVE>();
         }
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
@@ -240,28 +245,30 @@ __device__ __forceinline__ void fft_regs_stages(float2 (&h)[N / T], float2* buf,
             }
             Bfly<R, S>::run(v[p]);
             if constexpr (LAST_IN_REGS) {
-                // outputs j + r NS (NS = N / R here) = element t + (p + r NS / T) T
+                // outputs j + r NS (NS = N / R in the last stage) = element t + (p + r NS / T) T
 #pragma unroll
                 for (int r = 0; r < R; ++r) h[p + r * (NS / T)] = v[p][r];
             } else {
                 const int base = (j / NS) * NS * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) buf[lds_pos<PADSH>(base + r * NS)] = v[p][r];
+                for (int r = 0; r < R; ++r) buf[lds_pos<PADSH>(base + r * NS) * stride] = v[p][r];
             }
         }
-        if constexpr (!LAST_IN_REGS) group_sync<true>();
-        fft_regs_stages<N, T, S, PADSH, STAGE + 1, NS * R, OUT_REGS>(h, buf, t, tw);
+        if constexpr (!LAST_IN_REGS) group_sync<WAVE>();
+        fft_regs_stages<N, T, S, PADSH, STAGE + 1, NS * R, IN_REGS, OUT_REGS, WAVE>(h, buf, stride, t, tw);
     }
 }
 
-// Unnormalised length-N DFT of the row held in h (see fft_regs_ok), using
-// buf as the wave-local exchange buffer.  With OUT_REGS the result returns
-// to h; otherwise it is left in buf in natural order (visible to the wave).
-template <int N, int T, int S, int PADSH, bool OUT_REGS>
-__device__ __forceinline__ void fft_regs(float2 (&h)[N / T], float2* buf, int t, const float2* tw) {
-    static_assert(fft_len_ok(N) && fft_regs_ok<N, T>(), "row length and group size outside the register form");
-    group_sync<true>();  // the group's earlier reads of buf are done
-    fft_regs_stages<N, T, S, PADSH, 0, 1, OUT_REGS>(h, buf, t, tw);
+// Unnormalised length-N DFT (see fft_regs_ok) of the group's vector, held in
+// h (IN_REGS) or in buf[lds_pos(i) * stride]; the result goes to h (OUT_REGS)
+// or to buf in natural order, visible to the group.  Starts with a group
+// synchronisation, so earlier reads and writes of buf by the group are done.
+template <int N, int T, int S, int PADSH, bool IN_REGS, bool OUT_REGS, bool WAVE>
+__device__ __forceinline__ void fft_regs(float2 (&h)[N / T], float2* buf, int stride, int t, const float2* tw) {
+    static_assert(fft_len_ok(N) && fft_regs_ok<N, T>(), "length and group size outside the register form");
+    static_assert(!WAVE || (T <= 64 && 64 % T == 0), "a wave-local transform must lie inside one wave");
+    group_sync<WAVE>();
+    fft_regs_stages<N, T, S, PADSH, 0, 1, IN_REGS, OUT_REGS, WAVE>(h, buf, stride, t, tw);
 }
 
 }  // namespace clampk

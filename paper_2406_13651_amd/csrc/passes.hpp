@@ -195,7 +195,7 @@ struct RowLds {
 template <int NX, int TR, int S, int PAD, bool OUT_REGS, int PX>
 __device__ __forceinline__ void row_fft(float2 (&h)[PX], float2* rb, int t, const float2* tw) {
     if constexpr (NX % TR == 0 && fft_regs_ok<NX, TR>()) {
-        fft_regs<NX, TR, S, PAD, OUT_REGS>(h, rb, t, tw);
+        fft_regs<NX, TR, S, PAD, true, OUT_REGS, true>(h, rb, 1, t, tw);
     } else {
 #pragma unroll
         for (int k = 0; k < PX; ++k) {
@@ -462,13 +462,22 @@ __device__ __forceinline__ void col_inv_item(const ColArgs& a, int item, float2*
         }
         acc[0] = f;
     }
-    fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
-    {
-        const int co = tid % TC, bo = c0 + co;
+    const int co = tid % TC, bo = c0 + co;
+    float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bo;
+    if constexpr (fft_regs_ok<NY, TPC>()) {
+        // the last stage leaves each thread rows tid / TC + k TPC of its
+        // column, which it stores as band rows
+        float2 h[NY / TPC];
+        fft_regs<NY, TPC, +1, 0, false, true, false>(h, tile + co, TC, tid / TC, tw);
         if (bo < s.B) {
-            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bo;
-            for (int y = tid / TC; y < NY; y += TPC) st_stream(dst + (size_t)y * s.Bs, cscale(tile[y * TC + co], a.scale));
+#pragma unroll
+            for (int k = 0; k < NY / TPC; ++k)
+                st_stream(dst + (size_t)(tid / TC + k * TPC) * s.Bs, cscale(h[k], a.scale));
         }
+    } else {
+        fft_lds<NY, TPC, +1>(tile + co, TC, tid / TC, tw);
+        if (bo < s.B)
+            for (int y = tid / TC; y < NY; y += TPC) st_stream(dst + (size_t)y * s.Bs, cscale(tile[y * TC + co], a.scale));
     }
     if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
 }
