@@ -515,9 +515,11 @@ __device__ __forceinline__ void col_fwd_stream(int first, int count, int stride,
         const SceneTables& s = a.s;
         const int tile_i = ai.item % s.tiles;
         const int zl = ai.item / s.tiles;
-        __syncthreads();  // the previous item's readers of `tile` are done
+        // the item's band rows move to h (rows y_ld + k TPC of column c_ld),
+        // and pre is free for the next item's prefetch
+        float2 h[PT];
 #pragma unroll
-        for (int k = 0; k < PT; ++k) tile[(y_ld + k * TPC) * TC + c_ld] = pre[k];
+        for (int k = 0; k < PT; ++k) h[k] = pre[k];
         // Rows of column bc's pupil samples p0 + lane + k TPC (at most NY =
         // PT * TPC of them), loaded before the next item's prefetch so that
         // waiting for them does not wait for it; positions past p1 re-read
@@ -535,7 +537,16 @@ __device__ __forceinline__ void col_fwd_stream(int first, int count, int stride,
             }
         }
         if (pos + stride < count) load(pos + stride);
-        fft_lds<NY, TPC, -1>(tile + c_ld, TC, y_ld, tw);
+        // the transform's opening block barrier also orders it after the
+        // previous item's readers of `tile`
+        if constexpr (fft_regs_ok<NY, TPC>()) {
+            fft_regs<NY, TPC, -1, 0, true, false, false>(h, tile + c_ld, TC, y_ld, tw);
+        } else {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < PT; ++k) tile[(y_ld + k * TPC) * TC + c_ld] = h[k];
+            fft_lds<NY, TPC, -1>(tile + c_ld, TC, y_ld, tw);
+        }
         double acc[1] = {0.0};
         if (bc < s.B) {
             float2* dst = a.cmp_out + (size_t)zl * s.P;
