@@ -411,6 +411,12 @@ clamp_status clamp_unet_adam_step(clamp_unet* unet, float lr, void* hip_stream);
  * threads.  Creating events can fail with CLAMP_EDEVICE. */
 #define CLAMP_STAGES 14
 clamp_status clamp_plan_set_timing(clamp_plan* plan, int32_t enable);
+/* Timing of the stages whose bit is set in stage_mask only (bit s = stage s;
+ * 0 turns timing off, all CLAMP_STAGES bits equal clamp_plan_set_timing(1)):
+ * a benchmark can time its dominant stage with two events per call instead
+ * of a pair around every stage.  CLAMP_EINVAL for bits at or past
+ * CLAMP_STAGES. */
+clamp_status clamp_plan_set_timing_stages(clamp_plan* plan, uint32_t stage_mask);
 clamp_status clamp_plan_get_timing(clamp_plan* plan, double* total_ms, int32_t* launches);
 /* Name of a timing stage ("" outside [0, CLAMP_STAGES)). */
 const char* clamp_stage_name(int32_t stage);

@@ -93,6 +93,7 @@ def _load():
         "clamp_prior_gauss": [P, i32, ctypes.c_float, P, P, P, P],
         "clamp_mace_step": [P, i32, ctypes.POINTER(clamp_params), P, P, P, P, P, P],
         "clamp_plan_set_timing": [P, i32],
+        "clamp_plan_set_timing_stages": [P, ctypes.c_uint32],
         "clamp_batch_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
         "clamp_batch_create": [P, ctypes.POINTER(clamp_batch_scene), P, P, P, ctypes.POINTER(P)],
         "clamp_batch_destroy": [P],
@@ -305,6 +306,17 @@ def clamp_mace_step(plan, scene, params, w, r, wbar, conv_err, workspace, stream
 
 def clamp_plan_set_timing(plan, enable):
     _check(lib.clamp_plan_set_timing(plan.handle, 1 if enable else 0))
+
+
+def clamp_plan_set_timing_stages(plan, names):
+    """Time only the named stages (an empty collection turns timing off)."""
+    mask = 0
+    for name in names:
+        idx = [i for i in range(STAGES) if clamp_stage_name(i) == name]
+        if not idx:
+            raise ValueError("unknown timing stage %r" % name)
+        mask |= 1 << idx[0]
+    _check(lib.clamp_plan_set_timing_stages(plan.handle, ctypes.c_uint32(mask)))
 
 
 def clamp_plan_get_timing(plan):

@@ -98,7 +98,7 @@ struct clamp_plan {
     int device = 0;
     std::vector<Scene> scenes;
     size_t ws_bytes = 0;
-    bool timing = false;
+    uint32_t timing = 0u;  // bit s: record events around stage s
     std::vector<TimingRecord> records;
     std::vector<hipEvent_t> pool;
 };
@@ -310,7 +310,7 @@ hipEvent_t take_event(clamp_plan* p) {
 template <typename F>
 hipError_t timed(const clamp_plan* cplan, int stage, hipStream_t st, F&& launch) {
     clamp_plan* p = const_cast<clamp_plan*>(cplan);
-    if (!p->timing) return launch();
+    if (((p->timing >> stage) & 1u) == 0u) return launch();
     TimingRecord rec{stage, take_event(p), take_event(p)};
     if (rec.start == nullptr || rec.stop == nullptr) return hipErrorOutOfMemory;
     hipError_t e = hipEventRecord(rec.start, st);
@@ -734,7 +734,14 @@ clamp_status clamp_mace_step(const clamp_plan* plan, int32_t scene, const clamp_
 
 clamp_status clamp_plan_set_timing(clamp_plan* plan, int32_t enable) {
     if (plan == nullptr) return fail(CLAMP_EINVAL, "plan is NULL");
-    plan->timing = enable != 0;
+    plan->timing = enable != 0 ? (1u << CLAMP_STAGES) - 1u : 0u;
+    return CLAMP_OK;
+}
+
+clamp_status clamp_plan_set_timing_stages(clamp_plan* plan, uint32_t stage_mask) {
+    if (plan == nullptr) return fail(CLAMP_EINVAL, "plan is NULL");
+    if (stage_mask >> CLAMP_STAGES) return fail(CLAMP_EINVAL, "stage mask has bits at or past CLAMP_STAGES");
+    plan->timing = stage_mask;
     return CLAMP_OK;
 }
 
@@ -1125,8 +1132,8 @@ clamp_status clamp_batch_capture(clamp_batch* batch, void* hip_stream) {
     if (hip_stream == nullptr) return fail(CLAMP_EINVAL, "capture needs a non-NULL stream");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     clamp_plan* p = const_cast<clamp_plan*>(batch->plan);
-    const bool timing = p->timing;
-    p->timing = false;  // no event records inside the graph
+    const uint32_t timing = p->timing;
+    p->timing = 0u;  // no event records inside the graph
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     hipGraph_t g = nullptr;
     if (e == hipSuccess) {

@@ -67,6 +67,7 @@ def test_calls_reject_null_plan(lib):
     assert lib.clamp_fwd_agent(None, 0, None, None, None, None, None, None, None) == -1
     assert lib.clamp_mace_step(None, 0, None, None, None, None, None, None, None) == -1
     assert lib.clamp_prior_gauss(None, 0, ctypes.c_float(1.0), None, None, None, None) == -1
+    assert lib.clamp_plan_set_timing_stages(None, ctypes.c_uint32(1)) == -1
     assert lib.clamp_plan_destroy(None) == 0
     assert b"plan" in lib.clamp_last_error()
 

@@ -316,3 +316,27 @@ def test_full_size_run_properties(G):
     torch.cuda.synchronize()
     assert int(g.fault.item()) == 0
     assert np.all(np.isfinite(errs)) and errs[-1] < errs[0]
+
+
+def test_timing_of_selected_stages(G):
+    """clamp_plan_set_timing_stages records events around the chosen stages
+    only; clamp_plan_set_timing(1) around every stage of the call."""
+    import torch
+    from paper_2406_13651_amd import _clamp as C
+    spec = synth.CONFIGS["tiny"]
+    r_true, y, s2w = synth.make_problem(spec, 0)
+    g = G.ClampGPU(spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, 1e-3, with_prior=True)
+    g.init(to_gpu(y))
+    C.clamp_plan_set_timing_stages(g.plan, ["row_update"])
+    g.iterate()
+    torch.cuda.synchronize()
+    C.clamp_plan_set_timing(g.plan, False)
+    st = C.clamp_plan_get_timing(g.plan)
+    assert set(st) == {"row_update"} and st["row_update"][1] == 1 and st["row_update"][0] > 0.0
+    C.clamp_plan_set_timing(g.plan, True)
+    g.iterate()
+    C.clamp_plan_set_timing(g.plan, False)
+    st = C.clamp_plan_get_timing(g.plan)
+    assert {"col_inv", "row_grad", "col_fwd", "row_update", "mace_step", "prior_gauss"} <= set(st)
+    with pytest.raises(ValueError):
+        C.clamp_plan_set_timing_stages(g.plan, ["no such stage"])
