@@ -48,22 +48,33 @@ def clamp_init(y, mask, looks_with_prior=True, mu_scale=1.0):
 
 
 def clamp_iteration(state, y, mask, sigma_w2, sigma2, rho=0.5, prior=None,
-                    beta=None, r_update="quadratic"):
+                    beta=None, r_update="quadratic", workers=1):
     """One pass of the Alg. 2 loop body.  `prior` is a callable H(w_{L+1}) or
     None for forward-only runs; `r_update` is "quadratic" (App. A) or "exact"
-    (eq. surrogate-prox).  Returns a dict of diagnostics."""
+    (eq. surrogate-prox).  The looks' agents depend only on their own look's
+    state, so `workers` > 1 applies them from a thread pool; each look's
+    arithmetic is the same either way.  Returns a dict of diagnostics."""
     y = np.asarray(y, dtype=np.complex128)
     L = y.shape[0]
     alpha = aperture_fraction(mask)
     k = state.k + 1
     if beta is None:
         beta = beta_schedule(k)
-    infos = []
     r_new = state.r.copy()
     mu_new = state.mu.copy()
-    for l in range(L):
-        mu_l, r_l, info = forward_agent(state.mu[l], y[l], state.r[l], state.w[l],
-                                        mask, sigma_w2, sigma2, alpha, beta, r_update)
+
+    def agent(l):
+        return forward_agent(state.mu[l], y[l], state.r[l], state.w[l], mask, sigma_w2, sigma2, alpha, beta,
+                             r_update)
+
+    if workers > 1 and L > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(workers, L)) as ex:
+            results = list(ex.map(agent, range(L)))
+    else:
+        results = [agent(l) for l in range(L)]
+    infos = []
+    for l, (mu_l, r_l, info) in enumerate(results):
         mu_new[l] = mu_l
         r_new[l] = r_l
         infos.append(info)
@@ -85,14 +96,19 @@ def clamp_iteration(state, y, mask, sigma_w2, sigma2, rho=0.5, prior=None,
 
 
 def clamp_run(y, radius, sigma_w2, sigma2, iters, rho=0.5, with_prior=True,
-              mu_scale=1.0, prior_sigma=1.0, mask=None, r_update="quadratic"):
-    """Alg. 2 for `iters` iterations; returns (state, list of diagnostics)."""
+              mu_scale=1.0, prior_sigma=1.0, mask=None, r_update="quadratic", workers=1, keep_hist=True):
+    """Alg. 2 for `iters` iterations; returns (state, list of diagnostics).
+    keep_hist=False keeps only scalars and the last iteration's w_bar in the
+    diagnostics (large volumes)."""
     y = np.asarray(y)
     if mask is None:
         mask = pupil_mask(y.shape[-2], y.shape[-1], radius)
     state = clamp_init(y, mask, with_prior, mu_scale)
     prior = (lambda x: gaussian_smooth(x, prior_sigma)) if with_prior else None
     hist = []
-    for _ in range(iters):
-        hist.append(clamp_iteration(state, y, mask, sigma_w2, sigma2, rho, prior, r_update=r_update))
+    for it in range(iters):
+        h = clamp_iteration(state, y, mask, sigma_w2, sigma2, rho, prior, r_update=r_update, workers=workers)
+        if not keep_hist and it < iters - 1:
+            h.pop("wbar")
+        hist.append(h)
     return state, hist

@@ -7,7 +7,8 @@ III-C); the learned form here is a smaller residual network: 8 convolutions
 of 3x3x3 taps (1 -> 32, six 32 -> 32, 32 -> 1) with biases, zero padding,
 ReLU after the first seven, and output H(x) = x + N(x).  Training minimises
 the mean squared error to the target (Sec. III-C), and the same Adam update
-is written out here for reference.
+is written out here for reference, with the gradient-norm clipping the
+library's optimiser adds to it.
 
 Layouts: a volume is [C, D, H, W]; a weight is [27, Cin, Cout] with tap t =
 9 (dz + 1) + 3 (dy + 1) + (dx + 1) for offsets dz, dy, dx in {-1, 0, 1}; the
@@ -125,10 +126,8 @@ def loss_and_grads(xs, ts, params, act_round=False):
     return loss / n_vox, grads
 
 
-def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam update (bias-corrected first and second moments)."""
-    t = state.get("t", 0) + 1
-    state["t"] = t
+def _adam_moments(params, grads, state, t, lr, b1, b2, eps):
+    """Adam's moment updates and bias-corrected step at step count t."""
     new = []
     for i, ((w, b), (gw, gb)) in enumerate(zip(params, grads)):
         upd = []
@@ -144,6 +143,43 @@ def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
             upd.append(p - lr * mh / (np.sqrt(vh) + eps))
         new.append(tuple(upd))
     return new
+
+
+def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (bias-corrected first and second moments)."""
+    t = state.get("t", 0) + 1
+    state["t"] = t
+    return _adam_moments(params, grads, state, t, lr, b1, b2, eps)
+
+
+def adam_step_clipped(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8, clip=3.0, avg_weight=0.05):
+    """Adam with the training safeguards of the learned prior (not in the
+    paper, which trains with plain Adam): the gradient of all parameters,
+    taken as one vector, is scaled down to norm `clip` times a running
+    average of the past (scaled) gradient norms when its norm exceeds that;
+    the first step is not scaled and starts the average, which afterwards
+    moves by `avg_weight` towards each step's scaled norm.  A gradient whose
+    norm is not finite changes neither the parameters, the moments nor the
+    average; the step count of the bias correction still advances."""
+    t = state.get("t", 0) + 1
+    state["t"] = t
+    sq = 0.0
+    for gw, gb in grads:
+        sq += float(np.sum(gw * gw)) + float(np.sum(gb * gb))
+    norm = np.sqrt(sq)
+    if not np.isfinite(norm):
+        return [(w.copy(), b.copy()) for w, b in params]
+    run = state.get("run_norm", 0.0)
+    if run == 0.0:
+        scale = 1.0
+        run = norm
+    else:
+        cap = clip * run
+        scale = min(1.0, cap / norm) if norm > 0.0 else 1.0
+        run = (1.0 - avg_weight) * run + avg_weight * min(norm, cap)
+    state["run_norm"] = run
+    scaled = [(scale * gw, scale * gb) for gw, gb in grads]
+    return _adam_moments(params, scaled, state, t, lr, b1, b2, eps)
 
 
 def denoise(x, params, act_round=False):
