@@ -126,14 +126,23 @@ typedef struct {
 #define CLAMP_R_EXACT 1
 
 /* Per-look state of the forward agents (device memory, caller-owned).
- *   mu    complex64 [L][n]   posterior means mu_l (eq. mu2).
- *   resid complex64 [L][nz][P] D(a)(y_l - A mu_l) in the compact layout.
- *   r     float32 [n_agents][n]  agent outputs; r[l] (l < L) is also look l's
- *         surrogate anchor r'_l, and slice L (when present) is the prior's. */
+ *   mu      complex64 [L][n]   posterior means mu_l (eq. mu2).
+ *   resid   complex64 [L][nz][P] D(a)(y_l - A mu_l) in the compact layout.
+ *   r       float32 [n_agents][n]  agent outputs; r[l] (l < L) is also look
+ *           l's surrogate anchor r'_l, and slice L (when present) is the prior's.
+ *   y_pupil complex64 [L][nz][P] D(a) y_l in the compact layout, or NULL.
+ *           clamp_fwd_init fills it; clamp_fwd_refresh rebuilds resid from it.
+ *   ahy2    double [L] ||A^H y_l||^2 (= ||D(a) y_l||^2), or NULL.
+ *           clamp_fwd_init fills it; clamp_fwd_agent then reports the
+ *           mu-residual of eq. residual.
+ * With the 3D operator (range_support K >= 1) resid and y_pupil are
+ * [L][K][P]. */
 typedef struct {
     void* mu;
     void* resid;
     float* r;
+    void* y_pupil;
+    double* ahy2;
 } clamp_fwd_state;
 
 /* Builds device tables for `nscenes` scenes: FFT twiddles (computed in
@@ -174,10 +183,11 @@ clamp_status clamp_aperture_op(const clamp_plan* plan, int32_t scene, int32_t di
  *   b_l = A^H y_l;  r0 = (1/L) sum_l |b_l|^2, floored at 1e-12 mean(r0);
  *   mu_l = s_mu b_l;  resid_l = (1 - s_mu) D(a) y_l  (exact, as A A^H = D(a));
  *   state->r[j] = r0 and w[j] = r0 for every agent j < n_agents;
- *   ahy2[l] = ||A^H y_l||^2 (device double [L]) for the mu-residual. */
+ *   state->y_pupil = D(a) y_l and state->ahy2[l] = ||A^H y_l||^2 where those
+ *   pointers are not NULL. */
 clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene,
                             const clamp_params* params, const void* y_full,
-                            clamp_fwd_state* state, float* w, double* ahy2,
+                            clamp_fwd_state* state, float* w,
                             void* workspace, void* hip_stream);
 
 /* One application of every forward agent (Alg. 2, the per-look loop body;
@@ -189,15 +199,30 @@ clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene,
  *   r[l] = surrogate prox at v = w[l] with s = c + |mu|^2 (params->r_update:
  *   the quadratic surrogate of App. A with beta, or the exact prox).
  * w: float32 [L][n] (the forward agents' slices of the Mann state).
- * diag: device double [L][8] = {gamma, ||d||^2, ||A d||^2, sum omega|d|^2,
- *   ||resid||^2 before, sum omega|mu|^2 before, ||resid||^2 after,
- *   sum omega|mu|^2 after}; h = ||resid||^2/(2 sigma_w^2) + sum omega|mu|^2/2
- *   up to a constant, so h before - h after = gamma ||d||^2 / 2.
+ * diag: device double [L + 1][8].  Row l < L, look l:
+ *   {gamma, ||d||^2, ||A d||^2, h before, h after, mu-residual,
+ *    sum omega |d|^2, ||resid||^2 after},
+ *   where h = ||resid||^2 / (2 sigma_w^2) + sum omega |mu|^2 / 2 is the
+ *   objective of the mu-step (eq. mu-objective) less the constant
+ *   ||(1 - a) y_l||^2 / (2 sigma_w^2), so h before - h after = gamma ||d||^2 / 2;
+ *   and the mu-residual is the look's term of eq. residual in its
+ *   noise-floored form, ||d|| / ||A^H y_l / sigma_w^2|| with the d of this
+ *   step (0 when state->ahy2 is NULL).
+ *   Row L: {mu-residual of eq. residual (the mean of the looks' terms),
+ *   sum_l h before, sum_l h after, 0, 0, 0, 0, 0}.
  * fault: device uint32, OR-ed with CLAMP_FAULT_* bits (never cleared). */
 clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene,
                              const clamp_params* params, clamp_fwd_state* state,
                              const float* w, double* diag, uint32_t* fault,
                              void* workspace, void* hip_stream);
+
+/* Residual refresh: resid_l = y_pupil_l - D(a) F mu_l, recomputed from the
+ * data (Alg. 2 defines the residual by mu; the agent updates it by the
+ * recurrence resid -= gamma D(a) F d, whose float32 rounding accumulates over
+ * iterations).  Needs state->y_pupil (CLAMP_EINVAL otherwise); reads mu,
+ * writes resid. */
+clamp_status clamp_fwd_refresh(const clamp_plan* plan, int32_t scene, clamp_fwd_state* state,
+                               void* workspace, void* hip_stream);
 
 /* Fixed prior agent: out = periodic separable 3D Gaussian smoothing of in
  * (float32 [n] each; standard deviation sigma_vox voxels, 7 taps per axis,
@@ -239,7 +264,7 @@ typedef struct {
     clamp_fwd_state state;  /* mu, resid, r (r: float32 [n_agents][n])        */
     float* w;               /* float32 [n_agents][n]                          */
     float* wbar;            /* float32 [n]                                    */
-    double* diag;           /* double [L][8], as clamp_fwd_agent              */
+    double* diag;           /* double [L + 1][8], as clamp_fwd_agent          */
     float prior_sigma;      /* Gaussian prior width when n_agents = L + 1     */
 } clamp_batch_scene;
 

@@ -34,7 +34,9 @@ FAULT_NONFINITE = 1
 FAULT_RNONPOS = 2
 FAULT_GAMMA = 4
 
-DIAG = 8  # doubles of diagnostics per look
+DIAG = 8  # doubles of diagnostics per look; the diag array holds looks + 1 rows (the last: summary)
+# columns of a look's diag row
+DG_GAMMA, DG_DD, DG_AD, DG_H0, DG_H1, DG_MURES, DG_WD, DG_R2 = range(8)
 STAGES = 14  # timing stages
 
 
@@ -63,7 +65,8 @@ R_UPDATES = {"quadratic": CLAMP_R_QUADRATIC, "exact": CLAMP_R_EXACT}
 
 
 class clamp_fwd_state(ctypes.Structure):
-    _fields_ = [("mu", ctypes.c_void_p), ("resid", ctypes.c_void_p), ("r", ctypes.c_void_p)]
+    _fields_ = [("mu", ctypes.c_void_p), ("resid", ctypes.c_void_p), ("r", ctypes.c_void_p),
+                ("y_pupil", ctypes.c_void_p), ("ahy2", ctypes.c_void_p)]
 
 
 class clamp_batch_scene(ctypes.Structure):
@@ -87,7 +90,8 @@ def _load():
         "clamp_plan_pupil_index": [P, i32, ctypes.POINTER(i32)],
         "clamp_aperture_op": [P, i32, i32, P, P, i32, P, P],
         "clamp_fwd_init": [P, i32, ctypes.POINTER(clamp_params), P, ctypes.POINTER(clamp_fwd_state),
-                           P, P, P, P],
+                           P, P, P],
+        "clamp_fwd_refresh": [P, i32, ctypes.POINTER(clamp_fwd_state), P, P],
         "clamp_fwd_agent": [P, i32, ctypes.POINTER(clamp_params), ctypes.POINTER(clamp_fwd_state),
                             P, P, P, P, P],
         "clamp_prior_gauss": [P, i32, ctypes.c_float, P, P, P, P],
@@ -253,37 +257,56 @@ def make_params(sigma_w2, sigma2, rho, beta, mu_init_scale, upsilon, r_update="q
     return p
 
 
-def _state(plan, scene, mu, resid, r, n_agents):
+def _cmp_len(plan, scene):
+    """Complex values per look of the compact pupil arrays (resid, y_pupil)."""
     s = plan.scenes[scene]
     P = plan.info[scene]["P"]
+    return (s.range_support if getattr(s, "range_support", 0) > 0 else s.nz) * P
+
+
+def _state(plan, scene, mu, resid, r, n_agents, y_pupil=None, ahy2=None):
+    s = plan.scenes[scene]
     st = clamp_fwd_state(_ptr(mu, torch.complex64, s.looks * s.n, "mu").value,
-                         _ptr(resid, torch.complex64,
-                              s.looks * (s.range_support if getattr(s, "range_support", 0) > 0 else s.nz) * P,
-                              "resid").value,
-                         _ptr(r, torch.float32, n_agents * s.n, "r").value)
+                         _ptr(resid, torch.complex64, s.looks * _cmp_len(plan, scene), "resid").value,
+                         _ptr(r, torch.float32, n_agents * s.n, "r").value,
+                         None if y_pupil is None else
+                         _ptr(y_pupil, torch.complex64, s.looks * _cmp_len(plan, scene), "y_pupil").value,
+                         None if ahy2 is None else _ptr(ahy2, torch.float64, s.looks, "ahy2").value)
     return st
 
 
-def clamp_fwd_init(plan, scene, params, y_full, mu, resid, r, w, ahy2, workspace, stream=None):
+def clamp_fwd_init(plan, scene, params, y_full, mu, resid, r, w, workspace, stream=None, y_pupil=None, ahy2=None):
     s = plan.scenes[scene]
-    st = _state(plan, scene, mu, resid, r, params.n_agents)
+    st = _state(plan, scene, mu, resid, r, params.n_agents, y_pupil, ahy2)
     _check(lib.clamp_fwd_init(plan.handle, scene, ctypes.byref(params),
                               _ptr(y_full, torch.complex64, s.looks * s.n, "y_full"), ctypes.byref(st),
                               _ptr(w, torch.float32, params.n_agents * s.n, "w"),
-                              _ptr(ahy2, torch.float64, s.looks, "ahy2"),
                               _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
                               _stream(stream)))
 
 
-def clamp_fwd_agent(plan, scene, params, mu, resid, r, w, diag, fault, workspace, stream=None):
+def clamp_fwd_agent(plan, scene, params, mu, resid, r, w, diag, fault, workspace, stream=None, ahy2=None):
+    """diag: float64 [(looks + 1) * DIAG] (see include/clamp.h)."""
     s = plan.scenes[scene]
-    st = _state(plan, scene, mu, resid, r, s.looks)
+    st = _state(plan, scene, mu, resid, r, s.looks, None, ahy2)
     _check(lib.clamp_fwd_agent(plan.handle, scene, ctypes.byref(params), ctypes.byref(st),
                                _ptr(w, torch.float32, s.looks * s.n, "w"),
-                               _ptr(diag, torch.float64, s.looks * DIAG, "diag"),
+                               _ptr(diag, torch.float64, (s.looks + 1) * DIAG, "diag"),
                                _ptr(fault, torch.int32, 1, "fault"),
                                _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
                                _stream(stream)))
+
+
+def clamp_fwd_refresh(plan, scene, mu, resid, y_pupil, workspace, stream=None):
+    s = plan.scenes[scene]
+    st = clamp_fwd_state(_ptr(mu, torch.complex64, s.looks * s.n, "mu").value,
+                         _ptr(resid, torch.complex64, s.looks * _cmp_len(plan, scene), "resid").value,
+                         None,
+                         _ptr(y_pupil, torch.complex64, s.looks * _cmp_len(plan, scene), "y_pupil").value,
+                         None)
+    _check(lib.clamp_fwd_refresh(plan.handle, scene, ctypes.byref(st),
+                                 _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
+                                 _stream(stream)))
 
 
 def clamp_prior_gauss(plan, scene, sigma_vox, x, out, workspace, stream=None):
@@ -355,17 +378,17 @@ class Batch:
 
 def clamp_batch_create(plan, scenes, fault, conv_err, workspace):
     """scenes: list of dicts with params (clamp_params), mu, resid, r, w, wbar,
-    diag (tensors) and prior_sigma."""
+    diag (tensors), prior_sigma and optional ahy2 (tensor)."""
     arr = (clamp_batch_scene * len(scenes))()
     for i, sc in enumerate(scenes):
         s = plan.scenes[i]
         na = sc["params"].n_agents
-        st = _state(plan, i, sc["mu"], sc["resid"], sc["r"], na)
+        st = _state(plan, i, sc["mu"], sc["resid"], sc["r"], na, None, sc.get("ahy2"))
         arr[i].params = sc["params"]
         arr[i].state = st
         arr[i].w = _ptr(sc["w"], torch.float32, na * s.n, "w").value
         arr[i].wbar = _ptr(sc["wbar"], torch.float32, s.n, "wbar").value
-        arr[i].diag = _ptr(sc["diag"], torch.float64, s.looks * DIAG, "diag").value
+        arr[i].diag = _ptr(sc["diag"], torch.float64, (s.looks + 1) * DIAG, "diag").value
         arr[i].prior_sigma = float(sc.get("prior_sigma", 1.0))
     h = ctypes.c_void_p()
     _check(lib.clamp_batch_create(plan.handle, arr, _ptr(fault, torch.int32, 1, "fault"),

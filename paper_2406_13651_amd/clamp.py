@@ -32,9 +32,13 @@ class ClampGPU:
     """State and loop of one CLAMP reconstruction on the current GPU."""
 
     def __init__(self, nx, ny, nz, looks, radius, sigma_w2, sigma2, with_prior=True, rho=0.5,
-                 mu_scale=1.0, prior_sigma=1.0, mask=None, device="cuda", r_update="quadratic", range_support=0):
+                 mu_scale=1.0, prior_sigma=1.0, mask=None, device="cuda", r_update="quadratic", range_support=0,
+                 refresh_every=0, keep_y=True):
         """range_support = 0: per-slice 2D operator; K >= 1: the 3D operator
-        with the K range frequencies nearest DC (looks are 3D frequency grids)."""
+        with the K range frequencies nearest DC (looks are 3D frequency grids).
+        keep_y keeps D(a) y on the device (the residual refresh needs it);
+        refresh_every = m > 0 rebuilds the residual from it after every m-th
+        iteration."""
         self.scene = C.Scene(nx, ny, nz, looks, radius, mask, range_support)
         self.plan = C.clamp_plan_create([self.scene])
         self.info = self.plan.info[0]
@@ -55,10 +59,14 @@ class ClampGPU:
         self.mu = torch.zeros(looks, nz, ny, nx, dtype=torch.complex64, **f)
         self.resid = torch.zeros(looks, range_support if range_support > 0 else nz, self.info["P"],
                                  dtype=torch.complex64, **f)
+        self.y_pupil = torch.zeros_like(self.resid) if keep_y else None
+        self.refresh_every = int(refresh_every)
+        if self.refresh_every > 0 and not keep_y:
+            raise ValueError("the residual refresh needs keep_y")
         self.r = torch.zeros(self.N, nz, ny, nx, dtype=torch.float32, **f)
         self.w = torch.zeros(self.N, nz, ny, nx, dtype=torch.float32, **f)
         self.wbar = torch.zeros(nz, ny, nx, dtype=torch.float32, **f)
-        self.diag = torch.zeros(looks, C.DIAG, dtype=torch.float64, **f)
+        self.diag = torch.zeros(looks + 1, C.DIAG, dtype=torch.float64, **f)
         self.fault = torch.zeros(1, dtype=torch.int32, **f)
         self.conv = torch.zeros(1, dtype=torch.float64, **f)
         self.ahy2 = torch.zeros(looks, dtype=torch.float64, **f)
@@ -69,13 +77,18 @@ class ClampGPU:
 
     def init(self, y):
         """Alg. 2 initialisation from looks y (complex64 [L, nz, ny, nx], on the GPU)."""
-        C.clamp_fwd_init(self.plan, 0, self.params(), y, self.mu, self.resid, self.r, self.w, self.ahy2, self.ws)
+        C.clamp_fwd_init(self.plan, 0, self.params(), y, self.mu, self.resid, self.r, self.w, self.ws,
+                         y_pupil=self.y_pupil, ahy2=self.ahy2)
         self.fault.zero_()
         self.k = 0
 
     def fwd_agents(self, beta):
         C.clamp_fwd_agent(self.plan, 0, self.params(beta), self.mu, self.resid, self.r, self.w,
-                          self.diag, self.fault, self.ws)
+                          self.diag, self.fault, self.ws, ahy2=self.ahy2)
+
+    def refresh(self):
+        """Residual rebuilt from the data: resid = D(a) y - D(a) F mu."""
+        C.clamp_fwd_refresh(self.plan, 0, self.mu, self.resid, self.y_pupil, self.ws)
 
     def prior(self):
         C.clamp_prior_gauss(self.plan, 0, self.prior_sigma, self.w[self.L], self.r[self.L], self.ws)
@@ -87,6 +100,8 @@ class ClampGPU:
         """One pass of the Alg. 2 loop body; returns nothing (no host sync)."""
         self.k += 1
         self.fwd_agents(beta_schedule(self.k))
+        if self.refresh_every > 0 and self.k % self.refresh_every == 0:
+            self.refresh()
         if self.with_prior:
             self.prior()
         self.mace()
@@ -100,17 +115,15 @@ class ClampGPU:
 
     # -- diagnostics (these synchronise) ---------------------------------
     def h_values(self):
-        """(h before, h after) of each look's mu-step, up to a constant."""
-        d = self.diag.double().cpu()
-        h0 = d[:, 4] / (2 * self.sigma_w2) + d[:, 5] / 2
-        h1 = d[:, 6] / (2 * self.sigma_w2) + d[:, 7] / 2
-        return h0, h1
+        """(h before, h after) of each look's last mu-step as the library
+        reports them (eq. mu-objective less a constant per look)."""
+        d = self.diag.cpu()
+        return d[: self.L, C.DG_H0], d[: self.L, C.DG_H1]
 
     def mu_residual(self):
-        """Noise-floored mu-residual of eq. residual: mean_l ||d_l|| / ||A^H y_l / sigma_w^2||."""
-        d = self.diag.double().cpu()
-        a = self.ahy2.double().cpu()
-        return float(torch.mean(torch.sqrt(d[:, 1]) * self.sigma_w2 / torch.sqrt(a)))
+        """mu-residual of eq. residual (noise-floored form) of the last
+        forward-agent application, as the library reports it."""
+        return float(self.diag[self.L, 0].item())
 
     def conv_err(self):
         return float(self.conv.item())
@@ -149,7 +162,7 @@ class ClampBatchGPU:
                 "r": torch.zeros((N,) + shape, dtype=torch.float32, **f),
                 "w": torch.zeros((N,) + shape, dtype=torch.float32, **f),
                 "wbar": torch.zeros(shape, dtype=torch.float32, **f),
-                "diag": torch.zeros(L, C.DIAG, dtype=torch.float64, **f),
+                "diag": torch.zeros(L + 1, C.DIAG, dtype=torch.float64, **f),
                 "ahy2": torch.zeros(L, dtype=torch.float64, **f),
                 "prior_sigma": float(sc.get("prior_sigma", 1.0)),
             }
@@ -168,8 +181,8 @@ class ClampBatchGPU:
     def init_scene(self, i, y):
         """Alg. 2 initialisation of scene i from its looks (complex64 GPU tensor)."""
         st = self.states[i]
-        C.clamp_fwd_init(self.plan, i, st["params"], y, st["mu"], st["resid"], st["r"], st["w"], st["ahy2"],
-                         self.ws)
+        C.clamp_fwd_init(self.plan, i, st["params"], y, st["mu"], st["resid"], st["r"], st["w"], self.ws,
+                         ahy2=st["ahy2"])
 
     def restart(self):
         """Iteration counter and fault word back to zero (after init_scene calls)."""
@@ -187,7 +200,7 @@ class ClampBatchGPU:
                               beta, self.specs[i].get("mu_scale", 1.0), st["ups"],
                               self.specs[i].get("r_update", "quadratic"))
             C.clamp_fwd_agent(self.plan, i, p, st["mu"], st["resid"], st["r"], st["w"], st["diag"], self.fault,
-                              self.ws)
+                              self.ws, ahy2=st["ahy2"])
             L = self.specs[i]["looks"]
             if st["with_prior"]:
                 C.clamp_prior_gauss(self.plan, i, st["prior_sigma"], st["w"][L], st["r"][L], self.ws)

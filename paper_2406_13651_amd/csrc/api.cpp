@@ -62,7 +62,7 @@ bool size_supported(int n) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t T, T2, dfd, prow, pcf, pci, pupd, pres, pmace, scal, g0, g1;
+    size_t T, T2, dfd, prow, pcf, pci, pupd, pres, pmace, scal, cnt, g0, g1;
     size_t dfdb, pzi, pzf;  // 3D operator: box data [L][K][P], range-pass partial sums
     size_t total;
 };
@@ -236,6 +236,7 @@ void layout_scene(Scene& s) {
     w.pres = take(L * clampk::resid_blocks(s.tab) * sizeof(double));
     w.pmace = take((size_t)clampk::mace_blocks(s.n()) * 2 * sizeof(double));
     w.scal = take(64 * sizeof(double));
+    w.cnt = take(64 * sizeof(unsigned));
     w.g0 = take(s.n() * sizeof(float));
     w.g1 = take(s.n() * sizeof(float));
     if (s.K > 0) {
@@ -306,18 +307,33 @@ hipEvent_t take_event(clamp_plan* p) {
 }
 
 // Runs `launch` (returning hipError_t) with timing events around it when the
-// plan's timing is on.
+// plan's timing is on.  Events go back to the pool unless both were recorded,
+// so a record always refers to two recorded events.
 template <typename F>
 hipError_t timed(const clamp_plan* cplan, int stage, hipStream_t st, F&& launch) {
     clamp_plan* p = const_cast<clamp_plan*>(cplan);
     if (((p->timing >> stage) & 1u) == 0u) return launch();
     TimingRecord rec{stage, take_event(p), take_event(p)};
-    if (rec.start == nullptr || rec.stop == nullptr) return hipErrorOutOfMemory;
+    if (rec.start == nullptr || rec.stop == nullptr) {
+        if (rec.start != nullptr) p->pool.push_back(rec.start);
+        if (rec.stop != nullptr) p->pool.push_back(rec.stop);
+        return hipErrorOutOfMemory;
+    }
     hipError_t e = hipEventRecord(rec.start, st);
-    if (e == hipSuccess) e = launch();
-    if (e == hipSuccess) e = hipEventRecord(rec.stop, st);
-    p->records.push_back(rec);
-    return e;
+    if (e != hipSuccess) {
+        p->pool.push_back(rec.start);
+        p->pool.push_back(rec.stop);
+        return e;
+    }
+    e = launch();
+    const hipError_t es = hipEventRecord(rec.stop, st);
+    if (es == hipSuccess) {
+        p->records.push_back(rec);
+    } else {
+        p->pool.push_back(rec.start);
+        p->pool.push_back(rec.stop);
+    }
+    return e != hipSuccess ? e : es;
 }
 
 ColArgs col_args(const Scene& s, int looks) {
@@ -524,13 +540,12 @@ clamp_status clamp_aperture_op(const clamp_plan* plan, int32_t scene, int32_t di
 }
 
 clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene, const clamp_params* params, const void* y_full,
-                            clamp_fwd_state* state, float* w, double* ahy2, void* workspace, void* hip_stream) {
+                            clamp_fwd_state* state, float* w, void* workspace, void* hip_stream) {
     clamp_status st = check_plan_scene(plan, scene);
     if (st != CLAMP_OK) return st;
     const Scene& s = plan->scenes[scene];
     if ((st = check_params(s, params, false)) != CLAMP_OK) return st;
-    if (y_full == nullptr || state == nullptr || w == nullptr || ahy2 == nullptr)
-        return fail(CLAMP_EINVAL, "NULL argument");
+    if (y_full == nullptr || state == nullptr || w == nullptr) return fail(CLAMP_EINVAL, "NULL argument");
     if (state->mu == nullptr || state->resid == nullptr || state->r == nullptr)
         return fail(CLAMP_EINVAL, "state has a NULL array");
     if ((st = check_ws(workspace)) != CLAMP_OK) return st;
@@ -542,15 +557,18 @@ clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene, const clamp_p
     double* pm = at<double>(workspace, s.ws.pmace);
     double* scal = at<double>(workspace, s.ws.scal);
     float2* mu = static_cast<float2*>(state->mu);
+    float2* ypup = static_cast<float2*>(state->y_pupil);
 
     hipError_t e = hipSuccess;
     if (s.K > 0) {
-        // 3D operator: D(a) y on the cylinder, then A^H y = F2^H F_z^H (zero-filled box)
-        float2* box = at<float2>(workspace, s.ws.dfdb);
+        // 3D operator: D(a) y on the cylinder (kept as y_pupil when given),
+        // then A^H y = F2^H F_z^H (zero-filled box)
+        float2* box = ypup != nullptr ? ypup : at<float2>(workspace, s.ws.dfdb);
         double* pg = at<double>(workspace, s.ws.pzi);
         e = clampk::launch_range_gather(s.tab, L, static_cast<const float2*>(y_full), box,
                                         static_cast<float2*>(state->resid), 1.f - params->mu_init_scale, pg, stream);
-        if (e == hipSuccess) e = clampk::launch_sum(pg, clampk::gather_blocks(s.tab), L, 1.0, ahy2, stream);
+        if (e == hipSuccess && state->ahy2 != nullptr)
+            e = clampk::launch_sum(pg, clampk::gather_blocks(s.tab), L, 1.0, state->ahy2, stream);
         clampk::ZArgs za{s.tab, L, box, at<float2>(workspace, s.ws.dfd), at<double>(workspace, s.ws.pzf)};
         if (e == hipSuccess) e = clampk::launch_zpass(+1, za, stream);
         ColArgs ca = col_args(s, L);
@@ -563,6 +581,7 @@ clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene, const clamp_p
         ca.full_in = static_cast<const float2*>(y_full);
         ca.band_out = T;
         ca.cmp_out = static_cast<float2*>(state->resid);
+        ca.cmp_keep = ypup;
         ca.part = pci;
         ca.init_keep = 1.f - params->mu_init_scale;
         e = clampk::launch_col(clampk::COL_INV_INIT, ca, stream);
@@ -573,11 +592,48 @@ clamp_status clamp_fwd_init(const clamp_plan* plan, int32_t scene, const clamp_p
         ra.img_out = mu;
         e = clampk::launch_row(clampk::ROW_INV, ra, stream);
     }
-    if (e == hipSuccess && s.K == 0) e = clampk::launch_sum(pci, clampk::col_blocks(s.tab), L, 1.0, ahy2, stream);
+    if (e == hipSuccess && s.K == 0 && state->ahy2 != nullptr)
+        e = clampk::launch_sum(pci, clampk::col_blocks(s.tab), L, 1.0, state->ahy2, stream);
     if (e == hipSuccess) e = clampk::launch_init_r0(n, L, mu, params->mu_init_scale, state->r, pm, stream);
     if (e == hipSuccess) e = clampk::launch_sum(pm, clampk::mace_blocks(n), 1, 1.0 / (double)n, scal, stream);
     if (e == hipSuccess) e = clampk::launch_init_floor(n, params->n_agents, scal, state->r, w, stream);
     return hip_check(e, "clamp_fwd_init launch");
+}
+
+clamp_status clamp_fwd_refresh(const clamp_plan* plan, int32_t scene, clamp_fwd_state* state, void* workspace,
+                               void* hip_stream) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    if (state == nullptr || state->mu == nullptr || state->resid == nullptr)
+        return fail(CLAMP_EINVAL, "state or one of its mu/resid arrays is NULL");
+    if (state->y_pupil == nullptr) return fail(CLAMP_EINVAL, "state->y_pupil is NULL: nothing to refresh from");
+    if ((st = check_ws(workspace)) != CLAMP_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int L = s.sc.looks;
+    float2* T2 = at<float2>(workspace, s.ws.T2);
+    float2* dfd = at<float2>(workspace, s.ws.dfd);
+    // D(a) F mu on the pupil (and the range box), then resid = D(a) y - that
+    RowArgs ra = row_args(s, L);
+    ra.img_in = static_cast<const float2*>(state->mu);
+    ra.band_out = T2;
+    hipError_t e = clampk::launch_row(clampk::ROW_FWD, ra, stream);
+    ColArgs ca = col_args(s, L);
+    ca.band_in = T2;
+    ca.cmp_out = dfd;
+    if (e == hipSuccess) e = clampk::launch_col(clampk::COL_FWD_COMPACT, ca, stream);
+    const float2* amu = dfd;
+    if (e == hipSuccess && s.K > 0) {
+        float2* box = at<float2>(workspace, s.ws.dfdb);
+        clampk::ZArgs za{s.tab, L, dfd, box, at<double>(workspace, s.ws.pzf)};
+        e = clampk::launch_zpass(-1, za, stream);
+        amu = box;
+    }
+    const size_t count = (size_t)L * (s.K > 0 ? s.K : s.sc.nz) * s.P;
+    if (e == hipSuccess)
+        e = clampk::launch_csub(count, static_cast<const float2*>(state->y_pupil), amu,
+                                static_cast<float2*>(state->resid), stream);
+    return hip_check(e, "clamp_fwd_refresh launch");
 }
 
 clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_params* params,
@@ -662,9 +718,11 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_
         clampk::ZArgs za{s.tab, L, dfd, dfd_box, pz_fwd};
         e = timed(plan, ST_RANGE_FWD, stream, [&] { return clampk::launch_zpass(-1, za, stream); });
     }
+    unsigned* counter = at<unsigned>(workspace, s.ws.cnt);
     if (e == hipSuccess)
-        e = timed(plan, ST_GAMMA, stream,
-                  [&] { return clampk::launch_gamma(s.tab, L, prow, pz_fwd, pz_inv, 1.0 / s2w, diag, fault, stream); });
+        e = timed(plan, ST_GAMMA, stream, [&] {
+            return clampk::launch_gamma(s.tab, L, prow, pz_fwd, pz_inv, 1.0 / s2w, diag, fault, counter, stream);
+        });
     if (e == hipSuccess) {
         RowArgs u = ra;
         u.band_in = T;
@@ -675,7 +733,9 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_
         e = timed(plan, ST_RESID, stream,
                   [&] { return clampk::launch_resid_update(s.tab, L, resid, dfd_box, diag, pres, stream); });
     if (e == hipSuccess)
-        e = timed(plan, ST_DIAG, stream, [&] { return clampk::launch_diag_after(s.tab, L, pupd, pres, diag, stream); });
+        e = timed(plan, ST_DIAG, stream, [&] {
+            return clampk::launch_diag_after(s.tab, L, pupd, pres, s2w, state->ahy2, diag, counter, stream);
+        });
     return hip_check(e, "clamp_fwd_agent launch");
 }
 
@@ -932,11 +992,11 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         sb.cfwd.cmp_out = at<float2>(w0, s.ws.dfd);
         sb.cfwd.part = at<double>(w0, s.ws.pcf);
         sb.gam = GammaArgs{row_blocks(s.tab), col_blocks(s.tab), at<double>(w0, s.ws.prow), at<double>(w0, s.ws.pcf),
-                           at<double>(w0, s.ws.pci), 1.0 / s2w, bs.diag, fault};
+                           at<double>(w0, s.ws.pci), 1.0 / s2w, bs.diag, fault, at<unsigned>(w0, s.ws.cnt)};
         sb.res = ResidArgs{(size_t)s.sc.nz * s.P, resid_chunks(s.tab), static_cast<float2*>(bs.state.resid),
                            at<float2>(w0, s.ws.dfd), bs.diag, at<double>(w0, s.ws.pres)};
-        sb.dia = DiagArgs{row_blocks(s.tab), resid_chunks(s.tab), at<double>(w0, s.ws.pupd), at<double>(w0, s.ws.pres),
-                          bs.diag};
+        sb.dia = DiagArgs{row_blocks(s.tab), resid_chunks(s.tab), L, at<double>(w0, s.ws.pupd),
+                          at<double>(w0, s.ws.pres), s2w, bs.state.ahy2, bs.diag, at<unsigned>(w0, s.ws.cnt)};
         MaceArgs m{};
         m.n = n;
         m.n_agents = bs.params.n_agents;

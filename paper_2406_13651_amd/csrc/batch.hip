@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void kb_gamma(BatchLaunch b) {
     for (int it = blockIdx.x; it < b.count[Q_LOOK]; it += gridDim.x) {
         const BatchItem w = q[it];
         const GammaArgs g = load_uniform(&b.scenes[w.scene].gam);
-        gamma_item(w.a, g.nrow, g.ncol, g.prow, g.pcf, g.pci, g.inv_s2w, g.diag, g.fault);
+        gamma_item(w.a, g);
     }
 }
 
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void kb_diag(BatchLaunch b) {
     for (int it = blockIdx.x; it < b.count[Q_LOOK]; it += gridDim.x) {
         const BatchItem w = q[it];
         const DiagArgs d = load_uniform(&b.scenes[w.scene].dia);
-        diag_after_item(w.a, d.nrow, d.nres, d.pupd, d.pres, d.diag);
+        diag_after_item(w.a, d);
     }
 }
 

@@ -13,7 +13,11 @@ constexpr int kBlock = 256;      // threads per block for every kernel
 // length 256; 8 for longer columns, which keeps each thread's share of an
 // item at 16 values.
 __host__ __device__ constexpr int col_tile_cols(int ny) { return ny >= 384 ? 8 : 16; }
-constexpr int kDiag = 8;         // doubles of diagnostics per look
+constexpr int kDiag = 8;         // doubles of diagnostics per look (and of the summary row)
+// diag[l][.] of look l: gamma, ||d||^2, ||A d||^2, h before, h after,
+// mu-residual of the look, sum omega |d|^2, ||resid||^2 after; summary row
+// diag[L][.]: mu-residual averaged over looks, sum of h before, sum of h after.
+enum DiagSlot { DG_GAMMA = 0, DG_DD, DG_AD, DG_H0, DG_H1, DG_MURES, DG_WD, DG_R2 };
 
 // Device tables of one scene (owned by the plan).
 struct SceneTables {
@@ -95,6 +99,7 @@ struct ColArgs {
     const float2* band_in;     // band rows [looks][nz][ny][Bs]  (COL_FWD_COMPACT)
     float2* band_out;          // band rows                      (COL_INV_*)
     float2* cmp_out;           // compact out: D(a)F x (FWD), (1 - s) D(a) y (INIT)
+    float2* cmp_keep;          // compact out: D(a) y (INIT, optional)
     double* part;              // [looks][col_blocks] sum of |input or output|^2
     float scale;               // 1/sqrt(ny)
     float init_keep;           // 1 - s_mu (COL_INV_INIT)
@@ -131,12 +136,17 @@ hipError_t launch_scatter_full(const SceneTables& s, int looks, const float2* cm
                                float2* full, hipStream_t st);
 hipError_t launch_gamma(const SceneTables& s, int looks, const double* part_row,
                         const double* part_colfwd, const double* part_colinv,
-                        double inv_s2w, double* diag, uint32_t* fault, hipStream_t st);
+                        double inv_s2w, double* diag, uint32_t* fault, unsigned* counter, hipStream_t st);
 hipError_t launch_resid_update(const SceneTables& s, int looks, float2* resid,
                                const float2* dfd, const double* diag, double* part,
                                hipStream_t st);
+// h after, mu-residual and ||resid||^2 per look, then (last look done) the
+// summary row diag[looks]; ahy2 may be NULL (mu-residuals 0).
 hipError_t launch_diag_after(const SceneTables& s, int looks, const double* part_upd,
-                             const double* part_resid, double* diag, hipStream_t st);
+                             const double* part_resid, double s2w, const double* ahy2, double* diag,
+                             unsigned* counter, hipStream_t st);
+// out[i] = a[i] - b[i] over count complex values
+hipError_t launch_csub(size_t count, const float2* a, const float2* b, float2* out, hipStream_t st);
 hipError_t launch_init_r0(size_t n, int looks, float2* mu, float s_mu, float* r0,
                           double* part, hipStream_t st);
 // out[l] = scale * sum_i part[l * count + i] for l < looks
@@ -180,6 +190,7 @@ struct GammaArgs {
     double inv_s2w;
     double* diag;
     uint32_t* fault;
+    unsigned* counter;   // looks done by the diagnostics pass (zeroed here)
 };
 
 struct ResidArgs {
@@ -192,10 +203,13 @@ struct ResidArgs {
 };
 
 struct DiagArgs {
-    int nrow, nres;
+    int nrow, nres, looks;
     const double* pupd;
     const double* pres;
+    double s2w;
+    const double* ahy2;  // [looks] ||A^H y_l||^2, or NULL
     double* diag;
+    unsigned* counter;
 };
 
 struct PriorArgs {

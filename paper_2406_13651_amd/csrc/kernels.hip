@@ -79,6 +79,7 @@ __device__ __forceinline__ void col_dense_inv(const ColArgs& a, float2* tw, floa
                     val = src[(size_t)y * s.nx + v];
                     if constexpr (MODE == COL_INV_INIT) {
                         a.cmp_out[(size_t)zl * s.P + pi] = cscale(val, a.init_keep);
+                        if (a.cmp_keep != nullptr) a.cmp_keep[(size_t)zl * s.P + pi] = val;
                         f += cabs2(val);
                     }
                 }
@@ -172,11 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_full(SceneTables s, size_t t
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_gamma(int nrow, int ncol, const double* prow,
-                                                  const double* pcf, const double* pci,
-                                                  double inv_s2w, double* diag, uint32_t* fault) {
-    gamma_item(blockIdx.x, nrow, ncol, prow, pcf, pci, inv_s2w, diag, fault);
-}
+__global__ __launch_bounds__(kBlock) void k_gamma(GammaArgs a) { gamma_item(blockIdx.x, a); }
 
 __global__ __launch_bounds__(kBlock) void k_resid(size_t per_look, float2* resid, const float2* dfd,
                                                   const double* diag, double* part) {
@@ -188,9 +185,13 @@ __global__ __launch_bounds__(kBlock) void k_resid(size_t per_look, float2* resid
     block_sum_store<1>(acc, part + (size_t)look * gridDim.x + blockIdx.x);
 }
 
-__global__ __launch_bounds__(kBlock) void k_diag_after(int nrow, int nres, const double* pupd,
-                                                       const double* pres, double* diag) {
-    diag_after_item(blockIdx.x, nrow, nres, pupd, pres, diag);
+__global__ __launch_bounds__(kBlock) void k_diag_after(DiagArgs a) { diag_after_item(blockIdx.x, a); }
+
+__global__ __launch_bounds__(kBlock) void k_csub(size_t count, const float2* a, const float2* b, float2* out) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (size_t)gridDim.x * kBlock) {
+        const float2 x = a[i], y = b[i];
+        out[i] = make_float2(x.x - y.x, x.y - y.y);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_init_r0(size_t n, int looks, float2* mu, float s_mu,
@@ -418,11 +419,11 @@ hipError_t launch_scatter_full(const SceneTables& s, int looks, const float2* cm
 
 hipError_t launch_gamma(const SceneTables& s, int looks, const double* part_row, const double* part_colfwd,
                           const double* part_colinv, double inv_s2w, double* diag, uint32_t* fault,
-                          hipStream_t st) {
+                          unsigned* counter, hipStream_t st) {
     // with the 3D operator the column-side sums come from the range passes
     const int ncol = s.K > 0 ? zpass_blocks(s) : col_blocks(s);
-    hipLaunchKernelGGL(k_gamma, dim3(looks), dim3(kBlock), 0, st, row_blocks(s), ncol, part_row, part_colfwd,
-                       part_colinv, inv_s2w, diag, fault);
+    const GammaArgs a{row_blocks(s), ncol, part_row, part_colfwd, part_colinv, inv_s2w, diag, fault, counter};
+    hipLaunchKernelGGL(k_gamma, dim3(looks), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
@@ -435,9 +436,15 @@ hipError_t launch_resid_update(const SceneTables& s, int looks, float2* resid, c
 }
 
 hipError_t launch_diag_after(const SceneTables& s, int looks, const double* pupd, const double* pres,
-                             double* diag, hipStream_t st) {
-    hipLaunchKernelGGL(k_diag_after, dim3(looks), dim3(kBlock), 0, st, row_blocks(s), resid_blocks(s), pupd,
-                       pres, diag);
+                             double s2w, const double* ahy2, double* diag, unsigned* counter, hipStream_t st) {
+    const DiagArgs a{row_blocks(s), resid_blocks(s), looks, pupd, pres, s2w, ahy2, diag, counter};
+    hipLaunchKernelGGL(k_diag_after, dim3(looks), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_csub(size_t count, const float2* a, const float2* b, float2* out, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_csub, dim3(grid_cap(count, 8192)), dim3(kBlock), 0, st, count, a, b, out);
     return hipGetLastError();
 }
 

@@ -580,27 +580,30 @@ struct ColItemVal {
 };
 
 // ---------------------------------------------------------------------------
-// Exact step size of one look from the partial sums of the three passes.
-__device__ __forceinline__ void gamma_item(int look, int nrow, int ncol, const double* prow, const double* pcf,
-                                           const double* pci, double inv_s2w, double* diag, uint32_t* fault) {
+// Exact step size of one look from the partial sums of the three passes, and
+// h before the mu-step: h = ||resid||^2 / (2 sigma_w^2) + sum omega |mu|^2 / 2,
+// which is eq. mu-objective less the constant ||(1 - a) y||^2 / (2 sigma_w^2)
+// of the samples off the pupil.  Look 0 also zeroes the counter of looks the
+// diagnostics pass has finished.
+__device__ __forceinline__ void gamma_item(int look, const GammaArgs& a) {
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    strided_sums<3>(prow + (size_t)look * nrow * 3, nrow, 3, v);
-    strided_sums<1>(pcf + (size_t)look * ncol, ncol, 1, v + 3);
-    strided_sums<1>(pci + (size_t)look * ncol, ncol, 1, v + 4);
+    strided_sums<3>(a.prow + (size_t)look * a.nrow * 3, a.nrow, 3, v);
+    strided_sums<1>(a.pcf + (size_t)look * a.ncol, a.ncol, 1, v + 3);
+    strided_sums<1>(a.pci + (size_t)look * a.ncol, a.ncol, 1, v + 4);
     __shared__ double tot[5];
     block_sum_store<5>(v, tot);
     if (threadIdx.x == 0) {
         const double dd = tot[0], wd = tot[1], wm = tot[2], ad = tot[3], r2 = tot[4];
-        const double den = ad * inv_s2w + wd;
+        const double den = ad * a.inv_s2w + wd;
         const double g = dd > 0.0 ? dd / den : 0.0;
-        double* o = diag + (size_t)look * kDiag;
-        o[0] = g;
-        o[1] = dd;
-        o[2] = ad;
-        o[3] = wd;
-        o[4] = r2;
-        o[5] = wm;
-        if (!(g >= 0.0) || !isfinite(g)) atomicOr(fault, 4u | 1u);
+        double* o = a.diag + (size_t)look * kDiag;
+        o[DG_GAMMA] = g;
+        o[DG_DD] = dd;
+        o[DG_AD] = ad;
+        o[DG_H0] = 0.5 * (r2 * a.inv_s2w + wm);
+        o[DG_WD] = wd;
+        if (!(g >= 0.0) || !isfinite(g)) atomicOr(a.fault, 4u | 1u);
+        if (look == 0) *a.counter = 0u;
     }
 }
 
@@ -620,16 +623,45 @@ __device__ __forceinline__ float resid_range(float2* R, const float2* D, float g
     return f;
 }
 
-__device__ __forceinline__ void diag_after_item(int look, int nrow, int nres, const double* pupd,
-                                                const double* pres, double* diag) {
+// Diagnostics after the mu-step of one look: h after (the same omega as h
+// before, so h before - h after = gamma ||d||^2 / 2 up to rounding), the
+// look's mu-residual of eq. residual in its noise-floored form, ||d|| /
+// ||A^H y / sigma_w^2|| with d the gradient the step used (0 without
+// ||A^H y||^2), and ||resid||^2.  The block that finishes the last look of the
+// call writes the summary row diag[looks]: the mu-residual averaged over looks
+// (eq. residual), and the sums of h before and after, in look order.
+__device__ __forceinline__ void diag_after_item(int look, const DiagArgs& a) {
     double v[2] = {0.0, 0.0};
-    strided_sums<1>(pupd + (size_t)look * nrow, nrow, 1, v);
-    strided_sums<1>(pres + (size_t)look * nres, nres, 1, v + 1);
+    strided_sums<1>(a.pupd + (size_t)look * a.nrow, a.nrow, 1, v);
+    strided_sums<1>(a.pres + (size_t)look * a.nres, a.nres, 1, v + 1);
     __shared__ double tot[2];
     block_sum_store<2>(v, tot);
     if (threadIdx.x == 0) {
-        diag[(size_t)look * kDiag + 6] = tot[1];
-        diag[(size_t)look * kDiag + 7] = tot[0];
+        double* o = a.diag + (size_t)look * kDiag;
+        o[DG_H1] = 0.5 * (tot[1] / a.s2w + tot[0]);
+        o[DG_R2] = tot[1];
+        double m2 = 0.0;
+        if (a.ahy2 != nullptr) {
+            const double y2 = a.ahy2[look];
+            m2 = y2 > 0.0 ? a.s2w * sqrt(o[DG_DD] / y2) : 0.0;
+        }
+        o[DG_MURES] = m2;
+        __threadfence();  // this look's row is visible before it is counted
+        if (atomicAdd(a.counter, 1u) == (unsigned)(a.looks - 1)) {
+            __threadfence();
+            const volatile double* d = a.diag;
+            double m = 0.0, h0 = 0.0, h1 = 0.0;
+            for (int l = 0; l < a.looks; ++l) {
+                m += d[(size_t)l * kDiag + DG_MURES];
+                h0 += d[(size_t)l * kDiag + DG_H0];
+                h1 += d[(size_t)l * kDiag + DG_H1];
+            }
+            double* srow = a.diag + (size_t)a.looks * kDiag;
+            srow[0] = m / a.looks;
+            srow[1] = h0;
+            srow[2] = h1;
+            for (int k = 3; k < kDiag; ++k) srow[k] = 0.0;
+        }
     }
 }
 

@@ -68,10 +68,12 @@ def test_one_agent_application_matches_oracle(G, spec, r_update):
     y64 = y.astype(np.complex128)
     mu64 = mu.astype(np.complex128)
     resid = compact(y64 - oracle.apply_A(mu64, mask), idx).astype(np.complex64)
+    ahy2 = np.array([np.sum(np.abs(mask * y64[l]) ** 2) for l in range(spec.looks)])
     g.mu.copy_(to_gpu(mu))
     g.resid.copy_(to_gpu(resid))
     g.r[: spec.looks].copy_(to_gpu(rp))
     g.w[: spec.looks].copy_(to_gpu(w))
+    g.ahy2.copy_(to_gpu(ahy2))
     g.fwd_agents(beta)
     torch.cuda.synchronize()
     assert int(g.fault.item()) == 0
@@ -79,6 +81,7 @@ def test_one_agent_application_matches_oracle(G, spec, r_update):
     resid_g, diag = g.resid.cpu().numpy(), g.diag.cpu().numpy()
     alpha = oracle.aperture_fraction(mask)
     s2w32 = f32(s2w)
+    dds = []
     for l in range(spec.looks):
         m1, r1, info = oracle.forward_agent(mu64[l], y64[l], rp[l].astype(np.float64), w[l].astype(np.float64),
                                             mask, s2w32, sigma2, alpha, beta, r_update)
@@ -87,12 +90,26 @@ def test_one_agent_application_matches_oracle(G, spec, r_update):
         assert report("agent r " + tag, rel_l2(r_g[l], r1), TOL_OP) <= TOL_OP
         res1 = compact(y64[l] - oracle.apply_A(m1, mask), idx)
         assert report("agent resid " + tag, rel_l2(resid_g[l], res1), TOL_OP) <= TOL_OP
-        for k, key in ((0, "gamma"), (1, "dd"), (2, "ad"), (3, "wd")):
+        for k, key in ((G.DG_GAMMA, "gamma"), (G.DG_DD, "dd"), (G.DG_AD, "ad"), (G.DG_WD, "wd")):
             assert abs(diag[l, k] - info[key]) <= TOL_OP * abs(info[key]), (key, diag[l, k], info[key])
+        # the library's h leaves out the constant of the data off the pupil
+        const = np.sum(np.abs((~mask) * y64[l]) ** 2) / (2 * s2w32)
+        for k, key in ((G.DG_H0, "h0"), (G.DG_H1, "h1")):
+            want = info[key] - const
+            assert abs(diag[l, k] - want) <= TOL_OP * abs(want), (key, diag[l, k], want)
+        want = oracle.mu_residual([info["dd"]], [ahy2[l]], s2w32)
+        assert abs(diag[l, G.DG_MURES] - want) <= TOL_OP * want
+        np.testing.assert_allclose(diag[l, G.DG_R2], np.sum(np.abs(res1) ** 2), rtol=TOL_OP)
+        dds.append(info["dd"])
+    want = oracle.mu_residual(dds, ahy2, s2w32)
+    assert abs(g.mu_residual() - want) <= TOL_OP * want
+    np.testing.assert_allclose(diag[spec.looks, 1:3], diag[: spec.looks, [G.DG_H0, G.DG_H1]].sum(axis=0),
+                               rtol=1e-12)
     h0, h1 = g.h_values()
     h0, h1 = h0.numpy(), h1.numpy()
     assert np.all(h1 <= h0)
-    assert np.allclose(h0 - h1, 0.5 * diag[:, 0] * diag[:, 1], rtol=0, atol=1e-5 * np.max(h0))
+    assert np.allclose(h0 - h1, 0.5 * diag[: spec.looks, 0] * diag[: spec.looks, 1], rtol=0,
+                       atol=1e-5 * np.max(h0))
 
 
 def test_init_matches_oracle(G):
@@ -114,6 +131,8 @@ def test_init_matches_oracle(G):
         res = compact(y.astype(np.complex128) - oracle.apply_A(st.mu, mask), idx)
         got = g.resid.cpu().numpy()
         assert np.linalg.norm(got - res) <= TOL_OP * np.linalg.norm(compact(y.astype(np.complex128), idx))
+        # D(a) y kept for the residual refresh
+        assert np.array_equal(g.y_pupil.cpu().numpy(), compact(y, idx))
 
 
 def test_prior_and_mann_step_match_oracle(G):

@@ -1,6 +1,6 @@
 """Batched steps over uneven scenes (persistent launches over work queues,
-graph replay, autotuned grids) against per-scene single-scene steps, which
-the other GPU tests tie to the float64 oracle."""
+graph replay, autotuned grids) against per-scene single-scene steps and,
+scene by scene, against the float64 oracle."""
 
 import numpy as np
 import pytest
@@ -18,6 +18,8 @@ SPECS = [
     (128, 128, 6, 5, 32.0, True),
     (32, 32, 16, 4, 8.0, True),
     (256, 256, 2, 2, 64.0, True),
+    (384, 384, 2, 2, 96.0, True),    # 8-column tiles, radix 3
+    (512, 512, 2, 2, 128.0, False),  # 8-column tiles, the longest rows
 ]
 
 
@@ -71,17 +73,31 @@ def test_batch_steps_match_single_scene_runs(G):
         assert abs(b.conv[i].item() - g.conv_err()) <= 1e-9 * max(1.0, g.conv_err())
 
 
-def test_batch_first_scene_matches_oracle(G):
+def test_graph_replayed_batch_matches_oracle_on_every_scene(G):
+    """Every scene of the batch (every supported size class from 32 to 512,
+    with and without a prior) after 5 graph-replayed batched iterations,
+    against the float64 oracle's run of the same scene."""
     import torch
-    probs = _problems()[:1]
+    probs = _problems()
     b = _batch(G, probs)
-    for _ in range(5):
-        b.step()
+    stream = torch.cuda.Stream()
     torch.cuda.synchronize()
-    sp, y, s2, wp = probs[0]
-    st, hist = oracle.clamp_run(y, sp.radius, float(np.float32(s2)), float(np.float32(1e-3)), 5, with_prior=wp)
-    err = rel_l2(b.states[0]["wbar"].cpu().numpy(), hist[-1]["wbar"])
-    assert report("batch scene 0 vs oracle, 5 it", err, 1e-4) <= 1e-4
+    b.capture(stream)
+    b.replay(5, stream)
+    stream.synchronize()
+    assert int(b.fault.item()) == 0
+    for i, (sp, y, s2, wp) in enumerate(probs):
+        st, hist = oracle.clamp_run(y, sp.radius, float(np.float32(s2)), float(np.float32(1e-3)), 5, with_prior=wp)
+        tag = "batch scene %d %dx%dx%d L=%d prior=%d vs oracle, 5 graph replays" % (i, sp.nx, sp.ny, sp.nz,
+                                                                                   sp.looks, wp)
+        bs = b.states[i]
+        assert report(tag + " wbar", rel_l2(bs["wbar"].cpu().numpy(), hist[-1]["wbar"]), 1e-4) <= 1e-4
+        assert report(tag + " w", rel_l2(bs["w"].cpu().numpy(), st.w), 1e-4) <= 1e-4
+        assert report(tag + " mu", rel_l2(bs["mu"].cpu().numpy(), st.mu), 1e-4) <= 1e-4
+        ce = hist[-1]["conv_err"]
+        assert abs(b.conv[i].item() - ce) <= 1e-4 * ce
+        m2 = hist[-1]["mu_residual"]
+        assert abs(bs["diag"][sp.looks, 0].item() - m2) <= 1e-4 * m2
 
 
 def test_graph_replays_match_eager_steps(G):

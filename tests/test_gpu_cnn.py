@@ -135,18 +135,19 @@ def test_adam_steps_reduce_loss(C):
     assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 * losses[0]
 
 
-def test_adam_gradient_clipping_matches_model(C):
-    """Adam steps with gradient-norm clipping against a float64 model of the
-    documented rule, fed with the gradients the library computes: five
-    ordinary steps, one with the target scaled by 100 (its gradient norm far
-    above 3 times the running norm: clipped), two more."""
+def test_adam_gradient_clipping_matches_oracle(C):
+    """Adam steps with gradient-norm clipping against the oracle's clipped
+    rule (oracle.cnn.adam_step_clipped), fed with the gradients the library
+    computes: five ordinary steps, one with the target scaled by 100 (its
+    gradient norm far above 3 times the running norm: clipped), two more."""
+    from oracle import cnn as ocnn
     net, params, x, t, torch = _setup(C, seed=5, shape=(2, 4, 8, 32))
     xt = torch.from_numpy(x).cuda()
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     ws = torch.empty(C.clamp_cnn_workspace_size(*x.shape, True), dtype=torch.uint8, device="cuda")
     g = torch.empty(C.CNN_PARAMS, dtype=torch.float32, device="cuda")
-    p = C.clamp_cnn_get_params(net).astype(np.float64)
-    m, v, run, lr = np.zeros_like(p), np.zeros_like(p), 0.0, 1e-3
+    p = [(C.clamp_cnn_get_params(net).astype(np.float64), np.zeros(0))]
+    state, lr = {}, 1e-3
     clipped = []
     for k, sc in enumerate([1, 1, 1, 1, 1, 100, 1, 1], start=1):
         tt = torch.from_numpy((t * sc).astype(np.float32)).cuda()
@@ -154,19 +155,10 @@ def test_adam_gradient_clipping_matches_model(C):
         gk = g.cpu().numpy().astype(np.float64)
         C.clamp_cnn_grad(net, xt, tt, loss, ws)  # kept for the step
         C.clamp_cnn_adam_step(net, lr)
-        norm = np.sqrt(np.sum(gk * gk))
-        if run == 0.0:
-            c, run = 1.0, norm
-        else:
-            cap = 3.0 * run
-            c = min(1.0, cap / norm)
-            run = 0.95 * run + 0.05 * min(norm, cap)
-        clipped.append(c < 1.0)
-        ge = c * gk
-        m = 0.9 * m + 0.1 * ge
-        v = 0.999 * v + 0.001 * ge * ge
-        p = p - lr * (m / (1 - 0.9 ** k)) / (np.sqrt(v / (1 - 0.999 ** k)) + 1e-8)
-        np.testing.assert_allclose(C.clamp_cnn_get_params(net), p, rtol=1e-5, atol=1e-7)
+        run_before = state.get("run_norm", 0.0)
+        p = ocnn.adam_step_clipped(p, [(gk, np.zeros(0))], state, lr)
+        clipped.append(run_before > 0.0 and np.linalg.norm(gk) > 3.0 * run_before)
+        np.testing.assert_allclose(C.clamp_cnn_get_params(net), p[0][0], rtol=1e-5, atol=1e-7)
     print("clipped steps", clipped)
     assert clipped[5]
 

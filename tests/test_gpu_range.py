@@ -34,6 +34,8 @@ CASES = [
     (64, 32, 48, 32, 10.0, 2),    # q = 1.5: range length 48 (radix 3)
     (32, 64, 32, 32, 12.0, 1),    # full range box
     (32, 32, 64, 21, 9.0, 2),     # odd box
+    (32, 32, 96, 64, 8.0, 2),     # q = 1.5 with the benchmark's 64-frequency box (range length 96)
+    (32, 32, 128, 64, 8.0, 2),    # q = 2 with the benchmark's box (range length 128)
 ]
 
 
@@ -73,10 +75,11 @@ def _compact_box(y, mask3, idx, K):
     return flat[..., idx]
 
 
-def test_3d_agent_application_matches_oracle(G):
+@pytest.mark.parametrize("nz,K,L", [(16, 8, 3), (96, 64, 2), (128, 64, 2)])
+def test_3d_agent_application_matches_oracle(G, nz, K, L):
     import torch
     nx = ny = 32
-    nz, K, L, radius = 16, 8, 3, 8.0
+    radius = 8.0
     spec = synth.SceneSpec("r3", nx, ny, nz, L, radius, 20.0, 6, 0.1, 1, 7)
     r_true, y, s2w = synth.make_problem(spec, 0, range_support=K)
     mask = oracle.cylinder_mask(nz, ny, nx, radius, K)
@@ -104,17 +107,21 @@ def test_3d_agent_application_matches_oracle(G):
     for l in range(L):
         m1, r1, info = oracle.forward_agent(mu[l].astype(np.complex128), y64[l], rp[l].astype(np.float64),
                                             w[l].astype(np.float64), mask, f32(s2w), sigma2, alpha, beta)
-        assert report("3D agent mu look %d" % l, rel_l2(g.mu[l].cpu().numpy(), m1), TOL_OP) <= TOL_OP
-        assert report("3D agent r look %d" % l, rel_l2(g.r[l].cpu().numpy(), r1), TOL_OP) <= TOL_OP
+        assert report("3D agent mu nz=%d look %d" % (nz, l), rel_l2(g.mu[l].cpu().numpy(), m1), TOL_OP) <= TOL_OP
+        assert report("3D agent r nz=%d look %d" % (nz, l), rel_l2(g.r[l].cpu().numpy(), r1), TOL_OP) <= TOL_OP
         res1 = _compact_box((y64[l] - oracle.apply_A(m1, mask))[None], mask, idx, K)[0]
-        assert report("3D agent resid look %d" % l, rel_l2(g.resid[l].cpu().numpy(), res1), TOL_OP) <= TOL_OP
-        for k, key in ((0, "gamma"), (1, "dd"), (2, "ad"), (3, "wd")):
+        assert report("3D agent resid nz=%d look %d" % (nz, l), rel_l2(g.resid[l].cpu().numpy(), res1), TOL_OP) <= TOL_OP
+        for k, key in ((G.DG_GAMMA, "gamma"), (G.DG_DD, "dd"), (G.DG_AD, "ad"), (G.DG_WD, "wd")):
             assert abs(diag[l, k] - info[key]) <= TOL_OP * abs(info[key]), (key, diag[l, k], info[key])
+        const = np.sum(np.abs((~mask) * y64[l]) ** 2) / (2 * f32(s2w))
+        for k, key in ((G.DG_H0, "h0"), (G.DG_H1, "h1")):
+            want = info[key] - const
+            assert abs(diag[l, k] - want) <= TOL_OP * abs(want), (key, diag[l, k], want)
     h0, h1 = g.h_values()
     assert bool(torch.all(h1 <= h0))
 
 
-@pytest.mark.parametrize("nz,K,with_prior", [(16, 8, False), (48, 32, True)])
+@pytest.mark.parametrize("nz,K,with_prior", [(16, 8, False), (48, 32, True), (96, 64, True), (128, 64, True)])
 def test_3d_clamp_run_matches_oracle(G, nz, K, with_prior):
     import torch
     nx = ny = 32

@@ -190,7 +190,7 @@ def _grad_groups(v):
     return out
 
 
-@pytest.mark.parametrize("shape", [(2, 8, 8, 128)])
+@pytest.mark.parametrize("shape", [(2, 8, 8, 128), (1, 16, 16, 128)])
 def test_training_gradients_and_running_statistics(C, shape):
     """Training mode (batch statistics) against the oracle's backward pass
     with the same bf16 roundings: the loss, every parameter group's gradient,
@@ -224,14 +224,22 @@ def test_training_gradients_and_running_statistics(C, shape):
     # backward (dy - mean(dy) - xhat mean(dy xhat) cancels), moves the rounded
     # oracle's gradients from the unrounded ones by 1e-3 (output layer) to
     # ~0.3 (first encoder block); the kernels round at the same points from
-    # fp32 sums.  Per parameter group, the GPU must be no farther from the
-    # unrounded oracle than 1.5 times the rounded oracle is, plus 1e-3.
-    worst = 0.0
+    # fp32 sums, so a few values land on the neighbouring bf16 value and the
+    # GPU and the rounded oracle differ by up to ~0.2 in the early groups
+    # (0.195 worst over both shapes when the bound was set).  Two checks per
+    # parameter group: against the rounded oracle, a fixed bound of 0.25 (a
+    # wrong sign or a dropped term gives O(1)); against the unrounded oracle,
+    # no farther than 1.5 times the rounded oracle is, plus 1e-3.
+    worst, worst_rnd = 0.0, 0.0
     for k in got:
         budget = rel_l2(rnd[k], unr[k])
         err = rel_l2(got[k], unr[k])
-        print("grad %-8s vs unrounded %.3e budget %.3e vs rounded %.3e" % (k, err, budget, rel_l2(got[k], rnd[k])))
+        err_rnd = rel_l2(got[k], rnd[k])
+        print("UNETGRAD %s %-8s vs unrounded %.3e budget %.3e vs rounded %.3e"
+              % ("x".join(map(str, shape)), k, err, budget, err_rnd), flush=True)
         worst = max(worst, err / (1.5 * budget + 1e-3))
+        worst_rnd = max(worst_rnd, err_rnd)
+    assert report("unet training gradients vs rounded oracle (worst group)", worst_rnd, 0.25) <= 0.25
     assert report("unet training gradients (worst group / its bound)", worst, 1.0) <= 1.0
     # running statistics: momentum 0.1 from (0, 1) towards the batch statistics
     stats = U.init_stats()
