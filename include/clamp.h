@@ -244,6 +244,19 @@ clamp_status clamp_mace_step(const clamp_plan* plan, int32_t scene,
                              float* wbar, double* conv_err,
                              void* workspace, void* hip_stream);
 
+/* clamp_mace_step for callers that cannot allocate or pass a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same Mann step, with its reduction scratch in a 1 MiB
+ * array the library holds in device memory on each GPU it runs on (resolved
+ * on the first call on a device, kept until the process ends).  Volumes of
+ * at most 2^25 voxels (e.g. 512 x 512 x 128); larger ones return
+ * CLAMP_ESHAPE.  The plan's device must be current (CLAMP_EDEVICE
+ * otherwise).  Allocates nothing.  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap in time on one GPU (different streams) race. */
+clamp_status clamp_mace_step_noalloc(const clamp_plan* plan, int32_t scene,
+                                     const clamp_params* params, float* w, const float* r,
+                                     float* wbar, double* conv_err, void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Batches: every scene of a plan advanced together, one CLAMP iteration per
  * clamp_batch_step.  Each stage runs as persistent launches over device work

@@ -96,6 +96,7 @@ def _load():
                             P, P, P, P, P],
         "clamp_prior_gauss": [P, i32, ctypes.c_float, P, P, P, P],
         "clamp_mace_step": [P, i32, ctypes.POINTER(clamp_params), P, P, P, P, P, P],
+        "clamp_mace_step_noalloc": [P, i32, ctypes.POINTER(clamp_params), P, P, P, P, P],
         "clamp_plan_set_timing": [P, i32],
         "clamp_plan_set_timing_stages": [P, ctypes.c_uint32],
         "clamp_batch_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
@@ -325,6 +326,16 @@ def clamp_mace_step(plan, scene, params, w, r, wbar, conv_err, workspace, stream
                                _ptr(conv_err, torch.float64, 1, "conv_err"),
                                _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
                                _stream(stream)))
+
+
+def clamp_mace_step_noalloc(plan, scene, params, w, r, wbar, conv_err, stream=None):
+    """clamp_mace_step without a workspace (the library's own 1 MiB scratch)."""
+    s = plan.scenes[scene]
+    na = params.n_agents
+    _check(lib.clamp_mace_step_noalloc(plan.handle, scene, ctypes.byref(params),
+                                       _ptr(w, torch.float32, na * s.n, "w"), _ptr(r, torch.float32, na * s.n, "r"),
+                                       _ptr(wbar, torch.float32, s.n, "wbar"),
+                                       _ptr(conv_err, torch.float64, 1, "conv_err"), _stream(stream)))
 
 
 def clamp_plan_set_timing(plan, enable):

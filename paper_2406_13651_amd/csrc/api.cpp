@@ -792,6 +792,44 @@ clamp_status clamp_mace_step(const clamp_plan* plan, int32_t scene, const clamp_
     return hip_check(e, "clamp_mace_step launch");
 }
 
+clamp_status clamp_mace_step_noalloc(const clamp_plan* plan, int32_t scene, const clamp_params* params, float* w,
+                                     const float* r, float* wbar, double* conv_err, void* hip_stream) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    if ((st = check_params(s, params, false)) != CLAMP_OK) return st;
+    if (w == nullptr || r == nullptr || wbar == nullptr || conv_err == nullptr)
+        return fail(CLAMP_EINVAL, "NULL argument");
+    const size_t n = s.n();
+    if (n % 2 != 0) return fail(CLAMP_ESHAPE, "the Mann step needs an even voxel count");
+    const int blocks = clampk::mace_blocks(n);
+    if ((size_t)blocks * 2 > clampk::kMaceScratchDoubles)
+        return fail(CLAMP_ESHAPE,
+                    "volume of %zu voxels needs %zu bytes of scratch; clamp_mace_step_noalloc holds %zu "
+                    "(volumes up to 2^25 voxels); use clamp_mace_step with a workspace",
+                    n, (size_t)blocks * 2 * sizeof(double), clampk::kMaceScratchDoubles * sizeof(double));
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(e, "hipGetDevice");
+    if (dev != plan->device)
+        return fail(CLAMP_EDEVICE, "current device %d is not the plan's device %d", dev, plan->device);
+    double* part = nullptr;
+    if ((e = clampk::mace_scratch(dev, &part)) != hipSuccess) return hip_check(e, "hipGetSymbolAddress(scratch)");
+    clampk::MaceArgs a{};
+    a.n = n;
+    a.n_agents = params->n_agents;
+    for (int j = 0; j < params->n_agents; ++j) a.ups[j] = params->upsilon[j];
+    a.two_rho = 2.f * params->rho;
+    a.w = w;
+    a.r = r;
+    a.wbar = wbar;
+    a.part = part;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    e = clampk::launch_mace(a, stream);
+    if (e == hipSuccess) e = clampk::launch_mace_final(part, blocks, conv_err, stream);
+    return hip_check(e, "clamp_mace_step_noalloc launch");
+}
+
 clamp_status clamp_plan_set_timing(clamp_plan* plan, int32_t enable) {
     if (plan == nullptr) return fail(CLAMP_EINVAL, "plan is NULL");
     plan->timing = enable != 0 ? (1u << CLAMP_STAGES) - 1u : 0u;

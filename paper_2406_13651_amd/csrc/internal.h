@@ -167,6 +167,11 @@ struct MaceArgs {
 };
 hipError_t launch_mace(const MaceArgs& a, hipStream_t st);
 hipError_t launch_mace_final(const double* part, int blocks, double* conv_err, hipStream_t st);
+// Device address, on `device` (which must be current), of the static scratch
+// of clamp_mace_step_noalloc: kMaceScratchDoubles doubles (1 MiB), enough for
+// the partial sums of mace_blocks(n) blocks up to n = 2^25 voxels.
+constexpr size_t kMaceScratchDoubles = 131072;
+hipError_t mace_scratch(int device, double** out);
 
 hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float* in,
                         float* tmp0, float* tmp1, float* out, hipStream_t st);

@@ -16,6 +16,8 @@
 // d (16 bytes per voxel-look); T is only half a slice wide at R = N/4.
 #include <math.h>
 
+#include <mutex>
+
 #include "passes.hpp"
 
 namespace clampk {
@@ -485,6 +487,29 @@ hipError_t launch_mace(const MaceArgs& a, hipStream_t st) {
 hipError_t launch_mace_final(const double* part, int blocks, double* conv_err, hipStream_t st) {
     hipLaunchKernelGGL(k_mace_final, dim3(1), dim3(kBlock), 0, st, part, blocks, conv_err);
     return hipGetLastError();
+}
+
+// Scratch of the Mann step's entry point that allocates nothing: the block
+// partial sums of the convergence error, two doubles per block, in a
+// file-scope device array that every device holding the library keeps until
+// the process ends.  Host code never passes the array's name to a kernel:
+// its device address is resolved once per device with hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[kMaceScratchDoubles];
+
+hipError_t mace_scratch(int device, double** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex lock;
+    static double* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(lock);
+    if (addr[device] == nullptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<double*>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float* in, float* tmp0,
