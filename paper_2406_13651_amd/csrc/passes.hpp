@@ -636,6 +636,7 @@ __device__ __forceinline__ void diag_after_item(int look, const DiagArgs& a) {
     strided_sums<1>(a.pres + (size_t)look * a.nres, a.nres, 1, v + 1);
     __shared__ double tot[2];
     block_sum_store<2>(v, tot);
+    __shared__ int last;
     if (threadIdx.x == 0) {
         double* o = a.diag + (size_t)look * kDiag;
         o[DG_H1] = 0.5 * (tot[1] / a.s2w + tot[0]);
@@ -647,19 +648,43 @@ __device__ __forceinline__ void diag_after_item(int look, const DiagArgs& a) {
         }
         o[DG_MURES] = m2;
         __threadfence();  // this look's row is visible before it is counted
-        if (atomicAdd(a.counter, 1u) == (unsigned)(a.looks - 1)) {
-            __threadfence();
-            const volatile double* d = a.diag;
-            double m = 0.0, h0 = 0.0, h1 = 0.0;
-            for (int l = 0; l < a.looks; ++l) {
-                m += d[(size_t)l * kDiag + DG_MURES];
-                h0 += d[(size_t)l * kDiag + DG_H0];
-                h1 += d[(size_t)l * kDiag + DG_H1];
+        last = atomicAdd(a.counter, 1u) == (unsigned)(a.looks - 1);
+    }
+    __syncthreads();
+    if (last) {
+        // every look's row is written: one thread per look reads its row, and
+        // thread 0 sums them in look order
+        __shared__ double rows[3][kBlock];
+        __threadfence();
+        const volatile double* d = a.diag;
+        for (int l0 = 0; l0 < a.looks; l0 += kBlock) {
+            const int l = l0 + (int)threadIdx.x;
+            if (l < a.looks) {
+                rows[0][threadIdx.x] = d[(size_t)l * kDiag + DG_MURES];
+                rows[1][threadIdx.x] = d[(size_t)l * kDiag + DG_H0];
+                rows[2][threadIdx.x] = d[(size_t)l * kDiag + DG_H1];
             }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double m = l0 == 0 ? 0.0 : a.diag[(size_t)a.looks * kDiag + 0];
+                double h0 = l0 == 0 ? 0.0 : a.diag[(size_t)a.looks * kDiag + 1];
+                double h1 = l0 == 0 ? 0.0 : a.diag[(size_t)a.looks * kDiag + 2];
+                const int cnt = a.looks - l0 < kBlock ? a.looks - l0 : kBlock;
+                for (int i = 0; i < cnt; ++i) {
+                    m += rows[0][i];
+                    h0 += rows[1][i];
+                    h1 += rows[2][i];
+                }
+                double* srow = a.diag + (size_t)a.looks * kDiag;
+                srow[0] = m;
+                srow[1] = h0;
+                srow[2] = h1;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
             double* srow = a.diag + (size_t)a.looks * kDiag;
-            srow[0] = m / a.looks;
-            srow[1] = h0;
-            srow[2] = h1;
+            srow[0] /= a.looks;
             for (int k = 3; k < kDiag; ++k) srow[k] = 0.0;
         }
     }
