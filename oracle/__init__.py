@@ -37,4 +37,7 @@ from .mace import (  # noqa: F401
     agent_weights, weighted_average, mann_step, convergence_error, mu_residual,
 )
 from .clamp import ClampState, clamp_init, clamp_iteration, clamp_run  # noqa: F401
-from .metrics import scale_fit, nrmse, psnr  # noqa: F401
+from .metrics import scale_fit, nrmse, psnr, point_cloud, point_cloud_metrics  # noqa: F401
+from .regularizers import (  # noqa: F401
+    l21_prox, l21_norm, grad3, div3, tv_norm, tv_prox, tv_dual_gap, speckle_average,
+)
