@@ -9,7 +9,8 @@
  *   - the initialisation of Alg. 2 (clamp_fwd_init);
  *   - one application of every forward agent: covariance diagonal, one exact
  *     steepest-descent step on mu_l, quadratic-surrogate r-update of App. A
- *     (clamp_fwd_agent);
+ *     (clamp_fwd_agent; with the Mann step fused in, clamp_fwd_agent_mace),
+ *     and the residual refresh from the data (clamp_fwd_refresh);
  *   - a fixed Gaussian smoothing prior agent (clamp_prior_gauss);
  *   - the Mann consensus step of Alg. 1 with the convergence error
  *     (clamp_mace_step).
@@ -216,6 +217,35 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene,
                              const float* w, double* diag, uint32_t* fault,
                              void* workspace, void* hip_stream);
 
+/* One application of every forward agent with the Mann step of Alg. 1 fused
+ * into its last pass: the forward agents as clamp_fwd_agent, then (Alg. 1)
+ * x = 2 r - w, x_bar = sum_j upsilon_j x_j, w <- w + 2 rho (x_bar - r) over
+ * all n_agents agents, w_bar = sum_j upsilon_j w_j of the updated w, and
+ * conv_err (device double [1]) = ||r - G(w)|| / ||G(w)|| with G built from
+ * the w passed in (eq. mace-convergence-error).
+ * The prior agent reads only its own w, so Alg. 2's order (forward agents,
+ * prior, Mann step) is kept when the caller applies the prior before this
+ * call: with n_agents = L + 1, state->r slice L must already hold H(w[L]).
+ * Representation of the Mann state, which lets the pass read each look once:
+ *   w     float32 [n_agents][n]: slice l < L holds u_l = w_l - 2 rho x_bar,
+ *         slice L (with a prior) holds the prior agent's w_{L+1} itself;
+ *   xbar  float32 [n]: x_bar of the previous call (zeros after
+ *         clamp_fwd_init, which makes u_l = w_l); the call replaces it.
+ * The Mann state of look l is u_l + 2 rho x_bar.  wbar: float32 [n] out.
+ * diag and fault as clamp_fwd_agent; w is read and written. */
+clamp_status clamp_fwd_agent_mace(const clamp_plan* plan, int32_t scene,
+                                  const clamp_params* params, clamp_fwd_state* state,
+                                  float* w, float* xbar, float* wbar, double* diag,
+                                  double* conv_err, uint32_t* fault,
+                                  void* workspace, void* hip_stream);
+
+/* The Mann state of clamp_fwd_agent_mace's representation, written out:
+ * out[l] = w[l] + 2 rho xbar for the looks l < L, out[L] = w[L] (the prior
+ * agent's, when n_agents = L + 1).  w, out: float32 [n_agents][n], not
+ * overlapping; xbar: float32 [n]. */
+clamp_status clamp_mace_state(const clamp_plan* plan, int32_t scene, const clamp_params* params,
+                              const float* w, const float* xbar, float* out, void* hip_stream);
+
 /* Residual refresh: resid_l = y_pupil_l - D(a) F mu_l, recomputed from the
  * data (Alg. 2 defines the residual by mu; the agent updates it by the
  * recurrence resid -= gamma D(a) F d, whose float32 rounding accumulates over
@@ -233,6 +263,28 @@ clamp_status clamp_fwd_refresh(const clamp_plan* plan, int32_t scene, clamp_fwd_
 clamp_status clamp_prior_gauss(const clamp_plan* plan, int32_t scene, float sigma_vox,
                                const float* in, float* out,
                                void* workspace, void* hip_stream);
+
+/* Comparison regularizers of Sec. V as prior agents (the prior slot of
+ * Alg. 2), each the proximal map of its regularizer on the image in (float32
+ * [n]) into out (float32 [n], not overlapping in).  The paper names them
+ * without formulas or weights; this library reads them as follows.
+ *
+ * l_{2,1} (l2 in cross-range, l1 in range): R(r) = sum_z ||r[z, :, :]||_2
+ * over the range slices; out = argmin_r tau R(r) + ||r - in||^2 / 2, which
+ * scales each slice by max(0, 1 - tau / ||in_z||_2).  tau >= 0 (the weight
+ * times the proximal parameter). */
+clamp_status clamp_prior_l21(const clamp_plan* plan, int32_t scene, float tau,
+                             const float* in, float* out, void* workspace, void* hip_stream);
+
+/* Isotropic total variation: TV(r) = sum_voxels |grad r| with forward
+ * differences along z, y, x (a difference leaving the volume is zero);
+ * out approximates argmin_r lam TV(r) + ||r - in||^2 / 2 by `iters` steps of
+ * Chambolle's dual projection iteration from p = 0 (step 1/12):
+ * p <- (p + g / 12) / (1 + |g| / 12) with g = grad(div p - in / lam), then
+ * out = in - lam div p (div the negative adjoint of grad).  lam > 0,
+ * 0 <= iters <= 100000. */
+clamp_status clamp_prior_tv(const clamp_plan* plan, int32_t scene, float lam, int32_t iters,
+                            const float* in, float* out, void* workspace, void* hip_stream);
 
 /* Mann step of Alg. 1 over n_agents stacked images (float32 [n_agents][n]):
  *   x = 2 r - w;  w <- w + 2 rho (sum_j upsilon_j x_j - r);
@@ -447,7 +499,7 @@ clamp_status clamp_unet_adam_step(clamp_unet* unet, float lr, void* hip_stream);
  * (HOST arrays of CLAMP_STAGES entries, see clamp_stage_name) and forgets
  * the records.  Enabling timing makes the plan unsafe to share between
  * threads.  Creating events can fail with CLAMP_EDEVICE. */
-#define CLAMP_STAGES 14
+#define CLAMP_STAGES 15
 clamp_status clamp_plan_set_timing(clamp_plan* plan, int32_t enable);
 /* Timing of the stages whose bit is set in stage_mask only (bit s = stage s;
  * 0 turns timing off, all CLAMP_STAGES bits equal clamp_plan_set_timing(1)):

@@ -37,7 +37,7 @@ FAULT_GAMMA = 4
 DIAG = 8  # doubles of diagnostics per look; the diag array holds looks + 1 rows (the last: summary)
 # columns of a look's diag row
 DG_GAMMA, DG_DD, DG_AD, DG_H0, DG_H1, DG_MURES, DG_WD, DG_R2 = range(8)
-STAGES = 14  # timing stages
+STAGES = 15  # timing stages
 
 
 class ClampError(RuntimeError):
@@ -92,9 +92,14 @@ def _load():
         "clamp_fwd_init": [P, i32, ctypes.POINTER(clamp_params), P, ctypes.POINTER(clamp_fwd_state),
                            P, P, P],
         "clamp_fwd_refresh": [P, i32, ctypes.POINTER(clamp_fwd_state), P, P],
+        "clamp_fwd_agent_mace": [P, i32, ctypes.POINTER(clamp_params), ctypes.POINTER(clamp_fwd_state),
+                                 P, P, P, P, P, P, P, P],
+        "clamp_mace_state": [P, i32, ctypes.POINTER(clamp_params), P, P, P, P],
         "clamp_fwd_agent": [P, i32, ctypes.POINTER(clamp_params), ctypes.POINTER(clamp_fwd_state),
                             P, P, P, P, P],
         "clamp_prior_gauss": [P, i32, ctypes.c_float, P, P, P, P],
+        "clamp_prior_l21": [P, i32, ctypes.c_float, P, P, P, P],
+        "clamp_prior_tv": [P, i32, ctypes.c_float, i32, P, P, P, P],
         "clamp_mace_step": [P, i32, ctypes.POINTER(clamp_params), P, P, P, P, P, P],
         "clamp_mace_step_noalloc": [P, i32, ctypes.POINTER(clamp_params), P, P, P, P, P],
         "clamp_plan_set_timing": [P, i32],
@@ -298,6 +303,30 @@ def clamp_fwd_agent(plan, scene, params, mu, resid, r, w, diag, fault, workspace
                                _stream(stream)))
 
 
+def clamp_fwd_agent_mace(plan, scene, params, mu, resid, r, w, xbar, wbar, diag, conv_err, fault, workspace,
+                         stream=None, ahy2=None):
+    """Forward agents with the Mann step fused in (see include/clamp.h for the
+    representation of w and xbar)."""
+    s = plan.scenes[scene]
+    na = params.n_agents
+    st = _state(plan, scene, mu, resid, r, na, None, ahy2)
+    _check(lib.clamp_fwd_agent_mace(plan.handle, scene, ctypes.byref(params), ctypes.byref(st),
+                                    _ptr(w, torch.float32, na * s.n, "w"), _ptr(xbar, torch.float32, s.n, "xbar"),
+                                    _ptr(wbar, torch.float32, s.n, "wbar"),
+                                    _ptr(diag, torch.float64, (s.looks + 1) * DIAG, "diag"),
+                                    _ptr(conv_err, torch.float64, 1, "conv_err"), _ptr(fault, torch.int32, 1, "fault"),
+                                    _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
+                                    _stream(stream)))
+
+
+def clamp_mace_state(plan, scene, params, w, xbar, out, stream=None):
+    s = plan.scenes[scene]
+    na = params.n_agents
+    _check(lib.clamp_mace_state(plan.handle, scene, ctypes.byref(params), _ptr(w, torch.float32, na * s.n, "w"),
+                                _ptr(xbar, torch.float32, s.n, "xbar"), _ptr(out, torch.float32, na * s.n, "out"),
+                                _stream(stream)))
+
+
 def clamp_fwd_refresh(plan, scene, mu, resid, y_pupil, workspace, stream=None):
     s = plan.scenes[scene]
     st = clamp_fwd_state(_ptr(mu, torch.complex64, s.looks * s.n, "mu").value,
@@ -316,6 +345,22 @@ def clamp_prior_gauss(plan, scene, sigma_vox, x, out, workspace, stream=None):
                                  _ptr(out, torch.float32, s.n, "out"),
                                  _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
                                  _stream(stream)))
+
+
+def clamp_prior_l21(plan, scene, tau, x, out, workspace, stream=None):
+    s = plan.scenes[scene]
+    _check(lib.clamp_prior_l21(plan.handle, scene, float(tau), _ptr(x, torch.float32, s.n, "in"),
+                               _ptr(out, torch.float32, s.n, "out"),
+                               _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
+                               _stream(stream)))
+
+
+def clamp_prior_tv(plan, scene, lam, iters, x, out, workspace, stream=None):
+    s = plan.scenes[scene]
+    _check(lib.clamp_prior_tv(plan.handle, scene, float(lam), int(iters), _ptr(x, torch.float32, s.n, "in"),
+                              _ptr(out, torch.float32, s.n, "out"),
+                              _ptr(workspace, torch.uint8, clamp_plan_workspace_size(plan), "workspace"),
+                              _stream(stream)))
 
 
 def clamp_mace_step(plan, scene, params, w, r, wbar, conv_err, workspace, stream=None):

@@ -33,12 +33,18 @@ class ClampGPU:
 
     def __init__(self, nx, ny, nz, looks, radius, sigma_w2, sigma2, with_prior=True, rho=0.5,
                  mu_scale=1.0, prior_sigma=1.0, mask=None, device="cuda", r_update="quadratic", range_support=0,
-                 refresh_every=0, keep_y=True):
+                 refresh_every=0, keep_y=True, fused=True, prior="gauss", prior_weight=0.0, tv_iters=20):
         """range_support = 0: per-slice 2D operator; K >= 1: the 3D operator
         with the K range frequencies nearest DC (looks are 3D frequency grids).
         keep_y keeps D(a) y on the device (the residual refresh needs it);
         refresh_every = m > 0 rebuilds the residual from it after every m-th
-        iteration."""
+        iteration.  fused: the Mann step runs inside the forward agents' last
+        pass (clamp_fwd_agent_mace), and w holds that call's representation
+        of the Mann state (state_w() writes it out); otherwise the forward
+        agents and the Mann step are separate calls.  prior: the prior agent
+        of the plain form, "gauss" (fixed smoothing of width prior_sigma),
+        or the comparison regularizers of Sec. V: "l21" (threshold
+        prior_weight) or "tv" (weight prior_weight, tv_iters steps)."""
         self.scene = C.Scene(nx, ny, nz, looks, radius, mask, range_support)
         self.plan = C.clamp_plan_create([self.scene])
         self.info = self.plan.info[0]
@@ -53,6 +59,11 @@ class ClampGPU:
         self.rho = float(rho)
         self.mu_scale = float(mu_scale)
         self.prior_sigma = float(prior_sigma)
+        if prior not in ("gauss", "l21", "tv"):
+            raise ValueError("prior must be gauss, l21 or tv")
+        self.prior_kind = prior
+        self.prior_weight = float(prior_weight)
+        self.tv_iters = int(tv_iters)
         self.r_update = r_update
         self.upsilon = agent_weights(looks, with_prior)
         f = dict(device=self.dev)
@@ -66,6 +77,8 @@ class ClampGPU:
         self.r = torch.zeros(self.N, nz, ny, nx, dtype=torch.float32, **f)
         self.w = torch.zeros(self.N, nz, ny, nx, dtype=torch.float32, **f)
         self.wbar = torch.zeros(nz, ny, nx, dtype=torch.float32, **f)
+        self.fused = bool(fused)
+        self.xbar = torch.zeros(nz, ny, nx, dtype=torch.float32, **f) if self.fused else None
         self.diag = torch.zeros(looks + 1, C.DIAG, dtype=torch.float64, **f)
         self.fault = torch.zeros(1, dtype=torch.int32, **f)
         self.conv = torch.zeros(1, dtype=torch.float64, **f)
@@ -79,6 +92,11 @@ class ClampGPU:
         """Alg. 2 initialisation from looks y (complex64 [L, nz, ny, nx], on the GPU)."""
         C.clamp_fwd_init(self.plan, 0, self.params(), y, self.mu, self.resid, self.r, self.w, self.ws,
                          y_pupil=self.y_pupil, ahy2=self.ahy2)
+        if self.fused:
+            # every agent's w starts at r0: x_bar = 0 makes u_l = w_l, and the
+            # average of the state is r0 itself
+            self.xbar.zero_()
+            self.wbar.copy_(self.w[0])
         self.fault.zero_()
         self.k = 0
 
@@ -91,20 +109,52 @@ class ClampGPU:
         C.clamp_fwd_refresh(self.plan, 0, self.mu, self.resid, self.y_pupil, self.ws)
 
     def prior(self):
-        C.clamp_prior_gauss(self.plan, 0, self.prior_sigma, self.w[self.L], self.r[self.L], self.ws)
+        if self.prior_kind == "l21":
+            C.clamp_prior_l21(self.plan, 0, self.prior_weight, self.w[self.L], self.r[self.L], self.ws)
+        elif self.prior_kind == "tv":
+            C.clamp_prior_tv(self.plan, 0, self.prior_weight, self.tv_iters, self.w[self.L], self.r[self.L], self.ws)
+        else:
+            C.clamp_prior_gauss(self.plan, 0, self.prior_sigma, self.w[self.L], self.r[self.L], self.ws)
+
+    def speckle_average(self):
+        """The speckle average (1/L) sum_l |A^H y_l|^2, the comparison
+        reconstruction of Sec. V: the initial image clamp_fwd_init leaves in
+        every agent's anchor (floored at 1e-12 of its mean).  Call after
+        init()."""
+        return self.r[0].clone()
 
     def mace(self):
         C.clamp_mace_step(self.plan, 0, self.params(), self.w, self.r, self.wbar, self.conv, self.ws)
 
+    def fwd_agents_mace(self, beta):
+        C.clamp_fwd_agent_mace(self.plan, 0, self.params(beta), self.mu, self.resid, self.r, self.w, self.xbar,
+                               self.wbar, self.diag, self.conv, self.fault, self.ws, ahy2=self.ahy2)
+
     def iterate(self):
-        """One pass of the Alg. 2 loop body; returns nothing (no host sync)."""
+        """One pass of the Alg. 2 loop body; returns nothing (no host sync).
+        Fused: the prior agent first (it reads only its own w), then the
+        forward agents with the Mann step."""
         self.k += 1
-        self.fwd_agents(beta_schedule(self.k))
+        if self.fused:
+            if self.with_prior:
+                self.prior()
+            self.fwd_agents_mace(beta_schedule(self.k))
+        else:
+            self.fwd_agents(beta_schedule(self.k))
+            if self.with_prior:
+                self.prior()
+            self.mace()
         if self.refresh_every > 0 and self.k % self.refresh_every == 0:
             self.refresh()
-        if self.with_prior:
-            self.prior()
-        self.mace()
+
+    def state_w(self):
+        """The Mann state w [N, nz, ny, nx] (written out by the library from
+        the fused representation)."""
+        if not self.fused:
+            return self.w
+        out = torch.empty_like(self.w)
+        C.clamp_mace_state(self.plan, 0, self.params(), self.w, self.xbar, out)
+        return out
 
     def run(self, iters, on_iter=None):
         for _ in range(iters):

@@ -62,7 +62,7 @@ bool size_supported(int n) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t T, T2, dfd, prow, pcf, pci, pupd, pres, pmace, scal, cnt, g0, g1;
+    size_t T, T2, dfd, prow, pcf, pci, pupd, pres, pmace, scal, cnt, g0, g1, tvp, pl21;
     size_t dfdb, pzi, pzf;  // 3D operator: box data [L][K][P], range-pass partial sums
     size_t total;
 };
@@ -83,11 +83,11 @@ struct Scene {
 // Timing stages; the names are returned by clamp_stage_name.
 enum Stage {
     ST_COL_INV = 0, ST_ROW_GRAD, ST_COL_FWD, ST_GAMMA, ST_ROW_UPDATE, ST_RESID, ST_DIAG,
-    ST_PRIOR, ST_MACE, ST_INIT, ST_OPERATOR, ST_OTHER, ST_RANGE_INV, ST_RANGE_FWD
+    ST_PRIOR, ST_MACE, ST_INIT, ST_OPERATOR, ST_OTHER, ST_RANGE_INV, ST_RANGE_FWD, ST_ROW_UPDATE_MANN
 };
 const char* const kStageNames[CLAMP_STAGES] = {
     "col_inv", "row_grad", "col_fwd", "gamma", "row_update", "resid_update", "diag_after",
-    "prior_gauss", "mace_step", "init", "aperture_op", "other", "range_inv", "range_fwd"};
+    "prior_gauss", "mace_step", "init", "aperture_op", "other", "range_inv", "range_fwd", "row_update_mann"};
 
 struct TimingRecord {
     int stage;
@@ -234,11 +234,13 @@ void layout_scene(Scene& s) {
     w.pci = take(L * clampk::col_blocks(s.tab) * sizeof(double));
     w.pupd = take(L * clampk::row_blocks(s.tab) * sizeof(double));
     w.pres = take(L * clampk::resid_blocks(s.tab) * sizeof(double));
-    w.pmace = take((size_t)clampk::mace_blocks(s.n()) * 2 * sizeof(double));
+    w.pmace = take((size_t)std::max(clampk::mace_blocks(s.n()), clampk::row_blocks(s.tab)) * 2 * sizeof(double));
     w.scal = take(64 * sizeof(double));
     w.cnt = take(64 * sizeof(unsigned));
     w.g0 = take(s.n() * sizeof(float));
     w.g1 = take(s.n() * sizeof(float));
+    w.tvp = take(3 * s.n() * sizeof(float));
+    w.pl21 = take((size_t)s.sc.nz * clampk::l21_chunks(s.sc.nx, s.sc.ny) * sizeof(double));
     if (s.K > 0) {
         const size_t nz_blocks = (size_t)std::max(clampk::zpass_blocks(s.tab), clampk::gather_blocks(s.tab));
         w.dfdb = take(L * s.K * (size_t)s.P * sizeof(float2));
@@ -636,20 +638,57 @@ clamp_status clamp_fwd_refresh(const clamp_plan* plan, int32_t scene, clamp_fwd_
     return hip_check(e, "clamp_fwd_refresh launch");
 }
 
-clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_params* params,
-                             clamp_fwd_state* state, const float* w, double* diag, uint32_t* fault,
-                             void* workspace, void* hip_stream) {
-    clamp_status st = check_plan_scene(plan, scene);
-    if (st != CLAMP_OK) return st;
-    const Scene& s = plan->scenes[scene];
-    if ((st = check_params(s, params, true)) != CLAMP_OK) return st;
-    if (state == nullptr || w == nullptr || diag == nullptr || fault == nullptr)
-        return fail(CLAMP_EINVAL, "NULL argument");
-    if (state->mu == nullptr || state->resid == nullptr || state->r == nullptr)
-        return fail(CLAMP_EINVAL, "state has a NULL array");
-    if ((st = check_ws(workspace)) != CLAMP_OK) return st;
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+}  // extern "C"
+
+namespace {
+
+// Launches of one forward-agent application shared by clamp_fwd_agent and
+// clamp_fwd_agent_mace: everything up to the step size (range pass, inverse
+// column pass, gradient row pass, forward column pass, range pass, gamma),
+// then `update` (the update row pass, plain or with the Mann step), then the
+// residual update and the diagnostics.
+struct AgentRun {
+    const clamp_plan* plan;
+    const Scene& s;
+    const clamp_params* params;
+    clamp_fwd_state* state;
+    double* diag;
+    uint32_t* fault;
+    void* workspace;
+    hipStream_t stream;
+};
+
+RowArgs agent_row_args(const AgentRun& r, const float* w) {
+    const Scene& s = r.s;
+    const double s2w = r.params->sigma_w2;
+    const double beta = r.params->beta;
+    RowArgs ra = row_args(s, s.sc.looks);
+    ra.mu = static_cast<float2*>(r.state->mu);
+    ra.r = r.state->r;
+    ra.w = w;
+    ra.diag = r.diag;
+    ra.fault = r.fault;
+    ra.inv_s2w = (float)(1.0 / s2w);
+    ra.s2w = (float)s2w;
+    ra.floor_w = (float)(s2w / s.alpha);
+    ra.alpha = (float)s.alpha;
+    ra.sigma2 = r.params->sigma2;
+    ra.inv_sigma2 = (float)(1.0 / (double)r.params->sigma2);
+    ra.beta = (float)beta;
+    ra.inv_beta = (float)(1.0 / beta);
+    ra.k_up = (float)((1.0 + beta) / (beta * beta));
+    ra.k_dn = (float)(beta * (1.0 + beta));
+    return ra;
+}
+
+template <typename Update>
+hipError_t agent_launches(const AgentRun& r, const RowArgs& ra, Update&& update) {
+    const Scene& s = r.s;
+    const clamp_plan* plan = r.plan;
+    void* workspace = r.workspace;
+    hipStream_t stream = r.stream;
     const int L = s.sc.looks;
+    const double s2w = r.params->sigma_w2;
     float2* T = at<float2>(workspace, s.ws.T);
     float2* T2 = at<float2>(workspace, s.ws.T2);
     float2* dfd = at<float2>(workspace, s.ws.dfd);
@@ -658,28 +697,7 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_
     double* pci = at<double>(workspace, s.ws.pci);
     double* pupd = at<double>(workspace, s.ws.pupd);
     double* pres = at<double>(workspace, s.ws.pres);
-    float2* mu = static_cast<float2*>(state->mu);
-    float2* resid = static_cast<float2*>(state->resid);
-
-    const double s2w = params->sigma_w2;
-    const double beta = params->beta;
-    RowArgs ra = row_args(s, L);
-    ra.mu = mu;
-    ra.r = state->r;
-    ra.w = w;
-    ra.diag = diag;
-    ra.fault = fault;
-    ra.inv_s2w = (float)(1.0 / s2w);
-    ra.s2w = (float)s2w;
-    ra.floor_w = (float)(s2w / s.alpha);
-    ra.alpha = (float)s.alpha;
-    ra.sigma2 = params->sigma2;
-    ra.inv_sigma2 = (float)(1.0 / (double)params->sigma2);
-    ra.beta = (float)beta;
-    ra.inv_beta = (float)(1.0 / beta);
-    ra.k_up = (float)((1.0 + beta) / (beta * beta));
-    ra.k_dn = (float)(beta * (1.0 + beta));
-    const int upd_mode = params->r_update == CLAMP_R_EXACT ? clampk::ROW_UPDATE_EXACT : clampk::ROW_UPDATE;
+    float2* resid = static_cast<float2*>(r.state->resid);
 
     // 3D operator: the residual lives on the cylinder [K][P]; a range pass
     // spreads it over every slice first, and one after the forward column
@@ -721,22 +739,87 @@ clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_
     unsigned* counter = at<unsigned>(workspace, s.ws.cnt);
     if (e == hipSuccess)
         e = timed(plan, ST_GAMMA, stream, [&] {
-            return clampk::launch_gamma(s.tab, L, prow, pz_fwd, pz_inv, 1.0 / s2w, diag, fault, counter, stream);
+            return clampk::launch_gamma(s.tab, L, prow, pz_fwd, pz_inv, 1.0 / s2w, r.diag, r.fault, counter, stream);
         });
     if (e == hipSuccess) {
         RowArgs u = ra;
         u.band_in = T;
         u.part = pupd;
-        e = timed(plan, ST_ROW_UPDATE, stream, [&] { return clampk::launch_row(upd_mode, u, stream); });
+        e = update(u);
     }
     if (e == hipSuccess)
         e = timed(plan, ST_RESID, stream,
-                  [&] { return clampk::launch_resid_update(s.tab, L, resid, dfd_box, diag, pres, stream); });
+                  [&] { return clampk::launch_resid_update(s.tab, L, resid, dfd_box, r.diag, pres, stream); });
     if (e == hipSuccess)
         e = timed(plan, ST_DIAG, stream, [&] {
-            return clampk::launch_diag_after(s.tab, L, pupd, pres, s2w, state->ahy2, diag, counter, stream);
+            return clampk::launch_diag_after(s.tab, L, pupd, pres, s2w, r.state->ahy2, r.diag, counter, stream);
         });
+    return e;
+}
+
+clamp_status check_agent_args(const clamp_plan* plan, int32_t scene, const clamp_params* params,
+                              const clamp_fwd_state* state, const void* w, const double* diag, const uint32_t* fault,
+                              const void* workspace) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    if ((st = check_params(s, params, true)) != CLAMP_OK) return st;
+    if (state == nullptr || w == nullptr || diag == nullptr || fault == nullptr)
+        return fail(CLAMP_EINVAL, "NULL argument");
+    if (state->mu == nullptr || state->resid == nullptr || state->r == nullptr)
+        return fail(CLAMP_EINVAL, "state has a NULL array");
+    return check_ws(workspace);
+}
+
+}  // namespace
+
+extern "C" {
+
+clamp_status clamp_fwd_agent(const clamp_plan* plan, int32_t scene, const clamp_params* params,
+                             clamp_fwd_state* state, const float* w, double* diag, uint32_t* fault,
+                             void* workspace, void* hip_stream) {
+    clamp_status st = check_agent_args(plan, scene, params, state, w, diag, fault, workspace);
+    if (st != CLAMP_OK) return st;
+    const AgentRun run{plan, plan->scenes[scene], params, state, diag, fault, workspace,
+                       static_cast<hipStream_t>(hip_stream)};
+    const int mode = params->r_update == CLAMP_R_EXACT ? clampk::ROW_UPDATE_EXACT : clampk::ROW_UPDATE;
+    const hipError_t e = agent_launches(run, agent_row_args(run, w), [&](const RowArgs& u) {
+        return timed(plan, ST_ROW_UPDATE, run.stream, [&] { return clampk::launch_row(mode, u, run.stream); });
+    });
     return hip_check(e, "clamp_fwd_agent launch");
+}
+
+clamp_status clamp_fwd_agent_mace(const clamp_plan* plan, int32_t scene, const clamp_params* params,
+                                  clamp_fwd_state* state, float* w, float* xbar, float* wbar, double* diag,
+                                  double* conv_err, uint32_t* fault, void* workspace, void* hip_stream) {
+    clamp_status st = check_agent_args(plan, scene, params, state, w, diag, fault, workspace);
+    if (st != CLAMP_OK) return st;
+    if (xbar == nullptr || wbar == nullptr || conv_err == nullptr) return fail(CLAMP_EINVAL, "NULL argument");
+    const Scene& s = plan->scenes[scene];
+    const AgentRun run{plan, s, params, state, diag, fault, workspace, static_cast<hipStream_t>(hip_stream)};
+    const int L = s.sc.looks;
+    const size_t n = s.n();
+    clampk::FuseArgs f{};
+    f.u = w;
+    const bool prior = params->n_agents == L + 1;
+    f.wprior = prior ? w + (size_t)L * n : nullptr;
+    f.rprior = prior ? state->r + (size_t)L * n : nullptr;
+    f.xbar = xbar;
+    f.wbar = wbar;
+    f.part = at<double>(workspace, s.ws.pmace);
+    for (int j = 0; j < params->n_agents; ++j) f.ups[j] = params->upsilon[j];
+    f.two_rho = 2.f * params->rho;
+    f.n_agents = params->n_agents;
+    const int mode = params->r_update == CLAMP_R_EXACT ? clampk::ROW_UPDATE_EXACT : clampk::ROW_UPDATE;
+    hipError_t e = agent_launches(run, agent_row_args(run, w), [&](const RowArgs& u) {
+        return timed(plan, ST_ROW_UPDATE_MANN, run.stream,
+                     [&] { return clampk::launch_row_update_mann(mode, u, f, run.stream); });
+    });
+    if (e == hipSuccess)
+        e = timed(plan, ST_MACE, run.stream, [&] {
+            return clampk::launch_mace_final(f.part, clampk::row_blocks(s.tab), conv_err, run.stream);
+        });
+    return hip_check(e, "clamp_fwd_agent_mace launch");
 }
 
 clamp_status clamp_prior_gauss(const clamp_plan* plan, int32_t scene, float sigma_vox, const float* in, float* out,
@@ -765,6 +848,45 @@ clamp_status clamp_prior_gauss(const clamp_plan* plan, int32_t scene, float sigm
     return hip_check(e, "clamp_prior_gauss launch");
 }
 
+static clamp_status check_prior_io(const clamp_plan* plan, int32_t scene, const float* in, float* out,
+                                   const void* workspace) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    if (in == nullptr || out == nullptr) return fail(CLAMP_EINVAL, "in/out is NULL");
+    const size_t n = plan->scenes[scene].n();
+    if (in < out + n && out < in + n) return fail(CLAMP_EINVAL, "in and out must not overlap");
+    return check_ws(workspace);
+}
+
+clamp_status clamp_prior_l21(const clamp_plan* plan, int32_t scene, float tau, const float* in, float* out,
+                             void* workspace, void* hip_stream) {
+    clamp_status st = check_prior_io(plan, scene, in, out, workspace);
+    if (st != CLAMP_OK) return st;
+    if (!(std::isfinite(tau) && tau >= 0.f)) return fail(CLAMP_EINVAL, "tau must be finite and >= 0");
+    const Scene& s = plan->scenes[scene];
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const hipError_t e = timed(plan, ST_PRIOR, stream, [&] {
+        return clampk::launch_prior_l21(s.sc.nx, s.sc.ny, s.sc.nz, tau, in, out, at<double>(workspace, s.ws.pl21),
+                                        stream);
+    });
+    return hip_check(e, "clamp_prior_l21 launch");
+}
+
+clamp_status clamp_prior_tv(const clamp_plan* plan, int32_t scene, float lam, int32_t iters, const float* in,
+                            float* out, void* workspace, void* hip_stream) {
+    clamp_status st = check_prior_io(plan, scene, in, out, workspace);
+    if (st != CLAMP_OK) return st;
+    if (!finite_pos(lam)) return fail(CLAMP_EINVAL, "lam must be finite and > 0");
+    if (iters < 0 || iters > 100000) return fail(CLAMP_EINVAL, "iters must lie in [0, 100000]");
+    const Scene& s = plan->scenes[scene];
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const hipError_t e = timed(plan, ST_PRIOR, stream, [&] {
+        return clampk::launch_prior_tv(s.sc.nx, s.sc.ny, s.sc.nz, lam, iters, in, out, at<float>(workspace, s.ws.tvp),
+                                       at<float>(workspace, s.ws.g0), stream);
+    });
+    return hip_check(e, "clamp_prior_tv launch");
+}
+
 clamp_status clamp_mace_step(const clamp_plan* plan, int32_t scene, const clamp_params* params, float* w,
                              const float* r, float* wbar, double* conv_err, void* workspace, void* hip_stream) {
     clamp_status st = check_plan_scene(plan, scene);
@@ -790,6 +912,22 @@ clamp_status clamp_mace_step(const clamp_plan* plan, int32_t scene, const clamp_
         return x;
     });
     return hip_check(e, "clamp_mace_step launch");
+}
+
+clamp_status clamp_mace_state(const clamp_plan* plan, int32_t scene, const clamp_params* params, const float* w,
+                              const float* xbar, float* out, void* hip_stream) {
+    clamp_status st = check_plan_scene(plan, scene);
+    if (st != CLAMP_OK) return st;
+    const Scene& s = plan->scenes[scene];
+    if ((st = check_params(s, params, false)) != CLAMP_OK) return st;
+    if (w == nullptr || xbar == nullptr || out == nullptr) return fail(CLAMP_EINVAL, "NULL argument");
+    const size_t n = s.n();
+    const size_t total = n * (size_t)params->n_agents;
+    if ((const char*)out < (const char*)(w + total) && (const char*)w < (const char*)(out + total))
+        return fail(CLAMP_EINVAL, "w and out overlap");
+    const hipError_t e = clampk::launch_mann_state(n, s.sc.looks, params->n_agents, 2.f * params->rho, w, xbar,
+                                                   out, static_cast<hipStream_t>(hip_stream));
+    return hip_check(e, "clamp_mace_state launch");
 }
 
 clamp_status clamp_mace_step_noalloc(const clamp_plan* plan, int32_t scene, const clamp_params* params, float* w,

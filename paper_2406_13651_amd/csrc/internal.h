@@ -130,8 +130,28 @@ struct RowArgs {
     float k_dn;                // beta (1 + beta)        (xi = r'/beta)
 };
 
+// The Mann step fused into the update pass (one block walks every look of
+// its rows).  The forward agents' Mann state is kept as u_l = w_l - 2 rho
+// xbar with xbar the reflected average x_bar of the previous step, so that
+// the pass never re-reads a look: it forms v = u_l + 2 rho xbar_old, writes
+// u_l' = v - 2 rho r_l, and after the last look xbar_new, w_bar and the prior
+// agent's w (kept whole).
+struct FuseArgs {
+    float* u;             // [looks][n] in: u_l, out: u_l'
+    float* wprior;        // [n] the prior agent's w, in and out (NULL without a prior)
+    const float* rprior;  // [n] the prior agent's output H(w) (NULL without a prior)
+    float* xbar;          // [n] in: x_bar of the previous step, out: this step's
+    float* wbar;          // [n] out: sum_j upsilon_j w_j after the step
+    double* part;         // [row_blocks][2] partial sums of the convergence error
+    float ups[64];
+    float two_rho;
+    int n_agents;
+};
 hipError_t launch_col(int mode, const ColArgs& a, hipStream_t st);
 hipError_t launch_row(int mode, const RowArgs& a, hipStream_t st);
+// mode ROW_UPDATE or ROW_UPDATE_EXACT; a.w is unused (the fused pass forms v
+// from f.u and f.xbar); a.part gets one partial sum per (look, row block)
+hipError_t launch_row_update_mann(int mode, const RowArgs& a, const FuseArgs& f, hipStream_t st);
 hipError_t launch_scatter_full(const SceneTables& s, int looks, const float2* cmp,
                                float2* full, hipStream_t st);
 hipError_t launch_gamma(const SceneTables& s, int looks, const double* part_row,
@@ -167,11 +187,23 @@ struct MaceArgs {
 };
 hipError_t launch_mace(const MaceArgs& a, hipStream_t st);
 hipError_t launch_mace_final(const double* part, int blocks, double* conv_err, hipStream_t st);
+// out = the Mann state of the fused representation (see FuseArgs)
+hipError_t launch_mann_state(size_t n, int looks, int n_agents, float two_rho, const float* u, const float* xbar,
+                             float* out, hipStream_t st);
 // Device address, on `device` (which must be current), of the static scratch
 // of clamp_mace_step_noalloc: kMaceScratchDoubles doubles (1 MiB), enough for
 // the partial sums of mace_blocks(n) blocks up to n = 2^25 voxels.
 constexpr size_t kMaceScratchDoubles = 131072;
 hipError_t mace_scratch(int device, double** out);
+
+// Comparison regularizers (regularizers.hip): the l_{2,1} proximal map
+// (part: nz * l21_chunks(nx, ny) doubles) and the TV proximal map by
+// Chambolle's iteration (p: 3 n floats, u: n floats of scratch).
+int l21_chunks(int nx, int ny);
+hipError_t launch_prior_l21(int nx, int ny, int nz, float tau, const float* in, float* out, double* part,
+                            hipStream_t st);
+hipError_t launch_prior_tv(int nx, int ny, int nz, float lam, int iters, const float* in, float* out, float* p,
+                           float* u, hipStream_t st);
 
 hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float* in,
                         float* tmp0, float* tmp1, float* out, hipStream_t st);

@@ -164,6 +164,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     row_item<NX, ROW_GRAD>(a, blockIdx.y, blockIdx.x, (size_t)blockIdx.y * gridDim.x + blockIdx.x, L, true, bv);
 }
 
+// The update pass with the Mann step fused in: one block per row group,
+// walking every look (row_update_mann).  Held to three waves per SIMD (168
+// registers): the per-voxel sums across looks come on top of the update
+// pass's registers, and at four waves (128) the compiler spills 25 of them
+// to scratch inside the look loop.
+template <int NX, int MODE>
+__device__ __forceinline__ void row_upd_mann_block(const RowArgs& a, const FuseArgs& f) {
+    __shared__ float2 tw[NX];
+    __shared__ int bpos[NX];
+    __shared__ int bcol[NX];
+    __shared__ float2 buf[row_lds_floats2<NX>()];
+    __shared__ float ups[64];
+    __shared__ float keep[mann_lds_floats<NX>()];
+    const RowLds L{tw, bpos, bcol, buf};
+    const BetaVals bv{a.beta, a.inv_beta, a.k_up, a.k_dn};
+    row_update_mann<NX, MODE>(a, f, blockIdx.x, gridDim.x, L, bv, ups, keep);
+}
+template <int NX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_row_upd_mann(RowArgs a,
+                                                                                                FuseArgs f) {
+    row_upd_mann_block<NX, ROW_UPDATE>(a, f);
+}
+// The exact surrogate prox's float64 root solve needs more registers: two
+// waves per SIMD.
+template <int NX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_row_upd_mann_exact(
+    RowArgs a, FuseArgs f) {
+    row_upd_mann_block<NX, ROW_UPDATE_EXACT>(a, f);
+}
+
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_scatter_full(SceneTables s, size_t total,
                                                          const float2* cmp, float2* full) {
@@ -289,6 +319,17 @@ __global__ __launch_bounds__(kBlock) void k_mace(MaceArgs a) {
     block_sum_store<2>(v, a.part + (size_t)blockIdx.x * 2);
 }
 
+// Mann state from the fused pass's representation: out_l = u_l + 2 rho xbar
+// for the looks, out_L = w_L (the prior agent's, kept whole).
+__global__ __launch_bounds__(kBlock) void k_mann_state(size_t n, int looks, int n_agents, float two_rho,
+                                                       const float* u, const float* xbar, float* out) {
+    const size_t total = n * (size_t)n_agents;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
+        const size_t j = i / n, v = i - j * n;
+        out[i] = (int)j < looks ? u[i] + two_rho * xbar[v] : u[i];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_mace_final(const double* part, int blocks, double* conv) {
     double v[2] = {0.0, 0.0};
     strided_sums<2>(part, blocks, 2, v);
@@ -298,33 +339,94 @@ __global__ __launch_bounds__(kBlock) void k_mace_final(const double* part, int b
 }
 
 // ---------------------------------------------------------------------------
-// Periodic 7-tap filter along x (contiguous).
-// x pass: four voxels per thread (n and nx multiples of 4), one per thread
-// block-wise rather than a looping capped grid.
-__global__ __launch_bounds__(kBlock) void k_gauss_x(int nx, size_t n, Taps7 t, const float* in, float* out) {
-    const unsigned q = blockIdx.x * kBlock + threadIdx.x;
-    if (q < n / 4) reinterpret_cast<float4*>(out)[q] = gauss_x_quad(nx, t.g, in, q);
-}
-
-// Periodic 7-tap filter along a strided axis, CH samples per work unit.
-template <int CH>
-__global__ __launch_bounds__(kBlock) void k_gauss_strided(int len, size_t inner, size_t outer, Taps7 t,
-                                                          const float* in, float* out) {
-    const size_t work = outer * (size_t)((len + CH - 1) / CH);
-    for (size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x; idx < work; idx += (size_t)gridDim.x * kBlock)
-        gauss_strided_unit<CH>(len, inner, outer, t.g, in, out, idx);
-}
-
-static void gauss_axis(int len, size_t inner, size_t outer, const Taps7& t, const float* in, float* out,
-                       hipStream_t st) {
-    if (len >= 32) {
-        const size_t work = outer * ((len + 31) / 32);
-        hipLaunchKernelGGL(k_gauss_strided<32>, dim3(grid_cap(work, 8192)), dim3(kBlock), 0, st, len, inner, outer,
-                           t, in, out);
-    } else {
-        const size_t work = outer * ((len + 7) / 8);
-        hipLaunchKernelGGL(k_gauss_strided<8>, dim3(grid_cap(work, 8192)), dim3(kBlock), 0, st, len, inner, outer, t,
-                           in, out);
+// The periodic separable 7-tap smoothing of a volume in one pass.  Block
+// (x tile, y tile, z chunk) covers GTY rows x TX columns of GCZ output
+// slices.  It walks the chunk's input slices with their 3-slice halos: each
+// input slice's (GTY + 6) x (TX + 6) tile (periodic wrap) is read once,
+// prefetched into registers a slice ahead, filtered along x then y in LDS,
+// and every thread keeps the last seven filtered values of its outputs in
+// registers, from which each output slice is filtered along z.  Reads about
+// (GTY + 6)(TX + 6)/(GTY TX) (GCZ + 6)/GCZ of the input and writes the
+// output once, where three separate passes read and write the volume three
+// times.
+constexpr int kGaussTY = 8, kGaussCZ = 8;
+template <int TX>
+__global__ __launch_bounds__(kBlock) void k_gauss3d(int nx, int ny, int nz, Taps7 t, const float* in, float* out) {
+    constexpr int W = TX + 6, H = kGaussTY + 6;
+    constexpr int NIN = H * W;
+    constexpr int LPT = (NIN + kBlock - 1) / kBlock;
+    constexpr int OPT = kGaussTY * TX / kBlock;
+    static_assert(OPT >= 1 && kGaussTY * TX % kBlock == 0, "a tile's outputs divide among the threads");
+    __shared__ float tin[NIN];
+    __shared__ float txf[H * TX];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * kGaussTY, z0 = blockIdx.z * kGaussCZ;
+    const int zend = z0 + kGaussCZ < nz ? z0 + kGaussCZ : nz;
+    const unsigned slice = (unsigned)nx * (unsigned)ny;
+    unsigned goff[LPT];
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+        const int e = tid + j * kBlock;
+        const int r = (e < NIN ? e : 0) / W, c = (e < NIN ? e : 0) % W;
+        int gy = y0 - 3 + r, gx = x0 - 3 + c;
+        gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+        gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+        goff[j] = (unsigned)gy * nx + gx;
+    }
+    float pre[LPT];
+    auto load = [&](int zi) {
+        int zz = zi % nz;
+        zz = zz < 0 ? zz + nz : zz;
+        const float* src = in + (size_t)zz * slice;
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) pre[j] = src[goff[j]];
+    };
+    float ring[7][OPT];
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+#pragma unroll
+        for (int q = 0; q < OPT; ++q) ring[k][q] = 0.f;
+    load(z0 - 3);
+    for (int zi = z0 - 3; zi < zend + 3; ++zi) {
+        __syncthreads();  // the previous slice's readers of tin and txf are done
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int e = tid + j * kBlock;
+            if (e < NIN) tin[e] = pre[j];
+        }
+        if (zi + 1 < zend + 3) load(zi + 1);
+        __syncthreads();
+        for (int e = tid; e < H * TX; e += kBlock) {
+            const int r = e / TX, c = e % TX;
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) acc += t.g[k] * tin[r * W + c + k];
+            txf[e] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < OPT; ++q) {
+            const int o = tid + q * kBlock;
+            const int oy = o / TX, ox = o % TX;
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) acc += t.g[k] * txf[(oy + k) * TX + ox];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) ring[k][q] = ring[k + 1][q];
+            ring[6][q] = acc;
+        }
+        if (zi >= z0 + 3) {
+            const size_t zo = (size_t)(zi - 3) * slice;
+#pragma unroll
+            for (int q = 0; q < OPT; ++q) {
+                const int o = tid + q * kBlock;
+                const int oy = o / TX, ox = o % TX;
+                float acc = 0.f;
+#pragma unroll
+                for (int k = 0; k < 7; ++k) acc += t.g[k] * ring[k][q];
+                out[zo + (size_t)(y0 + oy) * nx + x0 + ox] = acc;
+            }
+        }
     }
 }
 
@@ -411,6 +513,34 @@ hipError_t launch_row(int mode, const RowArgs& a, hipStream_t st) {
     }
 }
 
+template <int MODE>
+static hipError_t row_update_mann_dispatch(const RowArgs& a, const FuseArgs& f, hipStream_t st) {
+    const dim3 grid((unsigned)row_blocks(a.s));
+    switch (a.s.nx) {
+#define CASE(N)                                                                          \
+    case N:                                                                              \
+        if constexpr (MODE == ROW_UPDATE_EXACT)                                          \
+            hipLaunchKernelGGL((k_row_upd_mann_exact<N>), grid, dim3(kBlock), 0, st, a, f); \
+        else                                                                             \
+            hipLaunchKernelGGL((k_row_upd_mann<N>), grid, dim3(kBlock), 0, st, a, f);    \
+        break;
+        CLAMP_SIZES(CASE)
+#undef CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_row_update_mann(int mode, const RowArgs& a, const FuseArgs& f, hipStream_t st) {
+    if (a.looks <= 0) return hipSuccess;
+    switch (mode) {
+        case ROW_UPDATE: return row_update_mann_dispatch<ROW_UPDATE>(a, f, st);
+        case ROW_UPDATE_EXACT: return row_update_mann_dispatch<ROW_UPDATE_EXACT>(a, f, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_scatter_full(const SceneTables& s, int looks, const float2* cmp, float2* full,
                                hipStream_t st) {
     const size_t total = (size_t)looks * s.nz * s.ny * s.nx;
@@ -484,6 +614,15 @@ hipError_t launch_mace(const MaceArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_mann_state(size_t n, int looks, int n_agents, float two_rho, const float* u, const float* xbar,
+                             float* out, hipStream_t st) {
+    const size_t total = n * (size_t)n_agents;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mann_state, dim3(grid_cap(total, 8192)), dim3(kBlock), 0, st, n, looks, n_agents, two_rho,
+                       u, xbar, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_mace_final(const double* part, int blocks, double* conv_err, hipStream_t st) {
     hipLaunchKernelGGL(k_mace_final, dim3(1), dim3(kBlock), 0, st, part, blocks, conv_err);
     return hipGetLastError();
@@ -514,14 +653,18 @@ hipError_t mace_scratch(int device, double** out) {
 
 hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float* in, float* tmp0,
                         float* tmp1, float* out, hipStream_t st) {
+    (void)tmp0;
+    (void)tmp1;
     Taps7 t;
     for (int k = 0; k < 7; ++k) t.g[k] = taps7[k];
-    const size_t n = (size_t)nx * ny * nz;
-    hipLaunchKernelGGL(k_gauss_x, dim3((unsigned)((n / 4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nx, n, t, in,
-                       tmp0);
-    // y: stride nx, outer index runs over (z, x); z: stride nx*ny, outer over (y, x)
-    gauss_axis(ny, (size_t)nx, (size_t)nz * nx, t, tmp0, tmp1, st);
-    gauss_axis(nz, (size_t)nx * ny, (size_t)nx * ny, t, tmp1, out, st);
+    if (ny % kGaussTY != 0 || nx % 32 != 0) return hipErrorInvalidValue;
+    const unsigned zc = (unsigned)((nz + kGaussCZ - 1) / kGaussCZ);
+    if (nx % 64 == 0)
+        hipLaunchKernelGGL(k_gauss3d<64>, dim3(nx / 64, ny / kGaussTY, zc), dim3(kBlock), 0, st, nx, ny, nz, t, in,
+                           out);
+    else
+        hipLaunchKernelGGL(k_gauss3d<32>, dim3(nx / 32, ny / kGaussTY, zc), dim3(kBlock), 0, st, nx, ny, nz, t, in,
+                           out);
     return hipGetLastError();
 }
 

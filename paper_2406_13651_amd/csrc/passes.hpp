@@ -179,6 +179,40 @@ __device__ __forceinline__ float exact_prox(float sf, float vf, float s2f) {
     return (float)best;  // 0 (flagged by the caller) only if no positive root was found
 }
 
+// Surrogate r-update of one voxel at the anchor r0 and prox point v, with the
+// updated mean m1: covariance diagonal c = sigma_w^2 r0 / (alpha r0 +
+// sigma_w^2) (A^H A ~ alpha I), s = c + |m1|^2, then the quadratic surrogate
+// of App. A (ROW_UPDATE) or the exact surrogate prox (ROW_UPDATE_EXACT).
+// Fault bits: 1 for a non-finite result or mean, 2 for r <= 0.
+template <int MODE>
+__device__ __forceinline__ float r_update_voxel(const RowArgs& a, const BetaVals& bv, float r0, float v, float2 m1,
+                                                uint32_t& fb) {
+    const float c = a.s2w * r0 / (a.alpha * r0 + a.s2w);
+    const float sv = c + cabs2(m1);
+    float rn;
+    if constexpr (MODE == ROW_UPDATE_EXACT) {
+        rn = exact_prox(sv, v, a.sigma2);
+        if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
+    } else {
+        // quadratic surrogate of r/r' + s/r, interpolating its derivative at
+        // r' and xi; written with s/r' first so that small anchors stay in
+        // float32 range
+        const float inv = 1.f / r0;
+        const float sr = sv * inv;
+        const float dq = inv * (1.f - sr);                  // q'(r')
+        const float D = dq + (r0 - v) * a.inv_sigma2;       // rho'(r')
+        const bool down = D > 0.f;
+        const float xi = down ? r0 * bv.inv_beta : r0 * bv.beta;
+        const float qa = sr * inv * inv * (down ? bv.k_dn : bv.k_up);
+        const float qb = dq - qa * r0;
+        rn = (v - a.sigma2 * qb) / (1.f + a.sigma2 * qa);
+        if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
+        rn = fminf(fmaxf(rn, fminf(r0, xi)), fmaxf(r0, xi));
+    }
+    if (!(rn > 0.f)) fb |= 2u;
+    return rn;
+}
+
 // LDS buffers of a row item: twiddles, band position and band column tables
 // (length NX each) and the padded row buffers.
 struct RowLds {
@@ -364,30 +398,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
                     const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
                     const float2 m1 = make_float2(m[k].x + gamma * d.x, m[k].y + gamma * d.y);
                     st_stream(&a.mu[img + x], m1);
-                    // covariance diagonal with A^H A ~ alpha I, and s = c + |mu|^2
-                    const float c = a.s2w * r0 / (a.alpha * r0 + a.s2w);
-                    const float sv = c + cabs2(m1);
-                    float rn;
-                    if constexpr (MODE == ROW_UPDATE_EXACT) {
-                        rn = exact_prox(sv, v, a.sigma2);
-                        if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
-                    } else {
-                        // quadratic surrogate of r/r' + s/r, interpolating its
-                        // derivative at r' and xi; written with s/r' first so that
-                        // small anchors stay in float32 range
-                        const float inv = 1.f / r0;
-                        const float sr = sv * inv;
-                        const float dq = inv * (1.f - sr);                  // q'(r')
-                        const float D = dq + (r0 - v) * a.inv_sigma2;       // rho'(r')
-                        const bool down = D > 0.f;
-                        const float xi = down ? r0 * bv.inv_beta : r0 * bv.beta;
-                        const float qa = sr * inv * inv * (down ? bv.k_dn : bv.k_up);
-                        const float qb = dq - qa * r0;
-                        rn = (v - a.sigma2 * qb) / (1.f + a.sigma2 * qa);
-                        if (!(rn == rn) || !isfinite(m1.x) || !isfinite(m1.y)) fb |= 1u;
-                        rn = fminf(fmaxf(rn, fminf(r0, xi)), fmaxf(r0, xi));
-                    }
-                    if (!(rn > 0.f)) fb |= 2u;
+                    const float rn = r_update_voxel<MODE>(a, bv, r0, v, m1, fb);
                     st_stream(&a.r[img + x], rn);
                     wm1 += om * cabs2(m1);
                 }
@@ -397,6 +408,179 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
         double acc[1] = {wm1};
         block_sum_store<1>(acc, a.part + slot);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Update pass with the Mann step of Alg. 1 fused in: the block walks every
+// look of rows [rgroup * RPB, rgroup * RPB + RPB).  Per look it does what
+// row_item's update does (recompute d, mu += gamma d, the r-update), with the
+// prox point v = u_l + 2 rho xbar_old, and writes u_l' = v - 2 rho r_l; across
+// looks it keeps, per voxel, sum_j upsilon_j r_j and sum_j (r_j - w_bar)^2,
+// where w_bar = sum_j upsilon_j w_j is the average of the Mann state passed
+// in (G(w)), which the previous call left in f.wbar.  After the last look it
+// adds the prior agent (its w and H(w)) and writes x_bar = sum_j upsilon_j
+// (2 r_j - w_j) = 2 sum_j upsilon_j r_j - w_bar, the new average w_bar +
+// 2 rho (sum_j upsilon_j r_j - w_bar) and the prior's new w.  Partial sums:
+// sum omega |mu'|^2 per (look, block) into a.part, the convergence error's
+// (sum_j (r_j - w_bar)^2, N w_bar^2) per block into f.part.
+template <int NX>
+__host__ __device__ constexpr int mann_lds_floats() {
+    return 2 * kBlock * ((NX + row_threads(NX) - 1) / row_threads(NX));
+}
+
+// LDS: ups[64] holds the agent weights, keep[mann_lds_floats<NX>()] each
+// thread's x_bar and w_bar of the previous call ([k][thread], conflict-free),
+// read back at every look instead of held in registers.
+template <int NX, int MODE>
+__device__ __forceinline__ void row_update_mann(const RowArgs& a, const FuseArgs& f, int rgroup, int nblk,
+                                                const RowLds& L, BetaVals bv, float* ups, float* keep) {
+    constexpr int TR = row_threads(NX);
+    constexpr int RPB = rows_per_block(NX);
+    constexpr int PX = (NX + TR - 1) / TR;
+    constexpr int PAD = kRowPad;
+    constexpr int RS = lds_len<NX, PAD>();
+    const SceneTables& s = a.s;
+    const int tid = threadIdx.x;
+    const int ri = tid / TR, t = tid % TR;
+    const int rows = s.nz * s.ny;
+    const int row = rgroup * RPB + ri;
+    const bool active = row < rows;
+    const size_t n = (size_t)rows * NX;
+    const size_t pix = (size_t)(active ? row : 0) * NX;
+    for (int i = tid; i < NX; i += kBlock) {
+        L.tw[i] = s.tw_x[i];
+        L.bpos[i] = s.band_pos[i];
+        const int bc = s.band_cols[i < s.B ? i : 0];
+        L.bcol[i] = i < s.B ? bc : 0;
+    }
+    // the agent weights go to LDS with constant indices: indexing the
+    // argument block by the look would make a private copy of it
+    if (tid == 0) {
+#pragma unroll
+        for (int j = 0; j < 64; ++j) ups[j] = f.ups[j];
+    }
+    float2* rb = L.buf + ri * RS;
+    float* xo = keep;                  // xo[k * kBlock + tid]
+    float* wb = keep + PX * kBlock;    // wb[k * kBlock + tid]
+    float sr[PX], e2[PX];
+    {
+        // all loads issued before the first is used (samples past the row
+        // end and inactive rows read the row's first sample)
+        float a0[PX], a1[PX];
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+            const int x = t + k * TR;
+            const size_t i = pix + ((NX % TR == 0 || x < NX) ? x : 0);
+            a0[k] = ld_stream(f.xbar + i);
+            a1[k] = ld_stream(f.wbar + i);
+        }
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+            xo[k * kBlock + tid] = a0[k];
+            wb[k * kBlock + tid] = a1[k];
+            sr[k] = e2[k] = 0.f;
+        }
+    }
+    __syncthreads();
+    uint32_t fb = 0u;
+    for (int l = 0; l < a.looks; ++l) {
+        const size_t img = (size_t)l * n + pix;
+        const size_t band = ((size_t)l * rows + (active ? row : 0)) * s.Bs;
+        float2 h[PX];
+        {
+            float2 bin[PX];
+            int bp[PX];
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                bp[k] = (active && (NX % TR == 0 || x < NX)) ? L.bpos[x] : -1;
+                bin[k] = ld_stream(a.band_in + band + (bp[k] >= 0 ? bp[k] : 0));
+            }
+#pragma unroll
+            for (int k = 0; k < PX; ++k) h[k] = bp[k] >= 0 ? bin[k] : make_float2(0.f, 0.f);
+        }
+        row_fft<NX, TR, +1, PAD, true>(h, rb, t, L.tw);
+        float2 m[PX];
+        float rp[PX], uv[PX];
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) {
+                    m[k] = ld_stream(&a.mu[img + x]);
+                    rp[k] = ld_stream(&a.r[img + x]);
+                    uv[k] = ld_stream(&f.u[img + x]);
+                }
+            }
+        }
+        const float gamma = (float)a.diag[(size_t)l * kDiag];
+        const float ul = ups[l];
+        float wm1 = 0.f;
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int x = t + k * TR;
+                if (NX % TR == 0 || x < NX) {
+                    const float2 ahr = cscale(h[k], a.scale);
+                    const float r0 = rp[k];
+                    const float om = 1.f / (r0 + a.floor_w);
+                    const float2 d = make_float2(ahr.x * a.inv_s2w - om * m[k].x, ahr.y * a.inv_s2w - om * m[k].y);
+                    const float2 m1 = make_float2(m[k].x + gamma * d.x, m[k].y + gamma * d.y);
+                    st_stream(&a.mu[img + x], m1);
+                    const float v = uv[k] + f.two_rho * xo[k * kBlock + tid];
+                    const float rn = r_update_voxel<MODE>(a, bv, r0, v, m1, fb);
+                    st_stream(&a.r[img + x], rn);
+                    st_stream(&f.u[img + x], v - f.two_rho * rn);
+                    sr[k] += ul * rn;
+                    const float e = rn - wb[k * kBlock + tid];
+                    e2[k] += e * e;
+                    wm1 += om * cabs2(m1);
+                }
+            }
+        }
+        double acc[1] = {wm1};
+        block_sum_store<1>(acc, a.part + (size_t)l * nblk + rgroup);
+    }
+    const bool prior = f.wprior != nullptr;
+    const float up = prior ? ups[a.looks] : 0.f;
+    const float N = (float)f.n_agents;
+    double num = 0.0, den = 0.0;
+    // the prior agent's output and w, every load issued before the first is
+    // used (without a prior the loads read x_bar, with weight 0, and nothing
+    // of them is stored)
+    float rpv[PX], wpv[PX];
+    {
+        const float* rsrc = prior ? f.rprior : f.xbar;
+        const float* wsrc = prior ? f.wprior : f.xbar;
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+            const int x = t + k * TR;
+            const size_t i = pix + ((NX % TR == 0 || x < NX) ? x : 0);
+            rpv[k] = rsrc[i];
+            wpv[k] = ld_stream(wsrc + i);
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+            const int x = t + k * TR;
+            if (NX % TR == 0 || x < NX) {
+                const float wbk = wb[k * kBlock + tid];
+                const float e = rpv[k] - wbk;
+                const float s_r = prior ? sr[k] + up * rpv[k] : sr[k];
+                const float nm = e2[k] + (prior ? e * e : 0.f);
+                const float xb = 2.f * s_r - wbk;
+                if (prior) st_stream(f.wprior + pix + x, wpv[k] + f.two_rho * (xb - rpv[k]));
+                st_stream(f.xbar + pix + x, xb);
+                st_stream(f.wbar + pix + x, wbk + f.two_rho * (s_r - wbk));
+                num += (double)nm;
+                den += (double)N * ((double)wbk * wbk);
+            }
+        }
+    }
+    wave_or_fault(fb, a.fault);
+    double acc2[2] = {num, den};
+    block_sum_store<2>(acc2, f.part + (size_t)rgroup * 2);
 }
 
 // ---------------------------------------------------------------------------

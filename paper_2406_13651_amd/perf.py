@@ -6,10 +6,11 @@ measured launch duration.  Sizes: complex64 = 8 bytes, float32 = 4 bytes.
 """
 
 
-def stage_bytes(nx, ny, nz, looks, P, B, n_agents, K=0):
+def stage_bytes(nx, ny, nz, looks, P, B, n_agents, K=0, fused=False):
     """Bytes per launch of each timing stage of one CLAMP iteration (K > 0:
     the 3D operator with K range frequencies, adding the two range passes and
-    keeping the residual on the K x P cylinder)."""
+    keeping the residual on the K x P cylinder; fused: the Mann step inside
+    the update pass, whose own launch is then only the final reduction)."""
     L = looks
     n = nx * ny * nz
     band = 8 * ny * B          # one slice's band rows (complex64)
@@ -37,6 +38,13 @@ def stage_bytes(nx, ny, nz, looks, P, B, n_agents, K=0):
         # every agent's w and r in, w out, and w_bar out
         "mace_step": n * (12 * n_agents + 4),
     }
+    if fused:
+        del out["row_update"], out["mace_step"]
+        # band rows, mu, anchor and u in, mu, r and u out per look; per voxel
+        # x_bar and w_bar in and out, and with a prior its output in and its w
+        # in and out
+        prior = 12 if n_agents == looks + 1 else 0
+        out["row_update_mann"] = L * nz * (band + ny * nx * (8 + 4 + 4 + 8 + 4 + 4)) + n * (16 + prior)
     out.update(extra)
     return out
 

@@ -226,7 +226,7 @@ def test_tiny_forward_only_20_iterations_exact_prox(G):
 def test_exact_prox_run_with_prior(G):
     spec = synth.SceneSpec("r", 64, 64, 16, 4, 16.0, 10.0, 8, 0.05, 1, 1)
     g, st, hist, errs = _run_pair(G, spec, 1e-3, 20, True, r_update="exact")
-    assert report("64x64x16 20 it exact w", rel_l2(g.w.cpu().numpy(), st.w), TOL_RUN) <= TOL_RUN
+    assert report("64x64x16 20 it exact w", rel_l2(g.state_w().cpu().numpy(), st.w), TOL_RUN) <= TOL_RUN
     assert report("64x64x16 20 it exact mu", rel_l2(g.mu.cpu().numpy(), st.mu), TOL_RUN) <= TOL_RUN
 
 
@@ -234,7 +234,7 @@ def test_reduced_full_recipe_50_iterations_with_prior(G):
     spec = synth.SceneSpec("r", 64, 64, 16, 4, 16.0, 10.0, 8, 0.05, 1, 1)
     g, st, hist, errs = _run_pair(G, spec, 1e-3, 50, True)
     assert report("64x64x16 50 it wbar", rel_l2(g.wbar.cpu().numpy(), hist[-1]["wbar"]), TOL_RUN) <= TOL_RUN
-    assert report("64x64x16 50 it w", rel_l2(g.w.cpu().numpy(), st.w), TOL_RUN) <= TOL_RUN
+    assert report("64x64x16 50 it w", rel_l2(g.state_w().cpu().numpy(), st.w), TOL_RUN) <= TOL_RUN
     assert report("64x64x16 50 it mu", rel_l2(g.mu.cpu().numpy(), st.mu), TOL_RUN) <= TOL_RUN
     mu_res = g.mu_residual()
     assert abs(mu_res - hist[-1]["mu_residual"]) <= 1e-3 * hist[-1]["mu_residual"]
@@ -344,18 +344,19 @@ def test_timing_of_selected_stages(G):
     from paper_2406_13651_amd import _clamp as C
     spec = synth.CONFIGS["tiny"]
     r_true, y, s2w = synth.make_problem(spec, 0)
-    g = G.ClampGPU(spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, 1e-3, with_prior=True)
-    g.init(to_gpu(y))
-    C.clamp_plan_set_timing_stages(g.plan, ["row_update"])
-    g.iterate()
-    torch.cuda.synchronize()
-    C.clamp_plan_set_timing(g.plan, False)
-    st = C.clamp_plan_get_timing(g.plan)
-    assert set(st) == {"row_update"} and st["row_update"][1] == 1 and st["row_update"][0] > 0.0
-    C.clamp_plan_set_timing(g.plan, True)
-    g.iterate()
-    C.clamp_plan_set_timing(g.plan, False)
-    st = C.clamp_plan_get_timing(g.plan)
-    assert {"col_inv", "row_grad", "col_fwd", "row_update", "mace_step", "prior_gauss"} <= set(st)
+    for fused, update in ((False, "row_update"), (True, "row_update_mann")):
+        g = G.ClampGPU(spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, 1e-3, with_prior=True, fused=fused)
+        g.init(to_gpu(y))
+        C.clamp_plan_set_timing_stages(g.plan, [update])
+        g.iterate()
+        torch.cuda.synchronize()
+        C.clamp_plan_set_timing(g.plan, False)
+        st = C.clamp_plan_get_timing(g.plan)
+        assert set(st) == {update} and st[update][1] == 1 and st[update][0] > 0.0
+        C.clamp_plan_set_timing(g.plan, True)
+        g.iterate()
+        C.clamp_plan_set_timing(g.plan, False)
+        st = C.clamp_plan_get_timing(g.plan)
+        assert {"col_inv", "row_grad", "col_fwd", update, "mace_step", "prior_gauss"} <= set(st)
     with pytest.raises(ValueError):
         C.clamp_plan_set_timing_stages(g.plan, ["no such stage"])

@@ -61,7 +61,9 @@ def test_batch_steps_match_single_scene_runs(G):
     torch.cuda.synchronize()
     assert int(b.fault.item()) == 0
     for i, (sp, y, s2, wp) in enumerate(probs):
-        g = G.ClampGPU(sp.nx, sp.ny, sp.nz, sp.looks, sp.radius, s2, 1e-3, with_prior=wp)
+        # the batch runs the Mann step as its own stage: compare with the
+        # single-scene calls in the same form
+        g = G.ClampGPU(sp.nx, sp.ny, sp.nz, sp.looks, sp.radius, s2, 1e-3, with_prior=wp, fused=False)
         g.init(torch.from_numpy(y).cuda())
         g.run(iters)
         torch.cuda.synchronize()
@@ -70,7 +72,9 @@ def test_batch_steps_match_single_scene_runs(G):
         assert report(tag + " w", rel_l2(st["w"].cpu().numpy(), g.w.cpu().numpy()), 1e-6) <= 1e-6
         assert report(tag + " mu", rel_l2(st["mu"].cpu().numpy(), g.mu.cpu().numpy()), 1e-6) <= 1e-6
         assert report(tag + " r", rel_l2(st["r"].cpu().numpy(), g.r.cpu().numpy()), 1e-6) <= 1e-6
-        assert abs(b.conv[i].item() - g.conv_err()) <= 1e-9 * max(1.0, g.conv_err())
+        # the batch's prior runs as three separable passes, the single-scene
+        # prior as one 3D pass: the same sums in another order
+        assert abs(b.conv[i].item() - g.conv_err()) <= 1e-6 * g.conv_err()
 
 
 def test_graph_replayed_batch_matches_oracle_on_every_scene(G):

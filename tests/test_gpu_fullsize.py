@@ -1,6 +1,7 @@
 """The full-size plain form (256x256x64, 16 looks, pupil radius 64, SNR 10 dB,
 forward agents + Gaussian prior + Mann step) against the float64 oracle after
-50 iterations of Alg. 2, in the launch configuration the benchmark times; the
+50 iterations of Alg. 2, in the launch configuration the benchmark times (the
+Mann step fused into the forward agents' update pass); the
 float32 drift of the residual recurrence over 100 iterations; and the
 residual refresh (resid = D(a) y - D(a) F mu) against the oracle."""
 
@@ -49,7 +50,7 @@ def test_full_size_50_iterations_match_oracle(capsys):
         mres.append(g.mu_residual())
     torch.cuda.synchronize()
     assert int(g.fault.item()) == 0
-    gpu = {"wbar": g.wbar.cpu().numpy(), "w": g.w.cpu().numpy(), "r": g.r.cpu().numpy(),
+    gpu = {"wbar": g.wbar.cpu().numpy(), "w": g.state_w().cpu().numpy(), "r": g.r.cpu().numpy(),
            "mu": g.mu.cpu().numpy()}
     del g
     torch.cuda.empty_cache()
