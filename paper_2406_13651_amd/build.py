@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libclamp.so")
-SOURCES = ["kernels.hip", "batch.hip", "range.hip", "cnn.hip", "unet.hip", "api.cpp", "cnn_api.cpp", "unet_api.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "range.hip", "regularizers.hip", "cnn.hip", "unet.hip", "api.cpp",
+           "cnn_api.cpp", "unet_api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
