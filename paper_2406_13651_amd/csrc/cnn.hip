@@ -636,19 +636,27 @@ __global__ __launch_bounds__(kCnnBlock) void k_loss_final(const double* part, in
 // A persistent grid walks work items (volume, 8 output rows x 32 x-voxels,
 // chunk of range slices).  Per range slice z the block holds in LDS, channel
 // major ("transposed", x contiguous): g of the 8 x 32 output tile, and act of
-// slices z - 1, z, z + 1 over 10 rows x 48 x (x0 - 8 .. x0 + 39, a one-voxel
-// halo padded to 16-byte alignment) in a ring of three slots.  Global data is
+// slices z - 1, z, z + 1 over 10 rows x 32 x-voxels (x0 .. x0 + 31) in a ring
+// of three slots, with the one-voxel x halo of each row and channel (voxels
+// x0 - 1 and x0 + 32) in a separate array [slot][row][side][channel], where
+// the 64 lanes of a wave read 64 consecutive dwords.  Global data is
 // channels-last; each fill unit loads 8 voxels x 8 channels and transposes
-// them in registers (byte permutes).  The dx = -1 and +1 operands come from
-// the aligned 8-voxel chunk and one neighbouring dword by byte alignment.
+// them in registers (byte permutes).
+// The MFMA's K = 16 voxels: lanes h = 0 and 1 of a channel take the x-voxels
+// x0 + 16 h .. x0 + 16 h + 15 over the two MFMAs of an output row (the K
+// index only has to agree between A and B).  The dx = -1 and +1 operands come
+// from the lane's two aligned 8-voxel chunks and one dword on either side:
+// the inner one from the other half of the wave (permlane32_swap), the outer
+// one from the halo array; no per-tap LDS dword read.
 // Wave (th, kh): taps 14 th .. 14 th + 13 (th = 0 also the bias), output rows
 // 4 kh .. 4 kh + 3.  Each wave writes its sums to part[2 block + kh][28][32][32]
 // (tap 27 = bias); k_wgrad_reduce adds the partial sums in a fixed order.
-// Channel planes are padded to an odd number of 16-byte chunks (61 and 33) so
-// that the 16 lanes of one 128-bit LDS phase hit distinct bank groups.
+// Channel planes are padded to an odd number of 16-byte chunks (41 and 33) so
+// that the lanes of one 128-bit LDS phase hit distinct bank groups.
 constexpr int kWgRows = 8;
-constexpr int kActPlane4 = 61;  // uint4 per channel plane of an act slot (10 x 48 bf16 + 8 pad)
+constexpr int kActPlane4 = 41;  // uint4 per channel plane of an act slot (10 x 32 bf16 + 8 pad)
 constexpr int kGPlane4 = 33;    // uint4 per channel plane of the g tile (8 x 32 bf16 + 8 pad)
+constexpr int kHaloSlot = 10 * 2 * 32;  // dwords of an act slot's halo array
 
 // 8 x 8 bf16 transpose: in[v][k] = dword k (channels 2k, 2k + 1) of voxel v;
 // out[c][p] = dword p (voxels 2p, 2p + 1) of channel c.
@@ -678,8 +686,29 @@ __device__ __forceinline__ void load8x8(const uint16_t* base, long vox0, int cg,
     }
 }
 
+// Operand of tap dx of an 8-voxel chunk c (voxels x .. x + 7): dx = 0 takes
+// x - 1 .. x + 6 (before: the dword holding x - 2, x - 1), dx = 2 takes
+// x + 1 .. x + 8 (after: the dword holding x + 8, x + 9).
+__device__ __forceinline__ uint4 shifted_chunk(uint4 c, uint32_t before, uint32_t after, int dx) {
+    if (dx == 1) return c;
+    uint4 q;
+    if (dx == 0) {
+        q.x = __builtin_amdgcn_alignbyte(c.x, before, 2);
+        q.y = __builtin_amdgcn_alignbyte(c.y, c.x, 2);
+        q.z = __builtin_amdgcn_alignbyte(c.z, c.y, 2);
+        q.w = __builtin_amdgcn_alignbyte(c.w, c.z, 2);
+    } else {
+        q.x = __builtin_amdgcn_alignbyte(c.y, c.x, 2);
+        q.y = __builtin_amdgcn_alignbyte(c.z, c.y, 2);
+        q.z = __builtin_amdgcn_alignbyte(c.w, c.z, 2);
+        q.w = __builtin_amdgcn_alignbyte(after, c.w, 2);
+    }
+    return q;
+}
+
 template <int TH, int CA, int CG>
-__device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 * kActPlane4], uint4* gt, int wave) {
+__device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 * kActPlane4],
+                                            uint32_t (*halo)[kHaloSlot], uint4* gt, int wave) {
     constexpr int T0 = 14 * TH;
     constexpr int NT = TH == 0 ? 14 : 13;
     const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5, kh = wave >> 1;
@@ -692,7 +721,8 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
 #pragma unroll
     for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
 
-    // fill-unit coordinates: act units 0..239 on threads 0..239, g units on threads 128..255
+    // fill-unit coordinates: act units 0..239 on threads 0..239 (chunk a_xc of
+    // a row: 0 and 5 are the halo chunks), g units on threads 128..255
     const int a_xc = u % 6, a_ys = (u / 6) % 10, a_cg = u / 60;
     const int gu = u - 128, g_xc = gu & 3, g_r = (gu >> 2) & 7, g_cg = gu >> 5;
     uint32_t pa[8][4], pg[8][4], tr[8][4];
@@ -722,10 +752,18 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
         auto store_act = [&](int zin) {
             if (u < 240) {
                 transpose8(pa, tr);
-                uint4* slot = act[(zin + 3) % 3];
+                const int s = (zin + 3) % 3;
+                if (a_xc == 0 || a_xc == 5) {  // keep the dword next to the tile: x0 - 2, x0 - 1 or x0 + 32, x0 + 33
+                    uint32_t* hs = halo[s] + (a_ys * 2 + (a_xc == 5 ? 1 : 0)) * 32 + a_cg * 8;
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    slot[(a_cg * 8 + k) * kActPlane4 + a_ys * 6 + a_xc] = make_uint4(tr[k][0], tr[k][1], tr[k][2], tr[k][3]);
+                    for (int k = 0; k < 8; ++k) hs[k] = a_xc == 0 ? tr[k][3] : tr[k][0];
+                } else {
+                    uint4* slot = act[s];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        slot[(a_cg * 8 + k) * kActPlane4 + a_ys * 4 + a_xc - 1] =
+                            make_uint4(tr[k][0], tr[k][1], tr[k][2], tr[k][3]);
+                }
             }
         };
         auto store_g = [&]() {
@@ -754,46 +792,39 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
                 fetch_act(z + 2);
                 fetch_g(z + 1);
             }
-            const uint32_t* act32[3];
-#pragma unroll
-            for (int dz = 0; dz < 3; ++dz) act32[dz] = reinterpret_cast<const uint32_t*>(act[(z + dz + 2) % 3]);
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
                 const int r = 4 * kh + rr;
+                // A of the row's two MFMAs: g at x0 + 16 h .. + 7 and x0 + 16 h + 8 .. + 15
+                const v8bf A0 = __builtin_bit_cast(v8bf, gt[m * kGPlane4 + r * 4 + 2 * h]);
+                const v8bf A1 = __builtin_bit_cast(v8bf, gt[m * kGPlane4 + r * 4 + 2 * h + 1]);
+                if constexpr (TH == 0) {
+                    accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, ones, accb, 0, 0, 0);
+                    accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, ones, accb, 0, 0, 0);
+                }
 #pragma unroll
-                for (int xh = 0; xh < 2; ++xh) {
-                    const v8bf A = __builtin_bit_cast(v8bf, gt[m * kGPlane4 + r * 4 + 2 * xh + h]);
-                    if constexpr (TH == 0) accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, ones, accb, 0, 0, 0);
+                for (int pair = 0; pair < 9; ++pair) {
+                    const int t_lo = pair * 3;
+                    if (t_lo + 2 < T0 || t_lo >= T0 + NT) continue;  // no tap of this wave
+                    const int dz = pair / 3, dy = pair % 3, s = (z + dz + 2) % 3;
+                    const uint4* row = act[s] + m * kActPlane4 + (r + dy) * 4 + 2 * h;
+                    const uint4 c0 = row[0], c1 = row[1];
+                    const uint32_t hw = halo[s][(r + dy) * 64 + lane];
+                    // lanes h = 0 need the upper half's c0.x (x0 + 16, 17); lanes h = 1 the lower half's c1.w (x0 + 14, 15)
+                    const uint32_t v = h ? c0.x : c1.w;
+                    const auto sw = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+                    const uint32_t inner = h ? sw[0] : sw[1];
+                    const uint32_t before = h ? inner : hw, after = h ? hw : inner;
 #pragma unroll
-                    for (int pair = 0; pair < 9; ++pair) {
-                        const int t_lo = pair * 3;
-                        if (t_lo + 2 < T0 || t_lo >= T0 + NT) continue;  // no tap of this wave
-                        const int dz = pair / 3, dy = pair % 3;
-                        const uint32_t* pl = act32[dz] + m * (kActPlane4 * 4) + (r + dy) * 24;
-                        const uint4 c4 = *reinterpret_cast<const uint4*>(pl + 4 + 8 * xh + 4 * h);
-#pragma unroll
-                        for (int dx = 0; dx < 3; ++dx) {
-                            const int t = t_lo + dx;
-                            if (t < T0 || t >= T0 + NT) continue;
-                            uint4 bq;
-                            if (dx == 1) {
-                                bq = c4;
-                            } else if (dx == 0) {  // voxels x - 1 .. x + 6
-                                const uint32_t dlo = pl[3 + 8 * xh + 4 * h];
-                                bq.x = __builtin_amdgcn_alignbyte(c4.x, dlo, 2);
-                                bq.y = __builtin_amdgcn_alignbyte(c4.y, c4.x, 2);
-                                bq.z = __builtin_amdgcn_alignbyte(c4.z, c4.y, 2);
-                                bq.w = __builtin_amdgcn_alignbyte(c4.w, c4.z, 2);
-                            } else {  // voxels x + 1 .. x + 8
-                                const uint32_t dhi = pl[8 + 8 * xh + 4 * h];
-                                bq.x = __builtin_amdgcn_alignbyte(c4.y, c4.x, 2);
-                                bq.y = __builtin_amdgcn_alignbyte(c4.z, c4.y, 2);
-                                bq.z = __builtin_amdgcn_alignbyte(c4.w, c4.z, 2);
-                                bq.w = __builtin_amdgcn_alignbyte(dhi, c4.w, 2);
-                            }
-                            acc[t - T0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, __builtin_bit_cast(v8bf, bq),
-                                                                                   acc[t - T0], 0, 0, 0);
-                        }
+                    for (int dx = 0; dx < 3; ++dx) {
+                        const int t = t_lo + dx;
+                        if (t < T0 || t >= T0 + NT) continue;
+                        const uint4 b0 = shifted_chunk(c0, before, c1.x, dx);
+                        const uint4 b1 = shifted_chunk(c1, c0.w, after, dx);
+                        acc[t - T0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, __builtin_bit_cast(v8bf, b0),
+                                                                               acc[t - T0], 0, 0, 0);
+                        acc[t - T0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, __builtin_bit_cast(v8bf, b1),
+                                                                               acc[t - T0], 0, 0, 0);
                     }
                 }
             }
@@ -820,10 +851,11 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
 template <int CA, int CG>
 __global__ __launch_bounds__(kCnnBlock, 1) void k_wgrad(WgradArgs a) {
     __shared__ uint4 act[3][32 * kActPlane4];
+    __shared__ uint32_t halo[3][kHaloSlot];
     __shared__ uint4 gt[32 * kGPlane4];
     const int wave = threadIdx.x >> 6;
-    if (wave & 1) wgrad_block<1, CA, CG>(a, act, gt, wave);
-    else wgrad_block<0, CA, CG>(a, act, gt, wave);
+    if (wave & 1) wgrad_block<1, CA, CG>(a, act, halo, gt, wave);
+    else wgrad_block<0, CA, CG>(a, act, halo, gt, wave);
 }
 
 // gw[(t * cin + ci) * cout + co] = sum over chunks of part[c][t][co][ci] and

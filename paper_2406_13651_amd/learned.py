@@ -5,12 +5,17 @@ Training (Sec. III-C trains its prior as an image denoiser on volumes with
 10% additive white Gaussian noise, MSE loss, Adam, batch 24, learning rate
 decayed by 0.975 every 300 batches, weights kept at the lowest validation
 loss).  Here the clean volumes are seeded facet scenes r of the synthetic
-recipe instead of rendered models; the default input is r plus white
-Gaussian noise of standard deviation U[0, 0.1] max(r), and the alternative
-("speckle") input is the speckle average (1/L) sum_l |A^H y_l|^2 of L
-simulated looks, computed by the library's own initialisation pass.  Inputs
-and targets are scaled to unit mean, and as a prior agent the network runs in
-the scale-free form H(w) = w + m N(w / m) with m = mean(w).
+recipe instead of rendered models.  The default input comes from the
+forward model itself: L looks of r are simulated on the GPU through the
+library's aperture operator (speckle and noise drawn there), and the input
+is their speckle average (1/L) sum_l |A^H y_l|^2, the initial image of Alg. 2
+("speckle").  "clamp" takes instead the consensus image of a
+forward-agents-only CLAMP run on such looks after k iterations, k drawn from
+{0, 2, 5, 10, 20, 40} (k = 0 is the speckle average) -- the kind of image the
+prior agent is handed inside the loop; "awgn" follows the paper's recipe:
+r plus white Gaussian noise of standard deviation U[0, 0.1] max(r).  Inputs and targets are scaled to unit mean, and as
+a prior agent the network runs in the scale-free form H(w) = w + m N(w / m)
+with m = mean(w).
 
 Fallback: the forward-model-only reconstruction (forward agents alone)
 replaces the learned form's result when the learned run raises a fault,
@@ -149,35 +154,63 @@ def unet_init_params(seed=0, last_scale=0.0, width=32, levels=3):
     return np.concatenate(parts).astype(np.float32)
 
 
-def make_pairs(n, seed=0, nz=32, ny=64, nx=64, looks=(4, 8, 16), snr_db=10.0, mode="awgn", noise=0.1,
-               device="cuda", workers=16):
+CLAMP_PAIR_ITERS = (0, 2, 5, 10, 20, 40)
+
+
+def simulate_looks(g, r, s2, gen):
+    """L looks y_l = A (sqrt(r) z_l) + eta_l (eq. forward-model) of the float32
+    GPU volume r, simulated on the GPU through the library's aperture operator
+    of g (a ClampGPU whose plan has L looks): speckle z_l ~ CN(0, I) (eq.
+    g-given-r) and noise eta_l ~ CN(0, s2 I), drawn from the CUDA generator
+    gen.  Returns complex64 [L, nz, ny, nx]."""
+    L = g.L
+    shape = (L,) + tuple(r.shape)
+    field = torch.randn(shape, dtype=torch.complex64, device=r.device, generator=gen)
+    field *= torch.sqrt(r)
+    y = torch.empty_like(field)
+    C.clamp_aperture_op(g.plan, 0, C.CLAMP_FWD, field, y, L, g.ws)
+    y += math.sqrt(s2) * torch.randn(shape, dtype=torch.complex64, device=r.device, generator=gen)
+    return y
+
+
+def make_pairs(n, seed=0, nz=32, ny=64, nx=64, looks=(4, 8, 16), snr_db=10.0, mode="speckle", noise=0.1,
+               device="cuda", sigma2=1e-3):
     """Training pairs (inputs, targets) as float32 [n, nz, ny, nx] GPU tensors,
-    both scaled to unit mean.  mode "speckle": the input is the speckle
-    average of L simulated looks; mode "awgn": the input is the target plus
+    both scaled to unit mean.  The targets are seeded facet scenes (drawn on
+    the host).  mode "speckle": the input is the speckle average of L looks
+    that the forward model simulates on the GPU; "clamp": the consensus image
+    of a forward-agents-only CLAMP run (proximal parameter sigma2) on such
+    looks after CLAMP_PAIR_ITERS[i % 6] iterations; "awgn": the target plus
     white Gaussian noise of standard deviation U[0, noise] max(target)."""
     import synth
     X = torch.empty((n, nz, ny, nx), dtype=torch.float32, device=device)
     T = torch.empty_like(X)
     gpus = {}
     rng = np.random.Generator(np.random.PCG64(seed))
+    gen = None
+    if mode in ("speckle", "clamp"):
+        gen = torch.Generator(device=device)
+        gen.manual_seed(2406_13651 + seed)
     for i in range(n):
         L = int(looks[i % len(looks)])
         facets = int(rng.integers(8, 33))
         spec = synth.SceneSpec("train%d" % i, nx, ny, nz, L, nx / 4.0, snr_db, facets, 0.05, 1, 5)
-        if mode == "speckle":
-            r, y, s2 = synth.make_problem(spec, seed * 100_000 + i, workers=workers)
+        r = synth.facet_scene(spec, np.random.Generator(np.random.PCG64(synth.seed_sequence(5, seed * 100_000 + i))))
+        t = r / r.mean()
+        if mode in ("speckle", "clamp"):
+            s2 = synth.noise_variance(r, snr_db)
             if L not in gpus:
-                gpus[L] = ClampGPU(nx, ny, nz, L, nx / 4.0, s2, 1e-3, with_prior=False, device=device)
+                gpus[L] = ClampGPU(nx, ny, nz, L, nx / 4.0, s2, sigma2, with_prior=False, device=device)
             g = gpus[L]
             g.sigma_w2 = s2
-            g.init(torch.from_numpy(y).to(device))
-            sa = g.r[0]
-            X[i] = sa / sa.mean()
             rt = torch.from_numpy(r.astype(np.float32)).to(device)
+            g.init(simulate_looks(g, rt, s2, gen))
+            k = CLAMP_PAIR_ITERS[i % len(CLAMP_PAIR_ITERS)] if mode == "clamp" else 0
+            g.run(k)
+            img = g.wbar if k > 0 else g.r[0]
+            X[i] = img / img.mean()
             T[i] = rt / rt.mean()
         else:
-            r = synth.facet_scene(spec, np.random.Generator(np.random.PCG64(synth.seed_sequence(5, seed * 100_000 + i))))
-            t = r / r.mean()
             sd = rng.uniform(0.0, noise) * t.max()
             x = t + sd * rng.standard_normal(t.shape)
             X[i] = torch.from_numpy(x.astype(np.float32)).to(device)

@@ -37,6 +37,41 @@ def trained(env):
     return prior
 
 
+def test_simulated_looks_have_the_forward_model_statistics(env):
+    """Looks simulated on the GPU for the training pairs follow eqs.
+    forward-model and g-given-r: with an orthonormal DFT, a pupil sample of
+    slice z has E|y|^2 = mean_xy(r[z]) + sigma^2 and a sample outside the
+    pupil E|y|^2 = sigma^2; the per-slice sample means agree within 5
+    standard errors (|y|^2 is exponential, so its standard deviation equals
+    its mean)."""
+    import paper_2406_13651_amd as G
+    import synth
+    import oracle
+    torch, Lm = env["torch"], env["Lm"]
+    nx, ny, nz, L = 64, 64, 16, 12
+    spec = synth.SceneSpec("sim", nx, ny, nz, L, 16.0, 10.0, 12, 0.05, 1, 6)
+    r = synth.facet_scene(spec, np.random.Generator(np.random.PCG64(7)))
+    s2 = synth.noise_variance(r, spec.snr_db)
+    g = G.ClampGPU(nx, ny, nz, L, spec.radius, s2, 1e-3, with_prior=False)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    y = Lm.simulate_looks(g, torch.from_numpy(r.astype(np.float32)).cuda(), s2, gen)
+    p2 = (y.abs() ** 2).double().cpu().numpy()          # [L, nz, ny, nx]
+    mask = oracle.pupil_mask(ny, nx, spec.radius)
+    n_in, n_out = int(mask.sum()) * L, int((~mask).sum()) * L
+    for z in range(nz):
+        want_in = float(r[z].mean()) + s2
+        got_in = float(p2[:, z][:, mask].mean())
+        assert abs(got_in - want_in) <= 5 * want_in / math.sqrt(n_in), (z, got_in, want_in)
+        got_out = float(p2[:, z][:, ~mask].mean())
+        assert abs(got_out - s2) <= 5 * s2 / math.sqrt(n_out), (z, got_out, s2)
+    # the speckle average the pairs feed the network is A^H y's mean power
+    g.init(y)
+    sa = oracle.speckle_average(y.cpu().numpy(), mask)
+    err = float(np.linalg.norm(g.r[0].cpu().numpy() - sa) / np.linalg.norm(sa))
+    assert err < 1e-5, err
+
+
 def _trace(g, env, iters):
     torch, Lm = env["torch"], env["Lm"]
     g.init(env["yt"])
