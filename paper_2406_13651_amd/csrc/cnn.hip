@@ -648,12 +648,16 @@ __global__ __launch_bounds__(kCnnBlock) void k_loss_final(const double* part, in
 // from the lane's two aligned 8-voxel chunks and one dword on either side:
 // the inner one from the other half of the wave (permlane32_swap), the outer
 // one from the halo array; no per-tap LDS dword read.
-// Wave (th, kh): taps 14 th .. 14 th + 13 (th = 0 also the bias), output rows
-// 4 kh .. 4 kh + 3.  Each wave writes its sums to part[2 block + kh][28][32][32]
-// (tap 27 = bias); k_wgrad_reduce adds the partial sums in a fixed order.
+// Eight waves per block, two per SIMD (each holds 7 accumulator tiles, 112
+// AGPRs), so that one wave's LDS waits, fills and barriers overlap the other's
+// MFMAs.  Wave (tg, kh): taps 7 tg .. 7 tg + 6 (tg = 3: taps 21 .. 26 and the
+// bias), output rows 4 kh .. 4 kh + 3.  Each wave writes its sums to
+// part[2 block + kh][28][32][32] (tap 27 = bias); k_wgrad_reduce adds the
+// partial sums in a fixed order.
 // Channel planes are padded to an odd number of 16-byte chunks (41 and 33) so
 // that the lanes of one 128-bit LDS phase hit distinct bank groups.
 constexpr int kWgRows = 8;
+constexpr int kWgBlock = 512;
 constexpr int kActPlane4 = 41;  // uint4 per channel plane of an act slot (10 x 32 bf16 + 8 pad)
 constexpr int kGPlane4 = 33;    // uint4 per channel plane of the g tile (8 x 32 bf16 + 8 pad)
 constexpr int kHaloSlot = 10 * 2 * 32;  // dwords of an act slot's halo array
@@ -706,12 +710,13 @@ __device__ __forceinline__ uint4 shifted_chunk(uint4 c, uint32_t before, uint32_
     return q;
 }
 
-template <int TH, int CA, int CG>
+template <int TG, int CA, int CG>
 __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 * kActPlane4],
                                             uint32_t (*halo)[kHaloSlot], uint4* gt, int wave) {
-    constexpr int T0 = 14 * TH;
-    constexpr int NT = TH == 0 ? 14 : 13;
-    const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5, kh = wave >> 1;
+    constexpr int T0 = 7 * TG;
+    constexpr int NT = TG == 3 ? 6 : 7;
+    constexpr bool BIAS = TG == 3;
+    const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5, kh = wave & 1;
     const int u = threadIdx.x;
     v16f acc[NT];
     v16f accb = {};
@@ -722,10 +727,12 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
     for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
 
     // fill-unit coordinates: act units 0..239 on threads 0..239 (chunk a_xc of
-    // a row: 0 and 5 are the halo chunks), g units on threads 128..255
+    // a row: 0 and 5 are the halo chunks), g units 0..127 on threads 256..383;
+    // the role is uniform per wave, and one prefetch buffer serves both
+    const bool act_role = u < 256;
     const int a_xc = u % 6, a_ys = (u / 6) % 10, a_cg = u / 60;
-    const int gu = u - 128, g_xc = gu & 3, g_r = (gu >> 2) & 7, g_cg = gu >> 5;
-    uint32_t pa[8][4], pg[8][4], tr[8][4];
+    const int gu = u - 256, g_xc = gu & 3, g_r = (gu >> 2) & 7, g_cg = gu >> 5;
+    uint32_t pf[8][4], tr[8][4];
 
     for (int item = blockIdx.x; item < a.items; item += gridDim.x) {
         int b = item;
@@ -742,16 +749,16 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
         auto fetch_act = [&](int zin) {
             const int y = y0 - 1 + a_ys, x = x0 - 8 + 8 * a_xc;
             const bool ok = u < 240 && zin >= 0 && zin < a.nz && y >= 0 && y < a.ny && x >= 0 && x < a.nx;
-            load8x8<CA>(a.act, ok ? vol_off + ((long)zin * a.ny + y) * a.nx + x : 0, a_cg, ok, pa);
+            load8x8<CA>(a.act, ok ? vol_off + ((long)zin * a.ny + y) * a.nx + x : 0, a_cg, ok, pf);
         };
         auto fetch_g = [&](int zz) {
             const int y = y0 + g_r, x = x0 + 8 * g_xc;
-            const bool ok = gu >= 0 && zz < a.nz && y < a.ny;
-            load8x8<CG>(a.g, ok ? vol_off + ((long)zz * a.ny + y) * a.nx + x : 0, g_cg, ok, pg);
+            const bool ok = gu >= 0 && gu < 128 && zz < a.nz && y < a.ny;
+            load8x8<CG>(a.g, ok ? vol_off + ((long)zz * a.ny + y) * a.nx + x : 0, g_cg, ok, pf);
         };
         auto store_act = [&](int zin) {
             if (u < 240) {
-                transpose8(pa, tr);
+                transpose8(pf, tr);
                 const int s = (zin + 3) % 3;
                 if (a_xc == 0 || a_xc == 5) {  // keep the dword next to the tile: x0 - 2, x0 - 1 or x0 + 32, x0 + 33
                     uint32_t* hs = halo[s] + (a_ys * 2 + (a_xc == 5 ? 1 : 0)) * 32 + a_cg * 8;
@@ -767,8 +774,8 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
             }
         };
         auto store_g = [&]() {
-            if (gu >= 0) {
-                transpose8(pg, tr);
+            if (gu >= 0 && gu < 128) {
+                transpose8(pf, tr);
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
                     gt[(g_cg * 8 + k) * kGPlane4 + g_r * 4 + g_xc] = make_uint4(tr[k][0], tr[k][1], tr[k][2], tr[k][3]);
@@ -776,21 +783,24 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
         };
 
         __syncthreads();  // the previous item's reads are done
-        fetch_act(z0 - 1);
-        store_act(z0 - 1);
-        fetch_act(z0);
-        store_act(z0);
-        fetch_act(z0 + 1);
-        store_act(z0 + 1);
-        fetch_g(z0);
-        store_g();
+        if (act_role) {
+            fetch_act(z0 - 1);
+            store_act(z0 - 1);
+            fetch_act(z0);
+            store_act(z0);
+            fetch_act(z0 + 1);
+            store_act(z0 + 1);
+        } else {
+            fetch_g(z0);
+            store_g();
+        }
         __syncthreads();
 
         for (int z = z0; z < z1; ++z) {
             const bool next = z + 1 < z1;
             if (next) {
-                fetch_act(z + 2);
-                fetch_g(z + 1);
+                if (act_role) fetch_act(z + 2);
+                else fetch_g(z + 1);
             }
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
@@ -798,7 +808,7 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
                 // A of the row's two MFMAs: g at x0 + 16 h .. + 7 and x0 + 16 h + 8 .. + 15
                 const v8bf A0 = __builtin_bit_cast(v8bf, gt[m * kGPlane4 + r * 4 + 2 * h]);
                 const v8bf A1 = __builtin_bit_cast(v8bf, gt[m * kGPlane4 + r * 4 + 2 * h + 1]);
-                if constexpr (TH == 0) {
+                if constexpr (BIAS) {
                     accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, ones, accb, 0, 0, 0);
                     accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, ones, accb, 0, 0, 0);
                 }
@@ -830,8 +840,8 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
             }
             if (next) {
                 __syncthreads();  // every wave is done with act slice z - 1 and g slice z
-                store_act(z + 2);
-                store_g();
+                if (act_role) store_act(z + 2);
+                else store_g();
                 __syncthreads();
             }
         }
@@ -842,20 +852,24 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int i = 0; i < 16; ++i) dst[(T0 + t) * 1024 + d_row(lane, i) * 32 + m] = acc[t][i];
-    if constexpr (TH == 0) {
+    if constexpr (BIAS) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) dst[27 * 1024 + d_row(lane, i) * 32 + m] = accb[i];
     }
 }
 
 template <int CA, int CG>
-__global__ __launch_bounds__(kCnnBlock, 1) void k_wgrad(WgradArgs a) {
+__global__ __launch_bounds__(kWgBlock, 1) void k_wgrad(WgradArgs a) {
     __shared__ uint4 act[3][32 * kActPlane4];
     __shared__ uint32_t halo[3][kHaloSlot];
     __shared__ uint4 gt[32 * kGPlane4];
     const int wave = threadIdx.x >> 6;
-    if (wave & 1) wgrad_block<1, CA, CG>(a, act, halo, gt, wave);
-    else wgrad_block<0, CA, CG>(a, act, halo, gt, wave);
+    switch (wave >> 1) {
+        case 0: wgrad_block<0, CA, CG>(a, act, halo, gt, wave); break;
+        case 1: wgrad_block<1, CA, CG>(a, act, halo, gt, wave); break;
+        case 2: wgrad_block<2, CA, CG>(a, act, halo, gt, wave); break;
+        default: wgrad_block<3, CA, CG>(a, act, halo, gt, wave); break;
+    }
 }
 
 // gw[(t * cin + ci) * cout + co] = sum over chunks of part[c][t][co][ci] and
@@ -1093,7 +1107,7 @@ hipError_t cnn_wgrad(int ca, int cg, WgradArgs a, int cin, int cout, float* gw, 
     if (items >= (1L << 31)) return hipErrorInvalidValue;
     a.items = (int)items;
     const int grid = (int)(items < grid_max ? items : grid_max);
-#define LAUNCH(A, G) hipLaunchKernelGGL((k_wgrad<A, G>), dim3(grid), dim3(kCnnBlock), 0, st, a)
+#define LAUNCH(A, G) hipLaunchKernelGGL((k_wgrad<A, G>), dim3(grid), dim3(kWgBlock), 0, st, a)
     if (ca == 8 && cg == 32) LAUNCH(8, 32);
     else if (ca == 32 && cg == 32) LAUNCH(32, 32);
     else if (ca == 32 && cg == 8) LAUNCH(32, 8);

@@ -33,8 +33,8 @@ def stage_bytes(nx, ny, nz, looks, P, B, n_agents, K=0, fused=False):
         "row_update": L * nz * (band + ny * nx * (8 + 4 + 4 + 8 + 4)),
         # resid and D(a) F d in, resid out
         "resid_update": L * (K if K > 0 else nz) * P * 24,
-        # three separable passes, each float32 in and out
-        "prior_gauss": 3 * n * 8,
+        # one pass over the volume: float32 in and out
+        "prior_gauss": n * 8,
         # every agent's w and r in, w out, and w_bar out
         "mace_step": n * (12 * n_agents + 4),
     }
