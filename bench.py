@@ -241,8 +241,10 @@ def run_batch(args):
     sb = {}
     for i, sp in enumerate(specs):
         info = b.plan.info[i]
-        for k, v in stage_bytes(sp.nx, sp.ny, sp.nz, sp.looks, info["P"], info["B"], sp.looks + 1).items():
+        for k, v in stage_bytes(sp.nx, sp.ny, sp.nz, sp.looks, info["P"], info["B"], sp.looks + 1,
+                                fused=b.fused).items():
             sb[k] = sb.get(k, 0) + v
+    fused_form = b.fused
     del b
     torch.cuda.empty_cache()
     # the same scenes through the single-scene driver (the update pass with
@@ -291,13 +293,14 @@ def run_batch(args):
         "config": {"workload": "batch of %d uneven scenes (N in {128,192,256,384,512}, nz in {32,64,128}, "
                                "4-32 looks, R = N/4, SNR 10 dB), %.3g voxel-looks per iteration, one graph "
                                "replay per CLAMP iteration" % (len(specs), total),
+                   "mann_step": "fused into the update pass" if fused_form else "a pass of its own",
                    "scenes": [[sp.nx, sp.nz, sp.looks] for sp in specs], "sigma2": args.sigma2},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
         "per_scene_launch": {"ms_per_step": round(per_scene_ms, 3),
                              "voxel_looks_per_s": total / (per_scene_ms * 1e-3),
-                             "what": "the batch's iteration through the single-scene calls (agents, prior, "
-                                     "Mann step), scene after scene"},
+                             "what": "the batch's iteration through the single-scene calls of the same form, "
+                                     "scene after scene, on the batch's state"},
         "per_scene_fused": {"ms_per_step": round(fused_ms, 3), "voxel_looks_per_s": total / (fused_ms * 1e-3),
                             "what": "single-scene drivers with the Mann step fused into the update pass, "
                                     "scene after scene"},

@@ -322,7 +322,17 @@ clamp_status clamp_mace_step_noalloc(const clamp_plan* plan, int32_t scene,
 typedef struct clamp_batch clamp_batch;
 
 /* One scene of a batch (device pointers, caller-owned; the same arrays the
- * single-scene calls take).  params.beta is ignored (see above). */
+ * single-scene calls take).  params.beta is ignored (see above).
+ * xbar selects the form of the Mann step for the whole batch (every scene
+ * has one, or none does; CLAMP_EINVAL otherwise):
+ *   NULL      the Mann step as its own pass after the prior agents
+ *             (clamp_fwd_agent, clamp_prior_gauss, clamp_mace_step);
+ *   non-NULL  float32 [n]: the Mann step fused into the update pass, with w
+ *             and xbar in clamp_fwd_agent_mace's representation (zeros in
+ *             xbar after clamp_fwd_init; w_bar = r0 then) and the prior
+ *             agents applied first (clamp_prior_gauss, clamp_fwd_agent_mace).
+ * A scene with a prior (n_agents = L + 1) needs ny a multiple of 8 and nx of
+ * 32 (CLAMP_EUNSUPPORTED otherwise). */
 typedef struct {
     clamp_params params;    /* n_agents = L or L + 1, at most 40 in a batch;  */
                             /* r_update CLAMP_R_QUADRATIC (else EUNSUPPORTED) */
@@ -331,6 +341,7 @@ typedef struct {
     float* wbar;            /* float32 [n]                                    */
     double* diag;           /* double [L + 1][8], as clamp_fwd_agent          */
     float prior_sigma;      /* Gaussian prior width when n_agents = L + 1     */
+    float* xbar;            /* NULL, or float32 [n] (see above)               */
 } clamp_batch_scene;
 
 /* Workspace bytes of a batch over every scene of the plan (the scenes'
@@ -350,7 +361,8 @@ clamp_status clamp_batch_destroy(clamp_batch* batch);
 clamp_status clamp_batch_set_iteration(clamp_batch* batch, int32_t done, void* hip_stream);
 
 /* One CLAMP iteration of every scene: forward agents, prior agents of the
- * scenes that have one, Mann step, then the counter advances. */
+ * scenes that have one, Mann step, then the counter advances (with xbar:
+ * prior agents, then the forward agents with the Mann step fused in). */
 clamp_status clamp_batch_step(clamp_batch* batch, void* hip_stream);
 
 /* Grid sizes of the row and column passes in blocks per compute unit, each

@@ -71,7 +71,8 @@ class clamp_fwd_state(ctypes.Structure):
 
 class clamp_batch_scene(ctypes.Structure):
     _fields_ = [("params", clamp_params), ("state", clamp_fwd_state), ("w", ctypes.c_void_p),
-                ("wbar", ctypes.c_void_p), ("diag", ctypes.c_void_p), ("prior_sigma", ctypes.c_float)]
+                ("wbar", ctypes.c_void_p), ("diag", ctypes.c_void_p), ("prior_sigma", ctypes.c_float),
+                ("xbar", ctypes.c_void_p)]
 
 
 def _load():
@@ -434,7 +435,8 @@ class Batch:
 
 def clamp_batch_create(plan, scenes, fault, conv_err, workspace):
     """scenes: list of dicts with params (clamp_params), mu, resid, r, w, wbar,
-    diag (tensors), prior_sigma and optional ahy2 (tensor)."""
+    diag (tensors), prior_sigma and optional ahy2 and xbar (tensors; xbar on
+    every scene selects the fused Mann step)."""
     arr = (clamp_batch_scene * len(scenes))()
     for i, sc in enumerate(scenes):
         s = plan.scenes[i]
@@ -446,6 +448,8 @@ def clamp_batch_create(plan, scenes, fault, conv_err, workspace):
         arr[i].wbar = _ptr(sc["wbar"], torch.float32, s.n, "wbar").value
         arr[i].diag = _ptr(sc["diag"], torch.float64, (s.looks + 1) * DIAG, "diag").value
         arr[i].prior_sigma = float(sc.get("prior_sigma", 1.0))
+        xb = sc.get("xbar")
+        arr[i].xbar = None if xb is None else _ptr(xb, torch.float32, s.n, "xbar").value
     h = ctypes.c_void_p()
     _check(lib.clamp_batch_create(plan.handle, arr, _ptr(fault, torch.int32, 1, "fault"),
                                   _ptr(conv_err, torch.float64, len(scenes), "conv_err"),

@@ -181,14 +181,18 @@ class ClampGPU:
 
 class ClampBatchGPU:
     """Many CLAMP reconstructions of uneven size advanced together: each
-    iteration is one batched step (persistent launches over work queues of
-    every scene), optionally replayed from a captured HIP graph."""
+    iteration is one batched step (launches over work queues of every scene,
+    one per stage and FFT length), optionally replayed from a captured HIP
+    graph."""
 
-    def __init__(self, scenes, device="cuda"):
+    def __init__(self, scenes, device="cuda", fused=True):
         """scenes: list of dicts with nx, ny, nz, looks, radius, sigma_w2,
         sigma2 and optional with_prior (default True), rho, mu_scale,
-        prior_sigma."""
+        prior_sigma.  fused: the Mann step inside the update pass, with each
+        scene's w in clamp_fwd_agent_mace's representation (state_w(i) writes
+        it out); otherwise a pass of its own."""
         self.dev = torch.device(device)
+        self.fused = bool(fused)
         self.specs = [dict(sc) for sc in scenes]
         self.plan = C.clamp_plan_create([C.Scene(sc["nx"], sc["ny"], sc["nz"], sc["looks"], sc["radius"], None,
                                                  sc.get("range_support", 0)) for sc in scenes])
@@ -216,6 +220,8 @@ class ClampBatchGPU:
                 "ahy2": torch.zeros(L, dtype=torch.float64, **f),
                 "prior_sigma": float(sc.get("prior_sigma", 1.0)),
             }
+            if self.fused:
+                st["xbar"] = torch.zeros(shape, dtype=torch.float32, **f)
             st["params"] = C.make_params(sc["sigma_w2"], sc["sigma2"], sc.get("rho", 0.5), 2.0,
                                          sc.get("mu_scale", 1.0), st["ups"], sc.get("r_update", "quadratic"))
             self.states.append(st)
@@ -233,6 +239,10 @@ class ClampBatchGPU:
         st = self.states[i]
         C.clamp_fwd_init(self.plan, i, st["params"], y, st["mu"], st["resid"], st["r"], st["w"], self.ws,
                          ahy2=st["ahy2"])
+        if self.fused:
+            # every agent's w starts at r0: x_bar = 0 makes u_l = w_l
+            st["xbar"].zero_()
+            st["wbar"].copy_(st["w"][0])
 
     def restart(self):
         """Iteration counter and fault word back to zero (after init_scene calls)."""
@@ -249,13 +259,30 @@ class ClampBatchGPU:
             p = C.make_params(self.specs[i]["sigma_w2"], self.specs[i]["sigma2"], self.specs[i].get("rho", 0.5),
                               beta, self.specs[i].get("mu_scale", 1.0), st["ups"],
                               self.specs[i].get("r_update", "quadratic"))
+            L = self.specs[i]["looks"]
+            if self.fused:
+                if st["with_prior"]:
+                    C.clamp_prior_gauss(self.plan, i, st["prior_sigma"], st["w"][L], st["r"][L], self.ws)
+                C.clamp_fwd_agent_mace(self.plan, i, p, st["mu"], st["resid"], st["r"], st["w"], st["xbar"],
+                                       st["wbar"], st["diag"], self.conv[i:i + 1], self.fault, self.ws,
+                                       ahy2=st["ahy2"])
+                continue
             C.clamp_fwd_agent(self.plan, i, p, st["mu"], st["resid"], st["r"], st["w"], st["diag"], self.fault,
                               self.ws, ahy2=st["ahy2"])
-            L = self.specs[i]["looks"]
             if st["with_prior"]:
                 C.clamp_prior_gauss(self.plan, i, st["prior_sigma"], st["w"][L], st["r"][L], self.ws)
             C.clamp_mace_step(self.plan, i, p, st["w"], st["r"], st["wbar"], self.conv[i:i + 1], self.ws)
         C.clamp_batch_set_iteration(self.batch, self.k)
+
+    def state_w(self, i):
+        """Scene i's Mann state w [N, nz, ny, nx] (written out from the fused
+        representation by the library)."""
+        st = self.states[i]
+        if not self.fused:
+            return st["w"]
+        out = torch.empty_like(st["w"])
+        C.clamp_mace_state(self.plan, i, st["params"], st["w"], st["xbar"], out)
+        return out
 
     def step(self, stream=None):
         C.clamp_batch_step(self.batch, stream)

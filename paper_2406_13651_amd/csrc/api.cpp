@@ -62,7 +62,7 @@ bool size_supported(int n) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t T, T2, dfd, prow, pcf, pci, pupd, pres, pmace, scal, cnt, g0, g1, tvp, pl21;
+    size_t T, T2, dfd, prow, pcf, pci, pupd, pres, pmace, scal, cnt, tvu, tvp, pl21;
     size_t dfdb, pzi, pzf;  // 3D operator: box data [L][K][P], range-pass partial sums
     size_t total;
 };
@@ -237,8 +237,7 @@ void layout_scene(Scene& s) {
     w.pmace = take((size_t)std::max(clampk::mace_blocks(s.n()), clampk::row_blocks(s.tab)) * 2 * sizeof(double));
     w.scal = take(64 * sizeof(double));
     w.cnt = take(64 * sizeof(unsigned));
-    w.g0 = take(s.n() * sizeof(float));
-    w.g1 = take(s.n() * sizeof(float));
+    w.tvu = take(s.n() * sizeof(float));
     w.tvp = take(3 * s.n() * sizeof(float));
     w.pl21 = take((size_t)s.sc.nz * clampk::l21_chunks(s.sc.nx, s.sc.ny) * sizeof(double));
     if (s.K > 0) {
@@ -842,8 +841,7 @@ clamp_status clamp_prior_gauss(const clamp_plan* plan, int32_t scene, float sigm
     for (int k = 0; k < 7; ++k) taps[k] = (float)(g[k] / sum);
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     hipError_t e = timed(plan, ST_PRIOR, stream, [&] {
-        return clampk::launch_gauss(s.sc.nx, s.sc.ny, s.sc.nz, taps, in, at<float>(workspace, s.ws.g0),
-                                    at<float>(workspace, s.ws.g1), out, stream);
+        return clampk::launch_gauss(s.sc.nx, s.sc.ny, s.sc.nz, taps, in, out, stream);
     });
     return hip_check(e, "clamp_prior_gauss launch");
 }
@@ -882,7 +880,7 @@ clamp_status clamp_prior_tv(const clamp_plan* plan, int32_t scene, float lam, in
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const hipError_t e = timed(plan, ST_PRIOR, stream, [&] {
         return clampk::launch_prior_tv(s.sc.nx, s.sc.ny, s.sc.nz, lam, iters, in, out, at<float>(workspace, s.ws.tvp),
-                                       at<float>(workspace, s.ws.g0), stream);
+                                       at<float>(workspace, s.ws.tvu), stream);
     });
     return hip_check(e, "clamp_prior_tv launch");
 }
@@ -1035,6 +1033,7 @@ struct clamp_batch {
     int row_per_cu = 0, col_per_cu = 4;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool fused = false;  // the Mann step inside the update pass (every scene has an xbar)
 };
 
 namespace {
@@ -1067,25 +1066,31 @@ void batch_grids(clamp_batch* b) {
     };
     for (int g = 0; g < L.nseg[0]; ++g) L.seg_grid[0][g] = cap(L.seg_count[0][g], b->row_per_cu);
     for (int g = 0; g < L.nseg[1]; ++g) L.seg_grid[1][g] = cap(L.seg_count[1][g], b->col_per_cu);
+    for (int g = 0; g < L.nseg[2]; ++g) L.seg_grid[2][g] = L.seg_count[2][g];
     L.grid[clampk::Q_LOOK] = L.count[clampk::Q_LOOK];
     L.grid[clampk::Q_SCENE] = L.count[clampk::Q_SCENE];
-    for (int q : {clampk::Q_RESID, clampk::Q_VOX, clampk::Q_PRIOR_X, clampk::Q_PRIOR_Y, clampk::Q_PRIOR_Z})
-        L.grid[q] = L.count[q];
+    for (int q : {clampk::Q_RESID, clampk::Q_VOX, clampk::Q_PRIOR64, clampk::Q_PRIOR32}) L.grid[q] = L.count[q];
 }
 
 hipError_t batch_run(clamp_batch* b, hipStream_t st) {
     using namespace clampk;
     const clamp_plan* p = b->plan;
-    const int stages[] = {BS_COL_INV, BS_ROW_GRAD, BS_COL_FWD, BS_GAMMA, BS_ROW_UPDATE, BS_RESID, BS_DIAG,
-                          BS_PRIOR};
-    const int timing_stage[] = {ST_COL_INV, ST_ROW_GRAD, ST_COL_FWD, ST_GAMMA, ST_ROW_UPDATE, ST_RESID, ST_DIAG,
-                                ST_PRIOR};
-    for (int i = 0; i < (int)(sizeof stages / sizeof stages[0]); ++i) {
+    // Alg. 2's order; with the Mann step fused into the update pass the prior
+    // agents (which read only their own w) run first
+    const int plain[] = {BS_COL_INV, BS_ROW_GRAD, BS_COL_FWD, BS_GAMMA, BS_ROW_UPDATE, BS_RESID, BS_DIAG, BS_PRIOR};
+    const int plain_t[] = {ST_COL_INV, ST_ROW_GRAD, ST_COL_FWD, ST_GAMMA, ST_ROW_UPDATE, ST_RESID, ST_DIAG, ST_PRIOR};
+    const int fused[] = {BS_PRIOR, BS_COL_INV, BS_ROW_GRAD, BS_COL_FWD, BS_GAMMA, BS_ROW_UPDATE_MANN, BS_RESID,
+                         BS_DIAG};
+    const int fused_t[] = {ST_PRIOR, ST_COL_INV, ST_ROW_GRAD, ST_COL_FWD, ST_GAMMA, ST_ROW_UPDATE_MANN, ST_RESID,
+                           ST_DIAG};
+    const int* stages = b->fused ? fused : plain;
+    const int* timing_stage = b->fused ? fused_t : plain_t;
+    for (int i = 0; i < 8; ++i) {
         const hipError_t e = timed(p, timing_stage[i], st, [&] { return batch_stage(stages[i], b->launch, st); });
         if (e != hipSuccess) return e;
     }
     hipError_t e = timed(p, ST_MACE, st, [&] {
-        hipError_t x = batch_stage(BS_MACE, b->launch, st);
+        hipError_t x = b->fused ? hipSuccess : batch_stage(BS_MACE, b->launch, st);
         if (x == hipSuccess) x = batch_stage(BS_MACE_FINAL, b->launch, st);
         return x;
     });
@@ -1118,7 +1123,12 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
     std::vector<SceneBatch> hb(ns);
     std::vector<BatchItem> q[Q_COUNT];
     // row and column items grouped by FFT length, longest first
-    std::vector<BatchItem> rows_by_len[kSizeClasses], cols_by_len[kSizeClasses];
+    std::vector<BatchItem> rows_by_len[kSizeClasses], cols_by_len[kSizeClasses], rowg_by_len[kSizeClasses];
+    int n_fused = 0;
+    for (int i = 0; i < ns; ++i) n_fused += scenes[i].xbar != nullptr ? 1 : 0;
+    if (n_fused != 0 && n_fused != ns)
+        return fail(CLAMP_EINVAL, "either every scene of a batch has an xbar (the fused Mann step) or none has");
+    const bool fused = n_fused == ns && ns > 0;
     size_t ws_off = 0;
     for (int i = 0; i < ns; ++i) {
         const Scene& s = plan->scenes[i];
@@ -1134,6 +1144,9 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         const bool with_prior = bs.params.n_agents == s.sc.looks + 1;
         if (with_prior && !finite_pos(bs.prior_sigma))
             return fail(CLAMP_EINVAL, "scene %d: prior_sigma must be > 0", i);
+        if (with_prior && (s.sc.ny % kGaussTY != 0 || s.sc.nx % 32 != 0))
+            return fail(CLAMP_EUNSUPPORTED, "scene %d: the Gaussian prior needs ny a multiple of %d and nx of 32", i,
+                        kGaussTY);
         void* w0 = static_cast<char*>(workspace) + ws_off;
         ws_off += align256(s.ws.total);
         const int L = s.sc.looks;
@@ -1183,7 +1196,20 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         m.wbar = bs.wbar;
         m.part = at<double>(w0, s.ws.pmace);
         sb.mace = m;
-        sb.mace_chunks = mace_blocks(n);
+        sb.mace_chunks = fused ? row_blocks(s.tab) : mace_blocks(n);
+        if (fused) {
+            FuseArgs f{};
+            f.u = bs.w;
+            f.wprior = with_prior ? bs.w + (size_t)L * n : nullptr;
+            f.rprior = with_prior ? bs.state.r + (size_t)L * n : nullptr;
+            f.xbar = bs.xbar;
+            f.wbar = bs.wbar;
+            f.part = m.part;
+            for (int j = 0; j < m.n_agents; ++j) f.ups[j] = m.ups[j];
+            f.two_rho = m.two_rho;
+            f.n_agents = m.n_agents;
+            sb.fuse = f;
+        }
         sb.with_prior = with_prior ? 1 : 0;
         sb.conv = conv_err + i;
         PriorArgs pr{};
@@ -1200,8 +1226,6 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
             for (int k = 0; k < 7; ++k) pr.g[k] = (float)(g[k] / sum);
             pr.in = bs.w + (size_t)L * n;
             pr.out = bs.state.r + (size_t)L * n;
-            pr.tmp0 = at<float>(w0, s.ws.g0);
-            pr.tmp1 = at<float>(w0, s.ws.g1);
         }
         sb.prior = pr;
         // work items
@@ -1212,30 +1236,33 @@ clamp_status clamp_batch_create(const clamp_plan* plan, const clamp_batch_scene*
         }
         for (int l = 0; l < L; ++l)
             for (int g = 0; g < row_blocks(s.tab); ++g) rows_by_len[li].push_back(BatchItem{i, l, g, 0});
+        if (fused)
+            for (int g = 0; g < row_blocks(s.tab); ++g) rowg_by_len[li].push_back(BatchItem{i, 0, g, 0});
         for (int it = 0; it < L * s.sc.nz * s.tiles; ++it) cols_by_len[ci].push_back(BatchItem{i, it, 0, 0});
         for (int l = 0; l < L; ++l) {
             q[Q_LOOK].push_back(BatchItem{i, l, 0, 0});
             for (int c = 0; c < resid_chunks(s.tab); ++c) q[Q_RESID].push_back(BatchItem{i, l, c, 0});
         }
-        for (int c = 0; c < sb.mace_chunks; ++c) q[Q_VOX].push_back(BatchItem{i, 0, c, 0});
+        if (!fused)
+            for (int c = 0; c < sb.mace_chunks; ++c) q[Q_VOX].push_back(BatchItem{i, 0, c, 0});
         q[Q_SCENE].push_back(BatchItem{i, 0, 0, 0});
         if (with_prior) {
-            const size_t ux = (n + kPriorChunk - 1) / kPriorChunk;
-            const size_t uy = ((size_t)prior_strided_units(s.sc.ny, (size_t)s.sc.nz * s.sc.nx) + kPriorChunk - 1) / kPriorChunk;
-            const size_t uz = ((size_t)prior_strided_units(s.sc.nz, (size_t)s.sc.nx * s.sc.ny) + kPriorChunk - 1) / kPriorChunk;
-            for (size_t c = 0; c < ux; ++c) q[Q_PRIOR_X].push_back(BatchItem{i, 0, (int)c, 0});
-            for (size_t c = 0; c < uy; ++c) q[Q_PRIOR_Y].push_back(BatchItem{i, 0, (int)c, 0});
-            for (size_t c = 0; c < uz; ++c) q[Q_PRIOR_Z].push_back(BatchItem{i, 0, (int)c, 0});
+            // output tiles of the single-pass Gaussian (gauss3d_tile)
+            const int tx = s.sc.nx % 64 == 0 ? 64 : 32;
+            const int tiles = tx == 64 ? gauss_tiles<64>(s.sc.nx, s.sc.ny, s.sc.nz)
+                                       : gauss_tiles<32>(s.sc.nx, s.sc.ny, s.sc.nz);
+            for (int c = 0; c < tiles; ++c) q[tx == 64 ? Q_PRIOR64 : Q_PRIOR32].push_back(BatchItem{i, 0, c, 0});
         }
     }
     clamp_batch* b = new (std::nothrow) clamp_batch();
     if (b == nullptr) return fail(CLAMP_ENOMEM, "host allocation failed");
     b->plan = plan;
     b->cus = device_cus();
+    b->fused = fused;
     BatchLaunch& L = b->launch;
-    for (int side = 0; side < 2; ++side) {
-        std::vector<BatchItem>* by = side == 0 ? rows_by_len : cols_by_len;
-        std::vector<BatchItem>& dst = q[side == 0 ? Q_ROW : Q_COL];
+    for (int side = 0; side < 3; ++side) {
+        std::vector<BatchItem>* by = side == 0 ? rows_by_len : side == 1 ? cols_by_len : rowg_by_len;
+        std::vector<BatchItem>& dst = q[side == 0 ? Q_ROW : side == 1 ? Q_COL : Q_ROWG];
         L.nseg[side] = 0;
         for (int k = 0; k < kSizeClasses; ++k) {
             if (by[k].empty()) continue;

@@ -13,16 +13,15 @@ namespace clampk {
 
 #define CLAMP_SIZES(X) X(32) X(64) X(128) X(192) X(256) X(384) X(512)
 
-__host__ __device__ inline size_t strided_units(int len, size_t outer) {
-    const int ch = len >= 32 ? 32 : 8;
-    return outer * (size_t)((len + ch - 1) / ch);
-}
-int prior_strided_units(int len, size_t outer) { return (int)strided_units(len, outer); }
-
 // Row pass over the segment [off, off + count) of the row queue, whose items
-// all have row length NX.
-template <int NX, int MODE>
-__global__ __launch_bounds__(kBlock) void kb_row(BatchLaunch b, int off, int count) {
+// all have row length NX.  PERSIST: a capped grid whose blocks walk the
+// segment; otherwise one block per item, which keeps the item loop's
+// hoisted values out of the registers (85 against 106 at NX = 256); held to
+// six waves per SIMD there, as the single-scene row kernels run (79
+// registers, no spills up to NX = 256).
+template <int NX, int MODE, bool PERSIST>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(!PERSIST && NX <= 256 ? 6 : 1))) void kb_row(
+    BatchLaunch b, int off, int count) {
     __shared__ float2 tw[NX];
     __shared__ int bpos[NX];
     __shared__ int bcol[NX];
@@ -34,15 +33,43 @@ __global__ __launch_bounds__(kBlock) void kb_row(BatchLaunch b, int off, int cou
         bv = beta_vals(b.beta_table[k < b.beta_len ? k : b.beta_len - 1]);
     }
     const BatchItem* q = b.queue[Q_ROW] + off;
-    int prev = -1;
-    for (int it = blockIdx.x; it < count; it += gridDim.x) {
-        const BatchItem w = q[it];
-        // a private copy: the item's stores cannot alias its arguments
-        const RowArgs a = load_uniform((MODE == ROW_GRAD) ? &b.scenes[w.scene].grad : &b.scenes[w.scene].update);
-        const bool load = w.scene != prev;
-        prev = w.scene;
-        row_item<NX, MODE>(a, w.a, w.b, (size_t)w.a * row_blocks(a.s) + w.b, L, load, bv);
+    if constexpr (!PERSIST) {
+        const BatchItem w = const_ref(q + blockIdx.x);
+        // the scene's arguments stay in the (read-only) table, read by scalar loads
+        const auto& a = const_ref((MODE == ROW_GRAD) ? &b.scenes[w.scene].grad : &b.scenes[w.scene].update);
+        row_item<NX, MODE>(a, w.a, w.b, (size_t)w.a * row_blocks(a.s) + w.b, L, true, bv);
+    } else {
+        int prev = -1;
+        for (int it = blockIdx.x; it < count; it += gridDim.x) {
+            const BatchItem w = const_ref(q + it);
+            const auto& a = const_ref((MODE == ROW_GRAD) ? &b.scenes[w.scene].grad : &b.scenes[w.scene].update);
+            const bool load = w.scene != prev;
+            prev = w.scene;
+            row_item<NX, MODE>(a, w.a, w.b, (size_t)w.a * row_blocks(a.s) + w.b, L, load, bv);
+        }
     }
+}
+
+// The update pass with the Mann step fused in, one block per row-group item
+// (scene, row group) of the segment starting at `off`, walking every look of
+// the scene (row_update_mann); three waves per SIMD, as the single-scene
+// kernel.
+template <int NX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void kb_row_mann(BatchLaunch b,
+                                                                                              int off) {
+    __shared__ float2 tw[NX];
+    __shared__ int bpos[NX];
+    __shared__ int bcol[NX];
+    __shared__ float2 buf[row_lds_floats2<NX>()];
+    __shared__ float ups[64];
+    __shared__ float keep[mann_lds_floats<NX>()];
+    const RowLds L{tw, bpos, bcol, buf};
+    const int k = *b.iter;
+    const BetaVals bv = beta_vals(b.beta_table[k < b.beta_len ? k : b.beta_len - 1]);
+    const BatchItem w = const_ref(b.queue[Q_ROWG] + off + blockIdx.x);
+    const auto& a = const_ref(&b.scenes[w.scene].update);
+    const auto& f = const_ref(&b.scenes[w.scene].fuse);
+    row_update_mann<NX, ROW_UPDATE>(a, f, w.b, row_blocks(a.s), L, bv, ups, keep);
 }
 
 // Column pass over the segment [off, off + count) of the column queue, whose
@@ -59,17 +86,16 @@ __global__ __launch_bounds__(kBlock) void kb_col(BatchLaunch b, int off, int cou
         __syncthreads();
         const SceneBatch* scenes = b.scenes;
         col_fwd_stream<NY>(blockIdx.x, count, gridDim.x, [scenes, q](int pos) {
-            const BatchItem w = q[pos];
-            return ColItemVal{load_uniform(&scenes[w.scene].cfwd), w.a};
+            const BatchItem w = const_ref(q + pos);
+            return ColItemConst{&const_ref(&scenes[w.scene].cfwd), w.a};
         }, tw, tile);
     } else {
         int prev = -1;
         for (int it = blockIdx.x; it < count; it += gridDim.x) {
-            const BatchItem w = q[it];
+            const BatchItem w = const_ref(q + it);
             const bool load = w.scene != prev;
             prev = w.scene;
-            const ColArgs a = load_uniform(&b.scenes[w.scene].cinv);
-            col_inv_item<NY>(a, w.a, tw, tile, load);
+            col_inv_item<NY>(const_ref(&b.scenes[w.scene].cinv), w.a, tw, tile, load);
         }
     }
 }
@@ -157,34 +183,14 @@ __global__ void kb_set_iter(int* iter, int value, int add) {
     if (threadIdx.x == 0 && blockIdx.x == 0) iter[0] = add ? iter[0] + value : value;
 }
 
-template <int AXIS>
-__global__ __launch_bounds__(kBlock) void kb_prior(BatchLaunch b) {
-    constexpr int Q = AXIS == 0 ? Q_PRIOR_X : AXIS == 1 ? Q_PRIOR_Y : Q_PRIOR_Z;
-    const BatchItem* q = b.queue[Q];
-    for (int it = blockIdx.x; it < b.count[Q]; it += gridDim.x) {
-        const BatchItem w = q[it];
-        const PriorArgs p = load_uniform(&b.scenes[w.scene].prior);
-        const size_t n = (size_t)p.nx * p.ny * p.nz;
-        const size_t begin = (size_t)w.b * kPriorChunk;
-        if constexpr (AXIS == 0) {
-            const size_t end = begin + kPriorChunk < n ? begin + kPriorChunk : n;
-            for (size_t i = begin + threadIdx.x; i < end; i += kBlock) p.tmp0[i] = gauss_x_voxel(p.nx, p.g, p.in, i);
-        } else {
-            const int len = AXIS == 1 ? p.ny : p.nz;
-            const size_t inner = AXIS == 1 ? (size_t)p.nx : (size_t)p.nx * p.ny;
-            const size_t outer = AXIS == 1 ? (size_t)p.nz * p.nx : (size_t)p.nx * p.ny;
-            const float* in = AXIS == 1 ? p.tmp0 : p.tmp1;
-            float* out = AXIS == 1 ? p.tmp1 : p.out;
-            const size_t units = strided_units(len, outer);
-            const size_t end = begin + kPriorChunk < units ? begin + kPriorChunk : units;
-            for (size_t u = begin + threadIdx.x; u < end; u += kBlock) {
-                if (len >= 32)
-                    gauss_strided_unit<32>(len, inner, outer, p.g, in, out, u);
-                else
-                    gauss_strided_unit<8>(len, inner, outer, p.g, in, out, u);
-            }
-        }
-    }
+// Gaussian prior agents: one block per output tile (scene, tile) of the
+// scenes whose nx is a multiple of TX (gauss3d_tile).
+template <int TX>
+__global__ __launch_bounds__(kBlock) void kb_gauss3d(BatchLaunch b) {
+    __shared__ float tin[gauss_in_floats<TX>()];
+    __shared__ float txf[gauss_xf_floats<TX>()];
+    const BatchItem w = const_ref(b.queue[TX == 64 ? Q_PRIOR64 : Q_PRIOR32] + blockIdx.x);
+    gauss3d_tile<TX>(const_ref(&b.scenes[w.scene].prior), w.b, tin, txf);
 }
 
 hipError_t batch_set_iter(int* iter, int value, hipStream_t st) {
@@ -197,10 +203,30 @@ static void launch_row_segments(const BatchLaunch& b, hipStream_t st) {
     for (int g = 0; g < b.nseg[0]; ++g) {
         const dim3 grid(b.seg_grid[0][g]);
         const int off = b.seg_off[0][g], cnt = b.seg_count[0][g];
+        const bool per_item = b.seg_grid[0][g] >= cnt;
         switch (b.seg_len[0][g]) {
-#define CASE(N)                                                                        \
-    case N:                                                                            \
-        hipLaunchKernelGGL((kb_row<N, MODE>), grid, dim3(kBlock), 0, st, b, off, cnt); \
+#define CASE(N)                                                                                   \
+    case N:                                                                                       \
+        if (per_item)                                                                             \
+            hipLaunchKernelGGL((kb_row<N, MODE, false>), dim3(cnt), dim3(kBlock), 0, st, b, off, cnt); \
+        else                                                                                      \
+            hipLaunchKernelGGL((kb_row<N, MODE, true>), grid, dim3(kBlock), 0, st, b, off, cnt);   \
+        break;
+            CLAMP_SIZES(CASE)
+#undef CASE
+            default:
+                break;
+        }
+    }
+}
+
+static void launch_rowg_segments(const BatchLaunch& b, hipStream_t st) {
+    for (int g = 0; g < b.nseg[2]; ++g) {
+        const int off = b.seg_off[2][g], cnt = b.seg_count[2][g];
+        switch (b.seg_len[2][g]) {
+#define CASE(N)                                                                            \
+    case N:                                                                                \
+        hipLaunchKernelGGL((kb_row_mann<N>), dim3(cnt), dim3(kBlock), 0, st, b, off);      \
         break;
             CLAMP_SIZES(CASE)
 #undef CASE
@@ -241,10 +267,10 @@ hipError_t batch_stage(int stage, const BatchLaunch& b, hipStream_t st) {
         case BS_RESID: go(Q_RESID, kb_resid); break;
         case BS_DIAG: go(Q_LOOK, kb_diag); break;
         case BS_PRIOR:
-            go(Q_PRIOR_X, kb_prior<0>);
-            go(Q_PRIOR_Y, kb_prior<1>);
-            go(Q_PRIOR_Z, kb_prior<2>);
+            go(Q_PRIOR64, kb_gauss3d<64>);
+            go(Q_PRIOR32, kb_gauss3d<32>);
             break;
+        case BS_ROW_UPDATE_MANN: launch_rowg_segments(b, st); break;
         case BS_MACE: go(Q_VOX, kb_mace); break;
         case BS_MACE_FINAL: go(Q_SCENE, kb_mace_final); break;
         case BS_NEXT_ITER: hipLaunchKernelGGL(kb_set_iter, dim3(1), dim3(64), 0, st, b.iter, 1, 1); break;

@@ -205,8 +205,7 @@ hipError_t launch_prior_l21(int nx, int ny, int nz, float tau, const float* in, 
 hipError_t launch_prior_tv(int nx, int ny, int nz, float lam, int iters, const float* in, float* out, float* p,
                            float* u, hipStream_t st);
 
-hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float* in,
-                        float* tmp0, float* tmp1, float* out, hipStream_t st);
+hipError_t launch_gauss(int nx, int ny, int nz, const float* taps7, const float* in, float* out, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Batched passes over many scenes.  Each stage is one persistent launch that
@@ -249,12 +248,17 @@ struct DiagArgs {
     unsigned* counter;
 };
 
+// The Gaussian prior agent of one volume (gauss3d_tile): output tiles of
+// kGaussTY rows by 64 or 32 x-voxels over kGaussCZ range slices.
+constexpr int kGaussTY = 8, kGaussCZ = 8;
+template <int TX>
+__host__ __device__ inline int gauss_tiles(int nx, int ny, int nz) {
+    return (nx / TX) * (ny / kGaussTY) * ((nz + kGaussCZ - 1) / kGaussCZ);
+}
 struct PriorArgs {
     int nx, ny, nz;
     float g[7];
     const float* in;
-    float* tmp0;
-    float* tmp1;
     float* out;
 };
 
@@ -265,14 +269,18 @@ struct SceneBatch {
     GammaArgs gam;
     ResidArgs res;
     DiagArgs dia;
-    MaceArgs mace;
+    MaceArgs mace;         // the Mann step as its own pass (mace.part also holds the fused form's partials)
+    FuseArgs fuse;         // the Mann step fused into the update pass
     PriorArgs prior;
-    int mace_chunks;
+    int mace_chunks;       // partial-sum slots of the scene's convergence error
     int with_prior;
     double* conv;
 };
 
-enum BatchQueue { Q_COL = 0, Q_ROW, Q_LOOK, Q_RESID, Q_VOX, Q_PRIOR_X, Q_PRIOR_Y, Q_PRIOR_Z, Q_SCENE, Q_COUNT };
+// Work queues: column tiles, row groups of a look, row groups walking every
+// look (the fused update pass), looks, residual chunks, Mann-step chunks,
+// Gaussian-prior tiles of 64 and 32 x-voxels, scenes.
+enum BatchQueue { Q_COL = 0, Q_ROW, Q_ROWG, Q_LOOK, Q_RESID, Q_VOX, Q_PRIOR64, Q_PRIOR32, Q_SCENE, Q_COUNT };
 
 constexpr int kSizeClasses = 7;  // supported FFT lengths
 
@@ -281,28 +289,25 @@ struct BatchLaunch {
     const BatchItem* queue[Q_COUNT];
     int count[Q_COUNT];
     int grid[Q_COUNT];          // persistent grid size of each stage
-    // The row and column queues are ordered by FFT length (nx for rows, ny
-    // for columns); each length class is a segment with its own launch.
-    int seg_len[2][kSizeClasses];
-    int seg_off[2][kSizeClasses];
-    int seg_count[2][kSizeClasses];
-    int seg_grid[2][kSizeClasses];
-    int nseg[2];
+    // The row, column and fused row-group queues (segment sides 0, 1, 2) are
+    // ordered by FFT length (nx for rows, ny for columns); each length class
+    // is a segment with its own launch.
+    int seg_len[3][kSizeClasses];
+    int seg_off[3][kSizeClasses];
+    int seg_count[3][kSizeClasses];
+    int seg_grid[3][kSizeClasses];
+    int nseg[3];
     const float* beta_table;    // device [beta_len]
     int beta_len;
     int* iter;                  // device iteration counter (iterations done)
     uint32_t* fault;
 };
 
-// Items of the batched prior passes: chunk sizes in work units.
-constexpr int kPriorChunk = 4 * kBlock;
-int prior_strided_units(int len, size_t outer);
-
 hipError_t batch_stage(int stage, const BatchLaunch& b, hipStream_t st);
 hipError_t batch_set_iter(int* iter, int value, hipStream_t st);
 enum BatchStage {
     BS_COL_INV = 0, BS_ROW_GRAD, BS_COL_FWD, BS_GAMMA, BS_ROW_UPDATE, BS_RESID, BS_DIAG,
-    BS_PRIOR, BS_MACE, BS_MACE_FINAL, BS_NEXT_ITER
+    BS_PRIOR, BS_MACE, BS_MACE_FINAL, BS_NEXT_ITER, BS_ROW_UPDATE_MANN
 };
 
 }  // namespace clampk

@@ -98,6 +98,25 @@ __device__ __forceinline__ void wave_or_fault(uint32_t bits, uint32_t* fault) {
     if ((threadIdx.x & 63) == 0 && bits != 0u && fault != nullptr) atomicOr(fault, bits);
 }
 
+// Read-only device tables (the batch's scene table and work queues) seen
+// through the constant address space.  Nothing writes them while a kernel
+// runs, so a read at a wave-uniform address is a scalar load that the
+// compiler may issue again where a field is used instead of holding the
+// whole block in registers -- as it does for kernel arguments.
+// (The host pass of this file compiles the kernels' declarations only, and
+// has no constant address space.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using ConstAS = const __attribute__((address_space(4))) T;
+#else
+template <class T>
+using ConstAS = const T;
+#endif
+template <class T>
+__device__ __forceinline__ ConstAS<T>& const_ref(const T* p) {
+    return *(ConstAS<T>*)p;
+}
+
 // Copy of a wave-uniform argument block from device memory into scalar
 // registers: the private copy cannot alias the item's stores, and
 // readfirstlane keeps it out of the vector register file.
@@ -184,8 +203,8 @@ __device__ __forceinline__ float exact_prox(float sf, float vf, float s2f) {
 // sigma_w^2) (A^H A ~ alpha I), s = c + |m1|^2, then the quadratic surrogate
 // of App. A (ROW_UPDATE) or the exact surrogate prox (ROW_UPDATE_EXACT).
 // Fault bits: 1 for a non-finite result or mean, 2 for r <= 0.
-template <int MODE>
-__device__ __forceinline__ float r_update_voxel(const RowArgs& a, const BetaVals& bv, float r0, float v, float2 m1,
+template <int MODE, class A>
+__device__ __forceinline__ float r_update_voxel(const A& a, const BetaVals& bv, float r0, float v, float2 m1,
                                                 uint32_t& fb) {
     const float c = a.s2w * r0 / (a.alpha * r0 + a.s2w);
     const float sv = c + cabs2(m1);
@@ -251,8 +270,8 @@ __device__ __forceinline__ void row_fft(float2 (&h)[PX], float2* rb, int t, cons
 // FFT of the band already applied): d = A^H r / sigma_w^2 - omega mu with
 // omega = 1 / (r' + sigma_w^2 / alpha), written back into h, plus the
 // thread's shares of ||d||^2, sum omega |d|^2 and sum omega |mu|^2.
-template <int NX, int TR, int PX>
-__device__ __forceinline__ void row_grad_pointwise(const RowArgs& a, float2 (&h)[PX], int t, const float2 (&m)[PX],
+template <int NX, int TR, int PX, class A>
+__device__ __forceinline__ void row_grad_pointwise(const A& a, float2 (&h)[PX], int t, const float2 (&m)[PX],
                                                    const float (&rp)[PX], float& dd, float& wd, float& wm) {
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
@@ -274,8 +293,8 @@ __device__ __forceinline__ void row_grad_pointwise(const RowArgs& a, float2 (&h)
 // Row pass over rows [rgroup * RPB, rgroup * RPB + RPB) of look `look`;
 // `slot` indexes the look's partial-sum slots.  `load_tables` reloads the
 // row tables (the caller skips it when the previous item had the same scene).
-template <int NX, int MODE>
-__device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup, size_t slot, const RowLds& L,
+template <int NX, int MODE, class A>
+__device__ __forceinline__ void row_item(const A& a, int look, int rgroup, size_t slot, const RowLds& L,
                                          bool load_tables, BetaVals bv) {
     constexpr int TR = row_threads(NX);
     constexpr int RPB = rows_per_block(NX);
@@ -290,7 +309,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, int look, int rgroup,
     // Stream prefetch pays off for the gradient pass; the update pass already
     // runs near the read/write bandwidth ceiling and loads its streams late.
     constexpr bool PREFETCH = (MODE == ROW_GRAD);
-    const SceneTables& s = a.s;
+    const auto& s = a.s;
     const int tid = threadIdx.x;
     const int ri = tid / TR, t = tid % TR;
     const int rows = s.nz * s.ny;
@@ -431,15 +450,15 @@ __host__ __device__ constexpr int mann_lds_floats() {
 // LDS: ups[64] holds the agent weights, keep[mann_lds_floats<NX>()] each
 // thread's x_bar and w_bar of the previous call ([k][thread], conflict-free),
 // read back at every look instead of held in registers.
-template <int NX, int MODE>
-__device__ __forceinline__ void row_update_mann(const RowArgs& a, const FuseArgs& f, int rgroup, int nblk,
+template <int NX, int MODE, class A, class F>
+__device__ __forceinline__ void row_update_mann(const A& a, const F& f, int rgroup, int nblk,
                                                 const RowLds& L, BetaVals bv, float* ups, float* keep) {
     constexpr int TR = row_threads(NX);
     constexpr int RPB = rows_per_block(NX);
     constexpr int PX = (NX + TR - 1) / TR;
     constexpr int PAD = kRowPad;
     constexpr int RS = lds_len<NX, PAD>();
-    const SceneTables& s = a.s;
+    const auto& s = a.s;
     const int tid = threadIdx.x;
     const int ri = tid / TR, t = tid % TR;
     const int rows = s.nz * s.ny;
@@ -588,12 +607,12 @@ __device__ __forceinline__ void row_update_mann(const RowArgs& a, const FuseArgs
 // tile is zeroed, the TC contiguous runs are scattered into it, and the
 // columns are transformed and written as band rows.  `item` = zl * tiles +
 // tile, which is also the partial-sum slot of the scene.
-template <int NY>
-__device__ __forceinline__ void col_inv_item(const ColArgs& a, int item, float2* tw, float2* tile,
+template <int NY, class A>
+__device__ __forceinline__ void col_inv_item(const A& a, int item, float2* tw, float2* tile,
                                              bool load_tables) {
     constexpr int TC = col_tile_cols(NY);
     constexpr int TPC = kBlock / TC;
-    const SceneTables& s = a.s;
+    const auto& s = a.s;
     const int tid = threadIdx.x;
     const int tile_i = item % s.tiles;
     const int zl = item / s.tiles;  // look * nz + z
@@ -683,8 +702,8 @@ __device__ __forceinline__ void col_fwd_stream(int first, int count, int stride,
     float2 pre[PT];
     auto load = [&](int pos) {
         const auto ai = item_of(pos);
-        const ColArgs& a = ai.get();
-        const SceneTables& s = a.s;
+        const auto& a = ai.get();
+        const auto& s = a.s;
         const int bc = (ai.item % s.tiles) * TC + c_ld;
         const float2* src = a.band_in + (size_t)(ai.item / s.tiles) * s.ny * s.Bs + bc;
 #pragma unroll
@@ -695,8 +714,8 @@ __device__ __forceinline__ void col_fwd_stream(int first, int count, int stride,
     if (pos < count) load(pos);
     for (; pos < count; pos += stride) {
         const auto ai = item_of(pos);
-        const ColArgs& a = ai.get();
-        const SceneTables& s = a.s;
+        const auto& a = ai.get();
+        const auto& s = a.s;
         const int tile_i = ai.item % s.tiles;
         const int zl = ai.item / s.tiles;
         // the item's band rows move to h (rows y_ld + k TPC of column c_ld),
@@ -761,6 +780,11 @@ struct ColItemVal {
     ColArgs args;
     int item;
     __device__ const ColArgs& get() const { return args; }
+};
+struct ColItemConst {
+    ConstAS<ColArgs>* args;
+    int item;
+    __device__ ConstAS<ColArgs>& get() const { return *args; }
 };
 
 // ---------------------------------------------------------------------------
@@ -911,74 +935,105 @@ __device__ __forceinline__ void mace_voxel(const MaceArgs& a, const float* ups, 
     den += (double)a.n_agents * wb * wb;
 }
 
-struct Taps7 {
+// Periodic 7-tap Gaussian smoothing along z, y and x in one pass over the
+// volume: one call produces an output tile of kGaussTY rows x TX voxels over
+// range slices z0 .. z0 + kGaussCZ - 1.  Tiles are numbered z chunk fastest,
+// then x, then y: tile t has bz = t % zc, bx = (t / zc) % (nx / TX),
+// by = t / (zc nx / TX), so that consecutive tiles share their halos.  It
+// walks the input slices z0 - 3 .. z0 + kGaussCZ + 2 in range order: each
+// slice's (kGaussTY + 6) x (TX + 6) window goes to LDS (the next slice is
+// loaded into registers meanwhile), is filtered along x, then along y, and
+// the y-filtered rows enter a 7-slice register ring per output voxel, whose
+// z-filter gives an output slice once the ring holds its last tap.  p holds
+// nx, ny, nz (ny a multiple of kGaussTY, nx of TX), the taps g[7], in and
+// out (not overlapping).
+template <int TX>
+__host__ __device__ constexpr int gauss_in_floats() { return (kGaussTY + 6) * (TX + 6); }
+template <int TX>
+__host__ __device__ constexpr int gauss_xf_floats() { return (kGaussTY + 6) * TX; }
+
+template <int TX, class P>
+__device__ __forceinline__ void gauss3d_tile(const P& p, int tile, float* tin, float* txf) {
+    constexpr int W = TX + 6, H = kGaussTY + 6;
+    constexpr int NIN = H * W;
+    constexpr int LPT = (NIN + kBlock - 1) / kBlock;
+    constexpr int OPT = kGaussTY * TX / kBlock;
+    static_assert(OPT >= 1 && kGaussTY * TX % kBlock == 0, "a tile's outputs divide among the threads");
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const float* in = p.in;
+    float* out = p.out;
     float g[7];
-};
-
-// Periodic 7-tap filter along x of voxel i (i < 2^31, nx >= 4): 32-bit index
-// arithmetic and the wrap as a compare, no 64-bit division.
-__device__ __forceinline__ float gauss_x_voxel(int nx, const float* g, const float* in, size_t i) {
-    const unsigned ii = (unsigned)i;
-    const int x = (int)(ii % (unsigned)nx);
-    const float* row = in + (ii - (unsigned)x);
-    float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        int xx = x + k - 3;
-        xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-        acc += g[k] * row[xx];
+    for (int k = 0; k < 7; ++k) g[k] = p.g[k];
+    const int tid = threadIdx.x;
+    const int zc = (nz + kGaussCZ - 1) / kGaussCZ, tx = nx / TX;
+    const int bz = tile % zc, bx = (tile / zc) % tx, by = tile / (zc * tx);
+    const int x0 = bx * TX, y0 = by * kGaussTY, z0 = bz * kGaussCZ;
+    const int zend = z0 + kGaussCZ < nz ? z0 + kGaussCZ : nz;
+    const unsigned slice = (unsigned)nx * (unsigned)ny;
+    unsigned goff[LPT];
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+        const int e = tid + j * kBlock;
+        const int r = (e < NIN ? e : 0) / W, c = (e < NIN ? e : 0) % W;
+        int gy = y0 - 3 + r, gx = x0 - 3 + c;
+        gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+        gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+        goff[j] = (unsigned)gy * nx + gx;
     }
-    return acc;
-}
-
-// The same filter for the four voxels 4 q .. 4 q + 3 of a row (nx a multiple
-// of 4): three float4 loads cover taps x - 4 .. x + 7, wrapped whole at the
-// row ends; each output sums its taps in the same order as gauss_x_voxel.
-__device__ __forceinline__ float4 gauss_x_quad(int nx, const float* g, const float* in, unsigned q) {
-    const unsigned i = 4u * q;
-    const int x = (int)(i % (unsigned)nx);
-    const float4* row = reinterpret_cast<const float4*>(in + (i - (unsigned)x));
-    const int c = x >> 2, nq = nx >> 2;
-    const float4 l = row[c == 0 ? nq - 1 : c - 1], m = row[c], r = row[c + 1 == nq ? 0 : c + 1];
-    const float v[12] = {l.x, l.y, l.z, l.w, m.x, m.y, m.z, m.w, r.x, r.y, r.z, r.w};
-    float o[4];
+    float pre[LPT];
+    auto load = [&](int zi) {
+        int zz = zi % nz;
+        zz = zz < 0 ? zz + nz : zz;
+        const float* src = in + (size_t)zz * slice;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        float acc = 0.f;
+        for (int j = 0; j < LPT; ++j) pre[j] = src[goff[j]];
+    };
+    float ring[7][OPT];
 #pragma unroll
-        for (int t = 0; t < 7; ++t) acc += g[t] * v[e + t + 1];
-        o[e] = acc;
-    }
-    return make_float4(o[0], o[1], o[2], o[3]);
-}
-
-// Periodic 7-tap filter along a strided axis of length len (stride `inner`
-// elements) for work unit idx = chunk * outer + o: the thread slides a
-// register window down CH samples, reading each input once plus a 6-sample
-// halo.
-template <int CH>
-__device__ __forceinline__ void gauss_strided_unit(int len, size_t inner, size_t outer, const float* g,
-                                                   const float* in, float* out, size_t idx) {
-    // every index is below 2^31 (a volume holds fewer voxels): 32-bit division
-    const unsigned in32 = (unsigned)inner, out32 = (unsigned)outer, id = (unsigned)idx;
-    const unsigned o = id % out32;
-    const int c = (int)(id / out32);
-    const unsigned base = (o / in32) * in32 * (unsigned)len + (o % in32);
-    const int y0 = c * CH;
-    float win[CH + 6];
+    for (int k = 0; k < 7; ++k)
 #pragma unroll
-    for (int k = 0; k < CH + 6; ++k) {
-        int yy = (y0 + k - 3) % len;
-        if (yy < 0) yy += len;
-        win[k] = in[base + (unsigned)yy * in32];
-    }
+        for (int q = 0; q < OPT; ++q) ring[k][q] = 0.f;
+    load(z0 - 3);
+    for (int zi = z0 - 3; zi < zend + 3; ++zi) {
+        __syncthreads();  // the previous slice's readers of tin and txf are done
 #pragma unroll
-    for (int k = 0; k < CH; ++k) {
-        if (y0 + k < len) {
+        for (int j = 0; j < LPT; ++j) {
+            const int e = tid + j * kBlock;
+            if (e < NIN) tin[e] = pre[j];
+        }
+        if (zi + 1 < zend + 3) load(zi + 1);
+        __syncthreads();
+        for (int e = tid; e < H * TX; e += kBlock) {
+            const int r = e / TX, c = e % TX;
             float acc = 0.f;
 #pragma unroll
-            for (int q = 0; q < 7; ++q) acc += g[q] * win[k + q];
-            out[base + (unsigned)(y0 + k) * in32] = acc;
+            for (int k = 0; k < 7; ++k) acc += g[k] * tin[r * W + c + k];
+            txf[e] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < OPT; ++q) {
+            const int o = tid + q * kBlock;
+            const int oy = o / TX, ox = o % TX;
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) acc += g[k] * txf[(oy + k) * TX + ox];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) ring[k][q] = ring[k + 1][q];
+            ring[6][q] = acc;
+        }
+        if (zi >= z0 + 3) {
+            const size_t zo = (size_t)(zi - 3) * slice;
+#pragma unroll
+            for (int q = 0; q < OPT; ++q) {
+                const int o = tid + q * kBlock;
+                const int oy = o / TX, ox = o % TX;
+                float acc = 0.f;
+#pragma unroll
+                for (int k = 0; k < 7; ++k) acc += g[k] * ring[k][q];
+                out[zo + (size_t)(y0 + oy) * nx + x0 + ox] = acc;
+            }
         }
     }
 }

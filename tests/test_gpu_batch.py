@@ -1,6 +1,7 @@
-"""Batched steps over uneven scenes (persistent launches over work queues,
-graph replay, autotuned grids) against per-scene single-scene steps and,
-scene by scene, against the float64 oracle."""
+"""Batched steps over uneven scenes (launches over work queues, graph replay,
+autotuned grids), in both forms of the Mann step, against per-scene
+single-scene steps of the same form and, scene by scene, against the float64
+oracle."""
 
 import numpy as np
 import pytest
@@ -44,36 +45,37 @@ def _scene_dicts(probs, sigma2=1e-3):
                  with_prior=wp) for sp, y, s2, wp in probs]
 
 
-def _batch(G, probs):
+def _batch(G, probs, fused=True):
     import torch
-    b = G.ClampBatchGPU(_scene_dicts(probs))
+    b = G.ClampBatchGPU(_scene_dicts(probs), fused=fused)
     b.init([torch.from_numpy(y).cuda() for sp, y, s2, wp in probs])
     return b
 
 
-def test_batch_steps_match_single_scene_runs(G):
+@pytest.mark.parametrize("fused", [True, False])
+def test_batch_steps_match_single_scene_runs(G, fused):
+    """6 batched steps against the single-scene calls in the same form (the
+    Mann step fused into the update pass, or a pass of its own): the same
+    item code, so equal to float32 rounding."""
     import torch
     probs = _problems()
-    b = _batch(G, probs)
+    b = _batch(G, probs, fused)
     iters = 6
     for _ in range(iters):
         b.step()
     torch.cuda.synchronize()
     assert int(b.fault.item()) == 0
     for i, (sp, y, s2, wp) in enumerate(probs):
-        # the batch runs the Mann step as its own stage: compare with the
-        # single-scene calls in the same form
-        g = G.ClampGPU(sp.nx, sp.ny, sp.nz, sp.looks, sp.radius, s2, 1e-3, with_prior=wp, fused=False)
+        g = G.ClampGPU(sp.nx, sp.ny, sp.nz, sp.looks, sp.radius, s2, 1e-3, with_prior=wp, fused=fused)
         g.init(torch.from_numpy(y).cuda())
         g.run(iters)
         torch.cuda.synchronize()
         st = b.states[i]
-        tag = "batch scene %d %dx%dx%d L=%d" % (i, sp.nx, sp.ny, sp.nz, sp.looks)
-        assert report(tag + " w", rel_l2(st["w"].cpu().numpy(), g.w.cpu().numpy()), 1e-6) <= 1e-6
+        tag = "batch scene %d %dx%dx%d L=%d fused=%d" % (i, sp.nx, sp.ny, sp.nz, sp.looks, fused)
+        assert report(tag + " w", rel_l2(b.state_w(i).cpu().numpy(), g.state_w().cpu().numpy()), 1e-6) <= 1e-6
+        assert report(tag + " wbar", rel_l2(st["wbar"].cpu().numpy(), g.wbar.cpu().numpy()), 1e-6) <= 1e-6
         assert report(tag + " mu", rel_l2(st["mu"].cpu().numpy(), g.mu.cpu().numpy()), 1e-6) <= 1e-6
         assert report(tag + " r", rel_l2(st["r"].cpu().numpy(), g.r.cpu().numpy()), 1e-6) <= 1e-6
-        # the batch's prior runs as three separable passes, the single-scene
-        # prior as one 3D pass: the same sums in another order
         assert abs(b.conv[i].item() - g.conv_err()) <= 1e-6 * g.conv_err()
 
 
@@ -96,7 +98,7 @@ def test_graph_replayed_batch_matches_oracle_on_every_scene(G):
                                                                                    sp.looks, wp)
         bs = b.states[i]
         assert report(tag + " wbar", rel_l2(bs["wbar"].cpu().numpy(), hist[-1]["wbar"]), 1e-4) <= 1e-4
-        assert report(tag + " w", rel_l2(bs["w"].cpu().numpy(), st.w), 1e-4) <= 1e-4
+        assert report(tag + " w", rel_l2(b.state_w(i).cpu().numpy(), st.w), 1e-4) <= 1e-4
         assert report(tag + " mu", rel_l2(bs["mu"].cpu().numpy(), st.mu), 1e-4) <= 1e-4
         ce = hist[-1]["conv_err"]
         assert abs(b.conv[i].item() - ce) <= 1e-4 * ce
@@ -142,6 +144,18 @@ def test_autotuned_grids_give_identical_results(G):
     for sa, sb in zip(a.states, b.states):
         assert np.array_equal(sa["w"].cpu().numpy(), sb["w"].cpu().numpy())
         assert np.array_equal(sa["mu"].cpu().numpy(), sb["mu"].cpu().numpy())
+
+
+def test_batch_rejects_mixed_forms_of_the_mann_step(G):
+    """xbar on some scenes only: CLAMP_EINVAL, nothing created."""
+    import torch
+    from paper_2406_13651_amd import _clamp as C
+    probs = _problems()[:2]
+    b = _batch(G, probs, fused=True)
+    states = [dict(st) for st in b.states]
+    del states[1]["xbar"]
+    with pytest.raises(C.ClampError):
+        C.clamp_batch_create(b.plan, states, b.fault, b.conv, torch.empty_like(b.ws))
 
 
 def test_batch_rejects_the_exact_prox():
