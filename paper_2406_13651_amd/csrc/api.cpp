@@ -179,8 +179,11 @@ clamp_status build_scene(const clamp_scene& in, Scene& s) {
     s.P = (int)s.row_idx.size();
     s.B = (int)s.band_cols.size();
     if (s.P == 0) return fail(CLAMP_EINVAL, "pupil passes no DFT sample");
-    s.Bs = (s.B + 15) / 16 * 16;
     s.tiles = (s.B + clampk::col_tile_cols(ny) - 1) / clampk::col_tile_cols(ny);
+    s.Bs = s.tiles * clampk::col_tile_cols(ny);
+    // the row passes' gather table: in-slice offsets of each column's band sample
+    for (int v = 0; v < nx; ++v)
+        if (s.band_pos[v] >= 0) s.band_pos[v] = clampk::band_col_off(s.band_pos[v], ny);
     s.K = in.range_support;
     s.alpha = s.K > 0 ? (double)s.P * s.K / ((double)nx * ny * in.nz) : (double)s.P / ((double)nx * ny);
     return CLAMP_OK;

@@ -13,6 +13,18 @@ constexpr int kBlock = 256;      // threads per block for every kernel
 // length 256; 8 for longer columns, which keeps each thread's share of an
 // item at 16 values.
 __host__ __device__ constexpr int col_tile_cols(int ny) { return ny >= 384 ? 8 : 16; }
+
+// Band buffers (the column transforms of a slice kept only on its B band
+// columns) hold each (look, slice) as ny Bs values, Bs = tiles TC with
+// TC = col_tile_cols(ny): column tile after column tile, each tile row-major
+// (TC values per row), so that a column pass moves a tile as one contiguous
+// block and a row pass touches TC consecutive values per tile.  In-slice
+// offsets of band column b and of row y (TC is 8 or 16: shifts):
+__host__ __device__ inline int band_col_off(int b, int ny) {
+    const int sh = col_tile_cols(ny) == 8 ? 3 : 4;
+    return ((b >> sh) * ny << sh) + (b & ((1 << sh) - 1));
+}
+__host__ __device__ inline int band_row_off(int y, int ny) { return y * col_tile_cols(ny); }
 constexpr int kDiag = 8;         // doubles of diagnostics per look (and of the summary row)
 // diag[l][.] of look l: gamma, ||d||^2, ||A d||^2, h before, h after,
 // mu-residual of the look, sum omega |d|^2, ||resid||^2 after; summary row
@@ -24,12 +36,12 @@ struct SceneTables {
     int nx, ny, nz;
     int P;       // pupil samples per slice
     int B;       // band columns (columns holding pupil samples)
-    int Bs;      // row stride of band-row buffers (B rounded up to 16)
+    int Bs;      // band-buffer values per slice row: tiles * col_tile_cols(ny)
     int tiles;   // ceil(B / col_tile_cols(ny))
     const float2* tw_x;     // [nx] exp(-2 pi i m / nx)
     const float2* tw_y;     // [ny]
     const int* band_cols;   // [B] natural column index of each band column
-    const int* band_pos;    // [nx] band index of a column, -1 outside the band
+    const int* band_pos;    // [nx] in-slice band-buffer offset of a column's band sample (band_col_off), -1 outside the band
     const int* col_off;     // [B + 1] compact offset of each band column
     const int* row_idx;     // [P] row of each compact entry
     const int* pidx;        // [ny * nx] compact index of a sample, -1 off-pupil
@@ -96,7 +108,7 @@ struct ColArgs {
     int looks;                 // looks in this launch
     const float2* cmp_in;      // compact [looks][nz][P]      (COL_INV_COMPACT)
     const float2* full_in;     // full grids [looks][nz][ny][nx] (COL_INV_FULL/INIT)
-    const float2* band_in;     // band rows [looks][nz][ny][Bs]  (COL_FWD_COMPACT)
+    const float2* band_in;     // band buffers [looks][nz][ny * Bs] (COL_FWD_COMPACT)
     float2* band_out;          // band rows                      (COL_INV_*)
     float2* cmp_out;           // compact out: D(a)F x (FWD), (1 - s) D(a) y (INIT)
     float2* cmp_keep;          // compact out: D(a) y (INIT, optional)

@@ -106,8 +106,8 @@ __device__ __forceinline__ void col_dense_inv(const ColArgs& a, float2* tw, floa
         fft_lds<NY, TPC, +1>(tile + tid % TC, TC, tid / TC, tw);
         const int c = tid % TC, bc = c0 + c;
         if (bc < s.B) {
-            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bc;
-            for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * s.Bs] = cscale(tile[y * TC + c], a.scale);
+            float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + (size_t)tile_i * s.ny * TC + c;  // the tile's block
+            for (int y = tid / TC; y < NY; y += TPC) dst[(size_t)y * TC] = cscale(tile[y * TC + c], a.scale);
         }
         // item index = (look * nz + z) * tiles + tile = look * col_blocks + z * tiles + tile
         if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);

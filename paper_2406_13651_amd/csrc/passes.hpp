@@ -316,7 +316,8 @@ __device__ __forceinline__ void row_item(const A& a, int look, int rgroup, size_
     const int row = rgroup * RPB + ri;
     const bool active = row < rows;
     const size_t img = ((size_t)look * rows + (active ? row : 0)) * NX;
-    const size_t band = ((size_t)look * rows + (active ? row : 0)) * s.Bs;
+    const int arow = active ? row : 0;
+    const size_t band = ((size_t)look * s.nz + arow / s.ny) * s.ny * s.Bs + band_row_off(arow % s.ny, s.ny);
 
     float2 m[FUSED ? PX : 1];
     float rp[FUSED ? PX : 1];
@@ -389,14 +390,16 @@ __device__ __forceinline__ void row_item(const A& a, int look, int rgroup, size_
     } else if constexpr (MODE == ROW_FWD) {
         row_fft<NX, TR, -1, PAD, false>(h, rb, t, L.tw);
         if (active)
-            for (int b = t; b < s.B; b += TR) a.band_out[band + b] = cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale);
+            for (int b = t; b < s.B; b += TR)
+                a.band_out[band + band_col_off(b, s.ny)] = cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale);
     } else if constexpr (MODE == ROW_GRAD) {
         row_fft<NX, TR, +1, PAD, true>(h, rb, t, L.tw);
         float dd = 0.f, wd = 0.f, wm = 0.f;
         if (active) row_grad_pointwise<NX, TR>(a, h, t, m, rp, dd, wd, wm);
         row_fft<NX, TR, -1, PAD, false>(h, rb, t, L.tw);
         if (active)
-            for (int b = t; b < s.B; b += TR) st_stream(a.band_out + band + b, cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale));
+            for (int b = t; b < s.B; b += TR)
+                st_stream(a.band_out + band + band_col_off(b, s.ny), cscale(rb[lds_pos<PAD>(L.bcol[b])], a.scale));
         double acc[3] = {dd, wd, wm};
         block_sum_store<3>(acc, a.part + slot * 3);
     } else {  // ROW_UPDATE
@@ -465,7 +468,8 @@ __device__ __forceinline__ void row_update_mann(const A& a, const F& f, int rgro
     const int row = rgroup * RPB + ri;
     const bool active = row < rows;
     const size_t n = (size_t)rows * NX;
-    const size_t pix = (size_t)(active ? row : 0) * NX;
+    const int arow = active ? row : 0;
+    const size_t pix = (size_t)arow * NX;
     for (int i = tid; i < NX; i += kBlock) {
         L.tw[i] = s.tw_x[i];
         L.bpos[i] = s.band_pos[i];
@@ -504,7 +508,7 @@ __device__ __forceinline__ void row_update_mann(const A& a, const F& f, int rgro
     uint32_t fb = 0u;
     for (int l = 0; l < a.looks; ++l) {
         const size_t img = (size_t)l * n + pix;
-        const size_t band = ((size_t)l * rows + (active ? row : 0)) * s.Bs;
+        const size_t band = ((size_t)l * s.nz + arow / s.ny) * s.ny * s.Bs + band_row_off(arow % s.ny, s.ny);
         float2 h[PX];
         {
             float2 bin[PX];
@@ -666,7 +670,7 @@ __device__ __forceinline__ void col_inv_item(const A& a, int item, float2* tw, f
         acc[0] = f;
     }
     const int co = tid % TC, bo = c0 + co;
-    float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + bo;
+    float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + (size_t)tile_i * s.ny * TC + co;  // the tile's block
     if constexpr (fft_regs_ok<NY, TPC>()) {
         // the last stage leaves each thread rows tid / TC + k TPC of its
         // column, which it stores as band rows
@@ -675,12 +679,12 @@ __device__ __forceinline__ void col_inv_item(const A& a, int item, float2* tw, f
         if (bo < s.B) {
 #pragma unroll
             for (int k = 0; k < NY / TPC; ++k)
-                st_stream(dst + (size_t)(tid / TC + k * TPC) * s.Bs, cscale(h[k], a.scale));
+                st_stream(dst + (size_t)(tid / TC + k * TPC) * TC, cscale(h[k], a.scale));
         }
     } else {
         fft_lds<NY, TPC, +1>(tile + co, TC, tid / TC, tw);
         if (bo < s.B)
-            for (int y = tid / TC; y < NY; y += TPC) st_stream(dst + (size_t)y * s.Bs, cscale(tile[y * TC + co], a.scale));
+            for (int y = tid / TC; y < NY; y += TPC) st_stream(dst + (size_t)y * TC, cscale(tile[y * TC + co], a.scale));
     }
     if (a.part != nullptr) block_sum_store<1>(acc, a.part + item);
 }
@@ -705,10 +709,12 @@ __device__ __forceinline__ void col_fwd_stream(int first, int count, int stride,
         const auto& a = ai.get();
         const auto& s = a.s;
         const int bc = (ai.item % s.tiles) * TC + c_ld;
-        const float2* src = a.band_in + (size_t)(ai.item / s.tiles) * s.ny * s.Bs + bc;
+        // the tile's contiguous block of the band buffer
+        const float2* src = a.band_in + (size_t)(ai.item / s.tiles) * s.ny * s.Bs +
+                            (size_t)(ai.item % s.tiles) * s.ny * TC + c_ld;
 #pragma unroll
         for (int k = 0; k < PT; ++k)
-            pre[k] = bc < s.B ? src[(size_t)(y_ld + k * TPC) * s.Bs] : make_float2(0.f, 0.f);
+            pre[k] = bc < s.B ? src[(size_t)(y_ld + k * TPC) * TC] : make_float2(0.f, 0.f);
     };
     int pos = first;
     if (pos < count) load(pos);
