@@ -491,11 +491,12 @@ def run_learned(args):
     print(json.dumps(result), flush=True)
 
 
-def run_large(args):
+def large_eval(args, dev, prior=None):
     """Large reconstruction: 512x512x128, 32 looks, SNR 5 dB, four objects;
-    CLAMP with the learned prior (trained as in the learned workload) for
-    `--eval-iters` iterations through the forward-only fallback driver, and the
-    forward-only reconstruction beside it as the reference for its error."""
+    CLAMP with the learned prior for `--eval-iters` iterations through the
+    forward-only fallback driver, and the forward-only reconstruction beside
+    it as the reference for its error.  prior: a trained CnnPrior, or None to
+    train one as in the learned workload.  Returns the figures as a dict."""
     import numpy as np
     import torch
 
@@ -505,13 +506,13 @@ def run_large(args):
     from paper_2406_13651_amd import learned as Lm
     from paper_2406_13651_amd.perf import stage_bytes
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    log("training pairs: %d volumes of 64x64x32" % args.train_pairs)
-    X, T = Lm.make_pairs(args.train_pairs, seed=0, mode=args.train_mode, noise=args.train_noise)
-    prior = Lm.CnnPrior(Lm.init_params(0), device=dev)
-    hist = Lm.train(prior, X, T, epochs=args.train_epochs, lr=args.lr)
-    del X, T
+    train_s = None
+    if prior is None:
+        log("training pairs: %d volumes of 64x64x32" % args.train_pairs)
+        X, T = Lm.make_pairs(args.train_pairs, seed=0, mode=args.train_mode, noise=args.train_noise)
+        prior = Lm.CnnPrior(Lm.init_params(0), device=dev)
+        train_s = Lm.train(prior, X, T, epochs=args.train_epochs, lr=args.lr)["seconds"]
+        del X, T
     spec = synth.CONFIGS["large"]
     log("synthesising %dx%dx%d, %d looks" % (spec.nx, spec.ny, spec.nz, spec.looks))
     t0 = time.perf_counter()
@@ -524,7 +525,7 @@ def run_large(args):
     iters = args.eval_iters
     units = spec.looks * spec.n
 
-    log("learned form, %d iterations" % iters)
+    log("large: learned form, %d iterations" % iters)
     g = Lm.LearnedClamp(*geo, prior=prior, device=dev)
     sb = stage_bytes(spec.nx, spec.ny, spec.nz, spec.looks, g.info["P"], g.info["B"], spec.looks + 1, fused=g.fused)
     g.init(yt)
@@ -553,12 +554,13 @@ def run_large(args):
     learned_nrmse = Lm.nrmse(out, rt)
     learned_out = out.clone()
     fault = int(g.fault.item())
+    conv = g.conv_err()
     if dom in timed:
         stages[dom] = timed[dom]
-    del g
+    del g, out
     torch.cuda.empty_cache()
 
-    log("forward-only reference, %d iterations" % iters)
+    log("large: forward-only reference, %d iterations" % iters)
     f = G.ClampGPU(*geo, with_prior=False, device=dev)
     f.init(yt)
     torch.cuda.synchronize()
@@ -568,6 +570,8 @@ def run_large(args):
     t_fwd = time.perf_counter() - t0
     fwd_nrmse = Lm.nrmse(f.wbar, rt)
     diff = Lm.nrmse(learned_out, f.wbar)
+    del f, learned_out, yt, rt
+    torch.cuda.empty_cache()
     per_stage = {}
     for name, (ms, cnt) in stages.items():
         e = {"avg_ms": round(ms / cnt, 4), "launches": cnt}
@@ -577,33 +581,50 @@ def run_large(args):
     dom_ms = stages[dom][0] / stages[dom][1]
     achieved = sb[dom] / (dom_ms * 1e-3) / 1e9
     ms_iter = t_learned / iters * 1e3
+    return {
+        "workload": "CLAMP with the learned prior, %dx%dx%d, %d looks, pupil radius %g, SNR %g dB, %d objects; "
+                    "%.2f GB of complex64 looks" % (spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, spec.snr_db,
+                                                    spec.n_objects, spec.n * spec.looks * 8 / 1e9),
+        "iterations": iters,
+        "ms_per_iter": round(ms_iter, 3),
+        "voxel_looks_per_s": units / (ms_iter * 1e-3),
+        "forward_only_voxel_looks_per_s": units * iters / t_fwd,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)},
+        "nrmse": {"learned": learned_nrmse, "forward_only": fwd_nrmse, "learned_vs_forward_only": diff},
+        "conv_err": conv,
+        "reductions": "float64 (step sizes, h, convergence error, mu-residual)",
+        "fallback": info,
+        "wall_s": {"learned": round(t_learned, 3), "forward_only": round(t_fwd, 3), "synthesis": round(t_syn, 1),
+                   "training": None if train_s is None else round(train_s, 2)},
+        "stages": per_stage,
+        "fault": fault,
+    }
+
+
+def run_large(args):
+    """The large reconstruction as its own bench line (large_eval)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    lg = large_eval(args, dev)
     result = {
         "metric": "fwd-agent voxel-looks/s + HBM GB/s vs peak; CLAMP iters/s at fixed NRMSE",
-        "value": units / (ms_iter * 1e-3),
+        "value": lg["voxel_looks_per_s"],
         "unit": "voxel-looks/s",
         "n_gpus": 1,
-        "steps": iters,
+        "steps": lg["iterations"],
         "warmup": args.warmup,
-        "ms_per_step": ms_iter,
+        "ms_per_step": lg["ms_per_iter"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (forward agents), bf16 with f32 accumulation (CNN)",
         "data": "synthetic",
-        "config": {"workload": "large: CLAMP with the learned prior, %dx%dx%d, %d looks, pupil radius %g, SNR %g dB, "
-                               "%d objects; %.2f GB of complex64 looks" % (spec.nx, spec.ny, spec.nz, spec.looks,
-                                                                          spec.radius, spec.snr_db, spec.n_objects,
-                                                                          spec.n * spec.looks * 8 / 1e9),
-                   "sigma2": args.sigma2, "iterations": iters},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
-        "wall_s": {"learned": round(t_learned, 3), "forward_only": round(t_fwd, 3), "synthesis": round(t_syn, 1),
-                   "training": round(hist["seconds"], 2)},
-        "forward_only_voxel_looks_per_s": units * iters / t_fwd,
-        "nrmse": {"learned": learned_nrmse, "forward_only": fwd_nrmse, "learned_vs_forward_only": diff},
-        "fallback": info,
-        "stages": per_stage,
-        "fault": fault,
+        "config": {"workload": "large: " + lg["workload"], "sigma2": args.sigma2, "iterations": lg["iterations"]},
+        "roofline": dict(lg["roofline"], traffic=None),
+        "large": lg,
     }
     print(json.dumps(result), flush=True)
 
@@ -836,6 +857,8 @@ def main():
     ap.add_argument("--r-update", default="quadratic", choices=("quadratic", "exact"),
                     help="forward-agent r-update: the quadratic surrogate (App. A) or the exact surrogate prox")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="full workload: skip the large configuration (512x512x128, 32 looks, learned prior)")
     ap.add_argument("--no-learned", action="store_true",
                     help="full workload: skip the equal-NRMSE comparison (CNN training and three 50-iteration runs)")
     ap.add_argument("--batch-cap", type=float, default=2.5e9,
@@ -1005,6 +1028,11 @@ def main():
                                      "%dx%dx%d, %d looks, pupil radius %g, SNR %g dB" %
                                      (sp.nx, sp.ny, sp.nz, sp.looks, sp.radius, sp.snr_db),
                                      training=ev["training"])
+        if not args.no_large:
+            # the large configuration with the same trained prior
+            lg = large_eval(args, dev, ev["prior"])
+            lg.pop("stages")
+            result["large"] = lg
     print(json.dumps(result), flush=True)
 
 

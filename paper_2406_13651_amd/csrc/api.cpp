@@ -71,7 +71,7 @@ struct Scene {
     clamp_scene sc{};
     int P = 0, B = 0, Bs = 0, tiles = 0, K = 0;
     double alpha = 0.0;
-    std::vector<int> band_cols, band_pos, col_off, row_idx, pidx;
+    std::vector<int> band_cols, band_pos, col_off, row_idx, pidx, pidxb;
     std::vector<void*> dev;  // device allocations owned by this scene
     SceneTables tab{};
     Layout ws{};
@@ -181,6 +181,9 @@ clamp_status build_scene(const clamp_scene& in, Scene& s) {
     if (s.P == 0) return fail(CLAMP_EINVAL, "pupil passes no DFT sample");
     s.tiles = (s.B + clampk::col_tile_cols(ny) - 1) / clampk::col_tile_cols(ny);
     s.Bs = s.tiles * clampk::col_tile_cols(ny);
+    s.pidxb.assign((size_t)ny * s.Bs, -1);
+    for (int u = 0; u < ny; ++u)
+        for (int b = 0; b < s.B; ++b) s.pidxb[(size_t)u * s.Bs + b] = s.pidx[(size_t)u * nx + s.band_cols[b]];
     // the row passes' gather table: in-slice offsets of each column's band sample
     for (int v = 0; v < nx; ++v)
         if (s.band_pos[v] >= 0) s.band_pos[v] = clampk::band_col_off(s.band_pos[v], ny);
@@ -206,6 +209,7 @@ clamp_status upload_scene(Scene& s) {
     if ((st = upload(s, s.col_off, &t.col_off)) != CLAMP_OK) return st;
     if ((st = upload(s, s.row_idx, &t.row_idx)) != CLAMP_OK) return st;
     if ((st = upload(s, s.pidx, &t.pidx)) != CLAMP_OK) return st;
+    if ((st = upload(s, s.pidxb, &t.pidxb)) != CLAMP_OK) return st;
     t.K = s.K;
     t.tw_z = nullptr;
     t.cpos = nullptr;

@@ -110,7 +110,9 @@ __host__ __device__ constexpr bool fft_len_ok(int n) {
 
 // Position of element i of a padded LDS vector: one float2 of padding after
 // every 16 elements (PADSH = 4) spreads the radix-R autosort stores over the
-// LDS banks; PADSH = 0 means no padding.
+// LDS banks; PADSH = 0 means no padding.  (An XOR swizzle of bits 3..7 into
+// bits 0..4, free of bank conflicts in every stage under a 64-bank model,
+// measured no faster in the row passes and cost the gradient pass a wave.)
 template <int PADSH>
 __host__ __device__ constexpr int lds_pos(int i) {
     if constexpr (PADSH > 0) return i + (i >> PADSH);

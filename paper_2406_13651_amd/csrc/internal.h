@@ -45,6 +45,7 @@ struct SceneTables {
     const int* col_off;     // [B + 1] compact offset of each band column
     const int* row_idx;     // [P] row of each compact entry
     const int* pidx;        // [ny * nx] compact index of a sample, -1 off-pupil
+    const int* pidxb;       // [ny * Bs] compact index of row y of band column b at y * Bs + b, -1 off-pupil
     int K;                  // range frequencies of the 3D aperture (0: per-slice 2D operator)
     const float2* tw_z;     // [nz] (3D operator only)
     const int* cpos;        // [P] u * nx + v of each compact entry (3D operator only)

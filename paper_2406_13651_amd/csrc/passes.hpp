@@ -608,9 +608,8 @@ __device__ __forceinline__ void row_update_mann(const A& a, const F& f, int rgro
 
 // ---------------------------------------------------------------------------
 // Inverse column pass of one tile from the column-major compact layout: the
-// tile is zeroed, the TC contiguous runs are scattered into it, and the
-// columns are transformed and written as band rows.  `item` = zl * tiles +
-// tile, which is also the partial-sum slot of the scene.
+// tile's columns are transformed and written as band columns.  `item` =
+// zl * tiles + tile, which is also the partial-sum slot of the scene.
 template <int NY, class A>
 __device__ __forceinline__ void col_inv_item(const A& a, int item, float2* tw, float2* tile,
                                              bool load_tables) {
@@ -621,67 +620,103 @@ __device__ __forceinline__ void col_inv_item(const A& a, int item, float2* tw, f
     const int tile_i = item % s.tiles;
     const int zl = item / s.tiles;  // look * nz + z
     const int c0 = tile_i * TC;
-    // Scatter of column bc's pupil samples p in [p0, p1): lane l takes p0 + l,
-    // p0 + l + TPC, ..., in chunks of CH whose loads are all issued before the
-    // first is used (positions past p1 re-read the column's last sample and
-    // are dropped).  A column holds at most NY = CH * TPC samples, so one
-    // chunk, loaded before the tile is cleared, covers it.
-    constexpr int CH = NY / TPC;
-    const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
-    const bool col = bc < s.B;
+    // the twiddles (when this block loads them) travel with the first loads,
+    // not after the barrier
+    constexpr int TWL = (NY + kBlock - 1) / kBlock;
+    float2 twv[TWL];
+    if (load_tables) {
+#pragma unroll
+        for (int j = 0; j < TWL; ++j) {
+            const int i = tid + j * kBlock;
+            twv[j] = s.tw_y[i < NY ? i : 0];
+        }
+    }
     const float2* src = a.cmp_in + (size_t)zl * s.P;
-    int p0 = 0, p1 = 0;
-    if (col) {
-        p0 = s.col_off[bc];
-        p1 = s.col_off[bc + 1];
-    }
-    float2 v[CH];
-    int ry[CH];
-    auto load_chunk = [&](int base) {
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            const int p = base + k * TPC;
-            const int pc = p < p1 ? p : p1 - 1;
-            v[k] = src[pc];
-            ry[k] = s.row_idx[pc];
-        }
-    };
-    int base = p0 + lane;
-    if (base < p1) load_chunk(base);
-    __syncthreads();  // the previous item's readers of the LDS buffers are done
-    if (load_tables)
-        for (int i = tid; i < NY; i += kBlock) tw[i] = s.tw_y[i];
-    for (int i = tid; i < NY * TC; i += kBlock) tile[i] = make_float2(0.f, 0.f);
-    __syncthreads();
-    double acc[1] = {0.0};
-    {
-        float f = 0.f;
-        while (base < p1) {
-#pragma unroll
-            for (int k = 0; k < CH; ++k) {
-                if (base + k * TPC < p1) {
-                    tile[ry[k] * TC + c] = v[k];
-                    f += cabs2(v[k]);
-                }
-            }
-            base += CH * TPC;
-            if (base < p1) load_chunk(base);
-        }
-        acc[0] = f;
-    }
     const int co = tid % TC, bo = c0 + co;
     float2* dst = a.band_out + (size_t)zl * s.ny * s.Bs + (size_t)tile_i * s.ny * TC + co;  // the tile's block
+    double acc[1] = {0.0};
     if constexpr (fft_regs_ok<NY, TPC>()) {
-        // the last stage leaves each thread rows tid / TC + k TPC of its
-        // column, which it stores as band rows
-        float2 h[NY / TPC];
-        fft_regs<NY, TPC, +1, 0, false, true, false>(h, tile + co, TC, tid / TC, tw);
-        if (bo < s.B) {
+        // Each thread fetches its own transform inputs, rows tid / TC + k TPC
+        // of band column bo, straight into registers: the compact index of
+        // each from pidxb (-1 off the pupil), then the samples, every load
+        // issued before the first is used.  No tile to clear, no scatter
+        // through LDS.
+        constexpr int PT = NY / TPC;
+        const int yo = tid / TC;
+        const bool col = bo < s.B;
+        int pi[PT];
 #pragma unroll
-            for (int k = 0; k < NY / TPC; ++k)
-                st_stream(dst + (size_t)(tid / TC + k * TPC) * TC, cscale(h[k], a.scale));
+        for (int k = 0; k < PT; ++k) pi[k] = col ? s.pidxb[(size_t)(yo + k * TPC) * s.Bs + bo] : -1;
+        float2 h[PT];
+#pragma unroll
+        for (int k = 0; k < PT; ++k) h[k] = src[pi[k] >= 0 ? pi[k] : 0];
+        float f = 0.f;
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            if (pi[k] < 0) h[k] = make_float2(0.f, 0.f);
+            f += cabs2(h[k]);
+        }
+        acc[0] = f;
+        __syncthreads();  // the previous item's readers of the LDS buffers are done
+        if (load_tables) {
+#pragma unroll
+            for (int j = 0; j < TWL; ++j) {
+                const int i = tid + j * kBlock;
+                if (i < NY) tw[i] = twv[j];
+            }
+        }
+        // the transform opens with a block barrier (the twiddles are then in
+        // place); its last stage leaves each thread rows yo + k TPC, which it
+        // stores into the tile's block
+        fft_regs<NY, TPC, +1, 0, true, true, false>(h, tile + co, TC, yo, tw);
+        if (col) {
+#pragma unroll
+            for (int k = 0; k < PT; ++k) st_stream(dst + (size_t)(yo + k * TPC) * TC, cscale(h[k], a.scale));
         }
     } else {
+        // Scatter of column bc's pupil samples p in [p0, p1): lane l takes
+        // p0 + l, p0 + l + TPC, ..., all loads issued before the first is
+        // used (positions past p1 re-read the column's last sample and are
+        // dropped); a column holds at most NY = CH * TPC samples, so one
+        // chunk, loaded before the tile is cleared, covers it.
+        constexpr int CH = NY / TPC;
+        const int c = tid / TPC, lane = tid % TPC, bc = c0 + c;
+        int p0 = 0, p1 = 0;
+        if (bc < s.B) {
+            p0 = s.col_off[bc];
+            p1 = s.col_off[bc + 1];
+        }
+        float2 v[CH];
+        int ry[CH];
+        const int base = p0 + lane;
+        if (base < p1) {
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int p = base + k * TPC;
+                const int pc = p < p1 ? p : p1 - 1;
+                v[k] = src[pc];
+                ry[k] = s.row_idx[pc];
+            }
+        }
+        __syncthreads();  // the previous item's readers of the LDS buffers are done
+        if (load_tables) {
+#pragma unroll
+            for (int j = 0; j < TWL; ++j) {
+                const int i = tid + j * kBlock;
+                if (i < NY) tw[i] = twv[j];
+            }
+        }
+        for (int i = tid; i < NY * TC; i += kBlock) tile[i] = make_float2(0.f, 0.f);
+        __syncthreads();
+        float f = 0.f;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (base + k * TPC < p1) {
+                tile[ry[k] * TC + c] = v[k];
+                f += cabs2(v[k]);
+            }
+        }
+        acc[0] = f;
         fft_lds<NY, TPC, +1>(tile + co, TC, tid / TC, tw);
         if (bo < s.B)
             for (int y = tid / TC; y < NY; y += TPC) st_stream(dst + (size_t)y * TC, cscale(tile[y * TC + co], a.scale));
