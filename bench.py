@@ -325,6 +325,21 @@ UNET_TRAIN_FLOP = 3 * UNET_FWD_FLOP - 1728
 BF16_PEAK_TFLOPS = 2500.0
 
 
+def copy_probe(args, dev):
+    """A device copy of --copy-probe MiB, the known-size reference for the
+    hardware byte counters (FETCH_SIZE, WRITE_SIZE)."""
+    import torch
+    if args.copy_probe <= 0:
+        return
+    nfl = args.copy_probe * (1 << 20) // 4
+    src = torch.ones(nfl, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy probe: %d bytes read, %d bytes written" % (nfl * 4, nfl * 4))
+    del src, dst
+
+
 def equal_nrmse_summary(out, iters):
     """Iterations and wall time of each form to bring the scale-fit NRMSE
     (Sec. V-A) 10% below that of the speckle average, the comparison
@@ -427,6 +442,7 @@ def run_learned(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    copy_probe(args, dev)
     ev = learned_eval(args, dev)
     out, hist, prior, spec, unet = ev["out"], ev["hist"], ev["prior"], ev["spec"], ev["unet"]
     pz, py, px = ev["patch"]
@@ -919,14 +935,7 @@ def main():
                    device=dev, r_update=args.r_update)
     yt = torch.from_numpy(y).to(dev)
     g.init(yt)
-    if args.copy_probe > 0:
-        nfl = args.copy_probe * (1 << 20) // 4
-        src = torch.ones(nfl, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy probe: %d bytes read, %d bytes written" % (nfl * 4, nfl * 4))
-        del src, dst
+    copy_probe(args, dev)
     info = g.info
     sb = stage_bytes(spec.nx, spec.ny, spec.nz, spec.looks, info["P"], info["B"], g.N, fused=g.fused)
     log("warmup %d iterations, a 10-iteration per-stage breakdown, then %d timed iterations"
