@@ -980,12 +980,13 @@ __device__ __forceinline__ void mace_voxel(const MaceArgs& a, const float* ups, 
 // volume: one call produces an output tile of kGaussTY rows x TX voxels over
 // range slices z0 .. z0 + kGaussCZ - 1.  Tiles are numbered z chunk fastest,
 // then x, then y: tile t has bz = t % zc, bx = (t / zc) % (nx / TX),
-// by = t / (zc nx / TX), so that consecutive tiles share their halos.  It
-// walks the input slices z0 - 3 .. z0 + kGaussCZ + 2 in range order: each
-// slice's (kGaussTY + 6) x (TX + 6) window goes to LDS (the next slice is
-// loaded into registers meanwhile), is filtered along x, then along y, and
-// the y-filtered rows enter a 7-slice register ring per output voxel, whose
-// z-filter gives an output slice once the ring holds its last tap.  p holds
+// by = t / (zc nx / TX), so that consecutive tiles share their halos.  Every
+// (kGaussTY + 6) x (TX + 6) window of the input slices z0 - 3 .. z0 +
+// kGaussCZ + 2 is loaded into registers up front, so that the block waits
+// for memory once, not once per slice, and is filtered along z there, each
+// thread over its own window positions.  Then, output slice by output slice,
+// the z-filtered window goes to LDS and is filtered along x, then along y
+// (the separable filter's three passes commute).  p holds
 // nx, ny, nz (ny a multiple of kGaussTY, nx of TX), the taps g[7], in and
 // out (not overlapping).
 template <int TX>
@@ -999,6 +1000,7 @@ __device__ __forceinline__ void gauss3d_tile(const P& p, int tile, float* tin, f
     constexpr int NIN = H * W;
     constexpr int LPT = (NIN + kBlock - 1) / kBlock;
     constexpr int OPT = kGaussTY * TX / kBlock;
+    constexpr int NZW = kGaussCZ + 6;  // input slices of a chunk
     static_assert(OPT >= 1 && kGaussTY * TX % kBlock == 0, "a tile's outputs divide among the threads");
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const float* in = p.in;
@@ -1022,28 +1024,33 @@ __device__ __forceinline__ void gauss3d_tile(const P& p, int tile, float* tin, f
         gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
         goff[j] = (unsigned)gy * nx + gx;
     }
-    float pre[LPT];
-    auto load = [&](int zi) {
-        int zz = zi % nz;
+    // the chunk's input windows, all loads issued before the first is used
+    // (in a chunk cut short by the end of the volume the slices past it wrap
+    // periodically and are filtered, but no output of theirs is stored)
+    float pre[NZW][LPT];
+#pragma unroll
+    for (int sl = 0; sl < NZW; ++sl) {
+        int zz = (z0 - 3 + sl) % nz;
         zz = zz < 0 ? zz + nz : zz;
         const float* src = in + (size_t)zz * slice;
 #pragma unroll
-        for (int j = 0; j < LPT; ++j) pre[j] = src[goff[j]];
-    };
-    float ring[7][OPT];
+        for (int j = 0; j < LPT; ++j) pre[sl][j] = src[goff[j]];
+    }
+    // Two barriers per output slice: the previous slice's second barrier has
+    // every reader of tin behind it before tin is rewritten, and this
+    // slice's first one every reader of txf before txf is rewritten.
 #pragma unroll
-    for (int k = 0; k < 7; ++k)
-#pragma unroll
-        for (int q = 0; q < OPT; ++q) ring[k][q] = 0.f;
-    load(z0 - 3);
-    for (int zi = z0 - 3; zi < zend + 3; ++zi) {
-        __syncthreads();  // the previous slice's readers of tin and txf are done
+    for (int o = 0; o < kGaussCZ; ++o) {
+        if (z0 + o >= zend) break;  // uniform over the block
+        // the window of output slice z0 + o filtered along z, in registers
 #pragma unroll
         for (int j = 0; j < LPT; ++j) {
             const int e = tid + j * kBlock;
-            if (e < NIN) tin[e] = pre[j];
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) acc += g[k] * pre[o + k][j];
+            if (e < NIN) tin[e] = acc;
         }
-        if (zi + 1 < zend + 3) load(zi + 1);
         __syncthreads();
         for (int e = tid; e < H * TX; e += kBlock) {
             const int r = e / TX, c = e % TX;
@@ -1053,28 +1060,15 @@ __device__ __forceinline__ void gauss3d_tile(const P& p, int tile, float* tin, f
             txf[e] = acc;
         }
         __syncthreads();
+        const size_t zo = (size_t)(z0 + o) * slice;
 #pragma unroll
         for (int q = 0; q < OPT; ++q) {
-            const int o = tid + q * kBlock;
-            const int oy = o / TX, ox = o % TX;
+            const int oq = tid + q * kBlock;
+            const int oy = oq / TX, ox = oq % TX;
             float acc = 0.f;
 #pragma unroll
             for (int k = 0; k < 7; ++k) acc += g[k] * txf[(oy + k) * TX + ox];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) ring[k][q] = ring[k + 1][q];
-            ring[6][q] = acc;
-        }
-        if (zi >= z0 + 3) {
-            const size_t zo = (size_t)(zi - 3) * slice;
-#pragma unroll
-            for (int q = 0; q < OPT; ++q) {
-                const int o = tid + q * kBlock;
-                const int oy = o / TX, ox = o % TX;
-                float acc = 0.f;
-#pragma unroll
-                for (int k = 0; k < 7; ++k) acc += g[k] * ring[k][q];
-                out[zo + (size_t)(y0 + oy) * nx + x0 + ox] = acc;
-            }
+            out[zo + (size_t)(y0 + oy) * nx + x0 + ox] = acc;
         }
     }
 }
