@@ -23,8 +23,8 @@ struct ConvArgs {
     const float* bias;             // fp32 [32] (EPI_RELU, EPI_FINAL)
     uint16_t* out;                 // bf16 [voxel][32] (EPI_RELU, EPI_DGRAD)
     float* out_f32;                // fp32 [voxel] (EPI_FINAL)
-    const float* xin;              // fp32 [voxel] residual input (EPI_FINAL)
-    const float* scale;            // device scalar m of the output (EPI_FINAL), NULL = 1
+    const float* xin;              // fp32 [voxel] residual input (EPI_FINAL), the input (first layer)
+    const float* scale;            // device scalar m of the output (EPI_FINAL), of the input (first layer); NULL = 1
     const uint16_t* relu_src;      // bf16 [voxel][32]: ReLU mask source (EPI_DGRAD)
 };
 
@@ -37,7 +37,12 @@ struct WgradArgs {
     float* part;                   // fp32 [2 * grid][28][32][32] partial sums (cnn_wgrad_part_bytes)
 };
 
+// cin = 1 with EPI_RELU: the first layer from the fp32 volume (xin, scale;
+// weights from cnn_prep_first); cin = 8 or 32: bf16 inputs of that many
+// channels.
 hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st);
+// First-layer weight fragments of k_conv_first (2048 bytes) from W [27][1][32].
+hipError_t cnn_prep_first(const float* W, uint16_t* wq, hipStream_t st);
 size_t cnn_wq_elems(int cinp);
 hipError_t cnn_prep_q(const float* W, int cin, int cout, int flip, int cinp, uint16_t* wq, hipStream_t st);
 hipError_t cnn_pack(const float* x, const float* scale, long nvox, uint16_t* x8, hipStream_t st);

@@ -264,6 +264,31 @@ __device__ constexpr int store_share(int q) {
     return left <= 0 ? 0 : left < 3 ? left : 3;
 }
 
+// Output run p (0 or 1) of one lane of a 32-channel output row: the lane
+// (voxel, half h) holds channels 8 g + 4 h + 0..3 (g = 0..3) in acc; with
+// RELU the bias is added and negatives cut, the values go to bf16, and a
+// swap between the lane halves turns groups 2 p and 2 p + 1 into the 8
+// consecutive channels 16 p + 8 h + 0..7 of the returned 16-byte run.
+template <bool RELU>
+__device__ __forceinline__ v4u out_run(const v16f& acc, int p, const float (&bias_r)[16]) {
+    uint32_t d[2][2];  // [group 2 p + e][channel pair]
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int i = 4 * (2 * p + e) + 2 * c;
+            float lo = acc[i], hi = acc[i + 1];
+            if constexpr (RELU) {
+                lo = fmaxf(lo + bias_r[i], 0.f);
+                hi = fmaxf(hi + bias_r[i + 1], 0.f);
+            }
+            d[e][c] = pack_bf16x2(lo, hi);
+        }
+    const auto s0 = __builtin_amdgcn_permlane32_swap(d[0][0], d[1][0], false, false);
+    const auto s1 = __builtin_amdgcn_permlane32_swap(d[0][1], d[1][1], false, false);
+    return v4u{s0[0], s1[0], s0[1], s1[1]};
+}
+
 template <int CIN, int EPI>
 __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
     static_assert(EPI == EPI_RELU || EPI == EPI_DGRAD || EPI == EPI_RAW, "the final layer runs in k_conv_final");
@@ -394,22 +419,7 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     const uint32_t off = out_off(r, p);
-                    uint32_t d[2][2];  // [group 2 p + e][channel pair]
-#pragma unroll
-                    for (int e = 0; e < 2; ++e)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) {
-                            const int i = 4 * (2 * p + e) + 2 * c;
-                            float lo = acc[r][i], hi = acc[r][i + 1];
-                            if constexpr (EPI == EPI_RELU) {
-                                lo = fmaxf(lo + bias_r[i], 0.f);
-                                hi = fmaxf(hi + bias_r[i + 1], 0.f);
-                            }
-                            d[e][c] = pack_bf16x2(lo, hi);
-                        }
-                    const auto s0 = __builtin_amdgcn_permlane32_swap(d[0][0], d[1][0], false, false);
-                    const auto s1 = __builtin_amdgcn_permlane32_swap(d[0][1], d[1][1], false, false);
-                    v4u q = {s0[0], s1[0], s0[1], s1[1]};
+                    v4u q = out_run<EPI == EPI_RELU>(acc[r], p, bias_r);
                     if constexpr (EPI == EPI_DGRAD) {
 #pragma unroll
                         for (int k = 0; k < 4; ++k) q[k] &= relu_keep2(keep[r][p][k]);
@@ -417,6 +427,154 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
                     __builtin_amdgcn_raw_buffer_store_b128(q, out_rs, off, 0, 0);
                 }
             }
+        }
+    }
+}
+
+// First layer of the forward pass (one input channel, 32 output channels,
+// bias and ReLU), straight from the fp32 volume.  The input of voxel v is
+// bf16(x[v] / m) (m = *scale, 1 without one), rounded as cnn_pack rounds it
+// for the 8-channel form.  With one channel, the 27 taps form the MFMA's K
+// dimension (padded to 32), so that an output row of 32 voxels takes two
+// 32x32x16 products where the 8-channel form takes eighteen.  Lane (voxel n,
+// half h) of K fragment f holds, for voxel n, the inputs of
+//   f = 0: range offset h, in-slice taps e = 0..7,
+//   f = 1, h = 0: range offset 2, in-slice taps e = 0..7,
+//   f = 1, h = 1: in-slice tap 8 of range offsets e = 0, 1, 2, then zeros,
+// where in-slice tap j is (dy, dx) = (j / 3, j % 3) (offsets +1); the model's
+// tap index is 9 dz + j (cnn_prep_first orders the weights alike).  The
+// weights W^T [32 channels][32 K] are the A operand and stay in registers.
+// The output tile is that of k_conv (16 rows x 32 x-voxels, wave w on rows
+// 4w..4w+3), and so are the persistent runs of tile-slices and the epilogue.
+// Input slices with halo (18 x 34 bf16) sit in a ring of four LDS slots:
+// step z reads the slots of inputs z - 1, z, z + 1 and writes input z + 2
+// (fetched into registers a step earlier) into the fourth, so one barrier
+// per step orders the writes before the next step's reads.
+constexpr int kFirstSlots = 4;
+constexpr int kFirstSlice = kRingRows * kRingCols;                      // voxels of an input slice with halo
+constexpr int kFirstFill = (kFirstSlice + kCnnBlock - 1) / kCnnBlock;   // values per thread per slice
+constexpr int kFirstSlot = kFirstFill * kCnnBlock;                      // slot size, padded for unguarded writes
+
+// In-slot offset of in-slice tap j.
+__host__ __device__ constexpr int first_tap_off(int j) { return (j / 3) * kRingCols + j % 3; }
+
+// Loads of input slice zin of the tile (with halo) as fp32, branch-free as
+// in tile_fetch: halo voxels outside the volume and slices outside it read 0.
+__device__ __forceinline__ void first_fetch(const ConvArgs& a, const float* in, int zin, int y0, int x0,
+                                            float (&pre)[kFirstFill], bool live) {
+    const bool zok = live && zin >= 0 && zin < a.nz;
+    const long plane = (long)a.ny * a.nx;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(in) + (zok ? zin : 0) * plane, 0, zok ? (uint32_t)(plane * 4) : 0u, kBufferWord3);
+#pragma unroll
+    for (int i = 0; i < kFirstFill; ++i) {
+        const int e = threadIdx.x + i * kCnnBlock;
+        const int xs = e % kRingCols, ys = e / kRingCols;
+        const int y = y0 - 1 + ys, x = x0 - 1 + xs;
+        const bool ok = e < kFirstSlice && y >= 0 && y < a.ny && x >= 0 && x < a.nx;
+        const uint32_t off = ok ? (uint32_t)((y * a.nx + x) * 4) : kBufferOutside;
+        pre[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+    }
+}
+
+// Input slice zi of the ring: slot zi mod 4 (zi >= -1), as an element offset.
+__device__ __forceinline__ int first_slot(int zi) { return ((zi + 4) & 3) * kFirstSlot; }
+
+__device__ __forceinline__ void first_store(uint16_t* ring, int zi, const float (&pre)[kFirstFill], float inv) {
+    uint16_t* slot = ring + first_slot(zi);
+#pragma unroll
+    for (int i = 0; i < kFirstFill; ++i) slot[threadIdx.x + i * kCnnBlock] = f2bf(pre[i] * inv);
+}
+
+__global__ __launch_bounds__(kCnnBlock, 2) void k_conv_first(ConvArgs a) {
+    __shared__ uint16_t ring[kFirstSlots * kFirstSlot];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, h = lane >> 5;
+    const float inv = a.scale != nullptr ? 1.f / *a.scale : 1.f;
+    // weight fragments: lane (channel m, half h) of fragment f (cnn_prep_first)
+    v8bf W[2];
+    {
+        const uint4* wq4 = reinterpret_cast<const uint4*>(a.wq);
+#pragma unroll
+        for (int f = 0; f < 2; ++f) W[f] = __builtin_bit_cast(v8bf, wq4[(2 * f + h) * 32 + m]);
+    }
+    // output channel of accumulator register i: (i / 4) 8 + 4 h + i % 4
+    float bias_r[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) bias_r[i] = a.bias[(i >> 2) * 8 + 4 * h + (i & 3)];
+
+    long t = (long)blockIdx.x * a.span;
+    const long total = (long)a.nvol * a.tiles_x * a.tiles_y * a.nz;
+    const long tend = t + a.span < total ? t + a.span : total;
+    ConvSeg sg;
+    while (next_seg(a, t, tend, sg)) {
+        const int x0 = sg.xt * kTileCols, y0 = sg.yt * kTileRows;
+        const int z0 = sg.z0, z1 = sg.z1;
+        const long vol_off = (long)sg.vol * a.nz * a.ny * a.nx;
+        const float* in = a.xin + vol_off;
+        // prologue: inputs z0 - 1, z0, z0 + 1 into their slots, z0 + 2 into
+        // registers; the leading barrier keeps the previous segment's readers
+        // away from the slots
+        float pre[kFirstFill];
+        {
+            float p0[kFirstFill], p1[kFirstFill], p2[kFirstFill];
+            first_fetch(a, in, z0 - 1, y0, x0, p0, true);
+            first_fetch(a, in, z0, y0, x0, p1, true);
+            first_fetch(a, in, z0 + 1, y0, x0, p2, z0 + 1 <= z1);
+            __syncthreads();
+            first_store(ring, z0 - 1, p0, inv);
+            first_store(ring, z0, p1, inv);
+            first_store(ring, z0 + 1, p2, inv);
+            first_fetch(a, in, z0 + 2, y0, x0, pre, z0 + 2 <= z1);
+            __syncthreads();
+        }
+        for (int z = z0; z < z1; ++z) {
+            // input z + 2 into its slot (read from the next step on), input
+            // z + 3 into registers
+            first_store(ring, z + 2, pre, inv);
+            first_fetch(a, in, z + 3, y0, x0, pre, z + 3 <= z1);
+            const int s0 = first_slot(z - 1), s1 = first_slot(z), s2 = first_slot(z + 1);
+            const int sh = h ? s1 : s0;  // fragment 0: range offset h
+            v16f acc[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int base = (4 * wave + r) * kRingCols + m;
+                uint32_t v0[8], v1[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    v0[e] = ring[sh + base + first_tap_off(e)];
+                    // fragment 1: lanes h = 0 read range offset 2, tap e; lanes
+                    // h = 1 read tap 8 of range offset e (e < 3), else zero
+                    const int i1 = e < 3 ? (h ? (e == 0 ? s0 : e == 1 ? s1 : s2) + base + first_tap_off(8)
+                                              : s2 + base + first_tap_off(e))
+                                         : s2 + base + first_tap_off(e);
+                    const uint32_t u = ring[i1];
+                    v1[e] = (e >= 3 && h) ? 0u : u;
+                }
+                const v8bf B0 = __builtin_bit_cast(
+                    v8bf, v4u{v0[0] | (v0[1] << 16), v0[2] | (v0[3] << 16), v0[4] | (v0[5] << 16), v0[6] | (v0[7] << 16)});
+                const v8bf B1 = __builtin_bit_cast(
+                    v8bf, v4u{v1[0] | (v1[1] << 16), v1[2] | (v1[3] << 16), v1[4] | (v1[5] << 16), v1[6] | (v1[7] << 16)});
+                acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(W[0], B0, v16f{}, 0, 0, 0);
+                acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(W[1], B1, acc[r], 0, 0, 0);
+            }
+            // epilogue as k_conv's: rows past the volume get an offset outside
+            // the output slice, which the hardware drops
+            const uint32_t slice_bytes = (uint32_t)(a.ny * a.nx) * 64u;
+            const long slice_off = vol_off + (long)z * a.ny * a.nx;
+            const __amdgpu_buffer_rsrc_t out_rs =
+                __builtin_amdgcn_make_buffer_rsrc(a.out + slice_off * 32, 0, slice_bytes, kBufferWord3);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int y = y0 + 4 * wave + r;
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const uint32_t off =
+                        y < a.ny ? (uint32_t)((y * a.nx + x0 + m) * 64 + 16 * h + 32 * p) : kBufferOutside;
+                    __builtin_amdgcn_raw_buffer_store_b128(out_run<true>(acc[r], p, bias_r), out_rs, off, 0, 0);
+                }
+            }
+            __syncthreads();  // slot z + 2 written; slot z - 1 free for input z + 3
         }
     }
 }
@@ -1034,6 +1192,26 @@ static hipError_t launch_conv(ConvArgs a, long total, hipStream_t st) {
     return hipGetLastError();
 }
 
+// First-layer fragments (k_conv_first): wq[f][h][n][8] = W[t][n] with the
+// model tap t = 9 dz + j of K element (f, h, k8) -- f = 0: dz = h, j = k8;
+// f = 1, h = 0: dz = 2, j = k8; f = 1, h = 1: dz = k8, j = 8 for k8 < 3,
+// else 0 -- for W [27][1][32] (tap, input, output).
+__global__ __launch_bounds__(kCnnBlock) void k_prep_first(const float* W, uint16_t* wq) {
+    const int e = blockIdx.x * kCnnBlock + threadIdx.x;
+    if (e >= 2 * 2 * 32 * 8) return;
+    const int k8 = e % 8, n = (e / 8) % 32, hh = (e / 256) % 2, f = e / 512;
+    int t = -1;
+    if (f == 0) t = 9 * hh + k8;
+    else if (hh == 0) t = 18 + k8;
+    else if (k8 < 3) t = 9 * k8 + 8;
+    wq[e] = f2bf(t >= 0 ? W[t * 32 + n] : 0.f);
+}
+
+hipError_t cnn_prep_first(const float* W, uint16_t* wq, hipStream_t st) {
+    hipLaunchKernelGGL(k_prep_first, dim3(4), dim3(kCnnBlock), 0, st, W, wq);
+    return hipGetLastError();
+}
+
 hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st) {
     // one slice of a 32-channel tensor must stay below the buffer offset that marks "outside"
     if ((long)a.ny * a.nx * 64 >= (long)kBufferOutside) return hipErrorInvalidValue;
@@ -1041,6 +1219,7 @@ hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st) {
     a.tiles_y = (a.ny + kTileRows - 1) / kTileRows;
     const long total = (long)a.nvol * a.tiles_x * a.tiles_y * a.nz;
     if (total <= 0) return hipSuccess;
+    if (cin == 1 && epi == EPI_RELU) return launch_conv<k_conv_first>(a, total, st);
     if (cin == 8 && epi == EPI_RELU) return launch_conv<k_conv<8, EPI_RELU>>(a, total, st);
     if (cin == 32 && epi == EPI_RELU) return launch_conv<k_conv<32, EPI_RELU>>(a, total, st);
     if (cin == 32 && epi == EPI_FINAL) return launch_conv<k_conv_final>(a, total, st);

@@ -105,6 +105,7 @@ struct clamp_cnn {
     float* clip = nullptr;        // gradient-norm clipping state [2]
     uint16_t* wq[kLayers] = {};   // forward weight fragments
     uint16_t* wqd[kLayers] = {};  // backward-data weight fragments
+    uint16_t* wq1 = nullptr;      // first-layer fragments of the one-channel form (evaluation)
     float* bias32[kLayers] = {};
     int step = 0;
     std::vector<void*> dev;
@@ -130,7 +131,7 @@ hipError_t prep_all(clamp_cnn* c, hipStream_t st) {
                                               c->bias32[l], st);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return clampk::cnn_prep_first(c->params + w_offset(0), c->wq1, st);
 }
 
 ConvArgs conv_args(int32_t nvol, int32_t nz, int32_t ny, int32_t nx) {
@@ -143,12 +144,15 @@ ConvArgs conv_args(int32_t nvol, int32_t nz, int32_t ny, int32_t nx) {
 }
 
 // Forward pass; stores every activation when `acts` is non-null (training),
-// else ping-pongs between two buffers.
+// else ping-pongs between two buffers.  Training packs the input into the
+// 8-channel bf16 form (x8), which the first layer's weight gradient reads;
+// evaluation runs the first layer straight from the fp32 volume.
 hipError_t forward(clamp_cnn* c, const float* x, float* out, const float* scale, int32_t nvol, int32_t nz,
                    int32_t ny, int32_t nx, uint16_t* x8, uint16_t* const* acts, uint16_t* ping, uint16_t* pong,
                    hipStream_t st) {
     const long nvox = (long)nvol * nz * ny * nx;
-    hipError_t e = clampk::cnn_pack(x, scale, nvox, x8, st);
+    const bool packed = acts != nullptr;
+    hipError_t e = packed ? clampk::cnn_pack(x, scale, nvox, x8, st) : hipSuccess;
     const uint16_t* in = x8;
     for (int l = 0; l < kLayers && e == hipSuccess; ++l) {
         ConvArgs a = conv_args(nvol, nz, ny, nx);
@@ -158,7 +162,15 @@ hipError_t forward(clamp_cnn* c, const float* x, float* out, const float* scale,
         if (l < kLayers - 1) {
             uint16_t* dst = acts ? acts[l + 1] : ((l % 2 == 0) ? ping : pong);
             a.out = dst;
-            e = clampk::cnn_conv(cinp_of(l), clampk::EPI_RELU, a, st);
+            if (l == 0 && !packed) {
+                a.in = nullptr;
+                a.xin = x;
+                a.scale = scale;
+                a.wq = c->wq1;
+                e = clampk::cnn_conv(1, clampk::EPI_RELU, a, st);
+            } else {
+                e = clampk::cnn_conv(cinp_of(l), clampk::EPI_RELU, a, st);
+            }
             in = dst;
         } else {
             a.out_f32 = out;
@@ -191,6 +203,7 @@ clamp_status clamp_cnn_create(clamp_cnn** out) {
         if (st == CLAMP_OK) st = alloc(c, clampk::cnn_wq_elems(coutp_of(l)), &c->wqd[l]);
         if (st == CLAMP_OK) st = alloc(c, 32, &c->bias32[l]);
     }
+    if (st == CLAMP_OK) st = alloc(c, 2 * 2 * 32 * 8, &c->wq1);
     if (st == CLAMP_OK) {
         std::vector<float> zero(CLAMP_CNN_PARAMS, 0.f);
         st = clamp_cnn_set_params(c, zero.data());
