@@ -185,7 +185,7 @@ def phases_counters(path, counters):
     return "\n".join(out)
 
 
-CNN_APPLY = (r"k_pack\(", r"k_conv<", r"k_conv_final\(", r"k_sum_partial\(", r"k_mean_final\(")
+CNN_APPLY = (r"k_pack\(", r"k_conv_first\(", r"k_conv<", r"k_conv_final\(", r"k_sum_partial\(", r"k_mean_final\(")
 
 
 def cnn_traffic(fetch_csv, write_csv, probe_mib):
@@ -256,7 +256,7 @@ def main(argv=None):
             rec = json.load(open(a.out)) if os.path.exists(a.out) else {}
             rec[a.workload] = {"source_sha256": kernel_source_hash("cnn"), "read_bytes": r["read_bytes"],
                                "write_bytes": r["write_bytes"],
-                               "launches": "pack, first, six middle and output convolutions, scale reductions"}
+                               "launches": "first (from the fp32 volume), six middle and output convolutions, scale reductions"}
             with open(a.out, "w") as f:
                 json.dump(rec, f, indent=1)
                 f.write("\n")

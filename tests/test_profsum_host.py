@@ -50,13 +50,14 @@ def test_traffic_scales_by_the_copy_probe_and_skips_first_launches(tmp_path):
 def test_cnn_application_bytes_from_the_evaluation_phase(tmp_path):
     """CNN kernels before the first CLAMP iteration kernel are training;
     after it, two applications (two output layers) of 10 + 30 + 20 fetched
-    units each."""
+    units each: one opening with the packed input, one with the first layer
+    read from the fp32 volume."""
     fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
     conv, fin = "void clampk::k_conv<32, 0>(clampk::ConvArgs)", "clampk::k_conv_final(clampk::ConvArgs)"
     rows = [(1, "__amd_rocclr_copyBuffer", 512.0), (2, conv, 777.0), (3, fin, 777.0),
             (4, "void clampk::k_row_grad<256>(clampk::RowArgs)", 5.0),
             (5, "clampk::k_pack(float const*, float const*, long, unsigned short*)", 10.0), (6, conv, 30.0),
-            (7, fin, 20.0), (8, "clampk::k_pack(float const*, float const*, long, unsigned short*)", 10.0),
+            (7, fin, 20.0), (8, "clampk::k_conv_first(clampk::ConvArgs)", 10.0),
             (9, conv, 30.0), (10, fin, 20.0)]
     _counter_csv(fetch, "FETCH_SIZE", rows)
     _counter_csv(write, "WRITE_SIZE", [(d, k, 1024.0 if "copy" in k else v) for d, k, v in rows])
