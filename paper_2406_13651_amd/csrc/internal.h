@@ -9,10 +9,12 @@ namespace clampk {
 
 constexpr int kBlock = 256;      // threads per block for every kernel
 
-// Band columns per column-pass work item: 16 (128-byte row segments) up to
-// length 256; 8 for longer columns, which keeps each thread's share of an
-// item at 16 values.
-__host__ __device__ constexpr int col_tile_cols(int ny) { return ny >= 384 ? 8 : 16; }
+// Band columns per column tile: 16, except 8 for 384-row columns, where a
+// 16-column tile takes the forward column pass past its registers (spills).
+// At 512, 16 columns give the row passes 128-byte runs per tile row (8 gave
+// 64-byte runs, 3-7% slower update and gradient passes), while the column
+// passes hold two blocks per CU instead of four at about the same time.
+__host__ __device__ constexpr int col_tile_cols(int ny) { return ny == 384 ? 8 : 16; }
 
 // Band buffers (the column transforms of a slice kept only on its B band
 // columns) hold each (look, slice) as ny Bs values, Bs = tiles TC with
