@@ -898,8 +898,8 @@ def main():
                          "known-size reference for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on one GPU and has no multi-GPU path "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":
