@@ -772,6 +772,11 @@ def run_compare(args):
     print(json.dumps(result), flush=True)
 
 
+# The padded workload's cases: (name, zero-padding factor q, all-pass
+# aperture); q = 1, 1.5, 2 are the factors of Sec. V.
+PADDED_CASES = [("q=1", 1.0, False), ("q=1.5", 1.5, False), ("q=2", 2.0, False), ("ablation a=1, q=1", 1.0, True)]
+
+
 def run_padded(args):
     """The 3D operator with zero-padding in range (Sec. II-A): the full-size
     scene with its 64 range samples padded by q in {1, 1.5, 2} (nz = 64 q, a
@@ -792,9 +797,9 @@ def run_padded(args):
     torch.cuda.set_device(dev)
     base = synth.CONFIGS["full"]
     K = base.nz
-    cases = [("q=1", 64, False), ("q=1.5", 96, False), ("q=2", 128, False), ("ablation a=1, q=1", 64, True)]
     rows = {}
-    for name, nz, allpass in cases:
+    for name, q, allpass in PADDED_CASES:
+        nz = int(round(base.nz * q))
         spec = synth.SceneSpec(base.name, base.nx, base.ny, nz, base.looks, base.radius, base.snr_db,
                                base.n_facets, base.r_min, base.n_objects, base.config_id)
         log("%s: %dx%dx%d, range box %d, %d looks" % (name, spec.nx, spec.ny, nz, K, spec.looks))
@@ -863,7 +868,7 @@ def run_padded(args):
     print(json.dumps(result), flush=True)
 
 
-def main():
+def parser():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -896,7 +901,11 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy MIB mebibytes once with a plain device copy, as a "
                          "known-size reference for hardware byte counters")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = parser().parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs on one GPU and has no multi-GPU path "
               "(got --gpus %d)" % args.gpus, file=sys.stderr)
