@@ -99,14 +99,15 @@ constexpr int kTileCols = 32;
 constexpr int kRingRows = kTileRows + 2;
 constexpr int kRingCols = kTileCols + 2;
 
-template <int CIN>
+// NT: threads of the block that fills the slots.
+template <int CIN, int NT = kCnnBlock>
 struct TileGeo {
     static constexpr int kChunks = CIN / 8;                              // 16-byte chunks per voxel
     static constexpr int kSlice = kRingRows * kRingCols * kChunks;      // chunks per input slot
     static constexpr int kQ = CIN == 32 ? 6 : 2;                         // K fragments per (dz, dy)
     static constexpr int kW = 9 * kQ * 64;                               // weight chunks (16 bytes)
-    static constexpr int kFill = (kSlice + kCnnBlock - 1) / kCnnBlock;  // chunks per thread per slice
-    static constexpr int kSlot = kFill * kCnnBlock;                      // slot size, padded for branch-free stores
+    static constexpr int kFill = (kSlice + NT - 1) / NT;                 // chunks per thread per slice
+    static constexpr int kSlot = kFill * NT;                             // slot size, padded for branch-free stores
 };
 
 template <int CIN>
@@ -119,10 +120,10 @@ __device__ __forceinline__ int ring_pos(int ys, int xs, int j) {
 // branch-free: buffer loads relative to the slice, whose size is 0 when the
 // slice lies outside the volume or is not wanted (live = false), and an
 // offset outside it for halo voxels outside the volume -- those read 0.
-template <int CIN>
+template <int CIN, int NT = kCnnBlock>
 __device__ __forceinline__ void tile_fetch(const ConvArgs& a, const uint16_t* in, int zin, int y0, int x0,
-                                           uint4 (&pre)[TileGeo<CIN>::kFill], bool live = true) {
-    using G = TileGeo<CIN>;
+                                           uint4 (&pre)[TileGeo<CIN, NT>::kFill], bool live = true) {
+    using G = TileGeo<CIN, NT>;
     const bool zok = live && zin >= 0 && zin < a.nz;
     const long plane = (long)a.ny * a.nx;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -130,7 +131,7 @@ __device__ __forceinline__ void tile_fetch(const ConvArgs& a, const uint16_t* in
         kBufferWord3);
 #pragma unroll
     for (int i = 0; i < G::kFill; ++i) {
-        const int e = threadIdx.x + i * kCnnBlock;
+        const int e = threadIdx.x + i * NT;
         const int j = e % G::kChunks, vox = e / G::kChunks;
         const int xs = vox % kRingCols, ys = vox / kRingCols;
         const int y = y0 - 1 + ys, x = x0 - 1 + xs;
@@ -145,19 +146,19 @@ __device__ __forceinline__ void tile_fetch(const ConvArgs& a, const uint16_t* in
 // the slice (e >= kSlice) are stored unguarded into the padding -- ring_pos
 // maps them to e itself, up to a permutation of its four chunks -- which
 // keeps the store free of branches.
-template <int CIN>
-__device__ __forceinline__ void tile_store(uint4* slot, const uint4 (&pre)[TileGeo<CIN>::kFill]) {
-    using G = TileGeo<CIN>;
+template <int CIN, int NT = kCnnBlock>
+__device__ __forceinline__ void tile_store(uint4* slot, const uint4 (&pre)[TileGeo<CIN, NT>::kFill]) {
+    using G = TileGeo<CIN, NT>;
 #pragma unroll
     for (int i = 0; i < G::kFill; ++i) {
-        const int e = threadIdx.x + i * kCnnBlock;
+        const int e = threadIdx.x + i * NT;
         const int j = e % G::kChunks, vox = e / G::kChunks;
         slot[ring_pos<CIN>(vox / kRingCols, vox % kRingCols, j)] = pre[i];
     }
 }
 
-template <int CIN>
-using RingSlots = uint4[2][TileGeo<CIN>::kSlot];
+template <int CIN, int NT = kCnnBlock>
+using RingSlots = uint4[2][TileGeo<CIN, NT>::kSlot];
 
 // Persistent work split of the convolutions: output tile-slices, numbered
 // t = ((vol tiles_y + yt) tiles_x + xt) nz + z (z fastest), go to blocks in
@@ -184,33 +185,34 @@ __device__ __forceinline__ bool next_seg(const ConvArgs& a, long& t, long tend, 
 // Segment prologue: inputs z0 - 1 and z0 into the two slots (fetched
 // together), input z0 + 1 into registers.  The leading barrier keeps the
 // previous segment's readers away from the slots.
-template <int CIN>
+template <int CIN, int NT>
 __device__ __forceinline__ void seg_prologue(const ConvArgs& a, const uint16_t* in, int z0, int y0, int x0,
-                                             RingSlots<CIN>& ring, uint4 (&pre)[TileGeo<CIN>::kFill]) {
-    uint4 pre0[TileGeo<CIN>::kFill];
-    tile_fetch<CIN>(a, in, z0 - 1, y0, x0, pre0);
-    tile_fetch<CIN>(a, in, z0, y0, x0, pre);
+                                             RingSlots<CIN, NT>& ring, uint4 (&pre)[TileGeo<CIN, NT>::kFill]) {
+    uint4 pre0[TileGeo<CIN, NT>::kFill];
+    tile_fetch<CIN, NT>(a, in, z0 - 1, y0, x0, pre0);
+    tile_fetch<CIN, NT>(a, in, z0, y0, x0, pre);
     __syncthreads();
-    tile_store<CIN>(ring[0], pre0);
-    tile_store<CIN>(ring[1], pre);
-    tile_fetch<CIN>(a, in, z0 + 1, y0, x0, pre);
+    tile_store<CIN, NT>(ring[0], pre0);
+    tile_store<CIN, NT>(ring[1], pre);
+    tile_fetch<CIN, NT>(a, in, z0 + 1, y0, x0, pre);
     __syncthreads();
 }
 
 // One stage of a convolution step: the MFMA operands of range offset dz
-// (index 0..2) and K fragment q -- six input rows of the wave (X) and the
-// weights of the three row offsets dy (W) -- and the twelve products they
-// feed: acc[r] += W[dy]^T X[r + dy]^T.  Operands of the next stage are loaded
-// while the current stage's products run, so that LDS latency overlaps the
-// matrix cores with a single wave per SIMD.
+// (index 0..2) and K fragment q -- the RPW + 2 input rows of the wave's RPW
+// output rows (X) and the weights of the three row offsets dy (W) -- and
+// the 3 RPW products they feed: acc[r] += W[dy]^T X[r + dy]^T.  Operands of
+// the next stage are loaded while the current stage's products run, so that
+// LDS latency overlaps the matrix cores.
+template <int RPW>
 struct ConvFrag {
-    v8bf X[6];
+    v8bf X[RPW + 2];
     v8bf W[3];
 };
 
-template <int CIN>
+template <int CIN, int RPW>
 __device__ __forceinline__ void frag_load(const uint4* slot, const uint4* wsh, int dz, int q, int wave, int m, int h,
-                                          ConvFrag& f) {
+                                          ConvFrag<RPW>& f) {
     using G = TileGeo<CIN>;
     int xs, j;
     if constexpr (CIN == 32) {
@@ -221,34 +223,43 @@ __device__ __forceinline__ void frag_load(const uint4* slot, const uint4* wsh, i
         j = 0;
     }
 #pragma unroll
-    for (int rr = 0; rr < 6; ++rr) f.X[rr] = __builtin_bit_cast(v8bf, slot[ring_pos<CIN>(4 * wave + rr, xs, j)]);
+    for (int rr = 0; rr < RPW + 2; ++rr)
+        f.X[rr] = __builtin_bit_cast(v8bf, slot[ring_pos<CIN>(RPW * wave + rr, xs, j)]);
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
         f.W[dy] = __builtin_bit_cast(v8bf, wsh[(((dz * 3 + dy) * G::kQ + q) * 2 + h) * 32 + m]);
 }
 
-__device__ __forceinline__ void frag_mma(const ConvFrag& f, v16f (&acc)[4]) {
+template <int RPW>
+__device__ __forceinline__ void frag_mma(const ConvFrag<RPW>& f, v16f (&acc)[RPW]) {
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.W[dy], f.X[r + dy], acc[r], 0, 0, 0);
+        for (int r = 0; r < RPW; ++r)
+            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.W[dy], f.X[r + dy], acc[r], 0, 0, 0);
 }
 
 // Instruction order of one pipelined stage (mask 0x100: LDS reads, 0x200: LDS
-// writes, 0x8: MFMA): each of the next stage's nine LDS reads issues beside
-// one of the current stage's MFMAs, so that they complete long before they
-// are waited on, and up to three LDS writes of a slice refill ride on the
-// stage's last three MFMAs.
+// writes, 0x8: MFMA): each of the next stage's RPW + 5 LDS reads issues
+// beside one of the current stage's 3 RPW MFMAs (two of them beside the
+// first MFMA when the reads outnumber the products), so that they complete
+// long before they are waited on, and up to three LDS writes of a slice
+// refill ride on the stage's last three MFMAs.
 // (The arguments are constants once the stage loops are unrolled.)
+template <int RPW>
 __device__ __forceinline__ void sched_stage(bool loads, int writes) {
+    constexpr int NM = 3 * RPW, NR = RPW + 5;
+    constexpr int PAIRED = NR < NM - 3 ? NR : NM - 3;  // reads beside the MFMAs before the last three
     if (loads) {
+        if constexpr (NR > PAIRED) __builtin_amdgcn_sched_group_barrier(0x100, NR - PAIRED, 0);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
+        for (int i = 0; i < PAIRED; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x8, 1, 0);
         }
+        if constexpr (NM - 3 > PAIRED) __builtin_amdgcn_sched_group_barrier(0x8, NM - 3 - PAIRED, 0);
     } else {
-        __builtin_amdgcn_sched_group_barrier(0x8, 9, 0);
+        __builtin_amdgcn_sched_group_barrier(0x8, NM - 3, 0);
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -258,9 +269,9 @@ __device__ __forceinline__ void sched_stage(bool loads, int writes) {
 }
 
 // LDS writes of the slice refill carried by stage q (three per stage).
-template <int CIN>
+template <int CIN, int NT>
 __device__ constexpr int store_share(int q) {
-    const int left = TileGeo<CIN>::kFill - 3 * q;
+    const int left = TileGeo<CIN, NT>::kFill - 3 * q;
     return left <= 0 ? 0 : left < 3 ? left : 3;
 }
 
@@ -289,28 +300,35 @@ __device__ __forceinline__ v4u out_run(const v16f& acc, int p, const float (&bia
     return v4u{s0[0], s1[0], s0[1], s1[1]};
 }
 
-template <int CIN, int EPI>
-__global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
+// RPW output rows per wave: 16 / RPW waves per block (one per SIMD at
+// RPW = 4, two at RPW = 2), each slot fill shared by all of them.
+template <int RPW>
+constexpr int conv_threads() { return 64 * kTileRows / RPW; }
+
+template <int CIN, int EPI, int RPW>
+__global__ __launch_bounds__(conv_threads<RPW>(), 1) void k_conv(ConvArgs a) {
     static_assert(EPI == EPI_RELU || EPI == EPI_DGRAD || EPI == EPI_RAW, "the final layer runs in k_conv_final");
-    using G = TileGeo<CIN>;
-    __shared__ RingSlots<CIN> ring;
+    constexpr int NT = conv_threads<RPW>();
+    constexpr int NRD = RPW + 5;  // LDS reads of one stage
+    using G = TileGeo<CIN, NT>;
+    __shared__ RingSlots<CIN, NT> ring;
     __shared__ uint4 wsh[G::kW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
 
     // weight fragments, once per block: every load in flight, then into LDS
     {
-        constexpr int kWl = (G::kW + kCnnBlock - 1) / kCnnBlock;
+        constexpr int kWl = (G::kW + NT - 1) / NT;
         const uint4* wq4 = reinterpret_cast<const uint4*>(a.wq);
         uint4 w[kWl];
 #pragma unroll
         for (int i = 0; i < kWl; ++i) {
-            const int e = threadIdx.x + i * kCnnBlock;
+            const int e = threadIdx.x + i * NT;
             w[i] = e < G::kW ? wq4[e] : make_uint4(0u, 0u, 0u, 0u);
         }
 #pragma unroll
         for (int i = 0; i < kWl; ++i) {
-            const int e = threadIdx.x + i * kCnnBlock;
+            const int e = threadIdx.x + i * NT;
             if (e < G::kW) wsh[e] = w[i];
         }
     }
@@ -329,13 +347,13 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
         const long vol_off = (long)sg.vol * a.nz * a.ny * a.nx;
         const uint16_t* in = a.in + vol_off * CIN;
         uint4 pre[G::kFill];
-        seg_prologue<CIN>(a, in, z0, y0, x0, ring, pre);
+        seg_prologue<CIN, NT>(a, in, z0, y0, x0, ring, pre);
 
         int old = 0;  // slot of input z - 1; the other slot holds input z
         for (int z = z0; z < z1; ++z) {
-            v16f acc[4];
+            v16f acc[RPW];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[r] = v16f{};
+            for (int r = 0; r < RPW; ++r) acc[r] = v16f{};
             constexpr int S = G::kQ;  // stages per range offset
             // output slice z: its byte size, element offset, and the byte offset of
             // lane (m, h)'s 16-byte run p of row r of the wave (outside the slice for
@@ -343,68 +361,68 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
             const uint32_t slice_bytes = (uint32_t)(a.ny * a.nx) * 64u;
             const long slice_off = vol_off + (long)z * a.ny * a.nx;
             auto out_off = [&](int r, int p) {
-                const int y = y0 + 4 * wave + r;
+                const int y = y0 + RPW * wave + r;
                 return y < a.ny ? (uint32_t)((y * a.nx + x0 + m) * 64 + 16 * h + 32 * p) : kBufferOutside;
             };
-            v4u keep[4][2];  // backward-data pass: ReLU mask of the layer input at the outputs
-            ConvFrag f[2];
+            v4u keep[RPW][2];  // backward-data pass: ReLU mask of the layer input at the outputs
+            ConvFrag<RPW> f[2];
             // dz = 0: input z - 1
-            frag_load<CIN>(ring[old], wsh, 0, 0, wave, m, h, f[0]);
-            __builtin_amdgcn_sched_group_barrier(0x100, 9, 0);
+            frag_load<CIN, RPW>(ring[old], wsh, 0, 0, wave, m, h, f[0]);
+            __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 if (q + 1 < S) {
-                    frag_load<CIN>(ring[old], wsh, 0, q + 1, wave, m, h, f[(q + 1) & 1]);
+                    frag_load<CIN, RPW>(ring[old], wsh, 0, q + 1, wave, m, h, f[(q + 1) & 1]);
                     frag_mma(f[q & 1], acc);
-                    sched_stage(true, 0);
+                    sched_stage<RPW>(true, 0);
                 } else {
                     frag_mma(f[q & 1], acc);
-                    sched_stage(false, 0);
+                    sched_stage<RPW>(false, 0);
                 }
             }
             __syncthreads();  // every wave is done with input z - 1
             // dz = 1: input z; meanwhile input z + 1 replaces z - 1 and z + 2 is fetched
-            frag_load<CIN>(ring[old ^ 1], wsh, 1, 0, wave, m, h, f[0]);
-            tile_store<CIN>(ring[old], pre);
-            tile_fetch<CIN>(a, in, z + 2, y0, x0, pre, z + 1 < z1);
+            frag_load<CIN, RPW>(ring[old ^ 1], wsh, 1, 0, wave, m, h, f[0]);
+            tile_store<CIN, NT>(ring[old], pre);
+            tile_fetch<CIN, NT>(a, in, z + 2, y0, x0, pre, z + 1 < z1);
             if constexpr (EPI == EPI_DGRAD) {
                 const __amdgpu_buffer_rsrc_t keep_rs = __builtin_amdgcn_make_buffer_rsrc(
                     const_cast<uint16_t*>(a.relu_src) + slice_off * 32, 0, slice_bytes, kBufferWord3);
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int r = 0; r < RPW; ++r)
 #pragma unroll
                     for (int p = 0; p < 2; ++p) keep[r][p] = __builtin_amdgcn_raw_buffer_load_b128(keep_rs, out_off(r, p), 0, 0);
             }
-            __builtin_amdgcn_sched_group_barrier(0x100, 9, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 if (q + 1 < S) {
-                    frag_load<CIN>(ring[old ^ 1], wsh, 1, q + 1, wave, m, h, f[(q + 1) & 1]);
+                    frag_load<CIN, RPW>(ring[old ^ 1], wsh, 1, q + 1, wave, m, h, f[(q + 1) & 1]);
                     frag_mma(f[q & 1], acc);
-                    sched_stage(true, store_share<CIN>(q));
+                    sched_stage<RPW>(true, store_share<CIN, NT>(q));
                 } else {
                     frag_mma(f[q & 1], acc);
-                    sched_stage(false, store_share<CIN>(q));
+                    sched_stage<RPW>(false, store_share<CIN, NT>(q));
                 }
             }
             __syncthreads();  // input z + 1 is in place
             // dz = 2: input z + 1
-            frag_load<CIN>(ring[old], wsh, 2, 0, wave, m, h, f[0]);
-            __builtin_amdgcn_sched_group_barrier(0x100, 9, 0);
+            frag_load<CIN, RPW>(ring[old], wsh, 2, 0, wave, m, h, f[0]);
+            __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 if (q + 1 < S) {
-                    frag_load<CIN>(ring[old], wsh, 2, q + 1, wave, m, h, f[(q + 1) & 1]);
+                    frag_load<CIN, RPW>(ring[old], wsh, 2, q + 1, wave, m, h, f[(q + 1) & 1]);
                     frag_mma(f[q & 1], acc);
-                    sched_stage(true, 0);
+                    sched_stage<RPW>(true, 0);
                 } else {
                     frag_mma(f[q & 1], acc);
-                    sched_stage(false, 0);
+                    sched_stage<RPW>(false, 0);
                 }
             }
             old ^= 1;
 
-            // epilogue: lane (voxel x0 + m, half h) of output row 4 wave + r holds
+            // epilogue: lane (voxel x0 + m, half h) of output row RPW wave + r holds
             // channels 8 g + 4 h + 0..3 (g = 0..3); a swap between the lane halves
             // turns the pairs of groups (2 p, 2 p + 1) into 8 consecutive channels
             // 16 p + 8 h + 0..7 per lane, stored as one 16-byte run.  Buffer
@@ -415,7 +433,7 @@ __global__ __launch_bounds__(kCnnBlock, 1) void k_conv(ConvArgs a) {
             const __amdgpu_buffer_rsrc_t out_rs =
                 __builtin_amdgcn_make_buffer_rsrc(a.out + slice_off * 32, 0, slice_bytes, kBufferWord3);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < RPW; ++r) {
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     const uint32_t off = out_off(r, p);
@@ -1177,20 +1195,25 @@ static int grid_for(long work, int per_block, int cap) {
 // once (resident blocks per CU, which the kernel's LDS and registers decide,
 // times the CU count; computed once per kernel), each with a contiguous run
 // of output tile-slices.
-template <void (*K)(ConvArgs)>
+template <void (*K)(ConvArgs), int NT = kCnnBlock>
 static hipError_t launch_conv(ConvArgs a, long total, hipStream_t st) {
     static int cap = 0;
     if (cap == 0) {
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K, kCnnBlock, 0) != hipSuccess || per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K, NT, 0) != hipSuccess || per_cu < 1)
             per_cu = 1;
         cap = per_cu * cnn_wgrad_grid();
     }
     a.span = (int)((total + cap - 1) / cap);
     const unsigned grid = (unsigned)((total + a.span - 1) / a.span);
-    hipLaunchKernelGGL(K, dim3(grid), dim3(kCnnBlock), 0, st, a);
+    hipLaunchKernelGGL(K, dim3(grid), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
+
+// Rows per wave of the 8- and 32-channel convolutions: two for the forward
+// layers, four for the backward-data ones.
+template <int EPI>
+constexpr int conv_rpw() { return EPI == EPI_RELU ? 2 : 4; }
 
 // First-layer fragments (k_conv_first): wq[f][h][n][8] = W[t][n] with the
 // model tap t = 9 dz + j of K element (f, h, k8) -- f = 0: dz = h, j = k8;
@@ -1220,13 +1243,15 @@ hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st) {
     const long total = (long)a.nvol * a.tiles_x * a.tiles_y * a.nz;
     if (total <= 0) return hipSuccess;
     if (cin == 1 && epi == EPI_RELU) return launch_conv<k_conv_first>(a, total, st);
-    if (cin == 8 && epi == EPI_RELU) return launch_conv<k_conv<8, EPI_RELU>>(a, total, st);
-    if (cin == 32 && epi == EPI_RELU) return launch_conv<k_conv<32, EPI_RELU>>(a, total, st);
+#define CONV(C, E) launch_conv<k_conv<C, E, conv_rpw<E>()>, conv_threads<conv_rpw<E>()>()>(a, total, st)
+    if (cin == 8 && epi == EPI_RELU) return CONV(8, EPI_RELU);
+    if (cin == 32 && epi == EPI_RELU) return CONV(32, EPI_RELU);
     if (cin == 32 && epi == EPI_FINAL) return launch_conv<k_conv_final>(a, total, st);
-    if (cin == 8 && epi == EPI_DGRAD) return launch_conv<k_conv<8, EPI_DGRAD>>(a, total, st);
-    if (cin == 32 && epi == EPI_DGRAD) return launch_conv<k_conv<32, EPI_DGRAD>>(a, total, st);
-    if (cin == 8 && epi == EPI_RAW) return launch_conv<k_conv<8, EPI_RAW>>(a, total, st);
-    if (cin == 32 && epi == EPI_RAW) return launch_conv<k_conv<32, EPI_RAW>>(a, total, st);
+    if (cin == 8 && epi == EPI_DGRAD) return CONV(8, EPI_DGRAD);
+    if (cin == 32 && epi == EPI_DGRAD) return CONV(32, EPI_DGRAD);
+    if (cin == 8 && epi == EPI_RAW) return CONV(8, EPI_RAW);
+    if (cin == 32 && epi == EPI_RAW) return CONV(32, EPI_RAW);
+#undef CONV
     return hipErrorInvalidValue;
 }
 
