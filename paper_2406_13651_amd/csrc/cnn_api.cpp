@@ -65,7 +65,7 @@ Layout layout(long nvox, bool train) {
         o = align256(o + bytes);
         return at;
     };
-    L.x8 = take(nvox * 16);
+    if (train) L.x8 = take(nvox * 16);  // evaluation reads the fp32 input in the first layer
     if (train) {
         for (int l = 1; l < kLayers; ++l) L.act[l] = take(nvox * 64);
         L.out = take(nvox * 4);
@@ -272,7 +272,7 @@ clamp_status clamp_cnn_apply(clamp_cnn* cnn, const float* x, float* out, int32_t
         e = clampk::cnn_mean(x, nvox, at<double>(workspace, L.part), mean, s);
     }
     if (e == hipSuccess)
-        e = forward(cnn, x, out, mean, nvol, nz, ny, nx, at<uint16_t>(workspace, L.x8), nullptr,
+        e = forward(cnn, x, out, mean, nvol, nz, ny, nx, nullptr, nullptr,
                     at<uint16_t>(workspace, L.act[1]), at<uint16_t>(workspace, L.act[2]), s);
     return hip_check(e, "clamp_cnn_apply launch");
 }

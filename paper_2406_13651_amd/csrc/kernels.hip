@@ -126,8 +126,11 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs a) {
 // col_fwd_stream.  Three waves per SIMD: the LDS tile allows three or four
 // blocks per CU, and the prefetched band rows plus the item's pupil rows
 // would otherwise take the register count just past the three-wave limit.
+// At 512 (16-column tiles of 64 KB, two blocks per CU) each thread holds 32
+// values of an item, and two waves per SIMD is what fits.
 template <int NY>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_col_fwd(ColArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NY == 512 ? 2 : 3))) void k_col_fwd(
+    ColArgs a) {
     __shared__ float2 tw[NY];
     __shared__ float2 tile[NY * col_tile_cols(NY)];
     for (int i = threadIdx.x; i < NY; i += kBlock) tw[i] = a.s.tw_y[i];

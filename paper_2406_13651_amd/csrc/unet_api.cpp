@@ -59,10 +59,10 @@ clamp_status hip_check(hipError_t e, const char* what) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace of the evaluation pass (V voxels at level 0, V / 8^k at level k):
-// level 0: packed input, e1 and two buffers; levels 1 and 2: e and two
-// buffers; level 3: the pooled bottom.
+// levels 0, 1 and 2: e and two buffers; level 3: the pooled bottom (the
+// first convolution reads the fp32 input itself).
 struct Layout {
-    size_t x8, e[kLevels], t[kLevels][2], p3, mean, part, total;
+    size_t e[kLevels], t[kLevels][2], p3, mean, part, total;
 };
 
 Layout layout(long nvox) {
@@ -73,7 +73,6 @@ Layout layout(long nvox) {
         o = align256(o + bytes);
         return at;
     };
-    L.x8 = take(nvox * 16);
     long v = nvox;
     for (int k = 0; k < kLevels; ++k, v /= 8) {
         L.e[k] = take(v * 64);
@@ -109,6 +108,7 @@ struct clamp_unet {
     float* wfold = nullptr;             // fp32 scratch [27][32][32] of one folded convolution
     float* bfold = nullptr;             // fp32 scratch [32]
     uint16_t* wq[kConvs + 1] = {};      // forward fragments of the 12 convolutions and the final one
+    uint16_t* wq1 = nullptr;            // the first convolution in the one-channel form (k_conv_first)
     float* bias32[kConvs + 1] = {};     // padded biases (folded for the 12)
     uint16_t* wup[kLevels] = {};        // transposed-convolution fragments (forward)
     bool eval_ready = false;
@@ -151,6 +151,9 @@ hipError_t prep_eval(clamp_unet* u, hipStream_t st) {
         if (e == hipSuccess)
             e = clampk::cnn_prep(u->wfold, u->bfold, cin_of(l), kWidth, cinp_of(l), kWidth, u->wq[l], nullptr,
                                  u->bias32[l], st);
+        // the first convolution also in the one-channel form, before the
+        // next fold overwrites the scratch
+        if (e == hipSuccess && l == 0) e = clampk::cnn_prep_first(u->wfold, u->wq1, st);
     }
     for (int j = 0; j < kLevels && e == hipSuccess; ++j) e = clampk::unet_prep_up(u->params + up_w(j), 0, u->wup[j], st);
     if (e == hipSuccess)
@@ -171,7 +174,6 @@ ConvArgs conv_args(int32_t nvol, int32_t nz, int32_t ny, int32_t nx) {
 // Evaluation-mode forward pass.
 hipError_t forward_eval(clamp_unet* u, const float* x, float* out, const float* scale, int32_t nvol, int32_t nz,
                         int32_t ny, int32_t nx, void* ws, const Layout& L, hipStream_t st) {
-    const long nvox = (long)nvol * nz * ny * nx;
     int dz[kLevels + 1], dy[kLevels + 1], dx[kLevels + 1];
     for (int k = 0; k <= kLevels; ++k) {
         dz[k] = nz >> k;
@@ -186,7 +188,6 @@ hipError_t forward_eval(clamp_unet* u, const float* x, float* out, const float* 
         a.out = o;
         return clampk::cnn_conv(cinp_of(l), clampk::EPI_RELU, a, st);
     };
-    uint16_t* x8 = at<uint16_t>(ws, L.x8);
     uint16_t* e_[kLevels];
     uint16_t* t[kLevels][2];
     for (int k = 0; k < kLevels; ++k) {
@@ -195,11 +196,22 @@ hipError_t forward_eval(clamp_unet* u, const float* x, float* out, const float* 
         t[k][1] = at<uint16_t>(ws, L.t[k][1]);
     }
     uint16_t* p3 = at<uint16_t>(ws, L.p3);
-    hipError_t e = clampk::cnn_pack(x, scale, nvox, x8, st);
-    // encoder: block k reads the pooled output of block k - 1 (held in t[k][1])
-    const uint16_t* in = x8;
+    // encoder: block k reads the pooled output of block k - 1 (held in
+    // t[k][1]); the first convolution reads the fp32 volume itself
+    hipError_t e = hipSuccess;
+    const uint16_t* in = nullptr;
     for (int k = 0; k < kLevels && e == hipSuccess; ++k) {
-        e = conv(2 * k, k, in, t[k][0]);
+        if (k == 0) {
+            ConvArgs a = conv_args(nvol, nz, ny, nx);
+            a.xin = x;
+            a.scale = scale;
+            a.wq = u->wq1;
+            a.bias = u->bias32[0];
+            a.out = t[0][0];
+            e = clampk::cnn_conv(1, clampk::EPI_RELU, a, st);
+        } else {
+            e = conv(2 * k, k, in, t[k][0]);
+        }
         if (e == hipSuccess) e = conv(2 * k + 1, k, t[k][0], e_[k]);
         uint16_t* pooled = k + 1 < kLevels ? t[k + 1][1] : p3;
         if (e == hipSuccess) e = clampk::unet_pool(e_[k], pooled, nvol, dz[k], dy[k], dx[k], st);
@@ -512,6 +524,7 @@ clamp_status clamp_unet_create(clamp_unet** out) {
         st = alloc(u, clampk::cnn_wq_elems(l == kConvs ? kWidth : cinp_of(l)), &u->wq[l]);
         if (st == CLAMP_OK) st = alloc(u, 32, &u->bias32[l]);
     }
+    if (st == CLAMP_OK) st = alloc(u, 2 * 2 * 32 * 8, &u->wq1);
     for (int j = 0; j < kLevels && st == CLAMP_OK; ++j) st = alloc(u, 8 * 2 * 64 * 8, &u->wup[j]);
     if (st == CLAMP_OK) st = alloc(u, CLAMP_UNET_PARAMS, &u->m);
     if (st == CLAMP_OK) st = alloc(u, CLAMP_UNET_PARAMS, &u->v);

@@ -137,7 +137,9 @@ def traffic(fetch_csv, write_csv, probe_mib, skip_first=1):
     return per, f_scale / 1024.0, w_scale / 1024.0
 
 
-CNN_KERNELS = (r"k_conv", r"k_wgrad", r"k_pack\(", r"k_grad_clip\(", r"k_prep_", r"k_adam\(", r"k_loss")
+CNN_KERNELS = (r"k_conv", r"k_wgrad", r"k_pack\(", r"k_grad_clip\(", r"k_prep_", r"k_adam\(", r"k_loss",
+               # the U-Net's own kernels (pooling, transposed convolutions, batch normalisation)
+               r"k_upconv", r"k_pool2", r"k_chan_", r"k_affine<", r"k_fold_bn\(", r"k_sum_blocks\(")
 
 
 def _phase_start(ids_names):
@@ -148,7 +150,7 @@ def _phase_start(ids_names):
 
 
 def _short(name):
-    return name.split("(")[0].replace("void ", "").replace("clampk::", "")
+    return name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("clampk::", "")
 
 
 def phases_trace(path, top=14):
@@ -160,9 +162,9 @@ def phases_trace(path, top=14):
         if any(re.search(p, r["Kernel_Name"]) for p in CNN_KERNELS):
             ph = "evaluation" if i >= start else "training"
             acc[(_short(r["Kernel_Name"]), ph)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    out = ["| kernel | phase | launches | avg us |", "|---|---|---:|---:|"]
+    out = ["| kernel | phase | launches | avg us | total us |", "|---|---|---:|---:|---:|"]
     for (k, ph), v in sorted(acc.items(), key=lambda kv: -sum(kv[1]))[:top]:
-        out.append("| `%s` | %s | %d | %.1f |" % (k, ph, len(v), sum(v) / len(v)))
+        out.append("| `%s` | %s | %d | %.1f | %.0f |" % (k, ph, len(v), sum(v) / len(v), sum(v)))
     return "\n".join(out)
 
 
@@ -232,6 +234,7 @@ def main(argv=None):
     t.add_argument("--out")
     ph = sub.add_parser("phases")
     ph.add_argument("--trace", help="kernel-trace CSV (kernel_trace.csv) of a learned-workload run")
+    ph.add_argument("--top", type=int, default=14, help="rows of the kernel-duration table")
     ph.add_argument("--counters", help="--pmc counter CSV of a learned-workload run")
     ph.add_argument("--names", nargs="*", default=["SQ_VALU_MFMA_BUSY_CYCLES", "SQ_INSTS_LDS",
                                                    "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS", "SQ_BUSY_CYCLES"])
@@ -244,7 +247,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "phases":
         if a.trace:
-            print(phases_trace(a.trace))
+            print(phases_trace(a.trace, a.top))
         if a.counters:
             print(phases_counters(a.counters, a.names))
         return 0

@@ -77,3 +77,29 @@ def test_traffic_record_is_written_with_the_source_hash(tmp_path):
     rec = json.load(open(out))["w"]
     assert rec["source_sha256"] == profsum.kernel_source_hash("fwd")
     assert rec["stages"]["row_grad"]["read_bytes"] == pytest.approx(3.0 * 2048)
+
+
+def test_phase_table_splits_at_the_first_clamp_kernel_and_names_unet_kernels(tmp_path):
+    """Kernel-duration table by phase: prior-agent kernels (the CNN's and the
+    U-Net's) before the first CLAMP iteration kernel are training, after it
+    evaluation; anonymous-namespace prefixes are dropped; rows by total time."""
+    trace = tmp_path / "trace.csv"
+    rows = [("void clampk::k_conv<32, 0, 2>(clampk::ConvArgs)", 0, 100),
+            ("clampk::(anonymous namespace)::k_upconv(clampk::UpArgs)", 200, 250),
+            ("void clampk::k_row_grad<256>(clampk::RowArgs)", 300, 310),
+            ("void clampk::k_conv<32, 0, 2>(clampk::ConvArgs)", 400, 420),
+            ("void clampk::k_conv<32, 0, 2>(clampk::ConvArgs)", 500, 540),
+            ("clampk::(anonymous namespace)::k_upconv(clampk::UpArgs)", 600, 605)]
+    with open(trace, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for k, t0, t1 in rows:
+            w.writerow({"Kernel_Name": k, "Start_Timestamp": t0 * 1000, "End_Timestamp": t1 * 1000})
+    table = profsum.phases_trace(str(trace)).splitlines()
+    assert table[0] == "| kernel | phase | launches | avg us | total us |"
+    body = table[2:]
+    assert body[0] == "| `k_conv<32, 0, 2>` | training | 1 | 100.0 | 100 |"
+    assert "| `k_upconv` | training | 1 | 50.0 | 50 |" in body
+    assert "| `k_conv<32, 0, 2>` | evaluation | 2 | 30.0 | 60 |" in body
+    assert "| `k_upconv` | evaluation | 1 | 5.0 | 5 |" in body
+    assert not any("k_row_grad" in r for r in body)
