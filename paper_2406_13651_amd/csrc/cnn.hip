@@ -70,23 +70,26 @@ __device__ __forceinline__ int d_row(int l, int i) { return (l / 32) * 4 + (i / 
 // Convolution (forward or backward-data), tiled implicit GEMM on the
 // 32x32x16 bf16 MFMA.
 //
-// A block of 4 waves owns an output tile of 16 rows x 32 x-voxels and walks a
+// A block of 16 / RPW waves (RPW output rows per wave: 4, or 2 for the
+// forward layers) owns an output tile of 16 rows x 32 x-voxels and walks a
 // chunk of range slices.  Input slices (tile plus a one-voxel halo: 18 rows x
 // 34 voxels, zero outside the volume) live in two LDS slots: output slice z
 // takes its dz = -1 and dz = 0 taps from the slots holding input z - 1 and z,
 // then input z + 1 (fetched into registers during the previous step) replaces
 // input z - 1 and the dz = +1 taps follow, while input z + 2 is fetched.
 // Every weight fragment of the layer stays in LDS for the whole block, so the
-// MFMA loop reads only LDS.  Wave w computes rows 4w..4w+3; for each (dz, dy)
-// tap pair and K fragment q it reads the six input rows its four output rows
-// need once and applies each to up to three output rows (the dy taps).  K
+// MFMA loop reads only LDS.  Wave w computes rows RPW w .. RPW w + RPW - 1;
+// for each (dz, dy) tap pair and K fragment q it reads the RPW + 2 input rows
+// its output rows need once and applies each to up to three output rows (the
+// dy taps).  K
 // fragments: for 32 input channels q = (dx, channel half), 6 per (dz, dy); for
 // 8 input channels q pairs two dx taps (q = 0: dx = -1 in k 0..7 and dx = 0 in
 // k 8..15; q = 1: dx = +1 and zeros).  The product is formed transposed,
 // D[channel][voxel] = W^T X^T (weights as the A operand, inputs as B), so that
 // each lane ends with 16 output channels of one voxel in runs of four
-// consecutive channels and stores them, after bias and ReLU, straight to the
-// channels-last output as 8-byte runs.
+// consecutive channels; after bias and ReLU a swap between the lane halves
+// makes 16-byte runs of eight channels, stored straight to the channels-last
+// output.
 //
 // LDS layouts.  Input slot: 16-byte chunks; for 32 channels the chunk j of
 // voxel (row ys, column xs) sits at (ys * 34 + xs) * 4 + (j ^ ((xs >> 2) & 3)),
