@@ -772,6 +772,77 @@ def run_compare(args):
     print(json.dumps(result), flush=True)
 
 
+# The paper's own configuration (Sec. III-D and Sec. V): a 128^3 image from
+# 64 range samples zero-padded by q = 2, 9 looks, the U-Net prior; it states
+# under 0.5 s per CLAMP iteration on one NVIDIA Quadro RTX 8000.
+PAPER_CONFIG = dict(n=128, looks=9, radius=32.0, range_box=64)
+PAPER_SECONDS_PER_ITERATION = 0.5
+
+
+def run_paper(args):
+    """CLAMP iterations at the paper's configuration with its U-Net prior, and
+    with the Gaussian and CNN priors beside it (untrained weights: the time
+    of an iteration does not depend on them).  The paper's figure is an upper
+    bound on its time per iteration, so vs_baseline is a lower bound on the
+    ratio of iteration rates."""
+    import torch
+
+    import synth
+    import paper_2406_13651_amd as G
+    from paper_2406_13651_amd import learned as Lm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    c = PAPER_CONFIG
+    n, L, R, K = c["n"], c["looks"], c["radius"], c["range_box"]
+    spec = synth.SceneSpec("paper", n, n, n, L, R, 10.0, 24, 0.05, 1, 1)
+    log("paper configuration: %dx%dx%d, %d looks, range box %d (q = %g)" % (n, n, n, L, K, n / K))
+    r_true, y, s2w = synth.make_problem(spec, 0, workers=16, range_support=K)
+    yt = torch.from_numpy(y).to(dev)
+    del y
+    geo = (n, n, n, L, R, s2w, args.sigma2)
+    forms = {
+        "unet": lambda: Lm.LearnedClamp(*geo, prior=Lm.UnetPrior(Lm.unet_init_params(0), device=dev),
+                                        range_support=K, device=dev),
+        "gaussian": lambda: G.ClampGPU(*geo, with_prior=True, range_support=K, device=dev),
+        "cnn": lambda: Lm.LearnedClamp(*geo, prior=Lm.CnnPrior(Lm.init_params(0), device=dev), range_support=K,
+                                       device=dev),
+    }
+    out = {}
+    for name, make in forms.items():
+        g = make()
+        g.init(yt)
+        for _ in range(args.warmup):
+            g.iterate()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.iterate()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        out[name] = {"ms_per_iter": round(ms, 4), "fault": int(g.fault.item())}
+        log("  %-8s %.3f ms per iteration" % (name, ms))
+        del g
+        torch.cuda.empty_cache()
+    ms = out["unet"]["ms_per_iter"]
+    units = n ** 3 * L
+    print(json.dumps({
+        "metric": "fwd-agent voxel-looks/s + HBM GB/s vs peak; CLAMP iters/s at fixed NRMSE",
+        "value": units / (ms * 1e-3), "unit": "voxel-looks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "iters_per_s": 1e3 / ms,
+        "vs_baseline": (1e3 / ms) / (1.0 / PAPER_SECONDS_PER_ITERATION),
+        "baseline": {"value": 1.0 / PAPER_SECONDS_PER_ITERATION, "unit": "iterations/s",
+                     "source": "Sec. III-D: under 0.5 s per CLAMP iteration at 128^3 on one NVIDIA Quadro RTX 8000",
+                     "note": "an upper bound on the paper's time, another machine; context, not a target"},
+        "dtype": "f32 (forward agents), bf16 with f32 accumulation (U-Net)", "data": "synthetic",
+        "config": {"workload": "the paper's configuration: CLAMP with the U-Net prior, %dx%dx%d from %d range "
+                               "samples (q = %g, 3D operator), %d looks, pupil radius %g, SNR 10 dB" % (
+                                   n, n, n, K, n / K, L, R)},
+        "forms": out,
+    }))
+
+
 # The padded workload's cases: (name, zero-padding factor q, all-pass
 # aperture); q = 1, 1.5, 2 are the factors of Sec. V.
 PADDED_CASES = [("q=1", 1.0, False), ("q=1.5", 1.5, False), ("q=2", 2.0, False), ("ablation a=1, q=1", 1.0, True)]
@@ -925,6 +996,9 @@ def main():
         return
     if args.workload == "compare":
         run_compare(args)
+        return
+    if args.workload == "paper":
+        run_paper(args)
         return
 
     import numpy as np

@@ -58,3 +58,14 @@ def test_zero_padding_factors_of_the_padded_workload(paper):
     import bench
     qs = sorted({q for _, q, allpass in bench.PADDED_CASES if not allpass})
     assert qs == paper["zero_padding_q"]["values"]
+
+
+def test_paper_timing_configuration_of_the_bench(paper):
+    """The paper workload of bench.py runs the configuration the paper times
+    (Sec. III-D, Sec. V-A, Sec. V-B) and quotes its bound."""
+    import bench
+    t = paper["timing_configuration"]
+    c = bench.PAPER_CONFIG
+    assert [c["n"]] * 3 == t["image"] and c["looks"] == t["looks"]
+    assert c["n"] / c["range_box"] == t["q"]
+    assert bench.PAPER_SECONDS_PER_ITERATION == t["seconds_per_iteration_below"]
