@@ -843,6 +843,101 @@ def run_paper(args):
     }))
 
 
+def run_tiny(args):
+    """The tiny forward-only scene (32x32x16, 4 looks, pupil radius 8, SNR
+    20 dB; the looks' forward agents and the Mann step, no prior): latency
+    per CLAMP iteration, launched call by call through the single-scene
+    driver, as eager one-scene batched steps, and replayed from the batch's
+    captured HIP graph (one graph launch per iteration).  At this size an
+    iteration moves about 3.5 MB and is bound by launch latency, so no
+    roofline is reported.  The graph-replayed state is compared with the
+    single-scene driver's after the same iterations; the CPU baseline is
+    the float64 oracle's time per iteration of the same run."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2406_13651_amd as G
+
+    spec = synth.CONFIGS["tiny"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    r_true, y, s2w = synth.make_problem(spec, 0)
+    yt = torch.from_numpy(y).to(dev)
+    log("tiny forward-only scene %dx%dx%d, %d looks: %d warmup and %d timed iterations per form"
+        % (spec.nx, spec.ny, spec.nz, spec.looks, args.warmup, args.steps))
+    g = G.ClampGPU(spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, s2w, args.sigma2, with_prior=False,
+                   device=dev)
+    g.init(yt)
+    g.run(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run(args.steps)
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t0) / args.steps * 1e3
+
+    b = G.ClampBatchGPU([dict(nx=spec.nx, ny=spec.ny, nz=spec.nz, looks=spec.looks, radius=spec.radius,
+                              sigma_w2=s2w, sigma2=args.sigma2, with_prior=False)], device=dev)
+    b.init([yt])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            b.step(stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.step(stream)
+        stream.synchronize()
+        batch_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        b.capture(stream)
+        b.replay(1, stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        b.replay(args.steps, stream)
+        stream.synchronize()
+        graph_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    torch.cuda.synchronize()
+    # the single-scene driver brought to the batch's iteration count
+    g.run(b.k - g.k)
+    torch.cuda.synchronize()
+    w_b, w_g = b.states[0]["wbar"].cpu().numpy(), g.wbar.cpu().numpy()
+    gap = float(np.linalg.norm(w_b - w_g) / np.linalg.norm(w_g))
+    fault = int(b.fault.item()) | int(g.fault.item())
+    log("  single-scene %.4f ms, batch eager %.4f ms, graph replay %.4f ms per iteration; "
+        "graph vs single-scene rel. L2 %.2e after %d iterations" % (single_ms, batch_ms, graph_ms, gap, b.k))
+    units = spec.looks * spec.n
+    result = {
+        "metric": "fwd-agent voxel-looks/s + HBM GB/s vs peak; CLAMP iters/s at fixed NRMSE",
+        "value": units / (graph_ms * 1e-3), "unit": "voxel-looks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": graph_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tiny forward-only CLAMP (looks' forward agents + Mann step, no prior), %dx%dx%d, "
+                               "%d looks, pupil radius %g, SNR %g dB, one graph replay per iteration"
+                               % (spec.nx, spec.ny, spec.nz, spec.looks, spec.radius, spec.snr_db)},
+        "latency_us": {"graph_replay": round(graph_ms * 1e3, 2), "batch_eager": round(batch_ms * 1e3, 2),
+                       "single_scene_calls": round(single_ms * 1e3, 2)},
+        "roofline": None,
+        "graph_vs_single_scene_rel_l2": gap,
+        "iterations_compared": b.k,
+        "fault": fault,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        f32 = lambda v: float(np.float32(v))  # noqa: E731
+        iters = 20
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.clamp_run(y, spec.radius, f32(s2w), f32(args.sigma2), iters, with_prior=False, keep_hist=False)
+            times.append(time.perf_counter() - t0)
+        t = sorted(times)[1]
+        result["cpu_baseline"] = {"value": units * iters / t, "unit": "voxel-looks/s", "cores": 1,
+                                  "kind": "oracle", "ms_per_iter": round(t / iters * 1e3, 3),
+                                  "sample": "%d forward-only iterations of the same scene in float64, median of 3"
+                                            % iters}
+    print(json.dumps(result), flush=True)
+
+
 # The padded workload's cases: (name, zero-padding factor q, all-pass
 # aperture); q = 1, 1.5, 2 are the factors of Sec. V.
 PADDED_CASES = [("q=1", 1.0, False), ("q=1.5", 1.5, False), ("q=2", 2.0, False), ("ablation a=1, q=1", 1.0, True)]
@@ -999,6 +1094,9 @@ def main():
         return
     if args.workload == "paper":
         run_paper(args)
+        return
+    if args.workload == "tiny":
+        run_tiny(args)
         return
 
     import numpy as np
