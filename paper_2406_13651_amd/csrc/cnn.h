@@ -19,7 +19,7 @@ struct ConvArgs {
     int tiles_x, tiles_y;          // output tiles of 32 x-voxels and 16 rows (set by cnn_conv)
     int span;                      // output tile-slices per block (set by cnn_conv)
     const uint16_t* in;            // bf16 [voxel][CIN]
-    const uint16_t* wq;            // bf16 weight fragments [9][kQ][2][32][8] (cnn_prep_q)
+    const uint16_t* wq;            // bf16 weight fragments [9][kQ][2][32][8] (cnn_prep)
     const float* bias;             // fp32 [32] (EPI_RELU, EPI_FINAL)
     uint16_t* out;                 // bf16 [voxel][32] (EPI_RELU, EPI_DGRAD)
     float* out_f32;                // fp32 [voxel] (EPI_FINAL)
@@ -44,7 +44,6 @@ hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st);
 // First-layer weight fragments of k_conv_first (2048 bytes) from W [27][1][32].
 hipError_t cnn_prep_first(const float* W, uint16_t* wq, hipStream_t st);
 size_t cnn_wq_elems(int cinp);
-hipError_t cnn_prep_q(const float* W, int cin, int cout, int flip, int cinp, uint16_t* wq, hipStream_t st);
 hipError_t cnn_pack(const float* x, const float* scale, long nvox, uint16_t* x8, hipStream_t st);
 int cnn_reduce_blocks(long nvox);
 hipError_t cnn_mean(const float* x, long nvox, double* part, float* mean, hipStream_t st);
@@ -54,8 +53,11 @@ int cnn_wgrad_grid();
 size_t cnn_wgrad_part_bytes();
 // Weight gradient gw[27][cin][cout] and bias gradient gb[cout] of one layer.
 hipError_t cnn_wgrad(int ca, int cg, WgradArgs a, int cin, int cout, float* gw, float* gb, hipStream_t st);
-// Adam step with gradient-norm clipping; clip: device float[2] state (zeroed
-// with the parameters), see k_grad_clip.
+// Adam step with gradient-norm clipping; clip: device float[kClipFloats],
+// 8-byte aligned: the state clip[0..1] (zeroed with the parameters, see
+// k_grad_clip), then kNormBlocks float64 partial sums of the squared norm.
+constexpr int kNormBlocks = 64;
+constexpr int kClipFloats = 2 + 2 * kNormBlocks;
 hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float lr, int step, float* clip,
                     hipStream_t st);
 // Weight fragments of a layer for the forward (wq, cinp input channels) and

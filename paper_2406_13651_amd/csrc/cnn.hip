@@ -95,7 +95,7 @@ __device__ __forceinline__ int d_row(int l, int i) { return (l / 32) * 4 + (i / 
 // voxel (row ys, column xs) sits at (ys * 34 + xs) * 4 + (j ^ ((xs >> 2) & 3)),
 // so that the 16 lanes of one 128-bit LDS access phase (16 consecutive voxels,
 // one chunk each) hit 16 distinct 16-byte bank groups of the 256-byte bank
-// window.  Weights: wq[g = 3 dz + dy][q][h][n][8] (see k_prep_q), 16 lanes of
+// window.  Weights: wq[g = 3 dz + dy][q][h][n][8] (see prep_q_elem), 16 lanes of
 // one phase reading 16 consecutive fragments rows.
 constexpr int kTileRows = 16;
 constexpr int kTileCols = 32;
@@ -814,13 +814,17 @@ __global__ __launch_bounds__(kCnnBlock) void k_loss_final(const double* part, in
 //
 // A persistent grid walks work items (volume, 8 output rows x 32 x-voxels,
 // chunk of range slices).  Per range slice z the block holds in LDS, channel
-// major ("transposed", x contiguous): g of the 8 x 32 output tile, and act of
-// slices z - 1, z, z + 1 over 10 rows x 32 x-voxels (x0 .. x0 + 31) in a ring
-// of three slots, with the one-voxel x halo of each row and channel (voxels
-// x0 - 1 and x0 + 32) in a separate array [slot][row][side][channel], where
-// the 64 lanes of a wave read 64 consecutive dwords.  Global data is
-// channels-last; each fill unit loads 8 voxels x 8 channels and transposes
-// them in registers (byte permutes).
+// major ("transposed", x contiguous): g of the 8 x 32 output tile (two
+// slots), and act of slices z - 1, z, z + 1 over 10 rows x 32 x-voxels (x0 ..
+// x0 + 31) in a ring of four slots, with the one-voxel x halo of each row and
+// channel (voxels x0 - 1 and x0 + 32) in a separate array
+// [slot][row][side][channel], where the 64 lanes of a wave read 64
+// consecutive dwords.  While step z runs, the filling waves store act slice
+// z + 2 and g slice z + 1, loaded during the previous step, into the slots
+// step z does not read, and load the next ones: one barrier per step, and
+// the loads have a whole step to arrive.  Global data is channels-last; each
+// fill unit loads 8 voxels x 8 channels and transposes them in registers
+// (byte permutes).
 // The MFMA's K = 16 voxels: lanes h = 0 and 1 of a channel take the x-voxels
 // x0 + 16 h .. x0 + 16 h + 15 over the two MFMAs of an output row (the K
 // index only has to agree between A and B).  The dx = -1 and +1 operands come
@@ -830,8 +834,9 @@ __global__ __launch_bounds__(kCnnBlock) void k_loss_final(const double* part, in
 // Eight waves per block, two per SIMD (each holds 7 accumulator tiles, 112
 // AGPRs), so that one wave's LDS waits, fills and barriers overlap the other's
 // MFMAs.  Wave (tg, kh): taps 7 tg .. 7 tg + 6 (tg = 3: taps 21 .. 26 and the
-// bias), output rows 4 kh .. 4 kh + 3.  Each wave writes its sums to
-// part[2 block + kh][28][32][32] (tap 27 = bias); k_wgrad_reduce adds the
+// bias), output rows 4 kh .. 4 kh + 3.  The two row halves of a tap group
+// are added through LDS at the end, and the block writes its sums to
+// part[block][28][32][32] (tap 27 = bias); k_wgrad_reduce adds the blocks'
 // partial sums in a fixed order.
 // Channel planes are padded to an odd number of 16-byte chunks (41 and 33) so
 // that the lanes of one 128-bit LDS phase hit distinct bank groups.
@@ -840,6 +845,8 @@ constexpr int kWgBlock = 512;
 constexpr int kActPlane4 = 41;  // uint4 per channel plane of an act slot (10 x 32 bf16 + 8 pad)
 constexpr int kGPlane4 = 33;    // uint4 per channel plane of the g tile (8 x 32 bf16 + 8 pad)
 constexpr int kHaloSlot = 10 * 2 * 32;  // dwords of an act slot's halo array
+static_assert(2 * 7 * 16 * 64 * sizeof(float) <= 4 * 32 * kActPlane4 * sizeof(uint4),
+              "the act slots hold two tap groups' sums for the row-half combine");
 
 // 8 x 8 bf16 transpose: in[v][k] = dword k (channels 2k, 2k + 1) of voxel v;
 // out[c][p] = dword p (voxels 2p, 2p + 1) of channel c.
@@ -855,18 +862,29 @@ __device__ __forceinline__ void transpose8(const uint32_t (&in)[8][4], uint32_t 
 }
 
 // Loads 8 voxels (x, x + 1, .., x + 7 of one row) x 8 channels (group cg) of
-// a channels-last tensor with C stored channels; zeros where `ok` is false.
+// a channels-last tensor with C stored channels.  Where `ok` is false (or the
+// group is past C) the lanes read the tensor's first 16 bytes instead, and
+// the returned flag is false: the caller zeroes them with mask8x8 when it
+// consumes them, so that nothing waits on the loads before then.
 template <int C>
-__device__ __forceinline__ void load8x8(const uint16_t* base, long vox0, int cg, bool ok, uint32_t (&v)[8][4]) {
+__device__ __forceinline__ bool load8x8(const uint16_t* base, long vox0, int cg, bool ok, uint32_t (&v)[8][4]) {
     ok = ok && cg * 8 < C;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const uint4 q = *reinterpret_cast<const uint4*>(base + (ok ? (vox0 + e) * C + cg * 8 : 0));
-        v[e][0] = ok ? q.x : 0u;
-        v[e][1] = ok ? q.y : 0u;
-        v[e][2] = ok ? q.z : 0u;
-        v[e][3] = ok ? q.w : 0u;
+        v[e][0] = q.x;
+        v[e][1] = q.y;
+        v[e][2] = q.z;
+        v[e][3] = q.w;
     }
+    return ok;
+}
+
+__device__ __forceinline__ void mask8x8(bool ok, uint32_t (&v)[8][4]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[e][k] = ok ? v[e][k] : 0u;
 }
 
 // Operand of tap dx of an 8-voxel chunk c (voxels x .. x + 7): dx = 0 takes
@@ -891,7 +909,7 @@ __device__ __forceinline__ uint4 shifted_chunk(uint4 c, uint32_t before, uint32_
 
 template <int TG, int CA, int CG>
 __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 * kActPlane4],
-                                            uint32_t (*halo)[kHaloSlot], uint4* gt, int wave) {
+                                            uint32_t (*halo)[kHaloSlot], uint4 (*gt)[32 * kGPlane4], int wave) {
     constexpr int T0 = 7 * TG;
     constexpr int NT = TG == 3 ? 6 : 7;
     constexpr bool BIAS = TG == 3;
@@ -906,12 +924,14 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
     for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
 
     // fill-unit coordinates: act units 0..239 on threads 0..239 (chunk a_xc of
-    // a row: 0 and 5 are the halo chunks), g units 0..127 on threads 256..383;
+    // a row: 0 and 5 are the halo chunks), g units 0..127 on threads 384..511
+    // (waves 6 and 7, so that no SIMD holds two filling waves of one kind);
     // the role is uniform per wave, and one prefetch buffer serves both
-    const bool act_role = u < 256;
+    const bool act_role = u < 256, g_role = u >= 384;
     const int a_xc = u % 6, a_ys = (u / 6) % 10, a_cg = u / 60;
-    const int gu = u - 256, g_xc = gu & 3, g_r = (gu >> 2) & 7, g_cg = gu >> 5;
+    const int gu = u - 384, g_xc = gu & 3, g_r = (gu >> 2) & 7, g_cg = gu >> 5;
     uint32_t pf[8][4], tr[8][4];
+    bool pf_ok = false;
 
     for (int item = blockIdx.x; item < a.items; item += gridDim.x) {
         int b = item;
@@ -928,17 +948,18 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
         auto fetch_act = [&](int zin) {
             const int y = y0 - 1 + a_ys, x = x0 - 8 + 8 * a_xc;
             const bool ok = u < 240 && zin >= 0 && zin < a.nz && y >= 0 && y < a.ny && x >= 0 && x < a.nx;
-            load8x8<CA>(a.act, ok ? vol_off + ((long)zin * a.ny + y) * a.nx + x : 0, a_cg, ok, pf);
+            pf_ok = load8x8<CA>(a.act, ok ? vol_off + ((long)zin * a.ny + y) * a.nx + x : 0, a_cg, ok, pf);
         };
         auto fetch_g = [&](int zz) {
             const int y = y0 + g_r, x = x0 + 8 * g_xc;
             const bool ok = gu >= 0 && gu < 128 && zz < a.nz && y < a.ny;
-            load8x8<CG>(a.g, ok ? vol_off + ((long)zz * a.ny + y) * a.nx + x : 0, g_cg, ok, pf);
+            pf_ok = load8x8<CG>(a.g, ok ? vol_off + ((long)zz * a.ny + y) * a.nx + x : 0, g_cg, ok, pf);
         };
         auto store_act = [&](int zin) {
             if (u < 240) {
+                mask8x8(pf_ok, pf);
                 transpose8(pf, tr);
-                const int s = (zin + 3) % 3;
+                const int s = (zin + 4) & 3;
                 if (a_xc == 0 || a_xc == 5) {  // keep the dword next to the tile: x0 - 2, x0 - 1 or x0 + 32, x0 + 33
                     uint32_t* hs = halo[s] + (a_ys * 2 + (a_xc == 5 ? 1 : 0)) * 32 + a_cg * 8;
 #pragma unroll
@@ -952,15 +973,21 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
                 }
             }
         };
-        auto store_g = [&]() {
+        auto store_g = [&](int zz) {
             if (gu >= 0 && gu < 128) {
+                mask8x8(pf_ok, pf);
                 transpose8(pf, tr);
+                uint4* gs = gt[zz & 1];
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
-                    gt[(g_cg * 8 + k) * kGPlane4 + g_r * 4 + g_xc] = make_uint4(tr[k][0], tr[k][1], tr[k][2], tr[k][3]);
+                    gs[(g_cg * 8 + k) * kGPlane4 + g_r * 4 + g_xc] = make_uint4(tr[k][0], tr[k][1], tr[k][2], tr[k][3]);
             }
         };
 
+        // Ring of four act slots (slice zin in slot zin mod 4) and two g
+        // slots: step z reads act slices z - 1 .. z + 1 and g slice z, while
+        // the filling waves store act slice z + 2 and g slice z + 1 (loaded a
+        // step earlier) into the slots it does not read; one barrier per step.
         __syncthreads();  // the previous item's reads are done
         if (act_role) {
             fetch_act(z0 - 1);
@@ -969,24 +996,22 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
             store_act(z0);
             fetch_act(z0 + 1);
             store_act(z0 + 1);
-        } else {
+            if (z0 + 1 < z1) fetch_act(z0 + 2);
+        } else if (g_role) {
             fetch_g(z0);
-            store_g();
+            store_g(z0);
+            if (z0 + 1 < z1) fetch_g(z0 + 1);
         }
         __syncthreads();
 
         for (int z = z0; z < z1; ++z) {
-            const bool next = z + 1 < z1;
-            if (next) {
-                if (act_role) fetch_act(z + 2);
-                else fetch_g(z + 1);
-            }
+            const uint4* gz = gt[z & 1];
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
                 const int r = 4 * kh + rr;
                 // A of the row's two MFMAs: g at x0 + 16 h .. + 7 and x0 + 16 h + 8 .. + 15
-                const v8bf A0 = __builtin_bit_cast(v8bf, gt[m * kGPlane4 + r * 4 + 2 * h]);
-                const v8bf A1 = __builtin_bit_cast(v8bf, gt[m * kGPlane4 + r * 4 + 2 * h + 1]);
+                const v8bf A0 = __builtin_bit_cast(v8bf, gz[m * kGPlane4 + r * 4 + 2 * h]);
+                const v8bf A1 = __builtin_bit_cast(v8bf, gz[m * kGPlane4 + r * 4 + 2 * h + 1]);
                 if constexpr (BIAS) {
                     accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, ones, accb, 0, 0, 0);
                     accb = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, ones, accb, 0, 0, 0);
@@ -995,7 +1020,7 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
                 for (int pair = 0; pair < 9; ++pair) {
                     const int t_lo = pair * 3;
                     if (t_lo + 2 < T0 || t_lo >= T0 + NT) continue;  // no tap of this wave
-                    const int dz = pair / 3, dy = pair % 3, s = (z + dz + 2) % 3;
+                    const int dz = pair / 3, dy = pair % 3, s = (z + dz + 3) & 3;
                     const uint4* row = act[s] + m * kActPlane4 + (r + dy) * 4 + 2 * h;
                     const uint4 c0 = row[0], c1 = row[1];
                     const uint32_t hw = halo[s][(r + dy) * 64 + lane];
@@ -1017,31 +1042,63 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
                     }
                 }
             }
-            if (next) {
-                __syncthreads();  // every wave is done with act slice z - 1 and g slice z
-                if (act_role) store_act(z + 2);
-                else store_g();
-                __syncthreads();
+            if (z + 1 < z1) {
+                if (act_role) {
+                    store_act(z + 2);
+                    if (z + 2 < z1) fetch_act(z + 3);
+                } else if (g_role) {
+                    store_g(z + 1);
+                    if (z + 2 < z1) fetch_g(z + 2);
+                }
+                __syncthreads();  // slices z + 2 and z + 1 are in; step z's slots are free for step z + 1's fill
             }
         }
     }
-    // partial sums: D[co][ci] with co = d_row(lane, i), ci = m
-    float* dst = a.part + (long)(2 * blockIdx.x + kh) * 28 * 1024;
+    // The two waves of a tap group (kh = 0, 1) hold sums over different
+    // output rows.  kh = 1 hands its sums to kh = 0 through LDS (the act
+    // slots, free once every wave is past its last item), two tap groups at a
+    // time, and kh = 0 writes the block's partial sums D[co][ci] (co =
+    // d_row(lane, i), ci = m) to part[block][28][32][32], tap 27 the bias.
+    // Every wave passes the same four barriers.
+    float* red = reinterpret_cast<float*>(&act[0][0]);
+    float* dst = a.part + (long)blockIdx.x * 28 * 1024;
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int phase = 0; phase < 2; ++phase) {
+        constexpr int kSlot = 7 * 16 * 64;  // floats of one tap group's sums
+        const bool mine = (TG >> 1) == phase;
+        float* slot = red + (TG & 1) * kSlot;
+        __syncthreads();  // the tiles (phase 0) or the previous phase's slots are free
+        if (mine && kh == 1) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) dst[(T0 + t) * 1024 + d_row(lane, i) * 32 + m] = acc[t][i];
-    if constexpr (BIAS) {
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) dst[27 * 1024 + d_row(lane, i) * 32 + m] = accb[i];
+                for (int i = 0; i < 16; ++i) slot[(t * 16 + i) * 64 + lane] = acc[t][i];
+            if constexpr (BIAS) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) slot[(6 * 16 + i) * 64 + lane] = accb[i];
+            }
+        }
+        __syncthreads();
+        if (mine && kh == 0) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    dst[(T0 + t) * 1024 + d_row(lane, i) * 32 + m] = acc[t][i] + slot[(t * 16 + i) * 64 + lane];
+            if constexpr (BIAS) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    dst[27 * 1024 + d_row(lane, i) * 32 + m] = accb[i] + slot[(6 * 16 + i) * 64 + lane];
+            }
+        }
     }
 }
 
 template <int CA, int CG>
 __global__ __launch_bounds__(kWgBlock, 1) void k_wgrad(WgradArgs a) {
-    __shared__ uint4 act[3][32 * kActPlane4];
-    __shared__ uint32_t halo[3][kHaloSlot];
-    __shared__ uint4 gt[32 * kGPlane4];
+    __shared__ uint4 act[4][32 * kActPlane4];
+    __shared__ uint32_t halo[4][kHaloSlot];
+    __shared__ uint4 gt[2][32 * kGPlane4];
     const int wave = threadIdx.x >> 6;
     switch (wave >> 1) {
         case 0: wgrad_block<0, CA, CG>(a, act, halo, gt, wave); break;
@@ -1089,47 +1146,49 @@ __global__ __launch_bounds__(kCnnBlock) void k_wgrad_reduce(const float* part, i
 // Gradient-norm clipping state: clip[0] the running norm of the (clipped)
 // gradients, clip[1] the factor for the coming step -- min(1, kClipRatio x
 // running norm / norm), 1 on the first step, 0 for a non-finite norm (the
-// step is skipped).  One block of 1024 threads, fixed reduction order.
-constexpr int kClipBlock = 1024;
+// step is skipped).  The squared norm is summed in a fixed order: block b of
+// k_grad_sq adds the float4s b x kCnnBlock + tid, stepping by the grid, into
+// clip's partial sums (float64, from byte 8), then k_grad_clip adds those in
+// block order.
 constexpr float kClipRatio = 3.f;
 constexpr float kClipDecay = 0.95f;
 
-__global__ __launch_bounds__(kClipBlock) void k_grad_clip(const float* g, int n, float* clip) {
-    __shared__ double part[kClipBlock];
+__global__ __launch_bounds__(kCnnBlock) void k_grad_sq(const float* g, int n, double* part) {
+    // the unaligned head (if any) and the tail one by one
+    const int head = (int)((16 - (reinterpret_cast<uintptr_t>(g) & 15)) & 15) / 4;
+    const int h = head < n ? head : n;
+    const int n4 = (n - h) / 4;
+    const float4* g4 = reinterpret_cast<const float4*>(g + h);
+    const int tid = blockIdx.x * kCnnBlock + threadIdx.x, stride = kNormBlocks * kCnnBlock;
     double acc = 0.0;
-    // eight independent loads in flight per thread, then summed in a fixed order
-    for (int i0 = threadIdx.x; i0 < n; i0 += 8 * kClipBlock) {
-        float v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u * kClipBlock;
-            v[u] = i < n ? g[i] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += (double)v[u] * v[u];
+    for (int i = tid; i < n4; i += stride) {
+        const float4 v = g4[i];
+        acc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
     }
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = kClipBlock / 2; w > 0; w /= 2) {
-        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-        __syncthreads();
+    if (tid < h) acc += (double)g[tid] * g[tid];
+    for (int i = h + 4 * n4 + tid; i < n; i += stride) acc += (double)g[i] * g[i];
+    double a[1] = {acc};
+    cnn_block_sum<1>(a, part + blockIdx.x);
+}
+
+__global__ void k_grad_clip(const double* part, float* clip) {
+    if (threadIdx.x != 0) return;
+    double sq = 0.0;
+    for (int b = 0; b < kNormBlocks; ++b) sq += part[b];
+    const float norm = (float)sqrt(sq);
+    const float run = clip[0];
+    float c;
+    if (!isfinite(norm)) {
+        c = 0.f;
+    } else if (run <= 0.f) {
+        c = 1.f;
+        clip[0] = norm;
+    } else {
+        const float cap = kClipRatio * run;
+        c = norm > cap ? cap / norm : 1.f;
+        clip[0] = kClipDecay * run + (1.f - kClipDecay) * fminf(norm, cap);
     }
-    if (threadIdx.x == 0) {
-        const float norm = (float)sqrt(part[0]);
-        const float run = clip[0];
-        float c;
-        if (!isfinite(norm)) {
-            c = 0.f;
-        } else if (run <= 0.f) {
-            c = 1.f;
-            clip[0] = norm;
-        } else {
-            const float cap = kClipRatio * run;
-            c = norm > cap ? cap / norm : 1.f;
-            clip[0] = kClipDecay * run + (1.f - kClipDecay) * fminf(norm, cap);
-        }
-        clip[1] = c;
-    }
+    clip[1] = c;
 }
 
 // Adam with bias correction on the flat parameter vector, with the gradient
@@ -1148,22 +1207,15 @@ __global__ __launch_bounds__(kCnnBlock) void k_adam(float* p, float* m, float* v
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// Zero-padded fp32 copy of a layer's bias.
-__global__ void k_prep_bias(const float* b, int cout, float* bias32) {
-    const int e = threadIdx.x;
-    if (e < 32) bias32[e] = e < cout ? b[e] : 0.f;
-}
-
 // Weight fragments of the tiled convolution: wq[g = 3 dz + dy][q][h][n][8]
 // (bf16) holds k = 8 h .. 8 h + 7 of K fragment q for output channel n, for
 // the input-channel count CINP (8 or 32), from the fp32 W[t][cin][cout].
 // Forward: the effective weight is W[t][ci][co]; backward data (flip):
 // W[26 - t][co][ci] with the channel roles swapped.  Entries beyond the real
 // channel counts and the zero half of the last 8-channel fragment are zero.
-__global__ __launch_bounds__(kCnnBlock) void k_prep_q(const float* W, int cin, int cout, int flip, int cinp,
-                                                     uint16_t* wq) {
+__device__ __forceinline__ void prep_q_elem(const float* W, int cin, int cout, int flip, int cinp, uint16_t* wq,
+                                            int e) {
     const int nq = cinp == 32 ? 6 : 2;
-    const int e = blockIdx.x * kCnnBlock + threadIdx.x;
     if (e >= 9 * nq * 32 * 16) return;
     const int k8 = e % 8, n = (e / 8) % 32, hh = (e / 256) % 2, q = (e / 512) % nq, g = e / (512 * nq);
     const int kk = 8 * hh + k8;
@@ -1184,6 +1236,23 @@ __global__ __launch_bounds__(kCnnBlock) void k_prep_q(const float* W, int cin, i
     if (!zero && ci < ein && n < eout)
         w = flip ? W[((26 - t) * cin + n) * cout + ci] : W[(t * cin + ci) * cout + n];
     wq[e] = f2bf(w);
+}
+
+// A layer's operands in one launch: the forward fragments (blocks 0 ..
+// nb_f - 1), the backward-data fragments (the next nb_d blocks; none without
+// wqd) and, in the last block, the zero-padded fp32 copy of the bias.
+__global__ __launch_bounds__(kCnnBlock) void k_prep_layer(const float* W, const float* b, int cin, int cout,
+                                                         int cinp, int coutp, uint16_t* wq, uint16_t* wqd,
+                                                         float* bias32, int nb_f, int nb_d) {
+    const int blk = blockIdx.x;
+    if (blk < nb_f) {
+        prep_q_elem(W, cin, cout, 0, cinp, wq, blk * kCnnBlock + threadIdx.x);
+    } else if (blk < nb_f + nb_d) {
+        prep_q_elem(W, cin, cout, 1, coutp, wqd, (blk - nb_f) * kCnnBlock + threadIdx.x);
+    } else {
+        const int e = threadIdx.x;
+        if (e < 32) bias32[e] = e < cout ? b[e] : 0.f;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1260,12 +1329,6 @@ hipError_t cnn_conv(int cin, int epi, ConvArgs a, hipStream_t st) {
 
 size_t cnn_wq_elems(int cinp) { return (size_t)9 * (cinp == 32 ? 6 : 2) * 32 * 16; }
 
-hipError_t cnn_prep_q(const float* W, int cin, int cout, int flip, int cinp, uint16_t* wq, hipStream_t st) {
-    const int n = (int)cnn_wq_elems(cinp);
-    hipLaunchKernelGGL(k_prep_q, dim3((n + kCnnBlock - 1) / kCnnBlock), dim3(kCnnBlock), 0, st, W, cin, cout, flip,
-                       cinp, wq);
-    return hipGetLastError();
-}
 
 hipError_t cnn_pack(const float* x, const float* scale, long nvox, uint16_t* x8, hipStream_t st) {
     hipLaunchKernelGGL(k_pack, dim3(grid_for(nvox, kCnnBlock, 8192)), dim3(kCnnBlock), 0, st, x, scale, nvox, x8);
@@ -1300,7 +1363,7 @@ int cnn_wgrad_grid() {
     return cus;
 }
 
-size_t cnn_wgrad_part_bytes() { return (size_t)2 * cnn_wgrad_grid() * 28 * 1024 * sizeof(float); }
+size_t cnn_wgrad_part_bytes() { return (size_t)cnn_wgrad_grid() * 28 * 1024 * sizeof(float); }
 
 hipError_t cnn_wgrad(int ca, int cg, WgradArgs a, int cin, int cout, float* gw, float* gb, hipStream_t st) {
     a.tiles_x = a.nx / 32;
@@ -1320,8 +1383,7 @@ hipError_t cnn_wgrad(int ca, int cg, WgradArgs a, int cin, int cout, float* gw, 
     else if (ca == 32 && cg == 8) LAUNCH(32, 8);
     else return hipErrorInvalidValue;
 #undef LAUNCH
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(28 * 1024 / 16), dim3(kCnnBlock), 0, st, a.part, 2 * grid, cin, cout, gw,
-                       gb);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(28 * 1024 / 16), dim3(kCnnBlock), 0, st, a.part, grid, cin, cout, gw, gb);
     return hipGetLastError();
 }
 
@@ -1329,7 +1391,9 @@ hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float l
                     hipStream_t st) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = (float)(1.0 - std::pow(0.9, step)), c2 = (float)(1.0 - std::pow(0.999, step));
-    hipLaunchKernelGGL(k_grad_clip, dim3(1), dim3(kClipBlock), 0, st, g, n, clip);
+    double* part = reinterpret_cast<double*>(clip + 2);
+    hipLaunchKernelGGL(k_grad_sq, dim3(kNormBlocks), dim3(kCnnBlock), 0, st, g, n, part);
+    hipLaunchKernelGGL(k_grad_clip, dim3(1), dim3(64), 0, st, (const double*)part, clip);
     hipLaunchKernelGGL(k_adam, dim3((n + kCnnBlock - 1) / kCnnBlock), dim3(kCnnBlock), 0, st, p, m, v, g, n, lr, b1, b2,
                        eps, c1, c2, (const float*)clip);
     return hipGetLastError();
@@ -1337,10 +1401,10 @@ hipError_t cnn_adam(float* p, float* m, float* v, const float* g, int n, float l
 
 hipError_t cnn_prep(const float* W, const float* b, int cin, int cout, int cinp, int coutp, uint16_t* wq,
                     uint16_t* wqd, float* bias32, hipStream_t st) {
-    hipError_t e = cnn_prep_q(W, cin, cout, 0, cinp, wq, st);
-    if (e == hipSuccess && wqd != nullptr) e = cnn_prep_q(W, cin, cout, 1, coutp, wqd, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_prep_bias, dim3(1), dim3(32), 0, st, b, cout, bias32);
+    const int nb_f = (int)((cnn_wq_elems(cinp) + kCnnBlock - 1) / kCnnBlock);
+    const int nb_d = wqd != nullptr ? (int)((cnn_wq_elems(coutp) + kCnnBlock - 1) / kCnnBlock) : 0;
+    hipLaunchKernelGGL(k_prep_layer, dim3(nb_f + nb_d + 1), dim3(kCnnBlock), 0, st, W, b, cin, cout, cinp, coutp, wq,
+                       wqd, bias32, nb_f, nb_d);
     return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ struct clamp_cnn {
     float* m = nullptr;
     float* v = nullptr;
     float* grad = nullptr;
-    float* clip = nullptr;        // gradient-norm clipping state [2]
+    float* clip = nullptr;        // gradient-norm clipping state [2] + norm partial sums
     uint16_t* wq[kLayers] = {};   // forward weight fragments
     uint16_t* wqd[kLayers] = {};  // backward-data weight fragments
     uint16_t* wq1 = nullptr;      // first-layer fragments of the one-channel form (evaluation)
@@ -197,7 +197,7 @@ clamp_status clamp_cnn_create(clamp_cnn** out) {
     if (st == CLAMP_OK) st = alloc(c, CLAMP_CNN_PARAMS, &c->m);
     if (st == CLAMP_OK) st = alloc(c, CLAMP_CNN_PARAMS, &c->v);
     if (st == CLAMP_OK) st = alloc(c, CLAMP_CNN_PARAMS, &c->grad);
-    if (st == CLAMP_OK) st = alloc(c, 2, &c->clip);
+    if (st == CLAMP_OK) st = alloc(c, clampk::kClipFloats, &c->clip);
     for (int l = 0; l < kLayers && st == CLAMP_OK; ++l) {
         st = alloc(c, clampk::cnn_wq_elems(cinp_of(l)), &c->wq[l]);
         if (st == CLAMP_OK) st = alloc(c, clampk::cnn_wq_elems(coutp_of(l)), &c->wqd[l]);

@@ -116,7 +116,7 @@ struct clamp_unet {
     float* m = nullptr;                 // Adam moments and gradient (CLAMP_UNET_PARAMS)
     float* v = nullptr;
     float* grad = nullptr;
-    float* clip = nullptr;              // gradient-norm clipping state [2]
+    float* clip = nullptr;              // gradient-norm clipping state [2] + norm partial sums
     float* zero32 = nullptr;            // zero bias of the batch-normalised convolutions
     float* bscratch = nullptr;          // [32] bias gradients the bias-free convolutions discard
     uint16_t* wqt[kConvs] = {};         // forward fragments of the unfolded convolutions
@@ -529,7 +529,7 @@ clamp_status clamp_unet_create(clamp_unet** out) {
     if (st == CLAMP_OK) st = alloc(u, CLAMP_UNET_PARAMS, &u->m);
     if (st == CLAMP_OK) st = alloc(u, CLAMP_UNET_PARAMS, &u->v);
     if (st == CLAMP_OK) st = alloc(u, CLAMP_UNET_PARAMS, &u->grad);
-    if (st == CLAMP_OK) st = alloc(u, 2, &u->clip);
+    if (st == CLAMP_OK) st = alloc(u, clampk::kClipFloats, &u->clip);
     if (st == CLAMP_OK) st = alloc(u, 32, &u->zero32);
     if (st == CLAMP_OK) st = alloc(u, 32, &u->bscratch);
     if (st == CLAMP_OK) st = alloc(u, 32, &u->bias_t);
