@@ -78,7 +78,10 @@ __global__ __launch_bounds__(kBlock) void k_pool2(const uint16_t* in, uint16_t* 
 // added, a swap between the lane halves gives it 8 consecutive channels 16 p +
 // 8 h + 0..7 (p = 0, 1) in fp32, to which the skip is added before rounding.
 __global__ __launch_bounds__(kBlock) void k_upconv(UpArgs a) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index read from the first lane: the run, the row bases and the
+    // buffer descriptors derived from it are then scalar (no per-lane loop
+    // around each buffer access)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int m = lane & 31, h = lane >> 5;
     const int runs = (a.nx + 31) / 32;
     const long total = (long)a.nvol * a.nz * a.ny * runs;
@@ -434,7 +437,10 @@ __global__ __launch_bounds__(kBlock) void k_pool2_bwd(const uint16_t* e, const u
 // ReLU pattern of relu_src when MASK.
 template <bool MASK>
 __global__ __launch_bounds__(kBlock) void k_upconv_dgrad(UpBwdArgs a) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index read from the first lane: the run, the row bases and the
+    // buffer descriptors derived from it are then scalar (no per-lane loop
+    // around each buffer access)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int m = lane & 31, h = lane >> 5;
     const int runs = (a.nx + 31) / 32;
     const long total = (long)a.nvol * a.nz * a.ny * runs;
