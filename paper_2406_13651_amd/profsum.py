@@ -137,7 +137,7 @@ def traffic(fetch_csv, write_csv, probe_mib, skip_first=1):
     return per, f_scale / 1024.0, w_scale / 1024.0
 
 
-CNN_KERNELS = (r"k_conv", r"k_wgrad", r"k_pack\(", r"k_grad_clip\(", r"k_prep_", r"k_adam\(", r"k_loss",
+CNN_KERNELS = (r"k_conv", r"k_wgrad", r"k_pack\(", r"k_grad_clip\(", r"k_grad_sq\(", r"k_prep_", r"k_adam\(", r"k_loss",
                # the U-Net's own kernels (pooling, transposed convolutions, batch normalisation)
                r"k_upconv", r"k_pool2", r"k_chan_", r"k_affine<", r"k_fold_bn\(", r"k_sum_blocks\(")
 
