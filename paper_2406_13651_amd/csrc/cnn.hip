@@ -925,8 +925,8 @@ __device__ __forceinline__ void wgrad_block(const WgradArgs& a, uint4 (*act)[32 
 
     // fill-unit coordinates: act units 0..239 on threads 0..239 (chunk a_xc of
     // a row: 0 and 5 are the halo chunks), g units 0..127 on threads 384..511
-    // (waves 6 and 7, so that no SIMD holds two filling waves of one kind);
-    // the role is uniform per wave, and one prefetch buffer serves both
+    // (waves 6 and 7); the role is uniform per wave, and one prefetch buffer
+    // serves both
     const bool act_role = u < 256, g_role = u >= 384;
     const int a_xc = u % 6, a_ys = (u / 6) % 10, a_cg = u / 60;
     const int gu = u - 384, g_xc = gu & 3, g_r = (gu >> 2) & 7, g_cg = gu >> 5;
