@@ -604,14 +604,16 @@ __global__ __launch_bounds__(kBlock) void k_upconv_wgrad(UpBwdArgs a, float* par
 __global__ __launch_bounds__(kBlock) void k_sum_blocks(const float* part, int blocks, int n, float* out) {
     const int e = blockIdx.x * kBlock + threadIdx.x;
     if (e >= n) return;
+    // partials added in block order, 32 loads in flight per thread (the grid
+    // is only n / kBlock blocks, so latency, not bandwidth, sets the time)
     float acc = 0.f;
     int b = 0;
-    for (; b + 8 <= blocks; b += 8) {
-        float q[8];
+    for (; b + 32 <= blocks; b += 32) {
+        float q[32];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) q[u] = part[(long)(b + u) * n + e];
+        for (int u = 0; u < 32; ++u) q[u] = part[(long)(b + u) * n + e];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += q[u];
+        for (int u = 0; u < 32; ++u) acc += q[u];
     }
     for (; b < blocks; ++b) acc += part[(long)b * n + e];
     out[e] = acc;
